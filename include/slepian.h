@@ -1,0 +1,217 @@
+/*
+ * slepian.h -- C ABI of libslepian, a gfx950 (MI355X) implementation of the
+ * fast Slepian transform of Karnik, Zhu, Wakin, Romberg and Davenport
+ * ("The Fast Slepian Transform", arXiv:1611.04950).
+ *
+ * Notation (Section 2.1-2.2 of the paper): N signal length, W in (0, 1/2)
+ * half bandwidth, B the N x N prolate matrix B[m,n] = sin(2 pi W (m-n)) /
+ * (pi (m-n)) (diagonal 2W), lambda_0 > ... > lambda_{N-1} its eigenvalues,
+ * S = [s_0 ... s_{N-1}] its orthonormal eigenvectors (the Slepian basis),
+ * S_K the first K columns, eps in (0, 1/2) the tolerance of the fast
+ * operators.  K defaults to round(2NW) with halves rounded away from zero
+ * (Section 4.1).
+ *
+ * Conventions shared by every call:
+ *   - Signals are real.  A batch of b signals of length N is column-major
+ *     N x b: signal s starts at x + s*ldx, ldx >= N.  All signal, output and
+ *     workspace pointers are DEVICE pointers on the plan's device, owned by
+ *     the caller; host pointers are marked "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls enqueue work on `stream` and return without synchronising unless
+ *     stated otherwise.  A plan is read-only after creation; concurrent calls
+ *     on different streams need separate workspaces.
+ *   - Workspace: pass work = NULL, work_bytes = 0 to let the plan use an
+ *     internal buffer (grown on demand; then calls on one plan must not run
+ *     concurrently), or pass a buffer of at least slepian_workspace_size()
+ *     bytes.
+ *   - Errors: every call returns SLEPIAN_OK (0) or a negative status.  All
+ *     argument checks happen before anything is enqueued, so a failed call
+ *     leaves outputs untouched.  Calls never abort the process.
+ */
+#ifndef SLEPIAN_H_
+#define SLEPIAN_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct slepian_plan_s *slepian_plan_t;
+typedef struct slepian_group_s *slepian_group_t;
+
+enum slepian_status {
+  SLEPIAN_OK = 0,
+  SLEPIAN_EINVAL = -1,     /* argument outside its domain (N < 2, W not in (0,1/2),
+                              eps not in (0,1/2), alpha <= 0, ld < N, batch < 0, ...) */
+  SLEPIAN_EGAP = -2,       /* K violates lambda_{K-1} > eps and lambda_K < 1 - eps
+                              (Corollary 2's condition on K) */
+  SLEPIAN_ENOMEM = -3,     /* device or host allocation failed, or workspace too small */
+  SLEPIAN_EHIP = -4,       /* a HIP runtime call failed */
+  SLEPIAN_ENOCONV = -5,    /* eigensolver check or iterative refinement did not converge */
+  SLEPIAN_ENOTSUP = -6,    /* size or mode not supported by this build */
+  SLEPIAN_ENONFINITE = -7, /* NaN or Inf found where finite values are required */
+  SLEPIAN_EIO = -8         /* plan file could not be read or written, or is malformed */
+};
+
+/* Arithmetic of the low-rank correction (the B x product is always FP32). */
+enum slepian_precision {
+  SLEPIAN_FP32 = 0,        /* FP32 correction */
+  SLEPIAN_MIXED = 1,       /* BF16 hi/lo split on matrix cores, FP32 accumulation */
+  SLEPIAN_BF16_RAW = 2     /* BF16 operands only (no lo terms); for error studies */
+};
+
+enum slepian_lsq_mode {
+  SLEPIAN_PINV = 0,        /* rank-K truncated pseudoinverse of B (Corollary 3) */
+  SLEPIAN_TIKHONOV = 1     /* (B^2 + alpha I)^{-1} B (Corollary 4) */
+};
+
+enum slepian_op {
+  SLEPIAN_OP_PROJECT = 0,
+  SLEPIAN_OP_COEFFS = 1,
+  SLEPIAN_OP_LSQ = 2
+};
+
+typedef struct {
+  double alpha;     /* > 0: also prepare the Tikhonov set for this alpha (Lemma 7); 0: none */
+  int64_t K;        /* 0: K = round(2NW); else 1 <= K <= N-1 */
+  int precision;    /* enum slepian_precision used by slepian_project */
+  int device;       /* HIP device ordinal, -1: the current device */
+} slepian_plan_opts;
+
+typedef struct {
+  int64_t N;
+  double W, eps, alpha;
+  int64_t K;
+  int64_t L;            /* FFT length used for B x: smallest power of two >= 2N */
+  int64_t r;            /* |I2 u I3| = #{eps < lambda < 1-eps} (Lemma 5) */
+  int64_t l_first;      /* index l of the first transition vector */
+  int64_t r_tik;        /* #{alpha(1+alpha)eps < lambda < 1-eps/3} (Lemma 7), 0 if alpha == 0 */
+  int64_t l_first_tik;
+  int64_t window_lo, window_hi;  /* eigen-indices solved at setup (inclusive) */
+  double lam_Km1, lam_K;         /* lambda_{K-1}, lambda_K */
+  double eps_achieved;  /* max(1 - lambda over I1, lambda over I4) seen at the window edges,
+                           an upper bound on ||S_K S_K^T - (B + U diag(d) U^T)|| (Lemma 5) */
+  int precision;
+  int device;
+} slepian_plan_info;
+
+typedef struct {
+  int iterations;           /* refinement sweeps taken */
+  double rel_residual;      /* max over the batch of ||By - (B^2+alpha I)x|| / ||By|| (Tikhonov) */
+  double rel_residual_first;/* the same for the unrefined fast solution */
+  int converged;            /* 1 if rel_residual <= tol */
+} slepian_lsq_report;
+
+/* Plan for length-N signals, half bandwidth W, tolerance eps, default options.
+ * Setup (Section 2.3 "fast precomputation", Section 4.1): the spectrum of the
+ * circulant embedding of B's first column, and the Slepian vectors with
+ * eps < lambda < 1-eps, from bisection and inverse iteration on the
+ * tridiagonal matrix that commutes with B (Slepian 1978) in FP64 on the GPU,
+ * with lambda_l = s_l^T B s_l in FP64.  Synchronous.  *out receives a new
+ * plan on success and is untouched on failure.
+ * Errors: EINVAL (domain), EGAP, ENOMEM, EHIP, ENOCONV. */
+int slepian_plan(int64_t N, double W, double eps, slepian_plan_t *out);
+
+/* As slepian_plan with options (opts may be NULL for defaults). */
+int slepian_plan_ex(int64_t N, double W, double eps, const slepian_plan_opts *opts,
+                    slepian_plan_t *out);
+
+/* Plan sizes and eigen-structure; info is host memory. */
+int slepian_plan_info_get(slepian_plan_t plan, slepian_plan_info *info);
+
+/* Eigenpairs held by the plan: the union of the transition sets it uses,
+ * indices l = *l_first .. *l_first + *count - 1.  lam_host (host, may be
+ * NULL) receives count FP64 eigenvalues; vecs (device, may be NULL) receives
+ * the N x count FP64 unit-norm vectors, column-major with leading dimension
+ * ldv >= N, each signed so that its first entry of magnitude >= 1e-3 of its
+ * largest magnitude is positive.  cap is the capacity (in eigenpairs) of
+ * lam_host/vecs; ENOMEM if smaller than count.  Synchronous. */
+int slepian_plan_eigenpairs(slepian_plan_t plan, int64_t *l_first, int64_t *count,
+                            double *lam_host, double *vecs, int64_t ldv, int64_t cap);
+
+/* Write / read a plan (spectrum, vectors, eigenvalues, sizes) to / from a
+ * file, so setup is not repeated.  load creates the plan on `device`
+ * (-1: current). Errors: EIO, ENOMEM, EHIP. */
+int slepian_plan_save(slepian_plan_t plan, const char *path);
+int slepian_plan_load(const char *path, int device, slepian_plan_t *out);
+
+/* Free a plan and its device buffers (NULL is a no-op). */
+int slepian_plan_destroy(slepian_plan_t plan);
+
+/* Workspace bytes needed by `op` on `batch` signals. */
+int slepian_workspace_size(slepian_plan_t plan, int op, int64_t batch, size_t *bytes);
+
+/* Fast projection onto span(S_K) (Corollary 2, Lemma 5; Section 2.3 "Fast
+ * projections onto the range of S_K"):
+ *     y = B x + U diag(d) U^T x,
+ * U = the transition vectors (eps < lambda < 1-eps), d = 1 - lambda for
+ * l < K and -lambda for l >= K, so ||y - S_K S_K^T x|| <= eps ||x|| plus
+ * FP32 rounding.  B x uses length-L FFTs (L the smallest power of two >= 2N).
+ * x: N x batch FP32 (ldx >= N); y: N x batch FP32 (ldy >= N); y may equal x
+ * (in place) but must not otherwise overlap it.  batch == 0 is a no-op. */
+int slepian_project(slepian_plan_t plan, const float *x, int64_t ldx, float *y, int64_t ldy,
+                    int64_t batch, void *work, size_t work_bytes, void *stream);
+
+/* As slepian_project with an explicit correction precision (enum
+ * slepian_precision) instead of the plan's default. */
+int slepian_project_ex(slepian_plan_t plan, int precision, const float *x, int64_t ldx,
+                       float *y, int64_t ldy, int64_t batch, void *work, size_t work_bytes,
+                       void *stream);
+
+/* Slepian coefficients c = S_K^T x (Section 2.3, "A fast factorization":
+ * the K numbers that represent x), exact (dense) semantics.  The first call
+ * computes all K Slepian vectors on the GPU and keeps them in the plan
+ * (N*K*4 bytes); ENOTSUP if that exceeds 16 GiB.  Vector signs follow the
+ * convention of slepian_plan_eigenpairs.  c: K x batch FP32, ldc >= K. */
+int slepian_coeffs(slepian_plan_t plan, const float *x, int64_t ldx, float *c, int64_t ldc,
+                   int64_t batch, void *work, size_t work_bytes, void *stream);
+
+/* Least squares with the prolate matrix (Section 2.3):
+ *   SLEPIAN_PINV:      x = B_K^+ y ~= B y + U diag(1/lambda - lambda | -lambda) U^T y
+ *                      (Corollary 3, error <= 3 eps ||y||); single pass, tol and
+ *                      max_iter ignored.
+ *   SLEPIAN_TIKHONOV:  x ~= (B^2 + alpha I)^{-1} B y, starting from the fast
+ *                      operator B y/(1+alpha) + U5 U5^T y (Corollary 4, error
+ *                      <= eps ||y||), then refined: with the FP64 residual
+ *                      rho = B y - (B^2 + alpha I) x, x += M rho, where M is an
+ *                      FP32 fast approximation of (B^2 + alpha I)^{-1}, until
+ *                      max_s ||rho_s|| / ||B y_s|| <= tol or max_iter sweeps.
+ *                      max_iter = 0 returns the fast operator's output.  alpha
+ *                      must equal the plan's alpha (opts.alpha).
+ * y: N x batch FP32; x: N x batch FP64 (FP64 so that the refined residual can
+ * reach 1e-10).  rep (host, nullable) receives iterations and residuals; a
+ * non-NULL rep or max_iter > 0 makes the call synchronous (the convergence
+ * test reads norms on the host).  ENOCONV if tol is not reached. */
+int slepian_lsq(slepian_plan_t plan, int mode, double alpha, const float *y, int64_t ldy,
+                double *x, int64_t ldx, int64_t batch, double tol, int max_iter,
+                void *work, size_t work_bytes, void *stream, slepian_lsq_report *rep);
+
+/* FP64 product y = B x with the same FFT method (used for residuals). */
+int slepian_apply_b64(slepian_plan_t plan, const double *x, int64_t ldx, double *y,
+                      int64_t ldy, int64_t batch, void *work, size_t work_bytes, void *stream);
+
+/* Groups: many independent plans (any mix of N, W, eps) projected together.
+ * plans (host array of n plan handles) must outlive the group; batch (host)
+ * gives each plan's signal count.  The group owns its workspace and a HIP
+ * graph of the whole batch, built on the first slepian_group_project call and
+ * re-launched as one graph while the pointer arrays stay the same. */
+int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batch,
+                         slepian_group_t *out);
+
+/* x, y: host arrays of n device pointers; plan i reads x[i] (N_i x batch_i,
+ * ld N_i) and writes y[i] (same shape).  Asynchronous on `stream`. */
+int slepian_group_project(slepian_group_t group, const float *const *x, float *const *y,
+                          void *stream);
+
+int slepian_group_destroy(slepian_group_t group);
+
+/* Static description of a status code. */
+const char *slepian_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLEPIAN_H_ */

@@ -315,11 +315,17 @@ def project_exact(N: int, W: float, x: np.ndarray, K: int | None = None) -> np.n
 
 def coeffs_exact(N: int, W: float, x: np.ndarray, K: int | None = None) -> np.ndarray:
     """S_K^T x, the K Slepian coefficients (Section 2.3, "A fast factorization"),
-    with the oracle's sign convention on each Slepian vector."""
+    with the oracle's sign convention on each Slepian vector.
+
+    The vectors come from the tridiagonal route: inside the clusters of
+    eigenvalues numerically equal to 1, a dense eigensolver of B returns an
+    arbitrary orthonormal basis of the cluster, while the individual Slepian
+    vectors are defined uniquely (the eigenvalues are distinct, Definition 1)
+    and are resolved by the tridiagonal matrix's well separated eigenvalues."""
     if K is None:
         K = choose_K(N, W)
-    _, S = dense_eig(N, W)
-    return S[:, :K].T @ np.asarray(x, dtype=np.float64)
+    _, S = slepian_vectors(N, W, 0, K - 1)
+    return S.T @ np.asarray(x, dtype=np.float64)
 
 
 def pinv_exact(N: int, W: float, y: np.ndarray, K: int | None = None) -> np.ndarray:

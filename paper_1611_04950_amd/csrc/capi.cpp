@@ -1,0 +1,1085 @@
+// C ABI of libslepian: plans, dispatch of the HIP kernels, least squares,
+// coefficients, groups and plan files.  Declarations and argument contracts
+// are in include/slepian.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "slepian.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace slp;
+
+namespace {
+
+struct Fail {
+  int status;
+};
+
+inline int hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? SLEPIAN_ENOMEM : SLEPIAN_EHIP; }
+
+#define HIPCHK(call)                          \
+  do {                                        \
+    hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) {                   \
+      (void)hipGetLastError();                \
+      throw Fail{hip_status(e_)};             \
+    }                                         \
+  } while (0)
+
+template <typename T>
+T *dalloc(size_t n) {
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, (n ? n : 1) * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Fail{SLEPIAN_ENOMEM};
+  }
+  return static_cast<T *>(p);
+}
+
+inline void dfree(void *p) {
+  if (p) (void)hipFree(p);
+}
+
+// Owns a device allocation for the duration of a scope.
+template <typename T>
+struct DBuf {
+  T *p = nullptr;
+  explicit DBuf(size_t n) : p(dalloc<T>(n)) {}
+  ~DBuf() { dfree(p); }
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+};
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (dev >= 0 && dev != prev) HIPCHK(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// Bump allocator over a workspace; with base == nullptr it only measures.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+  template <typename T>
+  T *take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+constexpr size_t kSliceBudget = (size_t)256 << 20;  // bytes of three-pass intermediates per slice
+constexpr int kMaxLogL = 22;                          // N <= 2^21
+constexpr size_t kCoeffsCap = (size_t)16 << 30;       // bytes of S_K kept for slepian_coeffs
+
+int ilog2_ceil(int64_t v) {
+  int l = 0;
+  while (((int64_t)1 << l) < v) ++l;
+  return l;
+}
+
+struct OpSet {
+  int64_t off = 0;   // first column within the plan's U
+  int64_t r = 0;
+  float *d32 = nullptr;
+  std::vector<double> d;
+};
+
+}  // namespace
+
+struct slepian_plan_s {
+  int device = 0;
+  int64_t N = 0, K = 0, L = 0;
+  double W = 0, eps = 0, alpha = 0;
+  int precision = SLEPIAN_FP32;
+  FftGeom g32, g64;
+  cpx<float> *tw32[3] = {nullptr, nullptr, nullptr};
+  cpx<double> *tw64[3] = {nullptr, nullptr, nullptr};
+  float *chat32 = nullptr;
+  double *chat64 = nullptr;
+  FftTables<float> tb32;
+  FftTables<double> tb64;
+  int64_t win_lo = 0, win_hi = -1;
+  std::vector<double> lam;  // eigenvalues over the window
+  int64_t u_l0 = 0, u_r = 0;  // U's columns are Slepian vectors l = u_l0 .. u_l0 + u_r - 1
+  double *U64 = nullptr;
+  float *U32 = nullptr;
+  OpSet proj, pinv, tik, tikm;
+  double lam_Km1 = 0, lam_K = 0, eps_ach = 0;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  float *SK = nullptr;
+
+  ~slepian_plan_s() {
+    for (auto *p : tw32) dfree(p);
+    for (auto *p : tw64) dfree(p);
+    dfree(chat32);
+    dfree(chat64);
+    dfree(U64);
+    dfree(U32);
+    for (OpSet *o : {&proj, &pinv, &tik, &tikm}) dfree(o->d32);
+    dfree(ws);
+    dfree(SK);
+  }
+};
+
+struct slepian_group_s {
+  std::vector<slepian_plan_t> plans;
+  std::vector<int64_t> batch;
+  int device = 0;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const float *> lx;
+  std::vector<float *> ly;
+  ~slepian_group_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    dfree(ws);
+  }
+};
+
+namespace {
+
+typedef slepian_plan_s Plan;
+
+// ---------------------------------------------------------------------------
+// Workspace layouts (shared by the size query and the calls)
+// ---------------------------------------------------------------------------
+
+bool fused_single(const Plan *P, const OpSet &op) { return P->g32.single() && op.r <= kMaxRankSingle; }
+
+struct ProjWs {
+  cpx<float> *Z = nullptr;
+  int64_t slice = 0;
+  float *part = nullptr, *dC = nullptr;
+};
+
+ProjWs carve_project(const Plan *P, const OpSet &op, int64_t b, Carver &cv) {
+  ProjWs w;
+  if (fused_single(P, op)) return w;
+  const int64_t pairs = (b + 1) / 2;
+  w.slice = (int64_t)conv_workspace_pairs(P->g32, pairs, sizeof(cpx<float>), kSliceBudget);
+  if (!P->g32.single()) w.Z = cv.take<cpx<float>>((size_t)w.slice * (size_t)P->L);
+  if (op.r > 0) {
+    const int rpad = corr_rpad((int)op.r);
+    w.part = cv.take<float>((size_t)corr_chunks(P->N) * rpad * b);
+    w.dC = cv.take<float>((size_t)b * rpad);
+  }
+  return w;
+}
+
+struct B64Ws {
+  cpx<double> *Z = nullptr;
+  int64_t slice = 0;
+};
+
+B64Ws carve_b64(const Plan *P, int64_t b, Carver &cv) {
+  B64Ws w;
+  const int64_t pairs = (b + 1) / 2;
+  w.slice = (int64_t)conv_workspace_pairs(P->g64, pairs, sizeof(cpx<double>), kSliceBudget);
+  if (!P->g64.single()) w.Z = cv.take<cpx<double>>((size_t)w.slice * (size_t)P->L);
+  return w;
+}
+
+struct TikWs {
+  float *x32, *rho32, *e32;
+  double *y64, *By, *t, *u, *rho, *nBy, *nr;
+  ProjWs pw;
+  B64Ws bw;
+};
+
+TikWs carve_tik(const Plan *P, int64_t b, Carver &cv) {
+  TikWs w;
+  const size_t nb = (size_t)P->N * (size_t)b;
+  w.x32 = cv.take<float>(nb);
+  w.rho32 = cv.take<float>(nb);
+  w.e32 = cv.take<float>(nb);
+  w.y64 = cv.take<double>(nb);
+  w.By = cv.take<double>(nb);
+  w.t = cv.take<double>(nb);
+  w.u = cv.take<double>(nb);
+  w.rho = cv.take<double>(nb);
+  w.nBy = cv.take<double>(b);
+  w.nr = cv.take<double>(b);
+  // the fast operators of the solve use the Tikhonov column set
+  w.pw = carve_project(P, P->tikm.r > P->tik.r ? P->tikm : P->tik, b, cv);
+  w.bw = carve_b64(P, b, cv);
+  return w;
+}
+
+size_t op_workspace(const Plan *P, int op, int64_t b) {
+  Carver cv(nullptr);
+  switch (op) {
+    case SLEPIAN_OP_PROJECT:
+      carve_project(P, P->proj, b, cv);
+      break;
+    case SLEPIAN_OP_COEFFS:
+      cv.take<float>((size_t)corr_chunks(P->N) * corr_rpad((int)P->K) * b);
+      break;
+    case SLEPIAN_OP_LSQ: {
+      Carver c1(nullptr), c2(nullptr);
+      c1.take<float>((size_t)P->N * b);
+      carve_project(P, P->pinv, b, c1);
+      carve_tik(P, b, c2);
+      return std::max(c1.off, c2.off) + 256;
+    }
+    default:
+      return 0;
+  }
+  return cv.off + 256;
+}
+
+// Workspace for a call: the caller's buffer or the plan's own.
+void *get_ws(Plan *P, void *work, size_t work_bytes, size_t need) {
+  if (work) {
+    if (work_bytes < need) throw Fail{SLEPIAN_ENOMEM};
+    return work;
+  }
+  if (P->ws_bytes < need) {
+    (void)hipDeviceSynchronize();
+    dfree(P->ws);
+    P->ws = nullptr;
+    P->ws_bytes = 0;
+    P->ws = dalloc<char>(need);
+    P->ws_bytes = need;
+  }
+  return P->ws;
+}
+
+// ---------------------------------------------------------------------------
+// Operators
+// ---------------------------------------------------------------------------
+
+// y = beta B x + gamma x + U_op diag(d_op) U_op^T x (FP32).
+void run_fast_op(const Plan *P, const OpSet &op, float beta, float gamma, const float *x, int64_t ldx, float *y,
+                 int64_t ldy, int64_t b, const ProjWs &w, hipStream_t st) {
+  const int64_t N = P->N;
+  const float *U = P->U32 + op.off * N;
+  if (fused_single(P, op)) {
+    Corr<float> c;
+    c.U = U;
+    c.ldu = N;
+    c.r = (int)op.r;
+    c.d = op.d32;
+    HIPCHK(conv_apply<float>(x, ldx, y, ldy, N, b, P->g32, P->tb32, beta, gamma, c, nullptr, 0, st));
+    return;
+  }
+  if (op.r > 0) {
+    HIPCHK(corr_partial(x, ldx, N, b, U, N, (int)op.r, w.part, st));
+    HIPCHK(corr_reduce(w.part, N, b, (int)op.r, op.d32, w.dC, st));
+  }
+  HIPCHK(conv_apply<float>(x, ldx, y, ldy, N, b, P->g32, P->tb32, beta, gamma, Corr<float>(), w.Z, w.slice, st));
+  if (op.r > 0) HIPCHK(corr_apply(y, ldy, N, b, U, N, (int)op.r, w.dC, st));
+}
+
+void run_b64(const Plan *P, const double *x, int64_t ldx, double *y, int64_t ldy, int64_t b, const B64Ws &w,
+             hipStream_t st) {
+  HIPCHK(conv_apply<double>(x, ldx, y, ldy, P->N, b, P->g64, P->tb64, 1.0, 0.0, Corr<double>(), w.Z, w.slice, st));
+}
+
+// ---------------------------------------------------------------------------
+// Setup
+// ---------------------------------------------------------------------------
+
+void upload_d(OpSet &o) {
+  if (o.r == 0) return;
+  std::vector<float> f(o.d.begin(), o.d.end());
+  o.d32 = dalloc<float>(o.r);
+  HIPCHK(hipMemcpy(o.d32, f.data(), o.r * sizeof(float), hipMemcpyHostToDevice));
+}
+
+void build_fft_state(Plan *P, hipStream_t st) {
+  const int logL = ilog2_ceil(2 * P->N);
+  P->L = (int64_t)1 << logL;
+  P->g32 = make_geom(logL, Lds<float>::logE);
+  P->g64 = make_geom(logL, Lds<double>::logE);
+  const int64_t L = P->L;
+  P->tw32[0] = dalloc<cpx<float>>((size_t)1 << P->g32.logT);
+  P->tw32[1] = dalloc<cpx<float>>((size_t)1 << P->g32.s);
+  P->tw32[2] = dalloc<cpx<float>>((size_t)1 << (logL - P->g32.s));
+  P->tw64[0] = dalloc<cpx<double>>((size_t)1 << P->g64.logT);
+  P->tw64[1] = dalloc<cpx<double>>((size_t)1 << P->g64.s);
+  P->tw64[2] = dalloc<cpx<double>>((size_t)1 << (logL - P->g64.s));
+  HIPCHK(build_tables<float>(P->g32, P->tw32[0], P->tw32[1], P->tw32[2], st));
+  HIPCHK(build_tables<double>(P->g64, P->tw64[0], P->tw64[1], P->tw64[2], st));
+  P->tb32.tw_sub = P->tw32[0];
+  P->tb32.tw_lo = P->tw32[1];
+  P->tb32.tw_hi = P->tw32[2];
+  P->tb64.tw_sub = P->tw64[0];
+  P->tb64.tw_lo = P->tw64[1];
+  P->tb64.tw_hi = P->tw64[2];
+  // spectrum of the circulant embedding of B's first column (Section 4.1)
+  DBuf<double> c(L);
+  DBuf<cpx<double>> spec(L);
+  HIPCHK(sinc_embed(c.p, L, P->N, P->W, st));
+  HIPCHK(fft_forward_real64(c.p, P->g64, P->tb64, spec.p, st));
+  P->chat32 = dalloc<float>(L);
+  P->chat64 = dalloc<double>(L);
+  HIPCHK(spectrum_relayout<float>(spec.p, P->g64, P->chat32, P->g32, st));
+  HIPCHK(spectrum_relayout<double>(spec.p, P->g64, P->chat64, P->g64, st));
+  P->tb32.chat = P->chat32;
+  P->tb64.chat = P->chat64;
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+struct Tridiag {
+  double *a = nullptr, *e2 = nullptr, *off = nullptr;
+  double gl = 0, gu = 0, pivmin = 0;
+  ~Tridiag() {
+    dfree(a);
+    dfree(e2);
+    dfree(off);
+  }
+};
+
+void build_tridiag(const Plan *P, Tridiag &T, hipStream_t st) {
+  const int64_t N = P->N;
+  T.a = dalloc<double>(N);
+  T.e2 = dalloc<double>(N);
+  T.off = dalloc<double>(N);
+  HIPCHK(tridiag_build(T.a, T.e2, N, P->W, st));
+  // off-diagonal itself (for inverse iteration), and Gershgorin bounds
+  std::vector<double> off(N > 1 ? N - 1 : 1), e2(N > 1 ? N - 1 : 1);
+  const double cw = std::cos(2.0 * M_PI * P->W);
+  double gl = INFINITY, gu = -INFINITY, emax = 0;
+  for (int64_t n = 0; n + 1 < N; ++n) {
+    off[n] = 0.5 * (double)(n + 1) * (double)(N - 1 - n);
+    emax = std::max(emax, off[n] * off[n]);
+  }
+  for (int64_t n = 0; n < N; ++n) {
+    const double h = 0.5 * (double)(N - 1) - (double)n;
+    const double an = h * h * cw;
+    const double r = (n > 0 ? off[n - 1] : 0.0) + (n + 1 < N ? off[n] : 0.0);
+    gl = std::min(gl, an - r);
+    gu = std::max(gu, an + r);
+  }
+  T.pivmin = DBL_MIN * std::max(1.0, emax);
+  const double tn = std::max(std::fabs(gl), std::fabs(gu));
+  const double pad = 2.1 * tn * DBL_EPSILON * (double)N + 4.0 * T.pivmin;
+  T.gl = gl - pad;
+  T.gu = gu + pad;
+  if (N > 1) HIPCHK(hipMemcpyAsync(T.off, off.data(), (N - 1) * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// Slepian vectors l = lo..hi into V (N x (hi-lo+1), FP64, column c <-> l = lo + c).
+void solve_vectors(const Plan *P, const Tridiag &T, int64_t lo, int64_t hi, double *V, hipStream_t st) {
+  const int64_t N = P->N;
+  const int64_t nv = hi - lo + 1;
+  DBuf<double> theta(nv);
+  // ascending index t = N-1-l; theta[j] <-> t = (N-1-hi) + j <-> l = hi - j
+  HIPCHK(tridiag_bisect(T.a, T.e2, N, T.gl, T.gu, T.pivmin, N - 1 - hi, nv, theta.p, st));
+  const size_t per = inviter_scratch_bytes(N, 1);
+  int64_t cv = (int64_t)(((size_t)2 << 30) / per);
+  cv = std::max<int64_t>(1, std::min(cv, nv));
+  DBuf<char> scratch(inviter_scratch_bytes(N, cv));
+  for (int64_t j0 = 0; j0 < nv; j0 += cv) {
+    const int64_t c = std::min(cv, nv - j0);
+    // theta[j0 + jj] -> column nv-1-(j0+jj) = (nv - j0 - c) + (c-1-jj)
+    HIPCHK(tridiag_inviter(T.a, T.off, N, theta.p + j0, c, V + (nv - j0 - c) * N, scratch.p, 3, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+double asymptotic_width(int64_t N, double e) {
+  return 2.0 / (M_PI * M_PI) * std::log((double)std::max<int64_t>(N, 2)) * std::log(1.0 / e - 1.0);
+}
+
+void build_eigen_state(Plan *P, hipStream_t st) {
+  const int64_t N = P->N, K = P->K;
+  double thr_lo = P->eps, thr_hi = 1.0 - P->eps;
+  if (P->alpha > 0) {
+    thr_lo = std::min(thr_lo, P->alpha * (1.0 + P->alpha) * P->eps);
+    thr_hi = std::max(thr_hi, 1.0 - P->eps / 3.0);
+  }
+  Tridiag T;
+  build_tridiag(P, T, st);
+  int64_t h = (int64_t)(2.0 * asymptotic_width(N, std::min(thr_lo, 1.0 - thr_hi)) + 30.0);
+  int64_t lo = std::max<int64_t>(0, K - h), hi = std::min<int64_t>(N - 1, K + h);
+  double *V = nullptr;
+  std::vector<double> lam, res;
+  for (int attempt = 0;; ++attempt) {
+    const int64_t nv = hi - lo + 1;
+    dfree(V);
+    V = dalloc<double>((size_t)N * nv);
+    solve_vectors(P, T, lo, hi, V, st);
+    B64Ws bw;
+    {
+      Carver c0(nullptr);
+      carve_b64(P, nv, c0);
+      DBuf<char> ws(c0.off + 256);
+      Carver cv(ws.p);
+      bw = carve_b64(P, nv, cv);
+      DBuf<double> BV((size_t)N * nv), dl(nv), dr(nv);
+      run_b64(P, V, N, BV.p, N, nv, bw, st);
+      HIPCHK(rayleigh(V, BV.p, N, nv, dl.p, dr.p, st));
+      lam.assign(nv, 0.0);
+      res.assign(nv, 0.0);
+      HIPCHK(hipMemcpyAsync(lam.data(), dl.p, nv * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(res.data(), dr.p, nv * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    for (int64_t c = 0; c < nv; ++c) {
+      if (!std::isfinite(lam[c]) || !(res[c] <= 1e-7)) {
+        dfree(V);
+        throw Fail{SLEPIAN_ENOCONV};
+      }
+    }
+    const bool ok_lo = lo == 0 || lam[0] >= thr_hi;
+    const bool ok_hi = hi == N - 1 || lam[nv - 1] <= thr_lo;
+    if (ok_lo && ok_hi) break;
+    if (attempt > 12) {
+      dfree(V);
+      throw Fail{SLEPIAN_ENOCONV};
+    }
+    h *= 2;
+    if (!ok_lo) lo = std::max<int64_t>(0, K - h);
+    if (!ok_hi) hi = std::min<int64_t>(N - 1, K + h);
+  }
+  const int64_t nv = hi - lo + 1;
+  P->win_lo = lo;
+  P->win_hi = hi;
+  P->lam = lam;
+  // K's gap condition (Corollary 2): lambda_{K-1} > eps, lambda_K < 1 - eps
+  P->lam_Km1 = lam[K - 1 - lo];
+  P->lam_K = lam[K - lo];
+  if (!(P->lam_Km1 > P->eps && P->lam_K < 1.0 - P->eps)) {
+    dfree(V);
+    throw Fail{SLEPIAN_EGAP};
+  }
+  auto range = [&](double a, double b, int64_t &c0, int64_t &c1) {
+    c0 = -1;
+    c1 = -1;
+    for (int64_t c = 0; c < nv; ++c)
+      if (lam[c] > a && lam[c] < b) {
+        if (c0 < 0) c0 = c;
+        c1 = c + 1;
+      }
+    if (c0 < 0) {
+      c0 = c1 = K - lo;
+      return;
+    }
+    for (int64_t c = c0; c < c1; ++c)
+      if (!(lam[c] > a && lam[c] < b)) throw Fail{SLEPIAN_ENOCONV};  // must be contiguous
+  };
+  int64_t p0, p1, t0 = 0, t1 = 0;
+  range(P->eps, 1.0 - P->eps, p0, p1);
+  if (P->alpha > 0) range(P->alpha * (1.0 + P->alpha) * P->eps, 1.0 - P->eps / 3.0, t0, t1);
+  int64_t u0 = p0, u1 = p1;
+  if (P->alpha > 0 && t1 > t0) {
+    if (p1 > p0) {
+      u0 = std::min(p0, t0);
+      u1 = std::max(p1, t1);
+    } else {
+      u0 = t0;
+      u1 = t1;
+    }
+  }
+  // Lemma 5's error: max(1 - lambda over I1, lambda over I4), seen at the set edges
+  double ea = 0.0;
+  if (p0 > 0) ea = std::max(ea, 1.0 - lam[p0 - 1]);
+  if (p1 < nv) ea = std::max(ea, lam[p1]);
+  P->eps_ach = ea;
+  P->u_l0 = lo + u0;
+  P->u_r = u1 - u0;
+  P->U64 = dalloc<double>((size_t)N * std::max<int64_t>(P->u_r, 1));
+  P->U32 = dalloc<float>((size_t)N * std::max<int64_t>(P->u_r, 1));
+  if (P->u_r > 0) {
+    HIPCHK(hipMemcpyAsync(P->U64, V + u0 * N, (size_t)N * P->u_r * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(cast_f64_to_f32(P->U64, N, P->U32, N, N, P->u_r, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  dfree(V);
+  // weights of the low-rank corrections (Lemmas 5, 6, 7)
+  const double al = P->alpha;
+  P->proj.off = P->pinv.off = p0 - u0;
+  P->proj.r = P->pinv.r = p1 - p0;
+  for (int64_t c = p0; c < p1; ++c) {
+    const double l = lam[c];
+    const bool in_i2 = lo + c < K;
+    P->proj.d.push_back(in_i2 ? 1.0 - l : -l);
+    P->pinv.d.push_back(in_i2 ? 1.0 / l - l : -l);
+  }
+  if (al > 0) {
+    P->tik.off = P->tikm.off = t0 - u0;
+    P->tik.r = P->tikm.r = t1 - t0;
+    for (int64_t c = t0; c < t1; ++c) {
+      const double l = lam[c];
+      P->tik.d.push_back(l / (l * l + al) - l / (1.0 + al));
+      // refinement operator: 1/(l^2+alpha) minus its interpolation
+      // 1/alpha + (1/(1+alpha) - 1/alpha) l between l = 0 and l = 1
+      P->tikm.d.push_back(1.0 / (l * l + al) - (1.0 / al + (1.0 / (1.0 + al) - 1.0 / al) * l));
+    }
+  }
+  for (OpSet *o : {&P->proj, &P->pinv, &P->tik, &P->tikm}) upload_d(*o);
+}
+
+int validate_domain(int64_t N, double W, double eps, const slepian_plan_opts *o) {
+  if (N < 2 || N > ((int64_t)1 << (kMaxLogL - 1))) return N < 2 ? SLEPIAN_EINVAL : SLEPIAN_ENOTSUP;
+  if (!(W > 0.0 && W < 0.5)) return SLEPIAN_EINVAL;
+  if (!(eps > 0.0 && eps < 0.5)) return SLEPIAN_EINVAL;
+  if (o) {
+    if (!(o->alpha >= 0.0) || !std::isfinite(o->alpha)) return SLEPIAN_EINVAL;
+    if (o->K < 0 || o->K > N - 1) return SLEPIAN_EINVAL;
+    if (o->precision < SLEPIAN_FP32 || o->precision > SLEPIAN_BF16_RAW) return SLEPIAN_EINVAL;
+  }
+  return SLEPIAN_OK;
+}
+
+template <typename F>
+int guarded(F &&f) {
+  try {
+    return f();
+  } catch (const Fail &e) {
+    return e.status;
+  } catch (...) {
+    return SLEPIAN_ENOMEM;
+  }
+}
+
+bool bad_signal_args(const Plan *P, const void *x, int64_t ldx, const void *y, int64_t ldy, int64_t b) {
+  if (!P || b < 0) return true;
+  if (b == 0) return false;
+  if (!x || !y || ldx < P->N || ldy < P->N) return true;
+  if (b > 32 * 65535) return true;
+  return false;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+const char *slepian_status_string(int s) {
+  switch (s) {
+    case SLEPIAN_OK: return "success";
+    case SLEPIAN_EINVAL: return "invalid argument";
+    case SLEPIAN_EGAP: return "K violates lambda_{K-1} > eps and lambda_K < 1-eps";
+    case SLEPIAN_ENOMEM: return "out of memory or workspace too small";
+    case SLEPIAN_EHIP: return "HIP runtime error";
+    case SLEPIAN_ENOCONV: return "eigensolver check or refinement did not converge";
+    case SLEPIAN_ENOTSUP: return "not supported";
+    case SLEPIAN_ENONFINITE: return "non-finite value";
+    case SLEPIAN_EIO: return "plan file error";
+    default: return "unknown status";
+  }
+}
+
+int slepian_plan_ex(int64_t N, double W, double eps, const slepian_plan_opts *opts, slepian_plan_t *out) {
+  if (!out) return SLEPIAN_EINVAL;
+  int v = validate_domain(N, W, eps, opts);
+  if (v != SLEPIAN_OK) return v;
+  return guarded([&]() -> int {
+    int dev = opts && opts->device >= 0 ? opts->device : -1;
+    if (dev < 0) HIPCHK(hipGetDevice(&dev));
+    DeviceGuard dg(dev);
+    Plan *P = new Plan();
+    P->device = dev;
+    P->N = N;
+    P->W = W;
+    P->eps = eps;
+    P->alpha = opts ? opts->alpha : 0.0;
+    P->precision = opts ? opts->precision : SLEPIAN_FP32;
+    P->K = (opts && opts->K > 0) ? opts->K : (int64_t)std::floor(2.0 * (double)N * W + 0.5);
+    if (P->K < 1 || P->K > N - 1) {
+      delete P;
+      return SLEPIAN_EGAP;
+    }
+    hipStream_t st = nullptr;
+    try {
+      HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      build_fft_state(P, st);
+      build_eigen_state(P, st);
+      HIPCHK(hipStreamSynchronize(st));
+      (void)hipStreamDestroy(st);
+    } catch (...) {
+      if (st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+      }
+      delete P;
+      throw;
+    }
+    *out = P;
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_plan(int64_t N, double W, double eps, slepian_plan_t *out) {
+  return slepian_plan_ex(N, W, eps, nullptr, out);
+}
+
+int slepian_plan_destroy(slepian_plan_t plan) {
+  if (!plan) return SLEPIAN_OK;
+  return guarded([&]() -> int {
+    DeviceGuard dg(plan->device);
+    (void)hipDeviceSynchronize();
+    delete plan;
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_plan_info_get(slepian_plan_t P, slepian_plan_info *info) {
+  if (!P || !info) return SLEPIAN_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  info->N = P->N;
+  info->W = P->W;
+  info->eps = P->eps;
+  info->alpha = P->alpha;
+  info->K = P->K;
+  info->L = P->L;
+  info->r = P->proj.r;
+  info->l_first = P->u_l0 + P->proj.off;
+  info->r_tik = P->tik.r;
+  info->l_first_tik = P->tik.r ? P->u_l0 + P->tik.off : 0;
+  info->window_lo = P->win_lo;
+  info->window_hi = P->win_hi;
+  info->lam_Km1 = P->lam_Km1;
+  info->lam_K = P->lam_K;
+  info->eps_achieved = P->eps_ach;
+  info->precision = P->precision;
+  info->device = P->device;
+  return SLEPIAN_OK;
+}
+
+int slepian_plan_eigenpairs(slepian_plan_t P, int64_t *l_first, int64_t *count, double *lam_host, double *vecs,
+                            int64_t ldv, int64_t cap) {
+  if (!P || !l_first || !count) return SLEPIAN_EINVAL;
+  *l_first = P->u_l0;
+  *count = P->u_r;
+  if ((lam_host || vecs) && cap < P->u_r) return SLEPIAN_ENOMEM;
+  if (vecs && ldv < P->N) return SLEPIAN_EINVAL;
+  if (lam_host)
+    for (int64_t c = 0; c < P->u_r; ++c) lam_host[c] = P->lam[P->u_l0 - P->win_lo + c];
+  if (vecs && P->u_r > 0) {
+    return guarded([&]() -> int {
+      DeviceGuard dg(P->device);
+      HIPCHK(hipMemcpy2D(vecs, ldv * sizeof(double), P->U64, P->N * sizeof(double), P->N * sizeof(double), P->u_r,
+                         hipMemcpyDeviceToDevice));
+      return SLEPIAN_OK;
+    });
+  }
+  return SLEPIAN_OK;
+}
+
+int slepian_workspace_size(slepian_plan_t P, int op, int64_t batch, size_t *bytes) {
+  if (!P || !bytes || batch < 0 || op < SLEPIAN_OP_PROJECT || op > SLEPIAN_OP_LSQ) return SLEPIAN_EINVAL;
+  *bytes = op_workspace(P, op, batch);
+  return SLEPIAN_OK;
+}
+
+int slepian_project_ex(slepian_plan_t P, int precision, const float *x, int64_t ldx, float *y, int64_t ldy,
+                       int64_t batch, void *work, size_t work_bytes, void *stream) {
+  if (bad_signal_args(P, x, ldx, y, ldy, batch)) return SLEPIAN_EINVAL;
+  if (precision < SLEPIAN_FP32 || precision > SLEPIAN_BF16_RAW) return SLEPIAN_EINVAL;
+  if (precision != SLEPIAN_FP32) return SLEPIAN_ENOTSUP;
+  if (batch == 0) return SLEPIAN_OK;
+  if (x != y) {
+    // in place is allowed; any other overlap is not
+    const char *xa = (const char *)x, *xe = (const char *)(x + (batch - 1) * ldx + P->N);
+    const char *ya = (const char *)y, *ye = (const char *)(y + (batch - 1) * ldy + P->N);
+    if (xa < ye && ya < xe) return SLEPIAN_EINVAL;
+  }
+  return guarded([&]() -> int {
+    DeviceGuard dg(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t need = op_workspace(P, SLEPIAN_OP_PROJECT, batch);
+    void *ws = get_ws(P, work, work_bytes, need);
+    Carver cv(ws);
+    ProjWs w = carve_project(P, P->proj, batch, cv);
+    run_fast_op(P, P->proj, 1.0f, 0.0f, x, ldx, y, ldy, batch, w, st);
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_project(slepian_plan_t P, const float *x, int64_t ldx, float *y, int64_t ldy, int64_t batch, void *work,
+                    size_t work_bytes, void *stream) {
+  if (!P) return SLEPIAN_EINVAL;
+  return slepian_project_ex(P, P->precision, x, ldx, y, ldy, batch, work, work_bytes, stream);
+}
+
+int slepian_apply_b64(slepian_plan_t P, const double *x, int64_t ldx, double *y, int64_t ldy, int64_t batch,
+                      void *work, size_t work_bytes, void *stream) {
+  if (bad_signal_args(P, x, ldx, y, ldy, batch)) return SLEPIAN_EINVAL;
+  if (batch == 0) return SLEPIAN_OK;
+  return guarded([&]() -> int {
+    DeviceGuard dg(P->device);
+    Carver c0(nullptr);
+    carve_b64(P, batch, c0);
+    void *ws = get_ws(P, work, work_bytes, c0.off + 256);
+    Carver cv(ws);
+    B64Ws w = carve_b64(P, batch, cv);
+    run_b64(P, x, ldx, y, ldy, batch, w, (hipStream_t)stream);
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_lsq(slepian_plan_t P, int mode, double alpha, const float *y, int64_t ldy, double *x, int64_t ldx,
+                int64_t batch, double tol, int max_iter, void *work, size_t work_bytes, void *stream,
+                slepian_lsq_report *rep) {
+  if (bad_signal_args(P, y, ldy, x, ldx, batch)) return SLEPIAN_EINVAL;
+  if (mode != SLEPIAN_PINV && mode != SLEPIAN_TIKHONOV) return SLEPIAN_EINVAL;
+  if (max_iter < 0 || !(tol >= 0.0)) return SLEPIAN_EINVAL;
+  if (mode == SLEPIAN_TIKHONOV) {
+    if (!(alpha > 0.0) || !(P->alpha > 0.0) || std::fabs(alpha - P->alpha) > 1e-12 * P->alpha)
+      return SLEPIAN_EINVAL;
+  }
+  if (rep) std::memset(rep, 0, sizeof(*rep));
+  if (batch == 0) return SLEPIAN_OK;
+  return guarded([&]() -> int {
+    DeviceGuard dg(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = P->N, b = batch;
+    void *ws = get_ws(P, work, work_bytes, op_workspace(P, SLEPIAN_OP_LSQ, b));
+    if (mode == SLEPIAN_PINV) {
+      Carver cv(ws);
+      float *t = cv.take<float>((size_t)N * b);
+      ProjWs w = carve_project(P, P->pinv, b, cv);
+      run_fast_op(P, P->pinv, 1.0f, 0.0f, y, ldy, t, N, b, w, st);
+      HIPCHK(cast_f32_to_f64(t, N, x, ldx, N, b, st));
+      if (rep) {
+        rep->converged = 1;
+        HIPCHK(hipStreamSynchronize(st));
+      }
+      return SLEPIAN_OK;
+    }
+    Carver cv(ws);
+    TikWs w = carve_tik(P, b, cv);
+    const float a = (float)alpha;
+    run_fast_op(P, P->tik, (float)(1.0 / (1.0 + alpha)), 0.0f, y, ldy, w.x32, N, b, w.pw, st);
+    HIPCHK(cast_f32_to_f64(w.x32, N, x, ldx, N, b, st));
+    (void)a;
+    if (max_iter == 0 && !rep) return SLEPIAN_OK;
+    HIPCHK(cast_f32_to_f64(y, ldy, w.y64, N, N, b, st));
+    run_b64(P, w.y64, N, w.By, N, b, w.bw, st);
+    HIPCHK(col_norms(w.By, N, N, b, w.nBy, st));
+    std::vector<double> nBy(b), nr(b);
+    HIPCHK(hipMemcpyAsync(nBy.data(), w.nBy, b * sizeof(double), hipMemcpyDeviceToHost, st));
+    const float betaM = (float)(1.0 / (1.0 + alpha) - 1.0 / alpha);
+    const float gammaM = (float)(1.0 / alpha);
+    int it = 0;
+    double rel = INFINITY, first = INFINITY;
+    bool conv = false;
+    for (;; ++it) {
+      run_b64(P, x, ldx, w.t, N, b, w.bw, st);
+      run_b64(P, w.t, N, w.u, N, b, w.bw, st);
+      HIPCHK(lsq_residual(w.By, w.u, x, ldx, alpha, w.rho, N, b, st));
+      HIPCHK(col_norms(w.rho, N, N, b, w.nr, st));
+      HIPCHK(hipMemcpyAsync(nr.data(), w.nr, b * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      rel = 0.0;
+      for (int64_t s = 0; s < b; ++s) {
+        const double v = nBy[s] > 0 ? nr[s] / nBy[s] : (nr[s] > 0 ? INFINITY : 0.0);
+        rel = std::max(rel, v);
+      }
+      if (it == 0) first = rel;
+      if (rel <= tol) {
+        conv = true;
+        break;
+      }
+      if (it >= max_iter) break;
+      HIPCHK(cast_f64_to_f32(w.rho, N, w.rho32, N, N, b, st));
+      run_fast_op(P, P->tikm, betaM, gammaM, w.rho32, N, w.e32, N, b, w.pw, st);
+      HIPCHK(add_f32_to_f64(w.e32, N, x, ldx, N, b, st));
+    }
+    if (rep) {
+      rep->iterations = it;
+      rep->rel_residual = rel;
+      rep->rel_residual_first = first;
+      rep->converged = conv ? 1 : 0;
+    }
+    if (max_iter > 0 && !conv) return SLEPIAN_ENOCONV;
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_coeffs(slepian_plan_t P, const float *x, int64_t ldx, float *c, int64_t ldc, int64_t batch, void *work,
+                   size_t work_bytes, void *stream) {
+  if (!P || batch < 0) return SLEPIAN_EINVAL;
+  if (batch > 0 && (!x || !c || ldx < P->N || ldc < P->K || batch > 32 * 65535)) return SLEPIAN_EINVAL;
+  if ((size_t)P->N * (size_t)P->K * sizeof(float) > kCoeffsCap) return SLEPIAN_ENOTSUP;
+  if (batch == 0) return SLEPIAN_OK;
+  return guarded([&]() -> int {
+    DeviceGuard dg(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = P->N, K = P->K;
+    if (!P->SK) {
+      // all K Slepian vectors, l = 0..K-1 (column l), FP64 then FP32
+      Tridiag T;
+      hipStream_t s2 = nullptr;
+      HIPCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+      float *SK = nullptr;
+      try {
+        build_tridiag(P, T, s2);
+        SK = dalloc<float>((size_t)N * K);
+        DBuf<double> theta(K);
+        HIPCHK(tridiag_bisect(T.a, T.e2, N, T.gl, T.gu, T.pivmin, N - K, K, theta.p, s2));
+        const size_t per = inviter_scratch_bytes(N, 1) + N * sizeof(double);
+        int64_t cv = std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)(((size_t)2 << 30) / per)));
+        DBuf<char> scratch(inviter_scratch_bytes(N, cv));
+        DBuf<double> V((size_t)N * cv);
+        for (int64_t j0 = 0; j0 < K; j0 += cv) {
+          const int64_t cc = std::min(cv, K - j0);
+          // theta[j0 + jj] <-> l = K-1-(j0+jj); normalised column cc-1-jj of V
+          HIPCHK(tridiag_inviter(T.a, T.off, N, theta.p + j0, cc, V.p, scratch.p, 3, s2));
+          HIPCHK(cast_f64_to_f32(V.p, N, SK + (K - j0 - cc) * N, N, N, cc, s2));
+        }
+        HIPCHK(hipStreamSynchronize(s2));
+        (void)hipStreamDestroy(s2);
+      } catch (...) {
+        (void)hipStreamSynchronize(s2);
+        (void)hipStreamDestroy(s2);
+        dfree(SK);
+        throw;
+      }
+      P->SK = SK;
+    }
+    const size_t need = op_workspace(P, SLEPIAN_OP_COEFFS, batch);
+    void *ws = get_ws(P, work, work_bytes, need);
+    Carver cv(ws);
+    float *part = cv.take<float>((size_t)corr_chunks(N) * corr_rpad((int)K) * batch);
+    HIPCHK(corr_partial(x, ldx, N, batch, P->SK, N, (int)K, part, st));
+    HIPCHK(corr_sum(part, N, batch, (int)K, c, ldc, st));
+    return SLEPIAN_OK;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Plan files
+// ---------------------------------------------------------------------------
+
+namespace {
+const char kMagic[8] = {'S', 'L', 'E', 'P', 'P', 'L', 'N', '1'};
+
+struct FileHeader {
+  char magic[8];
+  int64_t N, K, win_lo, win_hi, u_l0, u_r;
+  double W, eps, alpha;
+  int32_t precision, pad;
+  int64_t proj_off, proj_r, tik_off, tik_r;
+  double lam_Km1, lam_K, eps_ach;
+};
+}  // namespace
+
+int slepian_plan_save(slepian_plan_t P, const char *path) {
+  if (!P || !path) return SLEPIAN_EINVAL;
+  return guarded([&]() -> int {
+    DeviceGuard dg(P->device);
+    FileHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, kMagic, 8);
+    h.N = P->N;
+    h.K = P->K;
+    h.win_lo = P->win_lo;
+    h.win_hi = P->win_hi;
+    h.u_l0 = P->u_l0;
+    h.u_r = P->u_r;
+    h.W = P->W;
+    h.eps = P->eps;
+    h.alpha = P->alpha;
+    h.precision = P->precision;
+    h.proj_off = P->proj.off;
+    h.proj_r = P->proj.r;
+    h.tik_off = P->tik.off;
+    h.tik_r = P->tik.r;
+    h.lam_Km1 = P->lam_Km1;
+    h.lam_K = P->lam_K;
+    h.eps_ach = P->eps_ach;
+    std::vector<double> U((size_t)P->N * P->u_r);
+    if (P->u_r) HIPCHK(hipMemcpy(U.data(), P->U64, U.size() * sizeof(double), hipMemcpyDeviceToHost));
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return SLEPIAN_EIO;
+    bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1;
+    ok = ok && std::fwrite(P->lam.data(), sizeof(double), P->lam.size(), f) == P->lam.size();
+    for (const OpSet *o : {&P->proj, &P->pinv, &P->tik, &P->tikm})
+      ok = ok && std::fwrite(o->d.data(), sizeof(double), o->d.size(), f) == o->d.size();
+    ok = ok && std::fwrite(U.data(), sizeof(double), U.size(), f) == U.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? SLEPIAN_OK : SLEPIAN_EIO;
+  });
+}
+
+int slepian_plan_load(const char *path, int device, slepian_plan_t *out) {
+  if (!path || !out) return SLEPIAN_EINVAL;
+  return guarded([&]() -> int {
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return SLEPIAN_EIO;
+    FileHeader h;
+    auto bad = [&]() {
+      std::fclose(f);
+      return SLEPIAN_EIO;
+    };
+    if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, kMagic, 8) != 0) return bad();
+    slepian_plan_opts o{h.alpha, h.K, h.precision, device};
+    if (validate_domain(h.N, h.W, h.eps, &o) != SLEPIAN_OK) return bad();
+    const int64_t nw = h.win_hi - h.win_lo + 1;
+    if (nw < 1 || nw > h.N || h.u_r < 0 || h.u_r > nw || h.proj_r < 0 || h.tik_r < 0 ||
+        h.proj_off < 0 || h.tik_off < 0 || h.proj_off + h.proj_r > h.u_r || h.tik_off + h.tik_r > h.u_r)
+      return bad();
+    int dev = device;
+    if (dev < 0) HIPCHK(hipGetDevice(&dev));
+    DeviceGuard dg(dev);
+    Plan *P = new Plan();
+    try {
+      P->device = dev;
+      P->N = h.N;
+      P->K = h.K;
+      P->W = h.W;
+      P->eps = h.eps;
+      P->alpha = h.alpha;
+      P->precision = h.precision;
+      P->win_lo = h.win_lo;
+      P->win_hi = h.win_hi;
+      P->u_l0 = h.u_l0;
+      P->u_r = h.u_r;
+      P->lam_Km1 = h.lam_Km1;
+      P->lam_K = h.lam_K;
+      P->eps_ach = h.eps_ach;
+      P->lam.resize(nw);
+      bool ok = std::fread(P->lam.data(), sizeof(double), nw, f) == (size_t)nw;
+      P->proj.off = P->pinv.off = h.proj_off;
+      P->proj.r = P->pinv.r = h.proj_r;
+      P->tik.off = P->tikm.off = h.tik_off;
+      P->tik.r = P->tikm.r = h.tik_r;
+      for (OpSet *op : {&P->proj, &P->pinv, &P->tik, &P->tikm}) {
+        op->d.resize(op->r);
+        ok = ok && std::fread(op->d.data(), sizeof(double), op->r, f) == (size_t)op->r;
+      }
+      std::vector<double> U((size_t)P->N * P->u_r);
+      ok = ok && std::fread(U.data(), sizeof(double), U.size(), f) == U.size();
+      std::fclose(f);
+      f = nullptr;
+      if (!ok) throw Fail{SLEPIAN_EIO};
+      hipStream_t st = nullptr;
+      HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      try {
+        build_fft_state(P, st);
+        (void)hipStreamDestroy(st);
+      } catch (...) {
+        (void)hipStreamDestroy(st);
+        throw;
+      }
+      P->U64 = dalloc<double>((size_t)P->N * std::max<int64_t>(P->u_r, 1));
+      P->U32 = dalloc<float>((size_t)P->N * std::max<int64_t>(P->u_r, 1));
+      if (P->u_r) {
+        HIPCHK(hipMemcpy(P->U64, U.data(), U.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(cast_f64_to_f32(P->U64, P->N, P->U32, P->N, P->N, P->u_r, nullptr));
+        HIPCHK(hipDeviceSynchronize());
+      }
+      for (OpSet *op : {&P->proj, &P->pinv, &P->tik, &P->tikm}) upload_d(*op);
+    } catch (...) {
+      if (f) std::fclose(f);
+      delete P;
+      throw;
+    }
+    *out = P;
+    return SLEPIAN_OK;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Groups
+// ---------------------------------------------------------------------------
+
+int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batch, slepian_group_t *out) {
+  if (!plans || !batch || !out || n < 1) return SLEPIAN_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i] || batch[i] < 0 || batch[i] > 32 * 65535) return SLEPIAN_EINVAL;
+    if (plans[i]->device != plans[0]->device) return SLEPIAN_EINVAL;
+    if (plans[i]->precision != SLEPIAN_FP32) return SLEPIAN_ENOTSUP;
+  }
+  return guarded([&]() -> int {
+    DeviceGuard dg(plans[0]->device);
+    slepian_group_s *G = new slepian_group_s();
+    try {
+      G->device = plans[0]->device;
+      G->plans.assign(plans, plans + n);
+      G->batch.assign(batch, batch + n);
+      size_t need = 256;
+      for (int i = 0; i < n; ++i) need = std::max(need, op_workspace(plans[i], SLEPIAN_OP_PROJECT, batch[i]));
+      G->ws = dalloc<char>(need);
+      G->ws_bytes = need;
+      HIPCHK(hipStreamCreateWithFlags(&G->cap, hipStreamNonBlocking));
+    } catch (...) {
+      delete G;
+      throw;
+    }
+    *out = G;
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_group_project(slepian_group_t G, const float *const *x, float *const *y, void *stream) {
+  if (!G || !x || !y) return SLEPIAN_EINVAL;
+  const int n = (int)G->plans.size();
+  for (int i = 0; i < n; ++i)
+    if (G->batch[i] > 0 && (!x[i] || !y[i])) return SLEPIAN_EINVAL;
+  return guarded([&]() -> int {
+    DeviceGuard dg(G->device);
+    hipStream_t st = (hipStream_t)stream;
+    bool same = G->exec && G->lx.size() == (size_t)n;
+    for (int i = 0; same && i < n; ++i) same = G->lx[i] == x[i] && G->ly[i] == y[i];
+    if (!same) {
+      if (G->exec) (void)hipGraphExecDestroy(G->exec);
+      if (G->graph) (void)hipGraphDestroy(G->graph);
+      G->exec = nullptr;
+      G->graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(G->cap, hipStreamCaptureModeThreadLocal));
+      try {
+        for (int i = 0; i < n; ++i) {
+          const Plan *P = G->plans[i];
+          if (G->batch[i] == 0) continue;
+          Carver cv(G->ws);
+          ProjWs w = carve_project(P, P->proj, G->batch[i], cv);
+          run_fast_op(P, P->proj, 1.0f, 0.0f, x[i], P->N, y[i], P->N, G->batch[i], w, G->cap);
+        }
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(G->cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(G->cap, &G->graph));
+      HIPCHK(hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0));
+      G->lx.assign(x, x + n);
+      G->ly.assign(y, y + n);
+    }
+    HIPCHK(hipGraphLaunch(G->exec, st));
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_group_destroy(slepian_group_t G) {
+  if (!G) return SLEPIAN_OK;
+  return guarded([&]() -> int {
+    DeviceGuard dg(G->device);
+    (void)hipDeviceSynchronize();
+    delete G;
+    return SLEPIAN_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Shared device/host definitions for libslepian (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace slp {
+
+// Complex number with the alignment of a float2/double2 so that LDS and
+// global accesses are single 8/16-byte transactions.
+template <typename R>
+struct alignas(2 * sizeof(R)) cpx {
+  R x, y;
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ cpx<R> mk(R a, R b) { return cpx<R>{a, b}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename R>
+__device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> cscale(cpx<R> a, R s) { return {a.x * s, a.y * s}; }
+
+// Geometry of the length-L circular convolution used for B x.
+//   single pass (log1 == 0): one workgroup holds a whole length-L transform in LDS.
+//   three passes: L = L1 * L2, time index n = n2 + L2 * n1, frequency index
+//   k = k1 + L1 * k2; pass A does the length-L1 column transforms, pass B the
+//   length-L2 row transforms with the spectrum multiply in between, pass C the
+//   inverse column transforms.
+struct FftGeom {
+  int logL = 0;
+  int log1 = 0;   // L1 = 2^log1 (0: single pass)
+  int log2 = 0;   // L2 = 2^log2
+  int logCT = 0;  // columns per pass-A/C workgroup
+  int logT = 0;   // length of the sub-transform twiddle table
+  int s = 0;      // split of the two-level table for W_L^m: m = (hi << s) | lo
+  __host__ __device__ bool single() const { return log1 == 0; }
+};
+
+// Per-precision LDS budget: elements of cpx<R> held by one workgroup.
+template <typename R> struct Lds;
+template <> struct Lds<float> { static constexpr int E = 8192; static constexpr int logE = 13; };
+template <> struct Lds<double> { static constexpr int E = 4096; static constexpr int logE = 12; };
+
+constexpr int kThreads = 256;   // threads per FFT workgroup
+constexpr int kMaxRankSingle = 256;  // max correction columns handled inside the single-pass kernel
+
+// Device tables of one precision for one FFT geometry.
+template <typename R>
+struct FftTables {
+  const cpx<R> *tw_sub = nullptr;  // W_T^m = exp(-2 pi i m / T), m < T
+  const cpx<R> *tw_lo = nullptr;   // W_L^m, m < 2^s
+  const cpx<R> *tw_hi = nullptr;   // W_L^(m << s), m < 2^(logL - s)
+  const R *chat = nullptr;         // spectrum of B's circulant embedding / L, in pass layout
+};
+
+// Correction y += U diag(d) U^T x.  U is N x r column-major (ldu).
+template <typename R>
+struct Corr {
+  const R *U = nullptr;
+  int64_t ldu = 0;
+  int r = 0;
+  const R *d = nullptr;      // r weights
+};
+
+}  // namespace slp

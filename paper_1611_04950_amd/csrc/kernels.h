@@ -1,0 +1,79 @@
+// Host-side launchers of the HIP kernels (internal to libslepian).
+#pragma once
+
+#include "common.h"
+
+namespace slp {
+
+// ---- FFT product (fft.hip) ----
+FftGeom make_geom(int logL, int logE);
+
+template <typename R>
+hipError_t build_tables(const FftGeom &g, cpx<R> *tw_sub, cpx<R> *tw_lo, cpx<R> *tw_hi, hipStream_t st);
+
+hipError_t sinc_embed(double *c, int64_t L, int64_t N, double W, hipStream_t st);
+
+hipError_t fft_forward_real64(const double *c, const FftGeom &g, const FftTables<double> &tb,
+                              cpx<double> *spec, hipStream_t st);
+
+template <typename R>
+hipError_t spectrum_relayout(const cpx<double> *src, const FftGeom &gs, R *dst, const FftGeom &gd,
+                             hipStream_t st);
+
+size_t conv_workspace_pairs(const FftGeom &g, int64_t pairs, size_t elem_bytes, size_t budget);
+
+template <typename R>
+hipError_t conv_apply(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, int64_t b, const FftGeom &g,
+                      const FftTables<R> &tb, R beta, R gamma, const Corr<R> &corr, cpx<R> *Z,
+                      int64_t slice_pairs, hipStream_t st);
+
+// ---- Tridiagonal eigensolver and Rayleigh quotients (eig.hip) ----
+hipError_t tridiag_build(double *a, double *e2, int64_t N, double W, hipStream_t st);
+
+// Eigenvalues theta_t (ascending order index t = t0 .. t0+count-1) of the
+// tridiagonal matrix by multisection on Sturm counts.
+hipError_t tridiag_bisect(const double *a, const double *e2, int64_t N, double gl, double gu, double pivmin,
+                          int64_t t0, int64_t count, double *theta, hipStream_t st);
+
+// Inverse iteration for `count` eigenvalues; writes unit-norm, sign-fixed
+// vectors to V (N x count, column-major, ld N), column order reversed
+// (column count-1-j holds theta[j]) so columns run in descending theta.
+// `scratch` must hold inviter_scratch_bytes(N, count) bytes.
+size_t inviter_scratch_bytes(int64_t N, int64_t count);
+hipError_t tridiag_inviter(const double *a, const double *off, int64_t N, const double *theta, int64_t count,
+                           double *V, void *scratch, int iters, hipStream_t st);
+
+// lam[j] = v_j^T (B v_j), res[j] = ||B v_j - lam_j v_j|| for unit v_j.
+hipError_t rayleigh(const double *V, const double *BV, int64_t N, int64_t count, double *lam, double *res,
+                    hipStream_t st);
+
+// ---- Low-rank correction (corr.hip) ----
+// part[chunk][j][s] = sum over rows of the chunk of U[n,j] x_s[n].
+int corr_chunks(int64_t N);
+int corr_rpad(int r);
+hipError_t corr_partial(const float *x, int64_t ldx, int64_t N, int64_t b, const float *U, int64_t ldu, int r,
+                        float *part, hipStream_t st);
+// dC[s][j] = d[j] * sum_chunk part[chunk][j][s]
+hipError_t corr_reduce(const float *part, int64_t N, int64_t b, int r, const float *d, float *dC, hipStream_t st);
+// c[s*ldc + j] = sum_chunk part[chunk][j][s]
+hipError_t corr_sum(const float *part, int64_t N, int64_t b, int r, float *c, int64_t ldc, hipStream_t st);
+// y[s][n] += sum_j U[n,j] dC[s][j]
+hipError_t corr_apply(float *y, int64_t ldy, int64_t N, int64_t b, const float *U, int64_t ldu, int r,
+                      const float *dC, hipStream_t st);
+
+// ---- Small elementwise helpers (eig.hip) ----
+hipError_t cast_f64_to_f32(const double *src, int64_t ld_src, float *dst, int64_t ld_dst, int64_t rows,
+                           int64_t cols, hipStream_t st);
+hipError_t cast_f32_to_f64(const float *src, int64_t ld_src, double *dst, int64_t ld_dst, int64_t rows,
+                           int64_t cols, hipStream_t st);
+
+// ---- Least-squares refinement helpers (lsq.hip) ----
+// rho = By - u - alpha x (all FP64, N x b with leading dimension N except x: ldx)
+hipError_t lsq_residual(const double *By, const double *u, const double *x, int64_t ldx, double alpha, double *rho,
+                        int64_t N, int64_t b, hipStream_t st);
+// norms[s] = ||v_s||_2 (FP64)
+hipError_t col_norms(const double *v, int64_t ldv, int64_t N, int64_t b, double *norms, hipStream_t st);
+// x (FP64, ldx) += e (FP32, lde)
+hipError_t add_f32_to_f64(const float *e, int64_t lde, double *x, int64_t ldx, int64_t N, int64_t b, hipStream_t st);
+
+}  // namespace slp

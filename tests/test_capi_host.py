@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/slepian.h declares, and rejects bad arguments before
+touching a device."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1611_04950_amd import slepian as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "slepian.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(slepian_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_functions_are_exported():
+    names = _declared_functions()
+    assert len(names) >= 17
+    lib = C.CDLL(S.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(S.EXPORTED) == names
+
+
+def test_status_strings():
+    for st in range(-8, 1):
+        assert S.slepian_status_string(st) != "unknown status"
+    assert S.slepian_status_string(-99) == "unknown status"
+
+
+@pytest.mark.parametrize("N,W,eps,code", [
+    (1, 0.1, 1e-6, S.SLEPIAN_EINVAL),
+    (100, 0.0, 1e-6, S.SLEPIAN_EINVAL),
+    (100, 0.5, 1e-6, S.SLEPIAN_EINVAL),
+    (100, 0.1, 0.0, S.SLEPIAN_EINVAL),
+    (100, 0.1, 0.5, S.SLEPIAN_EINVAL),
+    (100, float("nan"), 1e-6, S.SLEPIAN_EINVAL),
+    (1 << 22, 0.1, 1e-6, S.SLEPIAN_ENOTSUP),
+])
+def test_plan_domain_checked_before_any_device_work(N, W, eps, code):
+    h = C.c_void_p()
+    assert S._lib.slepian_plan(N, W, eps, C.byref(h)) == code
+    assert h.value is None
+
+
+def test_plan_options_checked():
+    h = C.c_void_p()
+    for opts in (S.PlanOpts(-1.0, 0, 0, -1), S.PlanOpts(0.0, 100, 0, -1), S.PlanOpts(0.0, -2, 0, -1),
+                 S.PlanOpts(0.0, 0, 7, -1)):
+        assert S._lib.slepian_plan_ex(100, 0.1, 1e-6, C.byref(opts), C.byref(h)) == S.SLEPIAN_EINVAL
+
+
+def test_null_handles():
+    lib = S._lib
+    assert lib.slepian_plan_destroy(None) == S.SLEPIAN_OK
+    assert lib.slepian_group_destroy(None) == S.SLEPIAN_OK
+    n = C.c_size_t()
+    assert lib.slepian_workspace_size(None, 0, 4, C.byref(n)) == S.SLEPIAN_EINVAL
+    assert lib.slepian_project(None, None, 0, None, 0, 1, None, 0, None) == S.SLEPIAN_EINVAL
+    assert lib.slepian_lsq(None, 0, 0.0, None, 0, None, 0, 1, 0.0, 0, None, 0, None, None) == S.SLEPIAN_EINVAL
+    assert lib.slepian_coeffs(None, None, 0, None, 0, 1, None, 0, None) == S.SLEPIAN_EINVAL
+    assert lib.slepian_plan_info_get(None, None) == S.SLEPIAN_EINVAL
+    assert lib.slepian_plan_save(None, b"/tmp/x") == S.SLEPIAN_EINVAL
+    h = C.c_void_p()
+    assert lib.slepian_plan_load(b"/nonexistent/plan.bin", -1, C.byref(h)) == S.SLEPIAN_EIO
+    assert lib.slepian_group_create(None, 0, None, C.byref(h)) == S.SLEPIAN_EINVAL
+
+
+def test_plan_load_rejects_garbage(tmp_path):
+    p = tmp_path / "bad.plan"
+    p.write_bytes(b"not a plan file at all" * 10)
+    h = C.c_void_p()
+    assert S._lib.slepian_plan_load(str(p).encode(), -1, C.byref(h)) == S.SLEPIAN_EIO
+
+
+def test_synth_is_seeded_and_float32():
+    from paper_1611_04950_amd import synth
+    a = synth.config_signals(2, 512, 3, 0.125)
+    b = synth.config_signals(2, 512, 3, 0.125)
+    assert a.dtype.is_floating_point and a.dtype.itemsize == 4
+    assert a.shape == (3, 512)
+    assert (a == b).all()
+    c = synth.config_signals(1, 100, 2, 0.1)
+    assert abs(float(c.double().std()) - 1.0) < 0.2

@@ -283,11 +283,13 @@ def test_tikhonov_cg_matches_dense():
 def test_coeffs_reconstruct_projection():
     N, W = 128, 1 / 16
     x = np.random.default_rng(1).standard_normal((N, 2))
-    _, S = o.dense_eig(N, W)
     K = o.choose_K(N, W)
+    _, S = o.slepian_vectors(N, W, 0, K - 1)
     c = o.coeffs_exact(N, W, x)
     assert c.shape == (K, 2)
-    np.testing.assert_allclose(S[:, :K] @ c, o.project_exact(N, W, x), atol=1e-12)
+    # the tridiagonal vectors span the same subspace as dense eig's first K
+    np.testing.assert_allclose(S @ c, o.project_exact(N, W, x), atol=1e-11)
+    np.testing.assert_allclose(S.T @ S, np.eye(K), atol=1e-12)
     # energy in the band: ||c|| = ||P x|| <= ||x||
     assert np.all(np.linalg.norm(c, axis=0) <= np.linalg.norm(x, axis=0))
 
