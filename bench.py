@@ -1,0 +1,257 @@
+"""Benchmark of the fast Slepian projection on one MI355X.
+
+One step = one slepian_project call over the whole batch: B x by the FFT
+product plus the low-rank transition correction, every kernel of the path.
+Default workload: N = 65536, W = 1/8, eps = 1e-6, 256 signals of 64 random
+tones plus white noise at 20 dB SNR (synthetic stand-in for the paper's random
+vectors; Section 4.1 uses W = 1/4, 1/16, 1/64 and N up to 2^20).
+
+Prints one JSON line.  `value` is GSamples/s = N * batch * steps / elapsed
+seconds of the timed region (inputs already resident in HBM, HIP events on the
+library's stream, torch.cuda.synchronize() on both sides).  The run is only
+valid if sampled outputs match the CPU FP64 oracle to 1e-5 relative l2 error
+(checked before timing; the script exits non-zero otherwise).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GSamples/s projected at 1e-5 rel. err, batched mixed vs plain FP32; % HBM/MFMA roof"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (N, W, eps, batch, signal config)
+    "paper-scale N=65536 W=1/8 eps=1e-6 b=256": (65536, 1.0 / 8, 1e-6, 256, 2),
+    "small N=1024 W=1/16 eps=1e-6 b=8": (1024, 1.0 / 16, 1e-6, 8, 1),
+    "precision N=262144 W=0.05 eps=1e-4 b=1024": (262144, 0.05, 1e-4, 1024, 3),
+}
+DEFAULT = "paper-scale N=65536 W=1/8 eps=1e-6 b=256"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(name: str, N: int, b: int, L: int, r: int, pairs_per_launch: int) -> float:
+    """Algorithmic HBM bytes of one launch of each kernel of the path: what the
+    method must move (FP32 signal in/out 4 B/sample, complex64 intermediates
+    8 B/point, spectrum 4 B/point once, U 4 B/entry once)."""
+    P = pairs_per_launch
+    if name == "row_conv":
+        return P * 16.0 * L + 4.0 * L
+    if name == "col_fwd":
+        return P * (8.0 * N + 8.0 * L)
+    if name == "col_inv":
+        return P * (8.0 * L + 8.0 * N)
+    if name == "corr_partial":
+        return 4.0 * N * b + 4.0 * N * r
+    if name == "corr_apply":
+        return 8.0 * N * b + 4.0 * N * r
+    if name in ("conv_single", "conv_single_corr"):
+        return P * 8.0 * N + 4.0 * L + 4.0 * N * r
+    return float("nan")
+
+
+def read_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken with the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    try:
+        from paper_1611_04950_amd.build import source_digest
+        if vals.get("source_digest") != source_digest() or vals.get("workload") != workload:
+            return None
+        return float(vals["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(N, W, eps, x_sample, min_seconds):
+    """The oracle's FP64 fast projection timed on this host (1 thread)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import slepian_oracle as o
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        tp = o.transition_plan(N, W, eps, 1 - eps)
+        setup = time.perf_counter() - t0
+        xs = x_sample.T.astype(np.float64)
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            o.project_fast(N, W, eps, xs, tp=tp)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= min_seconds:
+                break
+    samples = reps * xs.shape[0] * xs.shape[1]
+    return {"value": samples / el / 1e6, "unit": "MSamples/s", "cores": 1, "kind": "oracle",
+            "sample": f"{xs.shape[1]} signals of the workload, projected {reps} times ({el:.1f} s); "
+                      f"oracle setup (transition vectors) {setup:.1f} s not included",
+            "setup_s": setup}, tp
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-signal FP32 comparison")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the workload's "
+              f"signals are independent and would shard across GPUs without communication.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1611_04950_amd import slepian as S
+    from paper_1611_04950_amd import synth
+
+    N, W, eps, b, cfg = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    log(f"bench: plan N={N} W={W} eps={eps}")
+    t0 = time.perf_counter()
+    plan = S.slepian_plan(N, W, eps)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = plan.info
+    log(f"bench: plan ready in {setup_s:.2f} s: K={info['K']} L={info['L']} r={info['r']}")
+
+    x = synth.config_signals(cfg, N, b, W, device=dev)
+    y = torch.empty_like(x)
+    wsz = S.slepian_workspace_size(plan, S.SLEPIAN_OP_PROJECT, b)
+    work = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    # parity gate on sampled signals against the CPU FP64 oracle
+    S.slepian_project(plan, x, y, work=work)
+    torch.cuda.synchronize()
+    idx = sorted(set([0, b // 2, b - 1]))
+    xs = x[idx].double().cpu().numpy()
+    ys = y[idx].double().cpu().numpy()
+    cpu = None
+    tp = None
+    if not args.no_cpu:
+        log("bench: timing the CPU oracle")
+        cpu, tp = cpu_baseline(N, W, eps, x[: min(b, 32)].double().cpu().numpy(), args.cpu_seconds)
+    from oracle import slepian_oracle as o
+    if tp is None:
+        tp = o.transition_plan(N, W, eps, 1 - eps)
+    ref = o.project_fast(N, W, eps, xs.T, tp=tp).T
+    err = float((np.linalg.norm(ys - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
+    log(f"bench: parity max rel err vs oracle on signals {idx}: {err:.3e}")
+    if not err <= 1e-5:
+        log("bench: parity gate failed; no throughput reported")
+        sys.exit(1)
+
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        S.slepian_project(plan, x, y, work=work)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        S.slepian_project(plan, x, y, work=work)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    el_ms = ev0.elapsed_time(ev1)
+    ms_per_step = el_ms / args.steps
+    value = N * b / (ms_per_step * 1e-3) / 1e9
+    log(f"bench: {ms_per_step:.4f} ms/step (wall {wall / args.steps * 1e3:.4f}), {value:.2f} GSamples/s")
+
+    # per-kernel durations with HIP events around each launch (traced pass)
+    S.slepian_trace_enable(True)
+    for _ in range(args.steps):
+        S.slepian_project(plan, x, y, work=work)
+    torch.cuda.synchronize()
+    stats = S.slepian_trace_read(reset=True)
+    S.slepian_trace_enable(False)
+    kernels = {}
+    slice_pairs = None
+    for name, s in stats.items():
+        launches_per_step = s["launches"] / args.steps
+        kernels[name] = {"avg_us": s["total_ms"] / s["launches"] * 1e3, "launches_per_step": launches_per_step,
+                         "share": s["total_ms"] / sum(v["total_ms"] for v in stats.values())}
+    pairs = (b + 1) // 2
+    dom = max(stats, key=lambda k: stats[k]["total_ms"])
+    per_step = kernels[dom]["launches_per_step"]
+    pairs_per_launch = pairs / per_step if dom not in ("corr_partial", "corr_apply") else pairs
+    nbytes = kernel_bytes(dom, N, b, info["L"], info["r"], pairs_per_launch)
+    avg_s = kernels[dom]["avg_us"] * 1e-6
+    achieved = nbytes / avg_s / 1e9
+    for name in kernels:
+        ppl = pairs / kernels[name]["launches_per_step"] if name not in ("corr_partial", "corr_apply") else pairs
+        kb = kernel_bytes(name, N, b, info["L"], info["r"], ppl)
+        kernels[name]["alg_GBs"] = kb / (kernels[name]["avg_us"] * 1e-6) / 1e9
+    traffic = read_traffic(dom, args.workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "alg_bytes_per_launch": nbytes, "avg_launch_us": round(kernels[dom]["avg_us"], 3)}
+
+    plain = None
+    if not args.no_plain:
+        # the plain per-signal FP32 path: one signal per call
+        nrep = 2
+        for s in range(min(b, 8)):
+            S.slepian_project(plan, x[s:s + 1], y[s:s + 1], work=work)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(nrep):
+            for s in range(b):
+                S.slepian_project(plan, x[s:s + 1], y[s:s + 1], work=work)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        pms = ev0.elapsed_time(ev1) / nrep
+        plain = {"value": N * b / (pms * 1e-3) / 1e9, "unit": "GSamples/s", "ms_per_step": pms,
+                 "speedup_batched": round(pms / ms_per_step, 2)}
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GSamples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "N": N, "W": W, "eps": eps, "batch": b, "K": info["K"],
+                   "L": info["L"], "r": info["r"], "precision": "fp32 FFT product, fp32 correction"},
+        "parity_max_rel_err": err,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain_fp32_per_signal": plain,
+        "compulsory_byte_efficiency": round(value * 1e9 * 8 / (HBM_PEAK_GBS * 1e9), 4),
+        "plan_setup_s": round(setup_s, 3),
+        "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kernels.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -207,6 +207,24 @@ int slepian_group_project(slepian_group_t group, const float *const *x, float *c
 
 int slepian_group_destroy(slepian_group_t group);
 
+/* Kernel tracing (profiling).  While enabled (process-wide, off by default),
+ * every hot-path kernel launch of the library is bracketed by two HIP events
+ * recorded on the launch's own stream, so the elapsed time between them is
+ * that kernel's device duration.  slepian_trace_read synchronises on the
+ * recorded events and returns per-kernel totals (name, launches, total/min/max
+ * milliseconds) into stats (host, cap entries); *count receives the number of
+ * distinct kernels (may exceed cap).  reset != 0 clears the records.  Tracing
+ * adds two event records per launch; do not enable it while a stream is being
+ * captured into a graph. */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double total_ms, min_ms, max_ms;
+} slepian_kernel_stat;
+
+int slepian_trace_enable(int on);
+int slepian_trace_read(slepian_kernel_stat *stats, int cap, int *count, int reset);
+
 /* Static description of a status code. */
 const char *slepian_status_string(int status);
 

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libslepian.so")
 
-SOURCES = ["fft.hip", "eig.hip", "corr.hip", "lsq.hip", "capi.cpp"]
+SOURCES = ["fft.hip", "eig.hip", "corr.hip", "lsq.hip", "capi.cpp", "trace.cpp"]
 ARCH = os.environ.get("SLEPIAN_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -31,6 +31,17 @@ FLAGS = [
     f"-I{INCLUDE}", f"-I{CSRC}",
     "-Wno-unused-result",
 ]
+
+
+def source_digest() -> str:
+    """Short hash of the library's sources (identifies which kernels a profile
+    was taken with)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
 
 
 def _compile(src: str) -> str:

@@ -6,6 +6,7 @@
 // X, and the chunk partials are summed in a fixed order (deterministic).
 #include "common.h"
 #include "kernels.h"
+#include "trace.h"
 
 namespace slp {
 
@@ -80,7 +81,7 @@ hipError_t corr_partial(const float *x, int64_t ldx, int64_t N, int64_t b, const
   if (b > 32 * 65535 || r > 32 * 65535) return hipErrorInvalidValue;
   const int rpad = corr_rpad(r);
   const dim3 grid(corr_chunks(N), (unsigned)((b + 31) / 32), rpad / 32);
-  hipLaunchKernelGGL(k_corr_partial, grid, dim3(256), 0, st, x, ldx, (int)N, (int)b, U, ldu, r, part, rpad);
+  SLP_LAUNCH("corr_partial", k_corr_partial, grid, dim3(256), 0, st, x, ldx, (int)N, (int)b, U, ldu, r, part, rpad);
   return hipGetLastError();
 }
 
@@ -97,7 +98,7 @@ __global__ void k_corr_reduce(const float *__restrict__ part, int chunks, int rp
 hipError_t corr_reduce(const float *part, int64_t N, int64_t b, int r, const float *d, float *dC, hipStream_t st) {
   if (r == 0 || b == 0) return hipSuccess;
   const int64_t tot = b * r;
-  hipLaunchKernelGGL(k_corr_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, corr_chunks(N),
+  SLP_LAUNCH("corr_reduce", k_corr_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, corr_chunks(N),
                      corr_rpad(r), (int)b, r, d, dC);
   return hipGetLastError();
 }
@@ -116,7 +117,7 @@ __global__ void k_corr_sum(const float *__restrict__ part, int chunks, int rpad,
 hipError_t corr_sum(const float *part, int64_t N, int64_t b, int r, float *c, int64_t ldc, hipStream_t st) {
   if (r == 0 || b == 0) return hipSuccess;
   const int64_t tot = b * r;
-  hipLaunchKernelGGL(k_corr_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, corr_chunks(N),
+  SLP_LAUNCH("corr_sum", k_corr_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, corr_chunks(N),
                      corr_rpad(r), (int)b, r, c, ldc);
   return hipGetLastError();
 }
@@ -158,7 +159,7 @@ hipError_t corr_apply(float *y, int64_t ldy, int64_t N, int64_t b, const float *
                       const float *dC, hipStream_t st) {
   if (r == 0 || b == 0) return hipSuccess;
   const dim3 grid((unsigned)((N + 255) / 256), (unsigned)((b + kApplySig - 1) / kApplySig));
-  hipLaunchKernelGGL(k_corr_apply, grid, dim3(256), 0, st, y, ldy, (int)N, (int)b, U, ldu, r, dC, corr_rpad(r));
+  SLP_LAUNCH("corr_apply", k_corr_apply, grid, dim3(256), 0, st, y, ldy, (int)N, (int)b, U, ldu, r, dC, corr_rpad(r));
   return hipGetLastError();
 }
 

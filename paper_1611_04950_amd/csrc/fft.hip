@@ -18,6 +18,7 @@
 // inverse column transforms).
 #include "common.h"
 #include "kernels.h"
+#include "trace.h"
 
 namespace slp {
 
@@ -485,10 +486,11 @@ hipError_t conv_apply(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, int
       const int bs = (int)(b - 2 * p0 < 2 * np ? b - 2 * p0 : 2 * np);
       Corr<R> c2 = corr;
       if (corr.r > 0) {
-        hipLaunchKernelGGL((k_conv_single<R, true>), dim3(np), dim3(kThreads), 0, st, xs, ldx, ys, ldy,
+        SLP_LAUNCH("conv_single_corr", (k_conv_single<R, true>), dim3(np), dim3(kThreads), 0, st, xs, ldx, ys, ldy,
                            (int)N, bs, g.logL, tb, g.logT, beta, gl, c2);
       } else {
-        hipLaunchKernelGGL((k_conv_single<R, false>), dim3(np), dim3(kThreads), 0, st, xs, ldx, ys, ldy,
+        SLP_LAUNCH(sizeof(R) == 4 ? "conv_single" : "conv_single_f64", (k_conv_single<R, false>), dim3(np),
+                   dim3(kThreads), 0, st, xs, ldx, ys, ldy,
                            (int)N, bs, g.logL, tb, g.logT, beta, gl, c2);
       }
     }
@@ -498,9 +500,12 @@ hipError_t conv_apply(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, int
     const int64_t np = pairs - p0 < slice_pairs ? pairs - p0 : slice_pairs;
     const dim3 gcol(1 << (g.log2 - g.logCT), (unsigned)np);
     const dim3 grow(1 << g.log1, (unsigned)np);
-    hipLaunchKernelGGL(k_col_fwd<R>, gcol, dim3(kThreads), 0, st, x, ldx, (int)N, (int)b, (int)p0, g, tb, Z);
-    hipLaunchKernelGGL((k_row<R, false>), grow, dim3(kThreads), 0, st, Z, g, tb, beta, gl);
-    hipLaunchKernelGGL(k_col_inv<R>, gcol, dim3(kThreads), 0, st, Z, g, tb, y, ldy, (int)N, (int)b, (int)p0);
+    const bool f = sizeof(R) == 4;
+    SLP_LAUNCH(f ? "col_fwd" : "col_fwd_f64", k_col_fwd<R>, gcol, dim3(kThreads), 0, st, x, ldx, (int)N, (int)b,
+               (int)p0, g, tb, Z);
+    SLP_LAUNCH(f ? "row_conv" : "row_conv_f64", (k_row<R, false>), grow, dim3(kThreads), 0, st, Z, g, tb, beta, gl);
+    SLP_LAUNCH(f ? "col_inv" : "col_inv_f64", k_col_inv<R>, gcol, dim3(kThreads), 0, st, Z, g, tb, y, ldy, (int)N,
+               (int)b, (int)p0);
   }
   return hipGetLastError();
 }

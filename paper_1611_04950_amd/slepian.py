@@ -39,6 +39,7 @@ EXPORTED = [
     "slepian_plan_save", "slepian_plan_load", "slepian_plan_destroy", "slepian_workspace_size",
     "slepian_project", "slepian_project_ex", "slepian_coeffs", "slepian_lsq", "slepian_apply_b64",
     "slepian_group_create", "slepian_group_project", "slepian_group_destroy", "slepian_status_string",
+    "slepian_trace_enable", "slepian_trace_read",
 ]
 
 
@@ -54,6 +55,11 @@ class PlanInfo(C.Structure):
         ("window_hi", C.c_int64), ("lam_Km1", C.c_double), ("lam_K", C.c_double),
         ("eps_achieved", C.c_double), ("precision", C.c_int), ("device", C.c_int),
     ]
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("min_ms", C.c_double), ("max_ms", C.c_double)]
 
 
 class LsqReport(C.Structure):
@@ -84,6 +90,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "slepian_group_project": [vp, C.POINTER(vp), C.POINTER(vp), vp],
         "slepian_group_destroy": [vp],
         "slepian_status_string": [i32],
+        "slepian_trace_enable": [i32],
+        "slepian_trace_read": [C.POINTER(KernelStat), i32, C.POINTER(i32), i32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -283,3 +291,18 @@ def slepian_group_project(group: Group, xs, ys) -> None:
 
 def slepian_status_string(status: int) -> str:
     return _lib.slepian_status_string(status).decode()
+
+
+def slepian_trace_enable(on: bool = True) -> None:
+    _check(_lib.slepian_trace_enable(1 if on else 0), "slepian_trace_enable")
+
+
+def slepian_trace_read(reset: bool = True) -> dict:
+    """{kernel name: {launches, total_ms, min_ms, max_ms}} over the traced launches."""
+    cap = 64
+    arr = (KernelStat * cap)()
+    n = C.c_int()
+    _check(_lib.slepian_trace_read(arr, cap, C.byref(n), 1 if reset else 0), "slepian_trace_read")
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "total_ms": arr[i].total_ms,
+                                   "min_ms": arr[i].min_ms, "max_ms": arr[i].max_ms}
+            for i in range(min(n.value, cap))}
