@@ -247,6 +247,8 @@ def main():
         "plain_fp32_per_signal": plain,
         "compulsory_byte_efficiency": round(value * 1e9 * 8 / (HBM_PEAK_GBS * 1e9), 4),
         "plan_setup_s": round(setup_s, 3),
+        "device": {"name": torch.cuda.get_device_name(dev),
+                   "cu": torch.cuda.get_device_properties(dev).multi_processor_count},
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
     }

@@ -109,8 +109,8 @@ struct slepian_plan_s {
   double W = 0, eps = 0, alpha = 0;
   int precision = SLEPIAN_FP32;
   FftGeom g32, g64;
-  cpx<float> *tw32[3] = {nullptr, nullptr, nullptr};
-  cpx<double> *tw64[3] = {nullptr, nullptr, nullptr};
+  cpx<float> *tw32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  cpx<double> *tw64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   float *chat32 = nullptr;
   double *chat64 = nullptr;
   FftTables<float> tb32;
@@ -311,8 +311,8 @@ void upload_d(OpSet &o) {
 void build_fft_state(Plan *P, hipStream_t st) {
   const int logL = ilog2_ceil(2 * P->N);
   P->L = (int64_t)1 << logL;
-  P->g32 = make_geom(logL, Lds<float>::logE);
-  P->g64 = make_geom(logL, Lds<double>::logE);
+  P->g32 = make_geom(logL, Lds<float>::logE, true);
+  P->g64 = make_geom(logL, Lds<double>::logE, true);
   const int64_t L = P->L;
   P->tw32[0] = dalloc<cpx<float>>((size_t)1 << P->g32.logT);
   P->tw32[1] = dalloc<cpx<float>>((size_t)1 << P->g32.s);
@@ -328,15 +328,31 @@ void build_fft_state(Plan *P, hipStream_t st) {
   P->tb64.tw_sub = P->tw64[0];
   P->tb64.tw_lo = P->tw64[1];
   P->tb64.tw_hi = P->tw64[2];
-  // spectrum of the circulant embedding of B's first column (Section 4.1)
+  if (P->g32.v2) {
+    P->tw32[3] = dalloc<cpx<float>>((size_t)P->g32.R1 * P->g32.R2 * P->g32.R3);
+    P->tw32[4] = dalloc<cpx<float>>((size_t)P->g32.R2 * P->g32.R3);
+    HIPCHK(build_row_tables<float>(P->g32, P->tw32[3], P->tw32[4], st));
+    P->tb32.row1 = P->tw32[3];
+    P->tb32.row2 = P->tw32[4];
+  }
+  if (P->g64.v2) {
+    P->tw64[3] = dalloc<cpx<double>>((size_t)P->g64.R1 * P->g64.R2 * P->g64.R3);
+    P->tw64[4] = dalloc<cpx<double>>((size_t)P->g64.R2 * P->g64.R3);
+    HIPCHK(build_row_tables<double>(P->g64, P->tw64[3], P->tw64[4], st));
+    P->tb64.row1 = P->tw64[3];
+    P->tb64.row2 = P->tw64[4];
+  }
+  // spectrum of the circulant embedding of B's first column (Section 4.1),
+  // by the generic FP64 transform, then stored in each path's layout
+  const FftGeom gen64 = generic_twin(P->g64);
   DBuf<double> c(L);
   DBuf<cpx<double>> spec(L);
   HIPCHK(sinc_embed(c.p, L, P->N, P->W, st));
-  HIPCHK(fft_forward_real64(c.p, P->g64, P->tb64, spec.p, st));
+  HIPCHK(fft_forward_real64(c.p, gen64, P->tb64, spec.p, st));
   P->chat32 = dalloc<float>(L);
   P->chat64 = dalloc<double>(L);
-  HIPCHK(spectrum_relayout<float>(spec.p, P->g64, P->chat32, P->g32, st));
-  HIPCHK(spectrum_relayout<double>(spec.p, P->g64, P->chat64, P->g64, st));
+  HIPCHK(spectrum_relayout<float>(spec.p, gen64, P->chat32, P->g32, st));
+  HIPCHK(spectrum_relayout<double>(spec.p, gen64, P->chat64, P->g64, st));
   P->tb32.chat = P->chat32;
   P->tb64.chat = P->chat64;
   HIPCHK(hipStreamSynchronize(st));

@@ -18,20 +18,20 @@ struct alignas(2 * sizeof(R)) cpx {
 template <typename R>
 __host__ __device__ __forceinline__ cpx<R> mk(R a, R b) { return cpx<R>{a, b}; }
 template <typename R>
-__device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.x + b.x, a.y + b.y}; }
+__host__ __device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename R>
-__device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.x - b.x, a.y - b.y}; }
+__host__ __device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.x - b.x, a.y - b.y}; }
 template <typename R>
-__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+__host__ __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 // a * conj(b)
 template <typename R>
-__device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {
+__host__ __device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {
   return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 template <typename R>
-__device__ __forceinline__ cpx<R> cscale(cpx<R> a, R s) { return {a.x * s, a.y * s}; }
+__host__ __device__ __forceinline__ cpx<R> cscale(cpx<R> a, R s) { return {a.x * s, a.y * s}; }
 
 // Geometry of the length-L circular convolution used for B x.
 //   single pass (log1 == 0): one workgroup holds a whole length-L transform in LDS.
@@ -46,6 +46,8 @@ struct FftGeom {
   int logCT = 0;  // columns per pass-A/C workgroup
   int logT = 0;   // length of the sub-transform twiddle table
   int s = 0;      // split of the two-level table for W_L^m: m = (hi << s) | lo
+  int v2 = 0;     // 1: register-stage kernels; rows of length R1 R2 R3
+  int R1 = 0, R2 = 0, R3 = 0;
   __host__ __device__ bool single() const { return log1 == 0; }
 };
 
@@ -64,6 +66,8 @@ struct FftTables {
   const cpx<R> *tw_lo = nullptr;   // W_L^m, m < 2^s
   const cpx<R> *tw_hi = nullptr;   // W_L^(m << s), m < 2^(logL - s)
   const R *chat = nullptr;         // spectrum of B's circulant embedding / L, in pass layout
+  const cpx<R> *row1 = nullptr;    // register-stage rows: W_L2^{t k1} stored [k1][t]
+  const cpx<R> *row2 = nullptr;    // register-stage rows: W_T^{m k2} stored [k2][m]
 };
 
 // Correction y += U diag(d) U^T x.  U is N x r column-major (ldu).

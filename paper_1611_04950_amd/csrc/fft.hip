@@ -388,8 +388,18 @@ __global__ void k_spectrum_relayout(const cpx<double> *__restrict__ src, FftGeom
   if (gs.single()) k = pos;
   else k = (pos >> gs.log2) + ((pos & (((int64_t)1 << gs.log2) - 1)) << gs.log1);
   int64_t pd;
-  if (gd.single()) pd = k;
-  else pd = ((k & (((int64_t)1 << gd.log1) - 1)) << gd.log2) + (k >> gd.log1);
+  if (gd.v2) {
+    // row k1c = k mod L1; within the row, digits of kr = d1 + R1 d2 + R1 R2 d3
+    // stored at (d1 R2 + d2) R3 + d3 (the order the row kernel produces)
+    const int64_t k1c = k & (((int64_t)1 << gd.log1) - 1);
+    const int64_t kr = k >> gd.log1;
+    const int64_t d1 = kr % gd.R1, d2 = (kr / gd.R1) % gd.R2, d3 = kr / ((int64_t)gd.R1 * gd.R2);
+    pd = (k1c << gd.log2) + (d1 * gd.R2 + d2) * gd.R3 + d3;
+  } else if (gd.single()) {
+    pd = k;
+  } else {
+    pd = ((k & (((int64_t)1 << gd.log1) - 1)) << gd.log2) + (k >> gd.log1);
+  }
   dst[pd] = (R)(src[pos].x / (double)L);
 }
 
@@ -397,7 +407,7 @@ __global__ void k_spectrum_relayout(const cpx<double> *__restrict__ src, FftGeom
 // Host launchers
 // ---------------------------------------------------------------------------
 
-FftGeom make_geom(int logL, int logE) {
+FftGeom make_geom(int logL, int logE, bool allow_v2) {
   FftGeom g;
   g.logL = logL;
   if (logL <= logE) {
@@ -414,7 +424,22 @@ FftGeom make_geom(int logL, int logE) {
     g.logT = g.log1 > g.log2 ? g.log1 : g.log2;
   }
   g.s = (logL + 1) / 2;
+  if (allow_v2 && g.log2 >= 9 && g.log2 <= 13 && g.log1 <= 6) {
+    static const int shapes[5][3] = {{8, 8, 8}, {16, 8, 8}, {16, 16, 8}, {16, 16, 16}, {32, 16, 16}};
+    const int *sh = shapes[g.log2 - 9];
+    g.v2 = 1;
+    g.R1 = sh[0];
+    g.R2 = sh[1];
+    g.R3 = sh[2];
+  }
   return g;
+}
+
+FftGeom generic_twin(const FftGeom &g) {
+  FftGeom t = g;
+  t.v2 = 0;
+  t.R1 = t.R2 = t.R3 = 0;
+  return t;
 }
 
 template <typename R>
@@ -475,6 +500,7 @@ template <typename R>
 hipError_t conv_apply(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, int64_t b, const FftGeom &g,
                       const FftTables<R> &tb, R beta, R gamma, const Corr<R> &corr, cpx<R> *Z,
                       int64_t slice_pairs, hipStream_t st) {
+  if (g.v2) return conv_apply_v2<R>(x, ldx, y, ldy, N, b, g, tb, beta, gamma, corr, Z, slice_pairs, st);
   const int64_t pairs = (b + 1) / 2;
   if (pairs == 0) return hipSuccess;
   const R gl = gamma / (R)((int64_t)1 << g.logL);

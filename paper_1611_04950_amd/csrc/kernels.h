@@ -5,8 +5,19 @@
 
 namespace slp {
 
-// ---- FFT product (fft.hip) ----
-FftGeom make_geom(int logL, int logE);
+// ---- FFT product (fft.hip, fft2.hip) ----
+// Geometry for transform length 2^logL with at most 2^logE points per
+// workgroup; register-stage kernels where a row shape and column length fit.
+FftGeom make_geom(int logL, int logE, bool allow_v2);
+FftGeom generic_twin(const FftGeom &g);
+
+template <typename R>
+hipError_t build_row_tables(const FftGeom &g, cpx<R> *rt1, cpx<R> *rt2, hipStream_t st);
+
+template <typename R>
+hipError_t conv_apply_v2(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, int64_t b, const FftGeom &g,
+                         const FftTables<R> &tb, R beta, R gamma, const Corr<R> &corr, cpx<R> *Z, int64_t slice_pairs,
+                         hipStream_t st);
 
 template <typename R>
 hipError_t build_tables(const FftGeom &g, cpx<R> *tw_sub, cpx<R> *tw_lo, cpx<R> *tw_hi, hipStream_t st);
