@@ -53,7 +53,7 @@ def kernel_bytes(name: str, N: int, b: int, L: int, r: int, pairs_per_launch: in
         return P * (8.0 * N + 8.0 * L)
     if name == "col_inv":
         return P * (8.0 * L + 8.0 * N)
-    if name == "corr_partial":
+    if name.startswith("corr_partial"):
         return 4.0 * N * b + 4.0 * N * r
     if name == "corr_apply":
         return 8.0 * N * b + 4.0 * N * r
@@ -80,6 +80,26 @@ def read_traffic(kernel: str, workload: str):
         return float(vals["hbm_bytes_per_launch"])
     except Exception:
         return None
+
+
+def copy_bandwidth(dev, mib=256, reps=10):
+    """Achieved bandwidth of a plain device copy (read + write bytes / time);
+    also the reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.randn(n, device=dev)
+    c = torch.empty_like(a)
+    c.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        c.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"copy_MiB": mib, "copy_ms": round(ms, 4), "copy_GBs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}
 
 
 def cpu_baseline(N, W, eps, x_sample, min_seconds):
@@ -117,7 +137,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-signal FP32 comparison")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only time a plain 256 MiB device-to-device copy (HBM calibration)")
+    ap.add_argument("--precision", choices=["mixed", "fp32"], default="mixed",
+                    help="correction arithmetic of the timed batched path (the FFT product is FP32 in both)")
     args = ap.parse_args()
+
+    if args.copy_only:
+        import torch
+        print(json.dumps(copy_bandwidth(torch.device("cuda:0"))), flush=True)
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the workload's "
@@ -170,28 +199,44 @@ def main():
         log("bench: parity gate failed; no throughput reported")
         sys.exit(1)
 
-    stream = torch.cuda.current_stream(dev)
-    for _ in range(args.warmup):
-        S.slepian_project(plan, x, y, work=work)
+    # parity of the mixed path (BF16 hi/lo matrix-core correction) on the same samples
+    prec = S.SLEPIAN_MIXED if args.precision == "mixed" else S.SLEPIAN_FP32
+    S.slepian_project(plan, x, y, work=work, precision=prec)
     torch.cuda.synchronize()
+    ys = y[idx].double().cpu().numpy()
+    err_sel = float((np.linalg.norm(ys - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
+    log(f"bench: parity ({args.precision}) max rel err vs oracle: {err_sel:.3e}")
+    if not err_sel <= 1e-5:
+        log("bench: parity gate failed; no throughput reported")
+        sys.exit(1)
+
+    stream = torch.cuda.current_stream(dev)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        S.slepian_project(plan, x, y, work=work)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    el_ms = ev0.elapsed_time(ev1)
-    ms_per_step = el_ms / args.steps
+
+    def timed(p):
+        for _ in range(args.warmup):
+            S.slepian_project(plan, x, y, work=work, precision=p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            S.slepian_project(plan, x, y, work=work, precision=p)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / args.steps, (time.perf_counter() - t0) / args.steps * 1e3
+
+    other = S.SLEPIAN_FP32 if prec == S.SLEPIAN_MIXED else S.SLEPIAN_MIXED
+    ms_other, _ = timed(other)
+    ms_per_step, wall_ms = timed(prec)
     value = N * b / (ms_per_step * 1e-3) / 1e9
-    log(f"bench: {ms_per_step:.4f} ms/step (wall {wall / args.steps * 1e3:.4f}), {value:.2f} GSamples/s")
+    log(f"bench: {ms_per_step:.4f} ms/step (wall {wall_ms:.4f}), {value:.2f} GSamples/s; "
+        f"other precision {ms_other:.4f} ms/step")
 
     # per-kernel durations with HIP events around each launch (traced pass)
     S.slepian_trace_enable(True)
     for _ in range(args.steps):
-        S.slepian_project(plan, x, y, work=work)
+        S.slepian_project(plan, x, y, work=work, precision=prec)
     torch.cuda.synchronize()
     stats = S.slepian_trace_read(reset=True)
     S.slepian_trace_enable(False)
@@ -204,12 +249,12 @@ def main():
     pairs = (b + 1) // 2
     dom = max(stats, key=lambda k: stats[k]["total_ms"])
     per_step = kernels[dom]["launches_per_step"]
-    pairs_per_launch = pairs / per_step if dom not in ("corr_partial", "corr_apply") else pairs
+    pairs_per_launch = pairs / per_step if not dom.startswith("corr") else pairs
     nbytes = kernel_bytes(dom, N, b, info["L"], info["r"], pairs_per_launch)
     avg_s = kernels[dom]["avg_us"] * 1e-6
     achieved = nbytes / avg_s / 1e9
     for name in kernels:
-        ppl = pairs / kernels[name]["launches_per_step"] if name not in ("corr_partial", "corr_apply") else pairs
+        ppl = pairs / kernels[name]["launches_per_step"] if not name.startswith("corr") else pairs
         kb = kernel_bytes(name, N, b, info["L"], info["r"], ppl)
         kernels[name]["alg_GBs"] = kb / (kernels[name]["avg_us"] * 1e-6) / 1e9
     traffic = read_traffic(dom, args.workload)
@@ -238,15 +283,21 @@ def main():
         "metric": METRIC, "value": round(value, 3), "unit": "GSamples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "precision": ("FP32 FFT product; correction on matrix cores, BF16 hi/lo operands, FP32 accumulation"
+                      if args.precision == "mixed" else "FP32 FFT product; FP32 matrix-core correction"),
+        "fp32_batched": {"value": round(N * b / (ms_other * 1e-3) / 1e9, 3) if prec == S.SLEPIAN_MIXED else None,
+                         "ms_per_step": round(ms_other, 5) if prec == S.SLEPIAN_MIXED else None},
         "data": "synthetic",
         "config": {"workload": args.workload, "N": N, "W": W, "eps": eps, "batch": b, "K": info["K"],
-                   "L": info["L"], "r": info["r"], "precision": "fp32 FFT product, fp32 correction"},
-        "parity_max_rel_err": err,
+                   "L": info["L"], "r": info["r"]},
+        "parity_max_rel_err": err_sel,
+        "parity_max_rel_err_fp32": err,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_fp32_per_signal": plain,
         "compulsory_byte_efficiency": round(value * 1e9 * 8 / (HBM_PEAK_GBS * 1e9), 4),
         "plan_setup_s": round(setup_s, 3),
+        "hbm_copy": copy_bandwidth(dev),
         "device": {"name": torch.cuda.get_device_name(dev),
                    "cu": torch.cuda.get_device_properties(dev).multi_processor_count},
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}

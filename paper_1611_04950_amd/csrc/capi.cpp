@@ -7,6 +7,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -84,7 +85,19 @@ struct Carver {
   }
 };
 
-constexpr size_t kSliceBudget = (size_t)256 << 20;  // bytes of three-pass intermediates per slice
+// Bytes of three-pass intermediates per batch slice (tuning override:
+// SLEPIAN_SLICE_MIB).
+size_t slice_budget() {
+  static size_t v = [] {
+    size_t mib = 256;
+    if (const char *e = std::getenv("SLEPIAN_SLICE_MIB")) {
+      const long t = std::atol(e);
+      if (t >= 1 && t <= 65536) mib = (size_t)t;
+    }
+    return mib << 20;
+  }();
+  return v;
+}
 constexpr int kMaxLogL = 22;                          // N <= 2^21
 constexpr size_t kCoeffsCap = (size_t)16 << 30;       // bytes of S_K kept for slepian_coeffs
 
@@ -118,13 +131,15 @@ struct slepian_plan_s {
   int64_t win_lo = 0, win_hi = -1;
   std::vector<double> lam;  // eigenvalues over the window
   int64_t u_l0 = 0, u_r = 0;  // U's columns are Slepian vectors l = u_l0 .. u_l0 + u_r - 1
-  double *U64 = nullptr;
-  float *U32 = nullptr;
+  double *U64 = nullptr;   // leading dimension N
+  float *U32 = nullptr;    // leading dimension ldu (16-byte aligned columns)
+  int64_t ldu = 0;
   OpSet proj, pinv, tik, tikm;
   double lam_Km1 = 0, lam_K = 0, eps_ach = 0;
   void *ws = nullptr;
   size_t ws_bytes = 0;
-  float *SK = nullptr;
+  float *SK = nullptr;   // all K Slepian vectors (slepian_coeffs), leading dimension ldsk
+  int64_t ldsk = 0;
 
   ~slepian_plan_s() {
     for (auto *p : tw32) dfree(p);
@@ -166,7 +181,9 @@ typedef slepian_plan_s Plan;
 // Workspace layouts (shared by the size query and the calls)
 // ---------------------------------------------------------------------------
 
-bool fused_single(const Plan *P, const OpSet &op) { return P->g32.single() && op.r <= kMaxRankSingle; }
+bool fused_single(const Plan *P, const OpSet &op, int prec) {
+  return P->g32.single() && op.r <= kMaxRankSingle && prec == SLEPIAN_FP32;
+}
 
 struct ProjWs {
   cpx<float> *Z = nullptr;
@@ -174,15 +191,15 @@ struct ProjWs {
   float *part = nullptr, *dC = nullptr;
 };
 
-ProjWs carve_project(const Plan *P, const OpSet &op, int64_t b, Carver &cv) {
+ProjWs carve_project(const Plan *P, const OpSet &op, int64_t b, Carver &cv, int prec = SLEPIAN_FP32) {
   ProjWs w;
-  if (fused_single(P, op)) return w;
+  if (fused_single(P, op, prec)) return w;
   const int64_t pairs = (b + 1) / 2;
-  w.slice = (int64_t)conv_workspace_pairs(P->g32, pairs, sizeof(cpx<float>), kSliceBudget);
+  w.slice = (int64_t)conv_workspace_pairs(P->g32, pairs, sizeof(cpx<float>), slice_budget());
   if (!P->g32.single()) w.Z = cv.take<cpx<float>>((size_t)w.slice * (size_t)P->L);
   if (op.r > 0) {
     const int rpad = corr_rpad((int)op.r);
-    w.part = cv.take<float>((size_t)corr_chunks(P->N) * rpad * b);
+    w.part = cv.take<float>((size_t)corr_nchunks(P->N, b, (int)op.r) * rpad * b);
     w.dC = cv.take<float>((size_t)b * rpad);
   }
   return w;
@@ -196,7 +213,7 @@ struct B64Ws {
 B64Ws carve_b64(const Plan *P, int64_t b, Carver &cv) {
   B64Ws w;
   const int64_t pairs = (b + 1) / 2;
-  w.slice = (int64_t)conv_workspace_pairs(P->g64, pairs, sizeof(cpx<double>), kSliceBudget);
+  w.slice = (int64_t)conv_workspace_pairs(P->g64, pairs, sizeof(cpx<double>), slice_budget());
   if (!P->g64.single()) w.Z = cv.take<cpx<double>>((size_t)w.slice * (size_t)P->L);
   return w;
 }
@@ -230,11 +247,15 @@ TikWs carve_tik(const Plan *P, int64_t b, Carver &cv) {
 size_t op_workspace(const Plan *P, int op, int64_t b) {
   Carver cv(nullptr);
   switch (op) {
-    case SLEPIAN_OP_PROJECT:
-      carve_project(P, P->proj, b, cv);
-      break;
+    case SLEPIAN_OP_PROJECT: {
+      // the largest of the precision modes
+      Carver c2(nullptr);
+      carve_project(P, P->proj, b, cv, SLEPIAN_FP32);
+      carve_project(P, P->proj, b, c2, SLEPIAN_MIXED);
+      return std::max(cv.off, c2.off) + 256;
+    }
     case SLEPIAN_OP_COEFFS:
-      cv.take<float>((size_t)corr_chunks(P->N) * corr_rpad((int)P->K) * b);
+      cv.take<float>((size_t)corr_nchunks(P->N, b, (int)P->K) * corr_rpad((int)P->K) * b);
       break;
     case SLEPIAN_OP_LSQ: {
       Carver c1(nullptr), c2(nullptr);
@@ -270,26 +291,28 @@ void *get_ws(Plan *P, void *work, size_t work_bytes, size_t need) {
 // Operators
 // ---------------------------------------------------------------------------
 
-// y = beta B x + gamma x + U_op diag(d_op) U_op^T x (FP32).
+// y = beta B x + gamma x + U_op diag(d_op) U_op^T x.  The product is FP32; the
+// correction follows `prec` (enum slepian_precision).
 void run_fast_op(const Plan *P, const OpSet &op, float beta, float gamma, const float *x, int64_t ldx, float *y,
-                 int64_t ldy, int64_t b, const ProjWs &w, hipStream_t st) {
+                 int64_t ldy, int64_t b, const ProjWs &w, hipStream_t st, int prec = SLEPIAN_FP32) {
   const int64_t N = P->N;
-  const float *U = P->U32 + op.off * N;
-  if (fused_single(P, op)) {
+  const float *U = P->U32 + op.off * P->ldu;
+  if (fused_single(P, op, prec)) {
     Corr<float> c;
     c.U = U;
-    c.ldu = N;
+    c.ldu = P->ldu;
     c.r = (int)op.r;
     c.d = op.d32;
     HIPCHK(conv_apply<float>(x, ldx, y, ldy, N, b, P->g32, P->tb32, beta, gamma, c, nullptr, 0, st));
     return;
   }
+  const int mode = prec == SLEPIAN_MIXED ? 1 : (prec == SLEPIAN_BF16_RAW ? 2 : 0);
   if (op.r > 0) {
-    HIPCHK(corr_partial(x, ldx, N, b, U, N, (int)op.r, w.part, st));
-    HIPCHK(corr_reduce(w.part, N, b, (int)op.r, op.d32, w.dC, st));
+    HIPCHK(corr_partial_mfma(mode, x, ldx, N, b, U, P->ldu, (int)op.r, w.part, st));
+    HIPCHK(corr_reduce_mfma(w.part, N, b, (int)op.r, op.d32, w.dC, st));
   }
   HIPCHK(conv_apply<float>(x, ldx, y, ldy, N, b, P->g32, P->tb32, beta, gamma, Corr<float>(), w.Z, w.slice, st));
-  if (op.r > 0) HIPCHK(corr_apply(y, ldy, N, b, U, N, (int)op.r, w.dC, st));
+  if (op.r > 0) HIPCHK(corr_apply_mfma(y, ldy, N, b, U, P->ldu, (int)op.r, w.dC, st));
 }
 
 void run_b64(const Plan *P, const double *x, int64_t ldx, double *y, int64_t ldy, int64_t b, const B64Ws &w,
@@ -311,7 +334,13 @@ void upload_d(OpSet &o) {
 void build_fft_state(Plan *P, hipStream_t st) {
   const int logL = ilog2_ceil(2 * P->N);
   P->L = (int64_t)1 << logL;
-  P->g32 = make_geom(logL, Lds<float>::logE, true);
+  int row32 = Lds<float>::logE;
+  if (const char *e = std::getenv("SLEPIAN_ROW_LOG2")) {
+    // tuning override of the FP32 row length of the three-pass product
+    const int v = std::atoi(e);
+    if (v >= 9 && v <= Lds<float>::logE) row32 = v;
+  }
+  P->g32 = make_geom(logL, logL <= Lds<float>::logE ? Lds<float>::logE : row32, true);
   P->g64 = make_geom(logL, Lds<double>::logE, true);
   const int64_t L = P->L;
   P->tw32[0] = dalloc<cpx<float>>((size_t)1 << P->g32.logT);
@@ -518,11 +547,12 @@ void build_eigen_state(Plan *P, hipStream_t st) {
   P->eps_ach = ea;
   P->u_l0 = lo + u0;
   P->u_r = u1 - u0;
+  P->ldu = (N + 3) / 4 * 4;
   P->U64 = dalloc<double>((size_t)N * std::max<int64_t>(P->u_r, 1));
-  P->U32 = dalloc<float>((size_t)N * std::max<int64_t>(P->u_r, 1));
+  P->U32 = dalloc<float>((size_t)P->ldu * std::max<int64_t>(P->u_r, 1));
   if (P->u_r > 0) {
     HIPCHK(hipMemcpyAsync(P->U64, V + u0 * N, (size_t)N * P->u_r * sizeof(double), hipMemcpyDeviceToDevice, st));
-    HIPCHK(cast_f64_to_f32(P->U64, N, P->U32, N, N, P->u_r, st));
+    HIPCHK(cast_f64_to_f32(P->U64, N, P->U32, P->ldu, N, P->u_r, st));
   }
   HIPCHK(hipStreamSynchronize(st));
   dfree(V);
@@ -711,7 +741,6 @@ int slepian_project_ex(slepian_plan_t P, int precision, const float *x, int64_t 
                        int64_t batch, void *work, size_t work_bytes, void *stream) {
   if (bad_signal_args(P, x, ldx, y, ldy, batch)) return SLEPIAN_EINVAL;
   if (precision < SLEPIAN_FP32 || precision > SLEPIAN_BF16_RAW) return SLEPIAN_EINVAL;
-  if (precision != SLEPIAN_FP32) return SLEPIAN_ENOTSUP;
   if (batch == 0) return SLEPIAN_OK;
   if (x != y) {
     // in place is allowed; any other overlap is not
@@ -725,8 +754,8 @@ int slepian_project_ex(slepian_plan_t P, int precision, const float *x, int64_t 
     const size_t need = op_workspace(P, SLEPIAN_OP_PROJECT, batch);
     void *ws = get_ws(P, work, work_bytes, need);
     Carver cv(ws);
-    ProjWs w = carve_project(P, P->proj, batch, cv);
-    run_fast_op(P, P->proj, 1.0f, 0.0f, x, ldx, y, ldy, batch, w, st);
+    ProjWs w = carve_project(P, P->proj, batch, cv, precision);
+    run_fast_op(P, P->proj, 1.0f, 0.0f, x, ldx, y, ldy, batch, w, st, precision);
     return SLEPIAN_OK;
   });
 }
@@ -850,7 +879,8 @@ int slepian_coeffs(slepian_plan_t P, const float *x, int64_t ldx, float *c, int6
       float *SK = nullptr;
       try {
         build_tridiag(P, T, s2);
-        SK = dalloc<float>((size_t)N * K);
+        const int64_t ldsk = (N + 3) / 4 * 4;
+        SK = dalloc<float>((size_t)ldsk * K);
         DBuf<double> theta(K);
         HIPCHK(tridiag_bisect(T.a, T.e2, N, T.gl, T.gu, T.pivmin, N - K, K, theta.p, s2));
         const size_t per = inviter_scratch_bytes(N, 1) + N * sizeof(double);
@@ -861,7 +891,7 @@ int slepian_coeffs(slepian_plan_t P, const float *x, int64_t ldx, float *c, int6
           const int64_t cc = std::min(cv, K - j0);
           // theta[j0 + jj] <-> l = K-1-(j0+jj); normalised column cc-1-jj of V
           HIPCHK(tridiag_inviter(T.a, T.off, N, theta.p + j0, cc, V.p, scratch.p, 3, s2));
-          HIPCHK(cast_f64_to_f32(V.p, N, SK + (K - j0 - cc) * N, N, N, cc, s2));
+          HIPCHK(cast_f64_to_f32(V.p, N, SK + (K - j0 - cc) * ldsk, ldsk, N, cc, s2));
         }
         HIPCHK(hipStreamSynchronize(s2));
         (void)hipStreamDestroy(s2);
@@ -872,13 +902,14 @@ int slepian_coeffs(slepian_plan_t P, const float *x, int64_t ldx, float *c, int6
         throw;
       }
       P->SK = SK;
+      P->ldsk = (N + 3) / 4 * 4;
     }
     const size_t need = op_workspace(P, SLEPIAN_OP_COEFFS, batch);
     void *ws = get_ws(P, work, work_bytes, need);
     Carver cv(ws);
-    float *part = cv.take<float>((size_t)corr_chunks(N) * corr_rpad((int)K) * batch);
-    HIPCHK(corr_partial(x, ldx, N, batch, P->SK, N, (int)K, part, st));
-    HIPCHK(corr_sum(part, N, batch, (int)K, c, ldc, st));
+    float *part = cv.take<float>((size_t)corr_nchunks(N, batch, (int)K) * corr_rpad((int)K) * batch);
+    HIPCHK(corr_partial_mfma(0, x, ldx, N, batch, P->SK, P->ldsk, (int)K, part, st));
+    HIPCHK(corr_sum_mfma(part, N, batch, (int)K, c, ldc, st));
     return SLEPIAN_OK;
   });
 }
@@ -998,11 +1029,12 @@ int slepian_plan_load(const char *path, int device, slepian_plan_t *out) {
         (void)hipStreamDestroy(st);
         throw;
       }
+      P->ldu = (P->N + 3) / 4 * 4;
       P->U64 = dalloc<double>((size_t)P->N * std::max<int64_t>(P->u_r, 1));
-      P->U32 = dalloc<float>((size_t)P->N * std::max<int64_t>(P->u_r, 1));
+      P->U32 = dalloc<float>((size_t)P->ldu * std::max<int64_t>(P->u_r, 1));
       if (P->u_r) {
         HIPCHK(hipMemcpy(P->U64, U.data(), U.size() * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(cast_f64_to_f32(P->U64, P->N, P->U32, P->N, P->N, P->u_r, nullptr));
+        HIPCHK(cast_f64_to_f32(P->U64, P->N, P->U32, P->ldu, P->N, P->u_r, nullptr));
         HIPCHK(hipDeviceSynchronize());
       }
       for (OpSet *op : {&P->proj, &P->pinv, &P->tik, &P->tikm}) upload_d(*op);

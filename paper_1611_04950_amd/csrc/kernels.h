@@ -78,6 +78,18 @@ hipError_t cast_f64_to_f32(const double *src, int64_t ld_src, float *dst, int64_
 hipError_t cast_f32_to_f64(const float *src, int64_t ld_src, double *dst, int64_t ld_dst, int64_t rows,
                            int64_t cols, hipStream_t st);
 
+// ---- Low-rank correction on the matrix cores (corr_mfma.hip) ----
+// mode: 0 FP32, 1 BF16 hi/lo (three products), 2 BF16 only.
+int corr_nchunks(int64_t N, int64_t b, int r);
+hipError_t corr_partial_mfma(int mode, const float *x, int64_t ldx, int64_t N, int64_t b, const float *U,
+                             int64_t ldu, int r, float *part, hipStream_t st);
+hipError_t corr_reduce_mfma(const float *part, int64_t N, int64_t b, int r, const float *d, float *dC,
+                            hipStream_t st);
+// c[s * ldc + j] = sum over chunks (no weights)
+hipError_t corr_sum_mfma(const float *part, int64_t N, int64_t b, int r, float *c, int64_t ldc, hipStream_t st);
+hipError_t corr_apply_mfma(float *y, int64_t ldy, int64_t N, int64_t b, const float *U, int64_t ldu, int r,
+                           const float *dC, hipStream_t st);
+
 // ---- Least-squares refinement helpers (lsq.hip) ----
 // rho = By - u - alpha x (all FP64, N x b with leading dimension N except x: ldx)
 hipError_t lsq_residual(const double *By, const double *u, const double *x, int64_t ldx, double alpha, double *rho,

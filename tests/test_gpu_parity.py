@@ -244,3 +244,23 @@ def test_group_matches_single_plans(plans):
             ref = S.slepian_project(p, x)
             torch.cuda.synchronize()
             assert torch.equal(y, ref), rep
+
+
+@pytest.mark.parametrize("N,W,eps,b", [(1024, 1 / 16, 1e-6, 8), (65536, 1 / 8, 1e-6, 6), (3000, 0.2, 1e-6, 70)])
+def test_project_precision_modes(plans, N, W, eps, b):
+    """MIXED (BF16 hi/lo matrix-core correction) meets the FP32 gate of 1e-5;
+    BF16 operands alone (no lo terms) meet the 3e-3 gate for an unrefined
+    BF16 correction."""
+    P = plans(N, W, eps)
+    x = synth.gaussian(N, b, 900 + N, device="cuda")
+    xh = x.double().cpu().numpy()
+    yf = o.project_fast(N, W, eps, xh.T, tp=otp(N, W, eps, 1 - eps)).T
+    errs = {}
+    for prec in (S.SLEPIAN_FP32, S.SLEPIAN_MIXED, S.SLEPIAN_BF16_RAW):
+        y = S.slepian_project(P, x, precision=prec)
+        torch.cuda.synchronize()
+        errs[prec] = rel_err(y.cpu().numpy(), yf).max()
+    _log(f"precision errors N={N}: {errs}")
+    assert errs[S.SLEPIAN_FP32] <= 1e-5
+    assert errs[S.SLEPIAN_MIXED] <= 1e-5
+    assert errs[S.SLEPIAN_BF16_RAW] <= 3e-3
