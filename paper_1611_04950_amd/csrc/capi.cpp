@@ -311,8 +311,21 @@ void run_fast_op(const Plan *P, const OpSet &op, float beta, float gamma, const 
     HIPCHK(corr_partial_mfma(mode, x, ldx, N, b, U, P->ldu, (int)op.r, w.part, st));
     HIPCHK(corr_reduce_mfma(w.part, N, b, (int)op.r, op.d32, w.dC, st));
   }
-  HIPCHK(conv_apply<float>(x, ldx, y, ldy, N, b, P->g32, P->tb32, beta, gamma, Corr<float>(), w.Z, w.slice, st));
-  if (op.r > 0) HIPCHK(corr_apply_mfma(y, ldy, N, b, U, P->ldu, (int)op.r, w.dC, st));
+  // the update U dC rides on the inverse column pass when its U tile fits in LDS
+  const int umode = mode == 0 ? 0 : 1;
+  const bool fused = op.r > 0 && P->g32.v2 && !P->g32.single() &&
+                     colinv_corr_lds(P->g32.log1, (int)op.r, umode) <= (size_t)64 * 1024;
+  Corr<float> c;
+  if (fused) {
+    c.U = U;
+    c.ldu = P->ldu;
+    c.r = (int)op.r;
+    c.d = op.d32;
+    c.dC = w.dC;
+    c.mode = umode;
+  }
+  HIPCHK(conv_apply<float>(x, ldx, y, ldy, N, b, P->g32, P->tb32, beta, gamma, c, w.Z, w.slice, st));
+  if (op.r > 0 && !fused) HIPCHK(corr_apply_mfma(y, ldy, N, b, U, P->ldu, (int)op.r, w.dC, st));
 }
 
 void run_b64(const Plan *P, const double *x, int64_t ldx, double *y, int64_t ldy, int64_t b, const B64Ws &w,

@@ -77,6 +77,11 @@ struct Corr {
   int64_t ldu = 0;
   int r = 0;
   const R *d = nullptr;      // r weights
+  // When set (three-pass path), the inverse column pass also adds U dC, with
+  // dC = d (.) U^T x already formed and stored [j][s] (leading dimension b);
+  // mode 0: FP32 matrix instructions, 1: BF16 hi/lo.
+  const R *dC = nullptr;
+  int mode = 0;
 };
 
 }  // namespace slp

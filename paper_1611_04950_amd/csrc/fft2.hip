@@ -310,6 +310,121 @@ __global__ __launch_bounds__(256) void k_colinv2(const cpx<R> *__restrict__ Z, i
   }
 }
 
+// Pass C fused with the correction update y += U dC (Corollary 2's U1 U2^T x
+// term).  A workgroup of CW wavefronts owns 16 columns c0..c0+15 and 8*CW
+// signal pairs; it stages U's rows n = c0 + col + L2 n1 (n1 < L1/2) for all j
+// in LDS once.  Lane (col, blk) = (lane % 16, lane / 16) of wavefront w runs the
+// inverse column DFTs of pairs 2 blk and 2 blk + 1 of the wavefront's eight
+// (one set of twiddles for both), and places the surviving rows straight into
+// 16 x 16 matrix-core accumulators D[signal][column] (row 4 blk + v, column
+// lane % 16), so the update U dC runs on the matrix cores over j with no
+// reshuffle: A = dC^T (signals x j) from memory, B = U^T (j x columns) from LDS.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int L1, int MODE, int CW>
+__global__ __launch_bounds__(64 * CW) void k_colinv_corr(const cpx<float> *__restrict__ Z, int N, int b, int pair0,
+                                                         int np, int logL, int log2, int s,
+                                                         const cpx<float> *__restrict__ tlo,
+                                                         const cpx<float> *__restrict__ thi, float *__restrict__ y,
+                                                         int64_t ldy, const float *__restrict__ U, int64_t ldu,
+                                                         int r, int rp, const float *__restrict__ dC) {
+  constexpr int ROWS = L1 > 1 ? L1 / 2 : 1;
+  extern __shared__ float Ut[];  // [n1][j][col], ROWS x rp x 16
+  const int c0 = blockIdx.x * 16;
+  for (int e = threadIdx.x; e < ROWS * rp * 16; e += 64 * CW) {
+    const int col = e & 15, j = (e >> 4) % rp, n1 = (e >> 4) / rp;
+    const int n = c0 + col + (n1 << log2);
+    Ut[e] = (j < r && n < N) ? U[(int64_t)j * ldu + n] : 0.f;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, blk = lane >> 4;
+  const int pw = blockIdx.y * 8 * CW + wave * 8;  // first pair of the wavefront, within the slice
+  if (pw >= np) return;                            // uniform per wavefront; no barrier follows
+  const int n2 = c0 + col;
+  const int mask = (1 << s) - 1;
+  cpx<float> tw[L1];
+#pragma unroll
+  for (int k1 = 1; k1 < L1; ++k1) {
+    const int m = n2 * k1;
+    tw[k1] = cmul(thi[m >> s], tlo[m & mask]);
+  }
+  f32x4 acc[ROWS];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int pl = pw + 2 * blk + h;
+    cpx<float> a[L1];
+    if (pl < np) {
+      const cpx<float> *Zp = Z + ((int64_t)pl << logL) + n2;
+      a[0] = Zp[0];
+#pragma unroll
+      for (int k1 = 1; k1 < L1; ++k1) a[k1] = cmulc(Zp[(int64_t)k1 << log2], tw[k1]);
+    } else {
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) a[k1] = cpx<float>{0.f, 0.f};
+    }
+    reg::dft<L1, +1>(a);
+#pragma unroll
+    for (int n1 = 0; n1 < ROWS; ++n1) {
+      acc[n1][2 * h] = a[n1].x;
+      acc[n1][2 * h + 1] = a[n1].y;
+    }
+  }
+  // signals of this wavefront: 2 (pair0 + pw) + 0..15; A row i = lane % 16
+  const int sa = 2 * (pair0 + pw) + (lane & 15);
+  const bool sav = sa < b && (pw + ((lane & 15) >> 1)) < np;
+  const int sac = sav ? sa : 0;
+  if constexpr (MODE == 0) {
+    for (int jb = 0; jb < rp; jb += 4) {
+      const int j = jb + blk;
+      const float av = (sav && j < r) ? dC[(int64_t)j * b + sac] : 0.f;
+#pragma unroll
+      for (int n1 = 0; n1 < ROWS; ++n1)
+        acc[n1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, Ut[(n1 * rp + j) * 16 + col], acc[n1], 0, 0, 0);
+    }
+  } else {
+    for (int jb = 0; jb < rp; jb += 32) {
+      bf16x8 ahi, alo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int j = jb + 8 * blk + e;
+        const float av = (sav && j < r) ? dC[(int64_t)j * b + sac] : 0.f;
+        const __bf16 hh = (__bf16)av;
+        ahi[e] = hh;
+        alo[e] = (__bf16)(av - (float)hh);
+      }
+#pragma unroll
+      for (int n1 = 0; n1 < ROWS; ++n1) {
+        bf16x8 bhi, blo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float uv = Ut[(n1 * rp + jb + 8 * blk + e) * 16 + col];
+          const __bf16 hh = (__bf16)uv;
+          bhi[e] = hh;
+          blo[e] = (__bf16)(uv - (float)hh);
+        }
+        acc[n1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[n1], 0, 0, 0);
+        acc[n1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[n1], 0, 0, 0);
+        acc[n1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[n1], 0, 0, 0);
+      }
+    }
+  }
+  // D[4 blk + v][col] -> signal 2 (pair0 + pw) + 4 blk + v at n = n2 + L2 n1
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int pl = pw + 2 * blk + (v >> 1);
+    const int sg = 2 * (pair0 + pw) + 4 * blk + v;
+    if (pl >= np || sg >= b) continue;
+    float *ys = y + (int64_t)sg * ldy;
+#pragma unroll
+    for (int n1 = 0; n1 < ROWS; ++n1) {
+      const int n = n2 + (n1 << log2);
+      if (n < N) ys[n] = acc[n1][v];
+    }
+  }
+}
+
 // Row twiddle tables: rt1[k1 T + t] = W_L2^{t k1}, rt2[k2 R3 + m'] = W_T^{m' k2}.
 template <typename R>
 __global__ void k_row_twiddles(cpx<R> *__restrict__ rt1, cpx<R> *__restrict__ rt2, int R1, int R2, int R3) {
@@ -389,6 +504,47 @@ static bool dispatch_cols(bool fwd, dim3 grid, hipStream_t st, const R *x, int64
   }
 }
 
+constexpr int kColCorrWaves = 4;
+
+int colinv_corr_rp(int r, int mode) { return mode == 0 ? (r + 3) / 4 * 4 : (r + 31) / 32 * 32; }
+
+size_t colinv_corr_lds(int log1, int r, int mode) {
+  const int rows = log1 > 0 ? (1 << log1) / 2 : 1;
+  return (size_t)rows * colinv_corr_rp(r, mode) * 16 * sizeof(float);
+}
+
+template <int L1, int MODE>
+static void launch_cic(dim3 grid, size_t lds, hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np,
+                       const FftGeom &g, const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c,
+                       int rp) {
+  SLP_LAUNCH(MODE ? "col_inv_corr_bf16x3" : "col_inv_corr", (k_colinv_corr<L1, MODE, kColCorrWaves>), grid,
+             dim3(64 * kColCorrWaves), lds, st, Z, N, b, p0, np, g.logL, g.log2, g.s, tb.tw_lo, tb.tw_hi, y, ldy, c.U,
+             c.ldu, c.r, rp, c.dC);
+}
+
+template <int MODE>
+static bool launch_cic_mode(hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np, const FftGeom &g,
+                            const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c) {
+  const int rp = colinv_corr_rp(c.r, MODE);
+  const size_t lds = colinv_corr_lds(g.log1, c.r, MODE);
+  const dim3 grid((1u << g.log2) / 16, (unsigned)((np + 8 * kColCorrWaves - 1) / (8 * kColCorrWaves)));
+  switch (g.log1) {
+    case 1: launch_cic<2, MODE>(grid, lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 2: launch_cic<4, MODE>(grid, lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 3: launch_cic<8, MODE>(grid, lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 4: launch_cic<16, MODE>(grid, lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 5: launch_cic<32, MODE>(grid, lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 6: launch_cic<64, MODE>(grid, lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    default: return false;
+  }
+}
+
+static bool launch_colinv_corr(hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np, const FftGeom &g,
+                               const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c) {
+  return c.mode == 0 ? launch_cic_mode<0>(st, Z, N, b, p0, np, g, tb, y, ldy, c)
+                     : launch_cic_mode<1>(st, Z, N, b, p0, np, g, tb, y, ldy, c);
+}
+
 #define SLP_ROW_SHAPES(X) \
   X(8, 8, 8)              \
   X(16, 8, 8)             \
@@ -440,6 +596,13 @@ hipError_t conv_apply_v2(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, 
     SLP_ROW_SHAPES(SLP_ROW)
 #undef SLP_ROW
     if (!ok) return hipErrorInvalidValue;
+    if constexpr (sizeof(R) == 4) {
+      if (corr.dC) {
+        if (!launch_colinv_corr(st, Z, (int)N, (int)b, (int)p0, (int)np, g, tb, y, ldy, corr))
+          return hipErrorInvalidValue;
+        continue;
+      }
+    }
     if (!dispatch_cols<R>(false, gcol, st, x, ldx, y, ldy, (int)N, (int)b, (int)p0, g, tb, Z))
       return hipErrorInvalidValue;
   }
