@@ -122,8 +122,8 @@ struct slepian_plan_s {
   double W = 0, eps = 0, alpha = 0;
   int precision = SLEPIAN_FP32;
   FftGeom g32, g64;
-  cpx<float> *tw32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  cpx<double> *tw64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  cpx<float> *tw32[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  cpx<double> *tw64[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   float *chat32 = nullptr;
   double *chat64 = nullptr;
   FftTables<float> tb32;
@@ -313,8 +313,7 @@ void run_fast_op(const Plan *P, const OpSet &op, float beta, float gamma, const 
   }
   // the update U dC rides on the inverse column pass when its U tile fits in LDS
   const int umode = mode == 0 ? 0 : 1;
-  const bool fused = op.r > 0 && P->g32.v2 && !P->g32.single() &&
-                     colinv_corr_lds(P->g32.log1, (int)op.r, umode) <= (size_t)64 * 1024;
+  const bool fused = op.r > 0 && P->g32.v2 && !P->g32.single() && colinv_corr_ok(P->g32.log1, (int)op.r, umode);
   Corr<float> c;
   if (fused) {
     c.U = U;
@@ -376,6 +375,11 @@ void build_fft_state(Plan *P, hipStream_t st) {
     HIPCHK(build_row_tables<float>(P->g32, P->tw32[3], P->tw32[4], st));
     P->tb32.row1 = P->tw32[3];
     P->tb32.row2 = P->tw32[4];
+    if (!P->g32.single()) {
+      P->tw32[5] = dalloc<cpx<float>>((size_t)L);
+      HIPCHK(build_col_table<float>(P->g32, P->tw32[5], st));
+      P->tb32.col = P->tw32[5];
+    }
   }
   if (P->g64.v2) {
     P->tw64[3] = dalloc<cpx<double>>((size_t)P->g64.R1 * P->g64.R2 * P->g64.R3);
@@ -383,6 +387,11 @@ void build_fft_state(Plan *P, hipStream_t st) {
     HIPCHK(build_row_tables<double>(P->g64, P->tw64[3], P->tw64[4], st));
     P->tb64.row1 = P->tw64[3];
     P->tb64.row2 = P->tw64[4];
+    if (!P->g64.single()) {
+      P->tw64[5] = dalloc<cpx<double>>((size_t)L);
+      HIPCHK(build_col_table<double>(P->g64, P->tw64[5], st));
+      P->tb64.col = P->tw64[5];
+    }
   }
   // spectrum of the circulant embedding of B's first column (Section 4.1),
   // by the generic FP64 transform, then stored in each path's layout

@@ -68,6 +68,7 @@ struct FftTables {
   const R *chat = nullptr;         // spectrum of B's circulant embedding / L, in pass layout
   const cpx<R> *row1 = nullptr;    // register-stage rows: W_L2^{t k1} stored [k1][t]
   const cpx<R> *row2 = nullptr;    // register-stage rows: W_T^{m k2} stored [k2][m]
+  const cpx<R> *col = nullptr;     // register-stage columns: W_L^{k1 n2} stored [k1][n2]
 };
 
 // Correction y += U diag(d) U^T x.  U is N x r column-major (ldu).

@@ -19,6 +19,9 @@
 // n = n2 + L2 n1, frequency index k = k1 + L1 k2) give each lane one column
 // n2 and do its length-L1 DFT entirely in registers, with the inter-pass
 // twiddle W_L^{n2 k1} applied there, so the row kernel needs none.
+#include <cstdio>
+#include <cstdlib>
+
 #include "common.h"
 #include "fft_reg.h"
 #include "kernels.h"
@@ -39,10 +42,12 @@ struct RowShape {
   static_assert(R1 % R2 == 0 && R1 % R3 == 0, "row radices");
 };
 
-// Forward transform, spectrum multiply (spec(z, offset) on each stage-3 job's
-// R3 values), inverse transform.  v: lane t's R1 samples x[t + T n1] in,
-// L2 * result out.  tw1: the lane's W_L2^{t k1} (k1 < R1), rt2: W_T^{m' k2}
-// stored [k2][m'].
+// Forward transform, spectrum multiply (spec(z, q) on the R3 values of the
+// lane's stage-3 job q, whose spectrum starts at offset (t + T q) R3 of the
+// row), inverse transform.  v: lane t's R1 samples x[t + T n1] in, L2 *
+// result out.  tw1: the lane's W_L2^{t k1} (k1 < R1); rt2: W_T^{m' k2} in LDS,
+// rows k2 of R3 + 1 elements (the padding keeps the stage-3 reads, whose lanes
+// differ in k2, free of bank conflicts).
 template <typename R, int R1, int R2, int R3, typename Spec>
 __device__ __forceinline__ void row_conv_core(cpx<R> (&v)[R1], cpx<R> *S, const cpx<R> (&tw1)[R1],
                                               const cpx<R> *__restrict__ rt2, Spec spec) {
@@ -68,7 +73,7 @@ __device__ __forceinline__ void row_conv_core(cpx<R> (&v)[R1], cpx<R> *S, const 
     const int g = t + T * q, mp = g % R3, k1 = g / R3;
     reg::dft<R2, -1>(w[q]);
 #pragma unroll
-    for (int k2 = 1; k2 < R2; ++k2) w[q][k2] = cmul(w[q][k2], rt2[k2 * R3 + mp]);
+    for (int k2 = 1; k2 < R2; ++k2) w[q][k2] = cmul(w[q][k2], rt2[k2 * (R3 + 1) + mp]);
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2) S[k1 * RS::S2K + k2 * RS::S2 + mp] = w[q][k2];
   }
@@ -80,10 +85,10 @@ __device__ __forceinline__ void row_conv_core(cpx<R> (&v)[R1], cpx<R> *S, const 
 #pragma unroll
     for (int m = 0; m < R3; ++m) z[q][m] = S[k1 * RS::S2K + k2 * RS::S2 + m];
     reg::dft<R3, -1>(z[q]);
-    spec(z[q], (k1 * R2 + k2) * R3);
+    spec(z[q], q);
     reg::dft<R3, +1>(z[q]);
 #pragma unroll
-    for (int m = 1; m < R3; ++m) z[q][m] = cmulc(z[q][m], rt2[k2 * R3 + m]);
+    for (int m = 1; m < R3; ++m) z[q][m] = cmulc(z[q][m], rt2[k2 * (R3 + 1) + m]);
   }
   __syncthreads();
 #pragma unroll
@@ -123,6 +128,27 @@ __device__ __forceinline__ void load_tw1(cpx<R> (&tw1)[R1], const cpx<R> *__rest
   for (int k1 = 1; k1 < R1; ++k1) tw1[k1] = rt1[k1 * T + threadIdx.x];
 }
 
+// W_T^{m' k2} into LDS rows of R3 + 1 (read after row_conv_core's first
+// barrier, so no barrier of its own is needed).
+template <typename R, int R1, int R2, int R3>
+__device__ __forceinline__ void stage_rt2(cpx<R> *rt2s, const cpx<R> *__restrict__ rt2) {
+  constexpr int T = R2 * R3;
+  const int t = threadIdx.x;
+  rt2s[(t / R3) * (R3 + 1) + t % R3] = rt2[t];
+}
+
+// The lane's kernel-spectrum values for its stage-3 jobs, fetched up front so
+// their latency overlaps the forward stages: job q covers the R3 contiguous
+// values at (t + T q) R3.
+template <typename R, int R1, int R2, int R3>
+__device__ __forceinline__ void load_spec(R (&chv)[R1 / R3][R3], const R *__restrict__ ch) {
+  constexpr int T = R2 * R3;
+#pragma unroll
+  for (int q = 0; q < R1 / R3; ++q)
+#pragma unroll
+    for (int k = 0; k < R3; ++k) chv[q][k] = ch[(threadIdx.x + T * q) * R3 + k];
+}
+
 // Middle pass of the three-pass product: row k1c of pair pl, in place.
 template <typename R, int R1, int R2, int R3>
 __global__ __launch_bounds__(R2 *R3) void k_row2(cpx<R> *__restrict__ Z, int logL, int log2,
@@ -130,18 +156,21 @@ __global__ __launch_bounds__(R2 *R3) void k_row2(cpx<R> *__restrict__ Z, int log
                                                  const R *__restrict__ chat, R beta, R gl) {
   using RS = RowShape<R1, R2, R3>;
   __shared__ cpx<R> S[RS::LDS];
+  __shared__ cpx<R> rt2s[R2 * (R3 + 1)];
   const int k1c = blockIdx.x, pl = blockIdx.y;
   cpx<R> *row = Z + ((int64_t)pl << logL) + ((int64_t)k1c << log2);
   const int t = threadIdx.x;
-  cpx<R> tw1[R1];
-  load_tw1<R, R1, R2, R3>(tw1, rt1);
   cpx<R> v[R1];
 #pragma unroll
   for (int n1 = 0; n1 < R1; ++n1) v[n1] = row[t + RS::T * n1];
-  const R *ch = chat + ((int64_t)k1c << log2);
-  row_conv_core<R, R1, R2, R3>(v, S, tw1, rt2, [&](cpx<R> *z, int off) {
+  cpx<R> tw1[R1];
+  load_tw1<R, R1, R2, R3>(tw1, rt1);
+  R chv[RS::J3][R3];
+  load_spec<R, R1, R2, R3>(chv, chat + ((int64_t)k1c << log2));
+  stage_rt2<R, R1, R2, R3>(rt2s, rt2);
+  row_conv_core<R, R1, R2, R3>(v, S, tw1, rt2s, [&](cpx<R> *z, int q) {
 #pragma unroll
-    for (int k = 0; k < R3; ++k) z[k] = cscale(z[k], beta * ch[off + k] + gl);
+    for (int k = 0; k < R3; ++k) z[k] = cscale(z[k], beta * chv[q][k] + gl);
   });
 #pragma unroll
   for (int n1 = 0; n1 < R1; ++n1) row[t + RS::T * n1] = v[n1];
@@ -160,6 +189,7 @@ __global__ __launch_bounds__(R2 *R3) void k_single2(const R *__restrict__ x, int
   constexpr int T = RS::T;
   constexpr int NW = T / 64;
   __shared__ cpx<R> S[RS::LDS];
+  __shared__ cpx<R> rt2s[R2 * (R3 + 1)];
   __shared__ R red[CORR ? NW * kMaxRankSingle * 2 : 2];
   __shared__ R dC[CORR ? 2 * kMaxRankSingle : 2];
   const int t = threadIdx.x;
@@ -170,6 +200,7 @@ __global__ __launch_bounds__(R2 *R3) void k_single2(const R *__restrict__ x, int
   const R *x1 = x + (int64_t)(has1 ? s1 : s0) * ldx;
   cpx<R> tw1[R1];
   load_tw1<R, R1, R2, R3>(tw1, rt1);
+  stage_rt2<R, R1, R2, R3>(rt2s, rt2);
   cpx<R> v[R1];
 #pragma unroll
   for (int n1 = 0; n1 < R1; ++n1) {
@@ -218,9 +249,11 @@ __global__ __launch_bounds__(R2 *R3) void k_single2(const R *__restrict__ x, int
       dC[2 * j + 1] = dj * c1;
     }
   }
-  row_conv_core<R, R1, R2, R3>(v, S, tw1, rt2, [&](cpx<R> *z, int off) {
+  R chv[RS::J3][R3];
+  load_spec<R, R1, R2, R3>(chv, chat);
+  row_conv_core<R, R1, R2, R3>(v, S, tw1, rt2s, [&](cpx<R> *z, int q) {
 #pragma unroll
-    for (int k = 0; k < R3; ++k) z[k] = cscale(z[k], beta * chat[off + k] + gl);
+    for (int k = 0; k < R3; ++k) z[k] = cscale(z[k], beta * chv[q][k] + gl);
   });
   R *y0 = y + (int64_t)s0 * ldy;
   R *y1 = y + (int64_t)(has1 ? s1 : s0) * ldy;
@@ -247,8 +280,8 @@ __global__ __launch_bounds__(R2 *R3) void k_single2(const R *__restrict__ x, int
 // Z[k1][n2].
 template <typename R, int L1>
 __global__ __launch_bounds__(256) void k_colfwd2(const R *__restrict__ x, int64_t ldx, int N, int b, int pair0,
-                                                 int logL, int log2, int s, const cpx<R> *__restrict__ tlo,
-                                                 const cpx<R> *__restrict__ thi, cpx<R> *__restrict__ Z) {
+                                                 int logL, int log2, const cpx<R> *__restrict__ tcol,
+                                                 cpx<R> *__restrict__ Z) {
   const int n2 = blockIdx.x * 256 + threadIdx.x;
   const int pl = blockIdx.y, p = pair0 + pl;
   const int s0 = 2 * p, s1 = 2 * p + 1;
@@ -268,13 +301,9 @@ __global__ __launch_bounds__(256) void k_colfwd2(const R *__restrict__ x, int64_
   }
   reg::dft<L1, -1>(a);
   cpx<R> *Zp = Z + ((int64_t)pl << logL) + n2;
-  const int mask = (1 << s) - 1;
   Zp[0] = a[0];
 #pragma unroll
-  for (int k1 = 1; k1 < L1; ++k1) {
-    const int m = n2 * k1;
-    Zp[(int64_t)k1 << log2] = cmul(a[k1], cmul(thi[m >> s], tlo[m & mask]));
-  }
+  for (int k1 = 1; k1 < L1; ++k1) Zp[(int64_t)k1 << log2] = cmul(a[k1], tcol[(k1 << log2) + n2]);
 }
 
 // Pass C: lane = column n2 of pair pl; Z[k1][n2] times W_L^{-n2 k1}, inverse
@@ -282,21 +311,17 @@ __global__ __launch_bounds__(256) void k_colfwd2(const R *__restrict__ x, int64_
 // (only n1 < L1/2 can hold such n because L >= 2N).
 template <typename R, int L1>
 __global__ __launch_bounds__(256) void k_colinv2(const cpx<R> *__restrict__ Z, int N, int b, int pair0, int logL,
-                                                 int log2, int s, const cpx<R> *__restrict__ tlo,
-                                                 const cpx<R> *__restrict__ thi, R *__restrict__ y, int64_t ldy) {
+                                                 int log2, const cpx<R> *__restrict__ tcol, R *__restrict__ y,
+                                                 int64_t ldy) {
   const int n2 = blockIdx.x * 256 + threadIdx.x;
   const int pl = blockIdx.y, p = pair0 + pl;
   const int s0 = 2 * p, s1 = 2 * p + 1;
   const bool has1 = s1 < b;
   const cpx<R> *Zp = Z + ((int64_t)pl << logL) + n2;
-  const int mask = (1 << s) - 1;
   cpx<R> a[L1];
   a[0] = Zp[0];
 #pragma unroll
-  for (int k1 = 1; k1 < L1; ++k1) {
-    const int m = n2 * k1;
-    a[k1] = cmulc(Zp[(int64_t)k1 << log2], cmul(thi[m >> s], tlo[m & mask]));
-  }
+  for (int k1 = 1; k1 < L1; ++k1) a[k1] = cmulc(Zp[(int64_t)k1 << log2], tcol[(k1 << log2) + n2]);
   reg::dft<L1, +1>(a);
   R *y0 = y + (int64_t)s0 * ldy;
   R *y1 = y + (int64_t)(has1 ? s1 : s0) * ldy;
@@ -311,116 +336,171 @@ __global__ __launch_bounds__(256) void k_colinv2(const cpx<R> *__restrict__ Z, i
 }
 
 // Pass C fused with the correction update y += U dC (Corollary 2's U1 U2^T x
-// term).  A workgroup of CW wavefronts owns 16 columns c0..c0+15 and 8*CW
-// signal pairs; it stages U's rows n = c0 + col + L2 n1 (n1 < L1/2) for all j
-// in LDS once.  Lane (col, blk) = (lane % 16, lane / 16) of wavefront w runs the
-// inverse column DFTs of pairs 2 blk and 2 blk + 1 of the wavefront's eight
-// (one set of twiddles for both), and places the surviving rows straight into
-// 16 x 16 matrix-core accumulators D[signal][column] (row 4 blk + v, column
-// lane % 16), so the update U dC runs on the matrix cores over j with no
-// reshuffle: A = dC^T (signals x j) from memory, B = U^T (j x columns) from LDS.
+// term).  A workgroup of CW wavefronts owns 16 columns c0..c0+15 and
+// 4 PPL CW signal pairs; it stages U's rows n = c0 + col + L2 n1 (n1 < L1/2)
+// for all j in LDS once.  Lane (col, blk) = (lane % 16, lane / 16) runs the
+// inverse column DFTs of PPL pairs (one set of twiddles for all) and places
+// the surviving rows straight into 16 x 16 matrix-core accumulators
+// D[signal slot][column] (row 4 blk + v, column lane % 16), so the update
+// U dC runs on the matrix cores over j with no reshuffle: A = dC^T (signal
+// slots x j) from memory, B = U^T (j x columns) from LDS.  With PPL = 1 the
+// slots 4 blk + 2, 4 blk + 3 stay zero: half the matrix rows are idle, which
+// costs little (the update is a small share of the pass) and halves the
+// registers that hold the DFT inputs, so more wavefronts keep loads in flight.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-template <int L1, int MODE, int CW>
+template <int L1, int MODE, int CW, int PPL>
 __global__ __launch_bounds__(64 * CW) void k_colinv_corr(const cpx<float> *__restrict__ Z, int N, int b, int pair0,
-                                                         int np, int logL, int log2, int s,
-                                                         const cpx<float> *__restrict__ tlo,
-                                                         const cpx<float> *__restrict__ thi, float *__restrict__ y,
+                                                         int np, int logL, int log2,
+                                                         const cpx<float> *__restrict__ tcol, float *__restrict__ y,
                                                          int64_t ldy, const float *__restrict__ U, int64_t ldu,
                                                          int r, int rp, const float *__restrict__ dC) {
   constexpr int ROWS = L1 > 1 ? L1 / 2 : 1;
-  extern __shared__ float Ut[];  // [n1][j][col], ROWS x rp x 16
-  const int c0 = blockIdx.x * 16;
-  for (int e = threadIdx.x; e < ROWS * rp * 16; e += 64 * CW) {
-    const int col = e & 15, j = (e >> 4) % rp, n1 = (e >> 4) / rp;
-    const int n = c0 + col + (n1 << log2);
-    Ut[e] = (j < r && n < N) ? U[(int64_t)j * ldu + n] : 0.f;
-  }
-  __syncthreads();
+  constexpr int NT = 64 * CW;
+  static_assert(PPL == 1 || PPL == 2, "pairs per lane");
+  // MODE 0: FP32 [n1][j][col]; MODE 1: BF16 hi and lo planes [n1][col][j]
+  // with rows of rp + 8 elements, so that a lane's eight consecutive j are
+  // one 16-byte read and the sixteen columns fall on distinct banks.
+  extern __shared__ float Ut[];
+  // Workgroups are dealt to the eight XCDs round-robin by linear id; give
+  // each XCD a contiguous run of column blocks, so the two 64-byte halves of
+  // a 128-byte line of y (and of U) are handled within one L2.
+  const int gx = gridDim.x;
+  const int cb = (gx & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (gx >> 3) + (int)(blockIdx.x >> 3);
+  const int c0 = cb * 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, blk = lane >> 4;
-  const int pw = blockIdx.y * 8 * CW + wave * 8;  // first pair of the wavefront, within the slice
-  if (pw >= np) return;                            // uniform per wavefront; no barrier follows
+  const int pw = (blockIdx.y * CW + wave) * 4 * PPL;  // first pair of the wavefront, within the slice
   const int n2 = c0 + col;
-  const int mask = (1 << s) - 1;
-  cpx<float> tw[L1];
+  // The wavefront's Z loads go out first, so their latency overlaps the
+  // staging of U below.
+  cpx<float> a[PPL][L1];
 #pragma unroll
-  for (int k1 = 1; k1 < L1; ++k1) {
-    const int m = n2 * k1;
-    tw[k1] = cmul(thi[m >> s], tlo[m & mask]);
+  for (int h = 0; h < PPL; ++h) {
+    const int pl = pw + PPL * blk + h;
+    const cpx<float> *Zp = Z + ((int64_t)(pl < np ? pl : 0) << logL) + n2;
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) a[h][k1] = Zp[(int64_t)k1 << log2];
   }
-  f32x4 acc[ROWS];
+  {
+    const int tc = threadIdx.x & 15;
+    const int n0 = c0 + tc;
+    if constexpr (MODE == 0) {
+      for (int j = threadIdx.x >> 4; j < rp; j += NT / 16) {
+        const float *u = U + (int64_t)j * ldu;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int pl = pw + 2 * blk + h;
-    cpx<float> a[L1];
-    if (pl < np) {
-      const cpx<float> *Zp = Z + ((int64_t)pl << logL) + n2;
-      a[0] = Zp[0];
-#pragma unroll
-      for (int k1 = 1; k1 < L1; ++k1) a[k1] = cmulc(Zp[(int64_t)k1 << log2], tw[k1]);
-    } else {
-#pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) a[k1] = cpx<float>{0.f, 0.f};
-    }
-    reg::dft<L1, +1>(a);
-#pragma unroll
-    for (int n1 = 0; n1 < ROWS; ++n1) {
-      acc[n1][2 * h] = a[n1].x;
-      acc[n1][2 * h + 1] = a[n1].y;
-    }
-  }
-  // signals of this wavefront: 2 (pair0 + pw) + 0..15; A row i = lane % 16
-  const int sa = 2 * (pair0 + pw) + (lane & 15);
-  const bool sav = sa < b && (pw + ((lane & 15) >> 1)) < np;
-  const int sac = sav ? sa : 0;
-  if constexpr (MODE == 0) {
-    for (int jb = 0; jb < rp; jb += 4) {
-      const int j = jb + blk;
-      const float av = (sav && j < r) ? dC[(int64_t)j * b + sac] : 0.f;
-#pragma unroll
-      for (int n1 = 0; n1 < ROWS; ++n1)
-        acc[n1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, Ut[(n1 * rp + j) * 16 + col], acc[n1], 0, 0, 0);
-    }
-  } else {
-    for (int jb = 0; jb < rp; jb += 32) {
-      bf16x8 ahi, alo;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int j = jb + 8 * blk + e;
-        const float av = (sav && j < r) ? dC[(int64_t)j * b + sac] : 0.f;
-        const __bf16 hh = (__bf16)av;
-        ahi[e] = hh;
-        alo[e] = (__bf16)(av - (float)hh);
+        for (int n1 = 0; n1 < ROWS; ++n1) {
+          const int n = n0 + (n1 << log2);
+          Ut[(n1 * rp + j) * 16 + tc] = (j < r && n < N) ? u[n] : 0.f;
+        }
       }
+    } else {
+      const int jp = rp + 8;
+      __bf16 *uh = reinterpret_cast<__bf16 *>(Ut);
+      __bf16 *ul = uh + ROWS * 16 * jp;
+      for (int j = threadIdx.x >> 4; j < rp; j += NT / 16) {
+        const float *u = U + (int64_t)j * ldu;
 #pragma unroll
-      for (int n1 = 0; n1 < ROWS; ++n1) {
-        bf16x8 bhi, blo;
+        for (int n1 = 0; n1 < ROWS; ++n1) {
+          const int n = n0 + (n1 << log2);
+          const float uv = (j < r && n < N) ? u[n] : 0.f;
+          const __bf16 hh = (__bf16)uv;
+          uh[(n1 * 16 + tc) * jp + j] = hh;
+          ul[(n1 * 16 + tc) * jp + j] = (__bf16)(uv - (float)hh);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (pw >= np) return;  // uniform per wavefront; no barrier follows
+  // W_L^{k1 n2} = W_L^{(k1 mod 8) n2} W_L^{8 (k1 div 8) n2}: eight plus L1/8
+  // table loads per lane instead of L1, one extra rounding per factor.
+  constexpr int TH = L1 > 8 ? L1 / 8 : 1;
+  cpx<float> tl[L1 < 8 ? L1 : 8], th[TH];
+#pragma unroll
+  for (int k = 1; k < (L1 < 8 ? L1 : 8); ++k) tl[k] = tcol[(k << log2) + n2];
+#pragma unroll
+  for (int m = 1; m < TH; ++m) th[m] = tcol[((8 * m) << log2) + n2];
+#pragma unroll
+  for (int h = 0; h < PPL; ++h) {
+#pragma unroll
+    for (int k1 = 1; k1 < L1; ++k1) {
+      const int kl = k1 & 7, kh = k1 >> 3;
+      const cpx<float> w = kh == 0 ? tl[kl] : (kl == 0 ? th[kh] : cmul(tl[kl], th[kh]));
+      a[h][k1] = cmulc(a[h][k1], w);
+    }
+    reg::dft<L1, +1>(a[h]);
+  }
+  // A row i = lane % 16 is signal slot i: slot 4 q + v holds signal
+  // 2 (pair0 + pw + PPL q) + v (PPL = 2), or 2 (pair0 + pw + q) + v for v < 2
+  // and nothing for v >= 2 (PPL = 1).
+  const int iq = (lane & 15) >> 2, iv = lane & 3;
+  const int ipl = pw + PPL * iq + (iv >> 1);
+  const int sa = 2 * (pair0 + ipl) + (iv & 1);
+  const bool sav = (PPL == 2 || iv < 2) && ipl < np && sa < b;
+  const int sac = sav ? sa : 0;
+  // Rows go through the matrix cores in chunks of at most eight, so only one
+  // chunk's accumulators are live next to the DFT outputs.
+  constexpr int RC = ROWS < 8 ? ROWS : 8;
+#pragma unroll
+  for (int rc = 0; rc < ROWS; rc += RC) {
+    f32x4 acc[RC];
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+      acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int h = 0; h < PPL; ++h) {
+        const bool live = pw + PPL * blk + h < np;
+        acc[i][2 * h] = live ? a[h][rc + i].x : 0.f;
+        acc[i][2 * h + 1] = live ? a[h][rc + i].y : 0.f;
+      }
+    }
+    if constexpr (MODE == 0) {
+      for (int jb = 0; jb < rp; jb += 4) {
+        const int j = jb + blk;
+        const float av = (sav && j < r) ? dC[(int64_t)j * b + sac] : 0.f;
+#pragma unroll
+        for (int i = 0; i < RC; ++i)
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, Ut[((rc + i) * rp + j) * 16 + col], acc[i], 0, 0, 0);
+      }
+    } else {
+      const int jp = rp + 8;
+      const __bf16 *uh = reinterpret_cast<const __bf16 *>(Ut);
+      const __bf16 *ul = uh + ROWS * 16 * jp;
+      for (int jb = 0; jb < rp; jb += 32) {
+        bf16x8 ahi, alo;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const float uv = Ut[(n1 * rp + jb + 8 * blk + e) * 16 + col];
-          const __bf16 hh = (__bf16)uv;
-          bhi[e] = hh;
-          blo[e] = (__bf16)(uv - (float)hh);
+          const int j = jb + 8 * blk + e;
+          const float av = (sav && j < r) ? dC[(int64_t)j * b + sac] : 0.f;
+          const __bf16 hh = (__bf16)av;
+          ahi[e] = hh;
+          alo[e] = (__bf16)(av - (float)hh);
         }
-        acc[n1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[n1], 0, 0, 0);
-        acc[n1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[n1], 0, 0, 0);
-        acc[n1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[n1], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+          const int o = ((rc + i) * 16 + col) * jp + jb + 8 * blk;
+          const bf16x8 bhi = *reinterpret_cast<const bf16x8 *>(uh + o);
+          const bf16x8 blo = *reinterpret_cast<const bf16x8 *>(ul + o);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[i], 0, 0, 0);
+        }
       }
     }
-  }
-  // D[4 blk + v][col] -> signal 2 (pair0 + pw) + 4 blk + v at n = n2 + L2 n1
+    // D[4 blk + v][col] -> signal slot 4 blk + v at n = n2 + L2 (rc + i)
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int pl = pw + 2 * blk + (v >> 1);
-    const int sg = 2 * (pair0 + pw) + 4 * blk + v;
-    if (pl >= np || sg >= b) continue;
-    float *ys = y + (int64_t)sg * ldy;
+    for (int v = 0; v < 2 * PPL; ++v) {
+      const int pl = pw + PPL * blk + (v >> 1);
+      const int sg = 2 * (pair0 + pl) + (v & 1);
+      if (pl >= np || sg >= b) continue;
+      float *ys = y + (int64_t)sg * ldy;
 #pragma unroll
-    for (int n1 = 0; n1 < ROWS; ++n1) {
-      const int n = n2 + (n1 << log2);
-      if (n < N) ys[n] = acc[n1][v];
+      for (int i = 0; i < RC; ++i) {
+        const int n = n2 + ((rc + i) << log2);
+        if (n < N) ys[n] = acc[i][v];
+      }
     }
   }
 }
@@ -444,6 +524,26 @@ __global__ void k_row_twiddles(cpx<R> *__restrict__ rt1, cpx<R> *__restrict__ rt
     sincospi(2.0 * (double)m / (double)T, &sn, &cs);
     rt2[i] = cpx<R>{(R)cs, (R)(-sn)};
   }
+}
+
+// Column-pass twiddles: tc[k1 L2 + n2] = W_L^{k1 n2} (k1 < L1, n2 < L2), so a
+// lane's factor for row k1 is one coalesced load.
+template <typename R>
+__global__ void k_col_twiddles(cpx<R> *__restrict__ tc, int log2, int logL) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ((int64_t)1 << logL)) return;
+  const int64_t k1 = i >> log2, n2 = i & (((int64_t)1 << log2) - 1);
+  double sn, cs;
+  sincospi(ldexp((double)(k1 * n2), 1 - logL), &sn, &cs);
+  tc[i] = cpx<R>{(R)cs, (R)(-sn)};
+}
+
+template <typename R>
+hipError_t build_col_table(const FftGeom &g, cpx<R> *tc, hipStream_t st) {
+  if (!g.v2 || g.single()) return hipSuccess;
+  const int64_t L = (int64_t)1 << g.logL;
+  hipLaunchKernelGGL(k_col_twiddles<R>, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, st, tc, g.log2, g.logL);
+  return hipGetLastError();
 }
 
 template <typename R>
@@ -483,10 +583,10 @@ static void launch_cols(bool fwd, dim3 grid, hipStream_t st, const R *x, int64_t
                         int b, int p0, const FftGeom &g, const FftTables<R> &tb, cpx<R> *Z) {
   if (fwd) {
     SLP_LAUNCH(sizeof(R) == 4 ? "col_fwd" : "col_fwd_f64", (k_colfwd2<R, L1>), grid, dim3(256), 0, st, x, ldx, N, b,
-               p0, g.logL, g.log2, g.s, tb.tw_lo, tb.tw_hi, Z);
+               p0, g.logL, g.log2, tb.col, Z);
   } else {
     SLP_LAUNCH(sizeof(R) == 4 ? "col_inv" : "col_inv_f64", (k_colinv2<R, L1>), grid, dim3(256), 0, st, Z, N, b, p0,
-               g.logL, g.log2, g.s, tb.tw_lo, tb.tw_hi, y, ldy);
+               g.logL, g.log2, tb.col, y, ldy);
   }
 }
 
@@ -504,22 +604,58 @@ static bool dispatch_cols(bool fwd, dim3 grid, hipStream_t st, const R *x, int64
   }
 }
 
-constexpr int kColCorrWaves = 4;
+// Fused pass C launch shape: PPL pairs per lane, CW wavefronts per workgroup
+// (4 PPL CW pairs share one staged U tile).  SLEPIAN_CIC_SHAPE = "PPLxCW"
+// (1x8, 1x4, 2x4) overrides the default for tuning.
+struct CicShape {
+  int ppl = 1, cw = 8;
+};
+
+static CicShape cic_shape() {
+  static const CicShape sh = [] {
+    CicShape c;
+    if (const char *e = std::getenv("SLEPIAN_CIC_SHAPE")) {
+      int p = 0, w = 0;
+      if (std::sscanf(e, "%dx%d", &p, &w) == 2 && ((p == 1 && (w == 4 || w == 8)) || (p == 2 && w == 4))) {
+        c.ppl = p;
+        c.cw = w;
+      }
+    }
+    return c;
+  }();
+  return sh;
+}
 
 int colinv_corr_rp(int r, int mode) { return mode == 0 ? (r + 3) / 4 * 4 : (r + 31) / 32 * 32; }
 
 size_t colinv_corr_lds(int log1, int r, int mode) {
   const int rows = log1 > 0 ? (1 << log1) / 2 : 1;
-  return (size_t)rows * colinv_corr_rp(r, mode) * 16 * sizeof(float);
+  const size_t rp = (size_t)colinv_corr_rp(r, mode);
+  return mode == 0 ? rows * rp * 16 * sizeof(float) : rows * 16 * (rp + 8) * 2 * sizeof(__bf16);
+}
+
+bool colinv_corr_ok(int log1, int r, int mode) {
+  return log1 >= 1 && log1 <= 5 && colinv_corr_lds(log1, r, mode) <= (size_t)64 * 1024;
+}
+
+template <int L1, int MODE, int CW, int PPL>
+static void launch_cic(size_t lds, hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np,
+                       const FftGeom &g, const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c,
+                       int rp) {
+  constexpr int PW = 4 * PPL * CW;  // pairs per workgroup
+  const dim3 grid((1u << g.log2) / 16, (unsigned)((np + PW - 1) / PW));
+  SLP_LAUNCH(MODE ? "col_inv_corr_bf16x3" : "col_inv_corr", (k_colinv_corr<L1, MODE, CW, PPL>), grid, dim3(64 * CW),
+             lds, st, Z, N, b, p0, np, g.logL, g.log2, tb.col, y, ldy, c.U, c.ldu, c.r, rp, c.dC);
 }
 
 template <int L1, int MODE>
-static void launch_cic(dim3 grid, size_t lds, hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np,
-                       const FftGeom &g, const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c,
-                       int rp) {
-  SLP_LAUNCH(MODE ? "col_inv_corr_bf16x3" : "col_inv_corr", (k_colinv_corr<L1, MODE, kColCorrWaves>), grid,
-             dim3(64 * kColCorrWaves), lds, st, Z, N, b, p0, np, g.logL, g.log2, g.s, tb.tw_lo, tb.tw_hi, y, ldy, c.U,
-             c.ldu, c.r, rp, c.dC);
+static void launch_cic_shape(size_t lds, hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np,
+                             const FftGeom &g, const FftTables<float> &tb, float *y, int64_t ldy,
+                             const Corr<float> &c, int rp) {
+  const CicShape sh = cic_shape();
+  if (sh.ppl == 1 && sh.cw == 8) launch_cic<L1, MODE, 8, 1>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
+  else if (sh.ppl == 1) launch_cic<L1, MODE, 4, 1>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
+  else launch_cic<L1, MODE, 4, 2>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
 }
 
 template <int MODE>
@@ -527,15 +663,13 @@ static bool launch_cic_mode(hipStream_t st, const cpx<float> *Z, int N, int b, i
                             const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c) {
   const int rp = colinv_corr_rp(c.r, MODE);
   const size_t lds = colinv_corr_lds(g.log1, c.r, MODE);
-  const dim3 grid((1u << g.log2) / 16, (unsigned)((np + 8 * kColCorrWaves - 1) / (8 * kColCorrWaves)));
   switch (g.log1) {
-    case 1: launch_cic<2, MODE>(grid, lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 2: launch_cic<4, MODE>(grid, lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 3: launch_cic<8, MODE>(grid, lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 4: launch_cic<16, MODE>(grid, lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 5: launch_cic<32, MODE>(grid, lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 6: launch_cic<64, MODE>(grid, lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    default: return false;
+    case 1: launch_cic_shape<2, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 2: launch_cic_shape<4, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 3: launch_cic_shape<8, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 4: launch_cic_shape<16, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 5: launch_cic_shape<32, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    default: return false;  // L1 = 64 holds too many registers; the caller does the update separately
   }
 }
 
@@ -611,6 +745,8 @@ hipError_t conv_apply_v2(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, 
 
 template hipError_t build_row_tables<float>(const FftGeom &, cpx<float> *, cpx<float> *, hipStream_t);
 template hipError_t build_row_tables<double>(const FftGeom &, cpx<double> *, cpx<double> *, hipStream_t);
+template hipError_t build_col_table<float>(const FftGeom &, cpx<float> *, hipStream_t);
+template hipError_t build_col_table<double>(const FftGeom &, cpx<double> *, hipStream_t);
 template hipError_t conv_apply_v2<float>(const float *, int64_t, float *, int64_t, int64_t, int64_t, const FftGeom &,
                                          const FftTables<float> &, float, float, const Corr<float> &, cpx<float> *,
                                          int64_t, hipStream_t);

@@ -13,9 +13,13 @@ FftGeom generic_twin(const FftGeom &g);
 
 template <typename R>
 hipError_t build_row_tables(const FftGeom &g, cpx<R> *rt1, cpx<R> *rt2, hipStream_t st);
+template <typename R>
+hipError_t build_col_table(const FftGeom &g, cpx<R> *tc, hipStream_t st);
 
 // LDS bytes of the fused inverse column pass (0 when not applicable).
 size_t colinv_corr_lds(int log1, int r, int mode);
+// whether the inverse column pass can carry the correction update (L1 <= 32, U tile <= 64 KB)
+bool colinv_corr_ok(int log1, int r, int mode);
 
 template <typename R>
 hipError_t conv_apply_v2(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, int64_t b, const FftGeom &g,

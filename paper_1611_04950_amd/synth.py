@@ -68,3 +68,21 @@ def config_signals(cfg: int, N: int, b: int, W: float, device="cpu") -> torch.Te
     if cfg == 5:
         return sinusoids(N, b, W, 200, 10.0, base, device)
     raise ValueError(cfg)
+
+
+def batching_plans(n_plans: int = 512, seed: int = 4000):
+    """Plan parameters of the many-plans workload: N log-uniform over
+    2^10..2^17 (rounded to an integer), W uniform in [0.01, 0.25], eps drawn
+    from {1e-3, 1e-6}, 4..64 signals per plan (uniform).  Returns a list of
+    (N, W, eps, b) tuples; the signals of plan i are gaussian(N, b, seed *
+    1000 + 100 * i)."""
+    g = _gen(seed, "cpu")
+    logn = torch.rand(n_plans, generator=g, dtype=torch.float64) * 7.0 + 10.0
+    w = torch.rand(n_plans, generator=g, dtype=torch.float64) * 0.24 + 0.01
+    e = torch.randint(0, 2, (n_plans,), generator=g)
+    nb = torch.randint(4, 65, (n_plans,), generator=g)
+    out = []
+    for i in range(n_plans):
+        N = int(round(2.0 ** float(logn[i])))
+        out.append((N, float(w[i]), 1e-3 if int(e[i]) == 0 else 1e-6, int(nb[i])))
+    return out
