@@ -449,6 +449,15 @@ void build_tridiag(const Plan *P, Tridiag &T, hipStream_t st) {
   HIPCHK(hipStreamSynchronize(st));
 }
 
+// Device memory for one batch of inverse iterations: every vector of a batch
+// runs its sequential sweeps in parallel with the others, so the batch should
+// hold the whole window; a quarter of the free memory, at most 16 GiB.
+size_t inviter_budget() {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)8 << 30;
+  return std::max<size_t>((size_t)256 << 20, std::min<size_t>((size_t)16 << 30, fr / 4));
+}
+
 // Slepian vectors l = lo..hi into V (N x (hi-lo+1), FP64, column c <-> l = lo + c).
 void solve_vectors(const Plan *P, const Tridiag &T, int64_t lo, int64_t hi, double *V, hipStream_t st) {
   const int64_t N = P->N;
@@ -457,7 +466,7 @@ void solve_vectors(const Plan *P, const Tridiag &T, int64_t lo, int64_t hi, doub
   // ascending index t = N-1-l; theta[j] <-> t = (N-1-hi) + j <-> l = hi - j
   HIPCHK(tridiag_bisect(T.a, T.e2, N, T.gl, T.gu, T.pivmin, N - 1 - hi, nv, theta.p, st));
   const size_t per = inviter_scratch_bytes(N, 1);
-  int64_t cv = (int64_t)(((size_t)2 << 30) / per);
+  int64_t cv = (int64_t)(inviter_budget() / per);
   cv = std::max<int64_t>(1, std::min(cv, nv));
   DBuf<char> scratch(inviter_scratch_bytes(N, cv));
   for (int64_t j0 = 0; j0 < nv; j0 += cv) {
@@ -906,7 +915,7 @@ int slepian_coeffs(slepian_plan_t P, const float *x, int64_t ldx, float *c, int6
         DBuf<double> theta(K);
         HIPCHK(tridiag_bisect(T.a, T.e2, N, T.gl, T.gu, T.pivmin, N - K, K, theta.p, s2));
         const size_t per = inviter_scratch_bytes(N, 1) + N * sizeof(double);
-        int64_t cv = std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)(((size_t)2 << 30) / per)));
+        int64_t cv = std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)(inviter_budget() / per)));
         DBuf<char> scratch(inviter_scratch_bytes(N, cv));
         DBuf<double> V((size_t)N * cv);
         for (int64_t j0 = 0; j0 < K; j0 += cv) {

@@ -40,13 +40,39 @@ hipError_t tridiag_build(double *a, double *e2, int64_t N, double W, hipStream_t
 
 // Number of eigenvalues of T below x: the count of negative pivots of the
 // LDL^T factorisation of T - x I (Sturm sequence).
+// The quotient e2/q uses the hardware reciprocal refined by two Newton steps
+// (a few ulp, far inside the perturbation the count tolerates; the |q| >=
+// pivmin guard keeps it away from zero), and T's entries are read eight at a
+// time ahead of the recurrence.
+__device__ __forceinline__ double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
+}
+
 __device__ __forceinline__ int sturm_count(const double *__restrict__ a, const double *__restrict__ e2,
                                            int64_t N, double x, double pivmin) {
   double q = a[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   int cnt = q < 0.0;
-  for (int64_t k = 1; k < N; ++k) {
-    q = (a[k] - x) - e2[k - 1] / q;
+  int64_t k = 1;
+  for (; k + 8 <= N; k += 8) {
+    double av[8], ev[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      av[i] = a[k + i];
+      ev[i] = e2[k - 1 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      q = (av[i] - x) - ev[i] * recip(q);
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+    }
+  }
+  for (; k < N; ++k) {
+    q = (a[k] - x) - e2[k - 1] * recip(q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
@@ -91,9 +117,12 @@ hipError_t tridiag_bisect(const double *a, const double *e2, int64_t N, double g
 }
 
 // Scratch of inverse iteration, interleaved [k][vector] so that the lanes of
-// a wavefront (one vector each) touch consecutive addresses.
+// a wavefront (one vector each) touch consecutive addresses: the iterate x,
+// the reciprocal pivots of U, U's first superdiagonal and the row-exchange
+// flags (U's second superdiagonal is off[k+1] after an exchange, else zero,
+// so it is not stored).
 struct InvScratch {
-  double *dl, *d, *du, *du2, *x;
+  double *x, *dinv, *du;
   unsigned char *piv;
 };
 
@@ -101,17 +130,15 @@ static InvScratch carve(void *p, int64_t N, int64_t count) {
   InvScratch s;
   const size_t nd = (size_t)N * (size_t)count;
   double *q = (double *)p;
-  s.dl = q;
-  s.d = q + nd;
+  s.x = q;
+  s.dinv = q + nd;
   s.du = q + 2 * nd;
-  s.du2 = q + 3 * nd;
-  s.x = q + 4 * nd;
-  s.piv = (unsigned char *)(q + 5 * nd);
+  s.piv = (unsigned char *)(q + 3 * nd);
   return s;
 }
 
 size_t inviter_scratch_bytes(int64_t N, int64_t count) {
-  return (size_t)N * (size_t)count * (5 * sizeof(double) + 1) + 256;
+  return (size_t)N * (size_t)count * (3 * sizeof(double) + 1) + 256;
 }
 
 __device__ __forceinline__ double start_value(int64_t k, int64_t j) {
@@ -122,9 +149,36 @@ __device__ __forceinline__ double start_value(int64_t k, int64_t j) {
   return 0.5 + (double)(h & 0xffffu) / 65536.0;
 }
 
-// One lane per eigenvalue: factor T - theta I = P L U (partial pivoting,
-// U with two superdiagonals), then `iters` rounds of x <- (T - theta I)^{-1} x
-// with normalisation.  The final (unnormalised) iterate is left in s.x.
+// Steps of the sequential sweeps whose operands are fetched one block ahead
+// of the arithmetic, so each lane's chain waits on memory once per block.
+constexpr int kIB = 8;
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Raw buffer access: one per-lane byte offset (the lane's column) and one
+// uniform byte offset (the row), so a step's four accesses share their
+// address arithmetic, which runs on the scalar unit.  Reads past num_records
+// return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, int64_t bytes) {
+  const int n = bytes > 0x7fffffff ? 0x7fffffff : (int)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, n, 0x00020000);
+}
+__device__ __forceinline__ double bld(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+__device__ __forceinline__ void bst(double v, __amdgpu_buffer_rsrc_t r, int vo, int so) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
+}
+
+// One lane per eigenvalue: `iters` rounds of x <- (T - theta I)^{-1} x with
+// normalisation.  Each round factors T - theta I = P L U on the fly
+// (Gaussian elimination with partial pivoting, LAPACK's choice for inverse
+// iteration on a tridiagonal matrix), applying each multiplier of L to the
+// iterate as it is produced, and stores what the backward substitution with
+// U needs.  The first round starts from a hashed vector.  The final
+// (unnormalised) iterate is left in s.x.  Rows of the scratch arrays are
+// addressed from a base that moves with the block, so no offset exceeds a
+// block's span.
 __global__ __launch_bounds__(64) void k_inviter(const double *__restrict__ a, const double *__restrict__ off,
                                                 int64_t N, const double *__restrict__ theta, int64_t count,
                                                 InvScratch s, double tiny, int iters) {
@@ -132,68 +186,138 @@ __global__ __launch_bounds__(64) void k_inviter(const double *__restrict__ a, co
   if (j >= count) return;
   const double th = theta[j];
   const int64_t C = count;
-  double cur_d = a[0] - th;
-  double cur_du = N > 1 ? off[0] : 0.0;
-  for (int64_t k = 0; k < N - 1; ++k) {
-    const double sub = off[k];
-    const double nd = a[k + 1] - th;
-    const double nu = k < N - 2 ? off[k + 1] : 0.0;
-    const int64_t o = k * C + j;
-    if (fabs(cur_d) >= fabs(sub)) {
-      double dk = cur_d;
-      if (dk == 0.0) dk = tiny;
-      const double f = sub / dk;
-      s.d[o] = dk;
-      s.du[o] = cur_du;
-      s.du2[o] = 0.0;
-      s.dl[o] = f;
-      s.piv[o] = 0;
-      cur_d = nd - f * cur_du;
-      cur_du = nu;
-    } else {
-      const double f = cur_d / sub;
-      s.d[o] = sub;
-      s.du[o] = nd;
-      s.du2[o] = nu;
-      s.dl[o] = f;
-      s.piv[o] = 1;
-      cur_d = cur_du - f * nd;
-      cur_du = -f * nu;
-    }
+  if (N == 1) {
+    s.x[j] = 1.0;
+    return;
   }
-  if (cur_d == 0.0) cur_d = tiny;
-  s.d[(N - 1) * C + j] = cur_d;
-  for (int64_t k = 0; k < N; ++k) s.x[k * C + j] = start_value(k, j);
+  const int64_t M = N - 1;  // elimination steps k = 0..N-2; off[k] valid for k < M
+  const int rs8 = (int)(C * 8), rs1 = (int)C;  // row strides in bytes (kIB rows stay far below 2^31)
+  const int vo8 = (int)j * 8, vo1 = (int)j;
+  // T's entries are the same for every lane; a per-lane byte offset keeps
+  // the prefetched blocks in vector registers.
+  const int tz = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u) * 8;
+  const __amdgpu_buffer_rsrc_t ra = rsrc(a, N * 8), ro = rsrc(off, M * 8);
+  auto rows = [&](int64_t r0, __amdgpu_buffer_rsrc_t &rx, __amdgpu_buffer_rsrc_t &rd, __amdgpu_buffer_rsrc_t &ru,
+                  __amdgpu_buffer_rsrc_t &rp) {
+    const int64_t o = r0 * C, n = (N - r0) * C;
+    rx = rsrc(s.x + o, n * 8);
+    rd = rsrc(s.dinv + o, n * 8);
+    ru = rsrc(s.du + o, n * 8);
+    rp = rsrc(s.piv + o, n);
+  };
   double scale = 1.0;
   for (int it = 0; it < iters; ++it) {
-    // forward: apply P and L^{-1}
-    double prev = s.x[j] * scale;
-    for (int64_t k = 0; k < N - 1; ++k) {
-      const int64_t o = k * C + j;
-      double nxt = s.x[o + C] * scale;
-      const double f = s.dl[o];
-      if (s.piv[o] == 0) {
-        s.x[o] = prev;
-        nxt -= f * prev;
-      } else {
-        s.x[o] = nxt;
-        nxt = prev - f * nxt;
+    // ---- forward: elimination with the multipliers applied to x ----
+    double cur_d = bld(ra, tz, 0) - th;
+    double cur_du = bld(ro, tz, 0);
+    double prev = it == 0 ? start_value(0, j) : s.x[j] * scale;
+    // block k0: x[k+1], a[k+1], off[k] for k = k0..k0+kIB-1, and off[k0+kIB]
+    auto load_fwd = [&](int64_t k0, double (&bx)[kIB], double (&ba)[kIB], double (&bo)[kIB + 1]) {
+      __amdgpu_buffer_rsrc_t rx, rd, ru, rp;
+      rows(k0 + 1 < N ? k0 + 1 : M, rx, rd, ru, rp);
+#pragma unroll
+      for (int i = 0; i < kIB; ++i) {
+        const int64_t k = k0 + i;
+        bx[i] = it == 0 ? start_value(k + 1, j) : bld(rx, vo8, i * rs8);
+        ba[i] = bld(ra, tz, (int)((k + 1) * 8));
+        bo[i] = bld(ro, tz, (int)(k * 8));
       }
-      prev = nxt;
+      bo[kIB] = bld(ro, tz, (int)((k0 + kIB) * 8));
+    };
+    double cx[kIB], ca[kIB], co[kIB + 1];
+    load_fwd(0, cx, ca, co);
+    for (int64_t k0 = 0; k0 < M; k0 += kIB) {
+      const bool more = k0 + kIB < M;
+      double nx[kIB], na[kIB], no[kIB + 1];
+      if (more) load_fwd(k0 + kIB, nx, na, no);
+      __amdgpu_buffer_rsrc_t rx, rd, ru, rp;
+      rows(k0, rx, rd, ru, rp);
+#pragma unroll
+      for (int i = 0; i < kIB; ++i) {
+        const int64_t k = k0 + i;
+        if (k >= M) break;  // uniform
+        const double sub = co[i];
+        const double nd = ca[i] - th;
+        const double nu = k + 1 < M ? co[i + 1] : 0.0;
+        const double nxt = cx[i] * scale;
+        const bool sw = fabs(cur_d) < fabs(sub);  // exchange rows k and k+1
+        const double pv = sw ? sub : (cur_d == 0.0 ? tiny : cur_d);
+        const double rk = 1.0 / pv;
+        const double f = (sw ? cur_d : sub) * rk;
+        bst(rk, rd, vo8, i * rs8);
+        bst(sw ? nd : cur_du, ru, vo8, i * rs8);
+        __builtin_amdgcn_raw_buffer_store_b8((unsigned char)(sw ? 1 : 0), rp, vo1, i * rs1, 0);
+        bst(sw ? nxt : prev, rx, vo8, i * rs8);
+        prev = sw ? prev - f * nxt : nxt - f * prev;
+        const double ncd = sw ? cur_du - f * nd : nd - f * cur_du;
+        cur_du = sw ? -f * nu : nu;
+        cur_d = ncd;
+      }
+      if (more) {
+#pragma unroll
+        for (int i = 0; i < kIB; ++i) {
+          cx[i] = nx[i];
+          ca[i] = na[i];
+          co[i] = no[i];
+        }
+        co[kIB] = no[kIB];
+      }
     }
-    s.x[(N - 1) * C + j] = prev;
-    // back substitution with U
-    double x2 = 0.0, x1 = 0.0, ss = 0.0;
-    for (int64_t k = N - 1; k >= 0; --k) {
-      const int64_t o = k * C + j;
-      double v = s.x[o];
-      if (k < N - 1) v -= s.du[o] * x1;
-      if (k < N - 2) v -= s.du2[o] * x2;
-      v /= s.d[o];
-      s.x[o] = v;
-      ss += v * v;
-      x2 = x1;
-      x1 = v;
+    s.dinv[M * C + j] = 1.0 / (cur_d == 0.0 ? tiny : cur_d);
+    s.x[M * C + j] = prev;
+    // ---- backward substitution with U, k = N-1 .. 0 ----
+    // block k0: rows k0, k0-1, .., k0-kIB+1 (x, 1/u_kk, u_k,k+1, flag, off[k+1]),
+    // addressed from row max(k0 - kIB + 1, 0)
+    auto load_bwd = [&](int64_t k0, double (&bx)[kIB], double (&bd)[kIB], double (&bu)[kIB],
+                        unsigned char (&bp)[kIB], double (&bo)[kIB]) {
+      const int64_t r0 = k0 - kIB + 1 > 0 ? k0 - kIB + 1 : 0;
+      __amdgpu_buffer_rsrc_t rx, rd, ru, rp;
+      rows(r0, rx, rd, ru, rp);
+#pragma unroll
+      for (int i = 0; i < kIB; ++i) {
+        const int64_t k = k0 - i >= 0 ? k0 - i : 0;
+        const int q = (int)(k - r0);
+        bx[i] = bld(rx, vo8, q * rs8);
+        bd[i] = bld(rd, vo8, q * rs8);
+        bu[i] = k < M ? bld(ru, vo8, q * rs8) : 0.0;
+        bp[i] = k < M ? __builtin_amdgcn_raw_buffer_load_b8(rp, vo1, q * rs1, 0) : 0;
+        bo[i] = k + 1 < M ? bld(ro, tz, (int)((k + 1) * 8)) : 0.0;
+      }
+    };
+    double x1 = 0.0, x2 = 0.0, ss = 0.0;
+    double rxv[kIB], rdv[kIB], ruv[kIB], rov[kIB];
+    unsigned char rpv[kIB];
+    load_bwd(M, rxv, rdv, ruv, rpv, rov);
+    for (int64_t k0 = M; k0 >= 0; k0 -= kIB) {
+      const bool more = k0 - kIB >= 0;
+      double nx[kIB], nd[kIB], nu[kIB], no[kIB];
+      unsigned char np[kIB];
+      if (more) load_bwd(k0 - kIB, nx, nd, nu, np, no);
+      const int64_t r0 = k0 - kIB + 1 > 0 ? k0 - kIB + 1 : 0;
+      __amdgpu_buffer_rsrc_t rx, rd, ru, rp;
+      rows(r0, rx, rd, ru, rp);
+#pragma unroll
+      for (int i = 0; i < kIB; ++i) {
+        const int64_t k = k0 - i;
+        if (k < 0) break;  // uniform
+        double v = rxv[i] - ruv[i] * x1;
+        if (rpv[i]) v -= rov[i] * x2;
+        v *= rdv[i];
+        bst(v, rx, vo8, (int)(k - r0) * rs8);
+        ss += v * v;
+        x2 = x1;
+        x1 = v;
+      }
+      if (more) {
+#pragma unroll
+        for (int i = 0; i < kIB; ++i) {
+          rxv[i] = nx[i];
+          rdv[i] = nd[i];
+          ruv[i] = nu[i];
+          rpv[i] = np[i];
+          rov[i] = no[i];
+        }
+      }
     }
     scale = 1.0 / sqrt(ss);
   }

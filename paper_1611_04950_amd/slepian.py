@@ -144,7 +144,8 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        # at interpreter exit the module globals may already be gone
+        if h is not None and h.value and _lib is not None:
             _lib.slepian_plan_destroy(h)
             self.handle = C.c_void_p(0)
 
@@ -264,7 +265,7 @@ class Group:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:
             _lib.slepian_group_destroy(h)
             self.handle = C.c_void_p(0)
 
