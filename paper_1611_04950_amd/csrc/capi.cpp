@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -14,6 +15,7 @@
 #include "slepian.h"
 #include "common.h"
 #include "kernels.h"
+#include "trace.h"
 
 using namespace slp;
 
@@ -158,18 +160,42 @@ struct slepian_group_s {
   std::vector<slepian_plan_t> plans;
   std::vector<int64_t> batch;
   int device = 0;
-  void *ws = nullptr;
-  size_t ws_bytes = 0;
-  hipStream_t cap = nullptr;
+  int prec = SLEPIAN_FP32;
+  // grouped path: a device table of per-plan operands and the spans of the
+  // grouped launches (index and start arrays in one device buffer)
+  std::vector<slp::GroupPlan> gp;
+  slp::GroupPlan *gp_dev = nullptr;
+  int *span_buf = nullptr;
+  std::vector<int> span_host;
+  struct Span {
+    size_t off = 0;  // of idx in span_host; start follows idx
+    int m = 0;
+    int64_t blocks = 0;
+  };
+  Span single[14], partial, reduce, colfwd[6], row, colinv[6];
+  size_t colinv_lds[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<int> grouped, other;  // plan indices
+  void *ws = nullptr;               // grouped workspace (Z, partials, dC per plan)
+  void *ws_other = nullptr;         // for the plans run one by one
+  size_t ws_other_bytes = 0;
+  hipStream_t cap = nullptr, cap2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  int graph_vec = -1;
   std::vector<const float *> lx;
   std::vector<float *> ly;
   ~slepian_group_s() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     if (cap) (void)hipStreamDestroy(cap);
+    if (cap2) (void)hipStreamDestroy(cap2);
+    dfree(gp_dev);
+    dfree(span_buf);
     dfree(ws);
+    dfree(ws_other);
   }
 };
 
@@ -1083,25 +1109,170 @@ int slepian_plan_load(const char *path, int device, slepian_plan_t *out) {
 // Groups
 // ---------------------------------------------------------------------------
 
+}  // extern "C"
+
+namespace {
+
+// Plans whose three passes the grouped kernels cover: register-stage rows of
+// 8192 points, at most 32 columns, a correction that rides on the inverse
+// column pass.
+bool group_three_pass(const Plan *P, int prec) {
+  const int umode = prec == SLEPIAN_MIXED ? 1 : 0;
+  const FftGeom &g = P->g32;
+  return g.v2 && !g.single() && g.log2 == 13 && g.log1 >= 1 && g.log1 <= 5 && P->proj.r > 0 &&
+         colinv_corr_ok(g.log1, (int)P->proj.r, umode);
+}
+
+GroupSpan span_of(const slepian_group_s *G, const slepian_group_s::Span &sp) {
+  GroupSpan g;
+  g.m = sp.m;
+  g.blocks = sp.blocks;
+  if (sp.m) {
+    g.idx = G->span_buf + sp.off;
+    g.start = G->span_buf + sp.off + sp.m;
+  }
+  return g;
+}
+
+// The grouped launches: single-pass plans on s2 (independent of the rest),
+// the three-pass chain on s1.
+void launch_grouped(const slepian_group_s *G, hipStream_t s1, hipStream_t s2, bool vec) {
+  const int umode = G->prec == SLEPIAN_MIXED ? 1 : 0;
+  for (int l2 = 9; l2 <= 13; ++l2) HIPCHK(group_single(l2, G->gp_dev, span_of(G, G->single[l2]), s2));
+  HIPCHK(group_corr_partial(umode, vec, G->gp_dev, span_of(G, G->partial), s1));
+  HIPCHK(group_corr_reduce(G->gp_dev, span_of(G, G->reduce), s1));
+  for (int l1 = 1; l1 <= 5; ++l1) HIPCHK(group_colfwd(l1, G->gp_dev, span_of(G, G->colfwd[l1]), s1));
+  HIPCHK(group_row(13, G->gp_dev, span_of(G, G->row), s1));
+  for (int l1 = 1; l1 <= 5; ++l1)
+    HIPCHK(group_colinv_corr(l1, umode, G->colinv_lds[l1], G->gp_dev, span_of(G, G->colinv[l1]), s1));
+}
+
+}  // namespace
+
+extern "C" {
+
 int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batch, slepian_group_t *out) {
   if (!plans || !batch || !out || n < 1) return SLEPIAN_EINVAL;
   for (int i = 0; i < n; ++i) {
     if (!plans[i] || batch[i] < 0 || batch[i] > 32 * 65535) return SLEPIAN_EINVAL;
     if (plans[i]->device != plans[0]->device) return SLEPIAN_EINVAL;
-    if (plans[i]->precision != SLEPIAN_FP32) return SLEPIAN_ENOTSUP;
+    if (plans[i]->precision != plans[0]->precision) return SLEPIAN_EINVAL;
+    if (plans[i]->precision == SLEPIAN_BF16_RAW) return SLEPIAN_ENOTSUP;
   }
   return guarded([&]() -> int {
     DeviceGuard dg(plans[0]->device);
     slepian_group_s *G = new slepian_group_s();
     try {
       G->device = plans[0]->device;
+      G->prec = plans[0]->precision;
       G->plans.assign(plans, plans + n);
       G->batch.assign(batch, batch + n);
-      size_t need = 256;
-      for (int i = 0; i < n; ++i) need = std::max(need, op_workspace(plans[i], SLEPIAN_OP_PROJECT, batch[i]));
-      G->ws = dalloc<char>(need);
-      G->ws_bytes = need;
+      const int umode = G->prec == SLEPIAN_MIXED ? 1 : 0;
+      // classify, and lay out the grouped workspace
+      G->gp.resize(n);
+      size_t wsz = 0;
+      auto reserve = [&](size_t bytes) {
+        wsz = (wsz + 255) & ~(size_t)255;
+        const size_t o = wsz;
+        wsz += bytes;
+        return o;
+      };
+      std::vector<size_t> zoff(n, 0), poff(n, 0), doff(n, 0);
+      for (int i = 0; i < n; ++i) {
+        const Plan *P = plans[i];
+        const int64_t b = batch[i];
+        if (b == 0) continue;
+        if (fused_single(P, P->proj, G->prec)) {
+          G->grouped.push_back(i);
+        } else if (group_three_pass(P, G->prec)) {
+          G->grouped.push_back(i);
+          const int r = (int)P->proj.r;
+          zoff[i] = reserve((size_t)((b + 1) / 2) * (size_t)P->L * sizeof(cpx<float>));
+          poff[i] = reserve((size_t)corr_nchunks(P->N, b, r) * corr_rpad(r) * b * sizeof(float));
+          doff[i] = reserve((size_t)corr_rpad(r) * b * sizeof(float));
+        } else {
+          G->other.push_back(i);
+          G->ws_other_bytes = std::max(G->ws_other_bytes, op_workspace(P, SLEPIAN_OP_PROJECT, b));
+        }
+      }
+      if (wsz) G->ws = dalloc<char>(wsz + 256);
+      if (G->ws_other_bytes) G->ws_other = dalloc<char>(G->ws_other_bytes);
+      char *ws = static_cast<char *>(G->ws);
+      for (int i : G->grouped) {
+        const Plan *P = plans[i];
+        GroupPlan &g = G->gp[i];
+        g.N = (int)P->N;
+        g.b = (int)batch[i];
+        g.np = (int)((batch[i] + 1) / 2);
+        g.ldx = g.ldy = P->N;
+        g.logL = P->g32.logL;
+        g.log2 = P->g32.log2;
+        g.log1 = P->g32.log1;
+        g.chat = P->tb32.chat;
+        g.rt1 = P->tb32.row1;
+        g.rt2 = P->tb32.row2;
+        g.tcol = P->tb32.col;
+        g.corr.U = P->U32 + P->proj.off * P->ldu;
+        g.corr.ldu = P->ldu;
+        g.corr.r = (int)P->proj.r;
+        g.corr.d = P->proj.d32;
+        if (!P->g32.single()) {
+          const int r = (int)P->proj.r;
+          g.corr.mode = umode;
+          g.rp = colinv_corr_rp(r, umode);
+          g.rpad = corr_rpad(r);
+          g.chunks = corr_nchunks(P->N, batch[i], r);
+          g.Z = reinterpret_cast<cpx<float> *>(ws + zoff[i]);
+          g.part = reinterpret_cast<float *>(ws + poff[i]);
+          g.corr.dC = reinterpret_cast<float *>(ws + doff[i]);
+        }
+      }
+      // spans
+      auto add_span = [&](slepian_group_s::Span &sp, const std::vector<int> &ids,
+                          int64_t (*blocks)(const GroupPlan &)) {
+        std::vector<int> idx, start;
+        int64_t tot = 0;
+        for (int i : ids) {
+          const int64_t nb = blocks(G->gp[i]);
+          if (nb <= 0) continue;
+          idx.push_back(i);
+          start.push_back((int)tot);
+          tot += nb;
+        }
+        if (tot > 0x7fffffff) throw Fail{SLEPIAN_ENOTSUP};
+        start.push_back((int)tot);
+        sp.m = (int)idx.size();
+        sp.blocks = tot;
+        sp.off = G->span_host.size();
+        G->span_host.insert(G->span_host.end(), idx.begin(), idx.end());
+        G->span_host.insert(G->span_host.end(), start.begin(), start.end());
+      };
+      std::vector<int> by_single[14], three, by_l1[6];
+      for (int i : G->grouped) {
+        const Plan *P = plans[i];
+        if (P->g32.single()) {
+          by_single[P->g32.log2].push_back(i);
+        } else {
+          three.push_back(i);
+          by_l1[P->g32.log1].push_back(i);
+          G->colinv_lds[P->g32.log1] =
+              std::max(G->colinv_lds[P->g32.log1], colinv_corr_lds(P->g32.log1, (int)P->proj.r, umode));
+        }
+      }
+      for (int l2 = 9; l2 <= 13; ++l2) add_span(G->single[l2], by_single[l2], group_blocks_single);
+      add_span(G->partial, three, group_blocks_partial);
+      add_span(G->reduce, three, group_blocks_reduce);
+      for (int l1 = 1; l1 <= 5; ++l1) add_span(G->colfwd[l1], by_l1[l1], group_blocks_colfwd);
+      add_span(G->row, three, group_blocks_row);
+      for (int l1 = 1; l1 <= 5; ++l1) add_span(G->colinv[l1], by_l1[l1], group_blocks_colinv);
+      G->span_buf = dalloc<int>(G->span_host.size());
+      HIPCHK(hipMemcpy(G->span_buf, G->span_host.data(), G->span_host.size() * sizeof(int), hipMemcpyHostToDevice));
+      G->gp_dev = dalloc<GroupPlan>(n);
+      HIPCHK(hipMemcpy(G->gp_dev, G->gp.data(), n * sizeof(GroupPlan), hipMemcpyHostToDevice));
       HIPCHK(hipStreamCreateWithFlags(&G->cap, hipStreamNonBlocking));
+      HIPCHK(hipStreamCreateWithFlags(&G->cap2, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&G->ev_fork, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&G->ev_join, hipEventDisableTiming));
     } catch (...) {
       delete G;
       throw;
@@ -1119,34 +1290,56 @@ int slepian_group_project(slepian_group_t G, const float *const *x, float *const
   return guarded([&]() -> int {
     DeviceGuard dg(G->device);
     hipStream_t st = (hipStream_t)stream;
-    bool same = G->exec && G->lx.size() == (size_t)n;
+    bool same = G->lx.size() == (size_t)n;
     for (int i = 0; same && i < n; ++i) same = G->lx[i] == x[i] && G->ly[i] == y[i];
+    bool vec = true;
     if (!same) {
-      if (G->exec) (void)hipGraphExecDestroy(G->exec);
-      if (G->graph) (void)hipGraphDestroy(G->graph);
-      G->exec = nullptr;
-      G->graph = nullptr;
-      HIPCHK(hipStreamBeginCapture(G->cap, hipStreamCaptureModeThreadLocal));
-      try {
-        for (int i = 0; i < n; ++i) {
-          const Plan *P = G->plans[i];
-          if (G->batch[i] == 0) continue;
-          Carver cv(G->ws);
-          ProjWs w = carve_project(P, P->proj, G->batch[i], cv);
-          run_fast_op(P, P->proj, 1.0f, 0.0f, x[i], P->N, y[i], P->N, G->batch[i], w, G->cap);
-        }
-      } catch (...) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(G->cap, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
+      for (int i : G->grouped) {
+        G->gp[i].x = x[i];
+        G->gp[i].y = y[i];
       }
-      HIPCHK(hipStreamEndCapture(G->cap, &G->graph));
-      HIPCHK(hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0));
+      // stream-ordered after any earlier launch of this group on `stream`
+      HIPCHK(hipMemcpyAsync(G->gp_dev, G->gp.data(), n * sizeof(GroupPlan), hipMemcpyHostToDevice, st));
       G->lx.assign(x, x + n);
       G->ly.assign(y, y + n);
     }
-    HIPCHK(hipGraphLaunch(G->exec, st));
+    for (int i : G->grouped) vec = vec && (reinterpret_cast<uintptr_t>(x[i]) & 15) == 0 && G->gp[i].ldx % 4 == 0;
+    if (!G->grouped.empty()) {
+      if (trace_enabled()) {
+        // per-kernel timing needs the launches themselves, not a graph
+        launch_grouped(G, st, st, vec);
+      } else {
+        if (!G->exec || G->graph_vec != (int)vec) {
+          if (G->exec) (void)hipGraphExecDestroy(G->exec);
+          if (G->graph) (void)hipGraphDestroy(G->graph);
+          G->exec = nullptr;
+          G->graph = nullptr;
+          HIPCHK(hipStreamBeginCapture(G->cap, hipStreamCaptureModeThreadLocal));
+          try {
+            HIPCHK(hipEventRecord(G->ev_fork, G->cap));
+            HIPCHK(hipStreamWaitEvent(G->cap2, G->ev_fork, 0));
+            launch_grouped(G, G->cap, G->cap2, vec);
+            HIPCHK(hipEventRecord(G->ev_join, G->cap2));
+            HIPCHK(hipStreamWaitEvent(G->cap, G->ev_join, 0));
+          } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(G->cap, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+          }
+          HIPCHK(hipStreamEndCapture(G->cap, &G->graph));
+          HIPCHK(hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0));
+          G->graph_vec = (int)vec;
+        }
+        HIPCHK(hipGraphLaunch(G->exec, st));
+      }
+    }
+    for (int i : G->other) {
+      const Plan *P = G->plans[i];
+      Carver cv(G->ws_other);
+      ProjWs w = carve_project(P, P->proj, G->batch[i], cv, G->prec);
+      run_fast_op(P, P->proj, 1.0f, 0.0f, x[i], P->N, y[i], P->N, G->batch[i], w, st, G->prec);
+    }
     return SLEPIAN_OK;
   });
 }

@@ -85,4 +85,31 @@ struct Corr {
   int mode = 0;
 };
 
+// One plan's operands for the grouped launches, held in a device table that
+// every grouped kernel indexes: signals, FFT tables, correction operands and
+// the plan's share of the group workspace (FP32 path).
+struct GroupPlan {
+  const float *x = nullptr;
+  float *y = nullptr;
+  int64_t ldx = 0, ldy = 0;
+  int N = 0, b = 0, np = 0;  // length, signals, signal pairs
+  int logL = 0, log2 = 0, log1 = 0;
+  const float *chat = nullptr;
+  const cpx<float> *rt1 = nullptr, *rt2 = nullptr, *tcol = nullptr;
+  float beta = 1.f, gl = 0.f;
+  Corr<float> corr;          // U, ldu, r, d (and dC on the three-pass path)
+  int rp = 0, rpad = 0, chunks = 0;
+  cpx<float> *Z = nullptr;   // three-pass intermediate, np * L
+  float *part = nullptr;     // correction partials, chunks * rpad * b
+};
+
+// A grouped launch covers the workgroups of several plans back to back:
+// plans idx[0..m), plan q owning workgroups start[q] .. start[q+1]-1.
+struct GroupSpan {
+  const int *idx = nullptr;
+  const int *start = nullptr;
+  int m = 0;
+  int64_t blocks = 0;
+};
+
 }  // namespace slp

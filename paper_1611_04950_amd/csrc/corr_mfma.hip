@@ -45,17 +45,17 @@ __device__ __forceinline__ void split_bf16(const float (&v)[8], bf16x8 &hi, bf16
 // clamped valid address and are zeroed by a select, so all loads stay in
 // flight together.  The one chunk that crosses N takes the checked path.
 template <int MODE, int NB, int KS, bool VEC>
-__global__ __launch_bounds__(256) void k_corr_partial_mfma(const float *__restrict__ X, int64_t ldx, int N, int b,
-                                                           const float *__restrict__ U, int64_t ldu, int r,
-                                                           float *__restrict__ part, int rpad) {
+__device__ __forceinline__ void corr_partial_body(const float *__restrict__ X, int64_t ldx, int N, int b,
+                                                  const float *__restrict__ U, int64_t ldu, int r,
+                                                  float *__restrict__ part, int rpad, int bx, int by, int bz) {
   __shared__ float red[3][NB][16][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = lane & 31, kb = lane >> 5;
-  const int s_base = blockIdx.y * 32 * NB;
-  const int j = blockIdx.z * 32 + i;
+  const int s_base = by * 32 * NB;
+  const int j = bz * 32 + i;
   const bool jv = j < r;
   constexpr int KC = KS * 16;
-  const int k_begin = (blockIdx.x * 4 + wave) * KC;
+  const int k_begin = (bx * 4 + wave) * KC;
   const int k_end = min(N, k_begin + KC);
   const float *Uj = U + (int64_t)(jv ? j : r - 1) * ldu;
   float ua[KS][8];
@@ -147,22 +147,29 @@ __global__ __launch_bounds__(256) void k_corr_partial_mfma(const float *__restri
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const float t = (acc[nb][v] + red[0][nb][v][lane]) + (red[1][nb][v][lane] + red[2][nb][v][lane]);
-      const int jj = blockIdx.z * 32 + 8 * (v >> 2) + 4 * kb + (v & 3);
-      if (jj < r && s < b) part[((int64_t)blockIdx.x * rpad + jj) * b + s] = t;
+      const int jj = bz * 32 + 8 * (v >> 2) + 4 * kb + (v & 3);
+      if (jj < r && s < b) part[((int64_t)bx * rpad + jj) * b + s] = t;
     }
   }
+}
+
+template <int MODE, int NB, int KS, bool VEC>
+__global__ __launch_bounds__(256) void k_corr_partial_mfma(const float *__restrict__ X, int64_t ldx, int N, int b,
+                                                           const float *__restrict__ U, int64_t ldu, int r,
+                                                           float *__restrict__ part, int rpad) {
+  corr_partial_body<MODE, NB, KS, VEC>(X, ldx, N, b, U, ldu, r, part, rpad, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // out[j * ldo_j + s * ldo_s] = d[j] * sum over chunks of part[chunk][j][s]
 // (d == nullptr: no weights).  16 outputs per workgroup (consecutive s),
 // 16 lanes per output each summing every 16th chunk with two accumulators,
 // then a fixed-order sum of the 16 through LDS.
-__global__ __launch_bounds__(256) void k_corr_reduce2(const float *__restrict__ part, int chunks, int rpad, int b,
-                                                      int r, const float *__restrict__ d, float *__restrict__ out,
-                                                      int64_t ldo_j, int64_t ldo_s) {
+__device__ __forceinline__ void corr_reduce_body(const float *__restrict__ part, int chunks, int rpad, int b, int r,
+                                                 const float *__restrict__ d, float *__restrict__ out, int64_t ldo_j,
+                                                 int64_t ldo_s, int bx) {
   __shared__ float red[16][17];
   const int og = threadIdx.x & 15, cg = threadIdx.x >> 4;
-  const int64_t o = (int64_t)blockIdx.x * 16 + og;  // o = j * b + s
+  const int64_t o = (int64_t)bx * 16 + og;  // o = j * b + s
   const bool valid = o < (int64_t)r * b;
   const int j = valid ? (int)(o / b) : 0, s = valid ? (int)(o % b) : 0;
   float a0 = 0.f, a1 = 0.f;
@@ -180,6 +187,12 @@ __global__ __launch_bounds__(256) void k_corr_reduce2(const float *__restrict__ 
     for (int q = 0; q < 16; ++q) t += red[q][og];
     out[(int64_t)j * ldo_j + (int64_t)s * ldo_s] = d ? d[j] * t : t;
   }
+}
+
+__global__ __launch_bounds__(256) void k_corr_reduce2(const float *__restrict__ part, int chunks, int rpad, int b,
+                                                      int r, const float *__restrict__ d, float *__restrict__ out,
+                                                      int64_t ldo_j, int64_t ldo_s) {
+  corr_reduce_body(part, chunks, rpad, b, r, d, out, ldo_j, ldo_s, blockIdx.x);
 }
 
 // Y tile (32 samples x 32*NB signals) += U tile (32 x r) dC (r x 32*NB), with
@@ -341,6 +354,72 @@ hipError_t corr_sum_mfma(const float *part, int64_t N, int64_t b, int r, float *
   const int64_t outs = (int64_t)r * b;
   SLP_LAUNCH("coeffs_sum", k_corr_reduce2, dim3((unsigned)((outs + 15) / 16)), dim3(256), 0, st, part,
              corr_nchunks(N, b, r), corr_rpad(r), (int)b, r, nullptr, c, (int64_t)1, ldc);
+  return hipGetLastError();
+}
+
+// ---- grouped launches ----
+
+__device__ __forceinline__ int group_slot_c(const int *__restrict__ start, int m, int bid) {
+  int lo = 0, hi = m;  // start[lo] <= bid < start[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= bid) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int MODE, bool VEC>
+__global__ __launch_bounds__(256) void k_corr_partial_group(const GroupPlan *__restrict__ gp,
+                                                            const int *__restrict__ idx,
+                                                            const int *__restrict__ start, int m) {
+  const int q = group_slot_c(start, m, blockIdx.x);
+  const GroupPlan &P = gp[idx[q]];
+  const int w = (int)blockIdx.x - start[q];
+  const int gx = P.chunks, gy = (P.b + 32 * kPartNB - 1) / (32 * kPartNB);
+  corr_partial_body<MODE, kPartNB, kPartKS, VEC>(P.x, P.ldx, P.N, P.b, P.corr.U, P.corr.ldu, P.corr.r, P.part,
+                                                 P.rpad, w % gx, (w / gx) % gy, w / (gx * gy));
+}
+
+__global__ __launch_bounds__(256) void k_corr_reduce_group(const GroupPlan *__restrict__ gp,
+                                                           const int *__restrict__ idx,
+                                                           const int *__restrict__ start, int m) {
+  const int q = group_slot_c(start, m, blockIdx.x);
+  const GroupPlan &P = gp[idx[q]];
+  corr_reduce_body(P.part, P.chunks, P.rpad, P.b, P.corr.r, P.corr.d, const_cast<float *>(P.corr.dC), (int64_t)P.b,
+                   (int64_t)1, (int)blockIdx.x - start[q]);
+}
+
+int64_t group_blocks_partial(const GroupPlan &P) {
+  if (P.corr.r == 0 || P.b == 0) return 0;
+  return (int64_t)P.chunks * ((P.b + 32 * kPartNB - 1) / (32 * kPartNB)) * ((P.corr.r + 31) / 32);
+}
+
+int64_t group_blocks_reduce(const GroupPlan &P) { return ((int64_t)P.corr.r * P.b + 15) / 16; }
+
+hipError_t group_corr_partial(int mode, bool vec, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
+  if (sp.m == 0 || sp.blocks == 0) return hipSuccess;
+  const dim3 grid((unsigned)sp.blocks);
+  if (mode == kModeF32) {
+    if (vec) SLP_LAUNCH("corr_partial_group", (k_corr_partial_group<kModeF32, true>), grid, dim3(256), 0, st, gp,
+                        sp.idx, sp.start, sp.m);
+    else SLP_LAUNCH("corr_partial_group", (k_corr_partial_group<kModeF32, false>), grid, dim3(256), 0, st, gp,
+                    sp.idx, sp.start, sp.m);
+  } else if (mode == kModeBF16x3) {
+    if (vec) SLP_LAUNCH("corr_partial_bf16x3_group", (k_corr_partial_group<kModeBF16x3, true>), grid, dim3(256), 0,
+                        st, gp, sp.idx, sp.start, sp.m);
+    else SLP_LAUNCH("corr_partial_bf16x3_group", (k_corr_partial_group<kModeBF16x3, false>), grid, dim3(256), 0,
+                    st, gp, sp.idx, sp.start, sp.m);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t group_corr_reduce(const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
+  if (sp.m == 0 || sp.blocks == 0) return hipSuccess;
+  SLP_LAUNCH("corr_reduce_group", k_corr_reduce_group, dim3((unsigned)sp.blocks), dim3(256), 0, st, gp, sp.idx,
+             sp.start, sp.m);
   return hipGetLastError();
 }
 

@@ -151,13 +151,12 @@ __device__ __forceinline__ void load_spec(R (&chv)[R1 / R3][R3], const R *__rest
 
 // Middle pass of the three-pass product: row k1c of pair pl, in place.
 template <typename R, int R1, int R2, int R3>
-__global__ __launch_bounds__(R2 *R3) void k_row2(cpx<R> *__restrict__ Z, int logL, int log2,
-                                                 const cpx<R> *__restrict__ rt1, const cpx<R> *__restrict__ rt2,
-                                                 const R *__restrict__ chat, R beta, R gl) {
+__device__ __forceinline__ void row_body(cpx<R> *__restrict__ Z, int logL, int log2, const cpx<R> *__restrict__ rt1,
+                                         const cpx<R> *__restrict__ rt2, const R *__restrict__ chat, R beta, R gl,
+                                         int k1c, int pl) {
   using RS = RowShape<R1, R2, R3>;
   __shared__ cpx<R> S[RS::LDS];
   __shared__ cpx<R> rt2s[R2 * (R3 + 1)];
-  const int k1c = blockIdx.x, pl = blockIdx.y;
   cpx<R> *row = Z + ((int64_t)pl << logL) + ((int64_t)k1c << log2);
   const int t = threadIdx.x;
   cpx<R> v[R1];
@@ -176,15 +175,22 @@ __global__ __launch_bounds__(R2 *R3) void k_row2(cpx<R> *__restrict__ Z, int log
   for (int n1 = 0; n1 < R1; ++n1) row[t + RS::T * n1] = v[n1];
 }
 
+template <typename R, int R1, int R2, int R3>
+__global__ __launch_bounds__(R2 *R3) void k_row2(cpx<R> *__restrict__ Z, int logL, int log2,
+                                                 const cpx<R> *__restrict__ rt1, const cpx<R> *__restrict__ rt2,
+                                                 const R *__restrict__ chat, R beta, R gl) {
+  row_body<R, R1, R2, R3>(Z, logL, log2, rt1, rt2, chat, beta, gl, blockIdx.x, blockIdx.y);
+}
+
 // Single-pass product of one signal pair (L = L2).  With CORR the kernel also
 // forms C = U^T [x1 x2] (per-lane partial sums, wavefront reductions, a
 // fixed-order sum over wavefronts), scales by d, and adds U (d C) to the
 // outputs: the whole fast operator of Corollaries 2-4 in one launch.
 template <typename R, int R1, int R2, int R3, bool CORR>
-__global__ __launch_bounds__(R2 *R3) void k_single2(const R *__restrict__ x, int64_t ldx, R *__restrict__ y,
-                                                    int64_t ldy, int N, int b, const cpx<R> *__restrict__ rt1,
-                                                    const cpx<R> *__restrict__ rt2, const R *__restrict__ chat,
-                                                    R beta, R gl, Corr<R> corr) {
+__device__ __forceinline__ void single_body(const R *__restrict__ x, int64_t ldx, R *__restrict__ y, int64_t ldy,
+                                            int N, int b, const cpx<R> *__restrict__ rt1,
+                                            const cpx<R> *__restrict__ rt2, const R *__restrict__ chat, R beta, R gl,
+                                            const Corr<R> &corr, int p) {
   using RS = RowShape<R1, R2, R3>;
   constexpr int T = RS::T;
   constexpr int NW = T / 64;
@@ -193,7 +199,6 @@ __global__ __launch_bounds__(R2 *R3) void k_single2(const R *__restrict__ x, int
   __shared__ R red[CORR ? NW * kMaxRankSingle * 2 : 2];
   __shared__ R dC[CORR ? 2 * kMaxRankSingle : 2];
   const int t = threadIdx.x;
-  const int p = blockIdx.x;
   const int s0 = 2 * p, s1 = 2 * p + 1;
   const bool has1 = s1 < b;
   const R *x0 = x + (int64_t)s0 * ldx;
@@ -275,15 +280,23 @@ __global__ __launch_bounds__(R2 *R3) void k_single2(const R *__restrict__ x, int
   }
 }
 
+template <typename R, int R1, int R2, int R3, bool CORR>
+__global__ __launch_bounds__(R2 *R3) void k_single2(const R *__restrict__ x, int64_t ldx, R *__restrict__ y,
+                                                    int64_t ldy, int N, int b, const cpx<R> *__restrict__ rt1,
+                                                    const cpx<R> *__restrict__ rt2, const R *__restrict__ chat,
+                                                    R beta, R gl, Corr<R> corr) {
+  single_body<R, R1, R2, R3, CORR>(x, ldx, y, ldy, N, b, rt1, rt2, chat, beta, gl, corr, blockIdx.x);
+}
+
 // Pass A: lane = column n2 of pair pl; length-L1 DFT of z[n2 + L2 n1] =
 // x1 + i x2 (zero for n >= N) in registers, times W_L^{n2 k1}, stored at
 // Z[k1][n2].
 template <typename R, int L1>
-__global__ __launch_bounds__(256) void k_colfwd2(const R *__restrict__ x, int64_t ldx, int N, int b, int pair0,
-                                                 int logL, int log2, const cpx<R> *__restrict__ tcol,
-                                                 cpx<R> *__restrict__ Z) {
-  const int n2 = blockIdx.x * 256 + threadIdx.x;
-  const int pl = blockIdx.y, p = pair0 + pl;
+__device__ __forceinline__ void colfwd_body(const R *__restrict__ x, int64_t ldx, int N, int b, int pair0, int logL,
+                                            int log2, const cpx<R> *__restrict__ tcol, cpx<R> *__restrict__ Z,
+                                            int bx, int pl) {
+  const int n2 = bx * 256 + threadIdx.x;
+  const int p = pair0 + pl;
   const int s0 = 2 * p, s1 = 2 * p + 1;
   const bool has1 = s1 < b;
   const R *x0 = x + (int64_t)s0 * ldx;
@@ -304,6 +317,13 @@ __global__ __launch_bounds__(256) void k_colfwd2(const R *__restrict__ x, int64_
   Zp[0] = a[0];
 #pragma unroll
   for (int k1 = 1; k1 < L1; ++k1) Zp[(int64_t)k1 << log2] = cmul(a[k1], tcol[(k1 << log2) + n2]);
+}
+
+template <typename R, int L1>
+__global__ __launch_bounds__(256) void k_colfwd2(const R *__restrict__ x, int64_t ldx, int N, int b, int pair0,
+                                                 int logL, int log2, const cpx<R> *__restrict__ tcol,
+                                                 cpx<R> *__restrict__ Z) {
+  colfwd_body<R, L1>(x, ldx, N, b, pair0, logL, log2, tcol, Z, blockIdx.x, blockIdx.y);
 }
 
 // Pass C: lane = column n2 of pair pl; Z[k1][n2] times W_L^{-n2 k1}, inverse
@@ -351,11 +371,11 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 template <int L1, int MODE, int CW, int PPL>
-__global__ __launch_bounds__(64 * CW) void k_colinv_corr(const cpx<float> *__restrict__ Z, int N, int b, int pair0,
-                                                         int np, int logL, int log2,
-                                                         const cpx<float> *__restrict__ tcol, float *__restrict__ y,
-                                                         int64_t ldy, const float *__restrict__ U, int64_t ldu,
-                                                         int r, int rp, const float *__restrict__ dC) {
+__device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ Z, int N, int b, int pair0, int np,
+                                                 int logL, int log2, const cpx<float> *__restrict__ tcol,
+                                                 float *__restrict__ y, int64_t ldy, const float *__restrict__ U,
+                                                 int64_t ldu, int r, int rp, const float *__restrict__ dC, int cb,
+                                                 int by) {
   constexpr int ROWS = L1 > 1 ? L1 / 2 : 1;
   constexpr int NT = 64 * CW;
   static_assert(PPL == 1 || PPL == 2, "pairs per lane");
@@ -363,15 +383,10 @@ __global__ __launch_bounds__(64 * CW) void k_colinv_corr(const cpx<float> *__res
   // with rows of rp + 8 elements, so that a lane's eight consecutive j are
   // one 16-byte read and the sixteen columns fall on distinct banks.
   extern __shared__ float Ut[];
-  // Workgroups are dealt to the eight XCDs round-robin by linear id; give
-  // each XCD a contiguous run of column blocks, so the two 64-byte halves of
-  // a 128-byte line of y (and of U) are handled within one L2.
-  const int gx = gridDim.x;
-  const int cb = (gx & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (gx >> 3) + (int)(blockIdx.x >> 3);
   const int c0 = cb * 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, blk = lane >> 4;
-  const int pw = (blockIdx.y * CW + wave) * 4 * PPL;  // first pair of the wavefront, within the slice
+  const int pw = (by * CW + wave) * 4 * PPL;  // first pair of the wavefront, within the slice
   const int n2 = c0 + col;
   // The wavefront's Z loads go out first, so their latency overlaps the
   // staging of U below.
@@ -505,6 +520,76 @@ __global__ __launch_bounds__(64 * CW) void k_colinv_corr(const cpx<float> *__res
   }
 }
 
+template <int L1, int MODE, int CW, int PPL>
+__global__ __launch_bounds__(64 * CW) void k_colinv_corr(const cpx<float> *__restrict__ Z, int N, int b, int pair0,
+                                                         int np, int logL, int log2,
+                                                         const cpx<float> *__restrict__ tcol, float *__restrict__ y,
+                                                         int64_t ldy, const float *__restrict__ U, int64_t ldu,
+                                                         int r, int rp, const float *__restrict__ dC) {
+  // Workgroups are dealt to the eight XCDs round-robin by linear id; give
+  // each XCD a contiguous run of column blocks, so the two 64-byte halves of
+  // a 128-byte line of y (and of U) are handled within one L2.
+  const int gx = gridDim.x;
+  const int cb = (gx & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (gx >> 3) + (int)(blockIdx.x >> 3);
+  colinv_corr_body<L1, MODE, CW, PPL>(Z, N, b, pair0, np, logL, log2, tcol, y, ldy, U, ldu, r, rp, dC, cb,
+                                      blockIdx.y);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped launches: workgroup -> (plan, local workgroup) by binary search over
+// the span's start offsets, then the same bodies as the single-plan kernels.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int group_slot(const int *__restrict__ start, int m, int bid) {
+  int lo = 0, hi = m;  // start[lo] <= bid < start[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= bid) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int R1, int R2, int R3>
+__global__ __launch_bounds__(R2 *R3) void k_single2_group(const GroupPlan *__restrict__ gp,
+                                                          const int *__restrict__ idx,
+                                                          const int *__restrict__ start, int m) {
+  const int q = group_slot(start, m, blockIdx.x);
+  const GroupPlan &P = gp[idx[q]];
+  single_body<float, R1, R2, R3, true>(P.x, P.ldx, P.y, P.ldy, P.N, P.b, P.rt1, P.rt2, P.chat, P.beta, P.gl, P.corr,
+                                       (int)blockIdx.x - start[q]);
+}
+
+template <int L1>
+__global__ __launch_bounds__(256) void k_colfwd2_group(const GroupPlan *__restrict__ gp, const int *__restrict__ idx,
+                                                       const int *__restrict__ start, int m) {
+  const int q = group_slot(start, m, blockIdx.x);
+  const GroupPlan &P = gp[idx[q]];
+  const int w = (int)blockIdx.x - start[q], sh = P.log2 - 8;  // 2^sh column blocks of 256
+  colfwd_body<float, L1>(P.x, P.ldx, P.N, P.b, 0, P.logL, P.log2, P.tcol, P.Z, w & ((1 << sh) - 1), w >> sh);
+}
+
+template <int R1, int R2, int R3>
+__global__ __launch_bounds__(R2 *R3) void k_row2_group(const GroupPlan *__restrict__ gp, const int *__restrict__ idx,
+                                                       const int *__restrict__ start, int m) {
+  const int q = group_slot(start, m, blockIdx.x);
+  const GroupPlan &P = gp[idx[q]];
+  const int w = (int)blockIdx.x - start[q];
+  row_body<float, R1, R2, R3>(P.Z, P.logL, P.log2, P.rt1, P.rt2, P.chat, P.beta, P.gl, w & ((1 << P.log1) - 1),
+                              w >> P.log1);
+}
+
+template <int L1, int MODE, int CW, int PPL>
+__global__ __launch_bounds__(64 * CW) void k_colinv_corr_group(const GroupPlan *__restrict__ gp,
+                                                               const int *__restrict__ idx,
+                                                               const int *__restrict__ start, int m) {
+  const int q = group_slot(start, m, blockIdx.x);
+  const GroupPlan &P = gp[idx[q]];
+  const int w = (int)blockIdx.x - start[q], sh = P.log2 - 4;  // 2^sh column blocks of 16
+  colinv_corr_body<L1, MODE, CW, PPL>(P.Z, P.N, P.b, 0, P.np, P.logL, P.log2, P.tcol, P.y, P.ldy, P.corr.U,
+                                      P.corr.ldu, P.corr.r, P.rp, P.corr.dC, w & ((1 << sh) - 1), w >> sh);
+}
+
 // Row twiddle tables: rt1[k1 T + t] = W_L2^{t k1}, rt2[k2 R3 + m'] = W_T^{m' k2}.
 template <typename R>
 __global__ void k_row_twiddles(cpx<R> *__restrict__ rt1, cpx<R> *__restrict__ rt2, int R1, int R2, int R3) {
@@ -610,6 +695,9 @@ static bool dispatch_cols(bool fwd, dim3 grid, hipStream_t st, const R *x, int64
 struct CicShape {
   int ppl = 1, cw = 8;
 };
+
+// the grouped launches use the default shape
+constexpr int kGroupCicPPL = 1, kGroupCicCW = 8;
 
 static CicShape cic_shape() {
   static const CicShape sh = [] {
@@ -739,6 +827,74 @@ hipError_t conv_apply_v2(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, 
     }
     if (!dispatch_cols<R>(false, gcol, st, x, ldx, y, ldy, (int)N, (int)b, (int)p0, g, tb, Z))
       return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---- grouped launch helpers ----
+
+int64_t group_blocks_single(const GroupPlan &P) { return P.np; }
+int64_t group_blocks_colfwd(const GroupPlan &P) { return (int64_t)P.np << (P.log2 - 8); }
+int64_t group_blocks_row(const GroupPlan &P) { return (int64_t)P.np << P.log1; }
+int64_t group_blocks_colinv(const GroupPlan &P) {
+  constexpr int PW = 4 * kGroupCicPPL * kGroupCicCW;
+  return ((int64_t)(P.np + PW - 1) / PW) << (P.log2 - 4);
+}
+
+hipError_t group_single(int log2, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
+  if (sp.m == 0) return hipSuccess;
+  const dim3 grid((unsigned)sp.blocks);
+  bool ok = false;
+#define SLP_GSINGLE(A, B, C)                                                                                  \
+  if (!ok && A * B * C == (1 << log2)) {                                                                      \
+    SLP_LAUNCH("single_group", (k_single2_group<A, B, C>), grid, dim3(B * C), 0, st, gp, sp.idx, sp.start,   \
+               sp.m);                                                                                         \
+    ok = true;                                                                                                \
+  }
+  SLP_ROW_SHAPES(SLP_GSINGLE)
+#undef SLP_GSINGLE
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
+}
+
+hipError_t group_colfwd(int log1, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
+  if (sp.m == 0) return hipSuccess;
+  const dim3 grid((unsigned)sp.blocks);
+  switch (log1) {
+#define SLP_GCF(LG, L1) \
+  case LG: SLP_LAUNCH("col_fwd_group", k_colfwd2_group<L1>, grid, dim3(256), 0, st, gp, sp.idx, sp.start, sp.m); break;
+    SLP_GCF(1, 2) SLP_GCF(2, 4) SLP_GCF(3, 8) SLP_GCF(4, 16) SLP_GCF(5, 32)
+#undef SLP_GCF
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t group_row(int log2, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
+  if (sp.m == 0) return hipSuccess;
+  if (log2 != 13) return hipErrorInvalidValue;
+  SLP_LAUNCH("row_conv_group", (k_row2_group<32, 16, 16>), dim3((unsigned)sp.blocks), dim3(256), 0, st, gp, sp.idx,
+             sp.start, sp.m);
+  return hipGetLastError();
+}
+
+hipError_t group_colinv_corr(int log1, int mode, size_t lds, const GroupPlan *gp, const GroupSpan &sp,
+                             hipStream_t st) {
+  if (sp.m == 0) return hipSuccess;
+  const dim3 grid((unsigned)sp.blocks), block(64 * kGroupCicCW);
+  constexpr int CW = kGroupCicCW, PPL = kGroupCicPPL;
+  switch (log1 * 2 + (mode ? 1 : 0)) {
+#define SLP_GCI(LG, L1)                                                                                            \
+  case 2 * LG:                                                                                                    \
+    SLP_LAUNCH("col_inv_corr_group", (k_colinv_corr_group<L1, 0, CW, PPL>), grid, block, lds, st, gp, sp.idx,   \
+               sp.start, sp.m);                                                                                   \
+    break;                                                                                                        \
+  case 2 * LG + 1:                                                                                                \
+    SLP_LAUNCH("col_inv_corr_bf16x3_group", (k_colinv_corr_group<L1, 1, CW, PPL>), grid, block, lds, st, gp,    \
+               sp.idx, sp.start, sp.m);                                                                           \
+    break;
+    SLP_GCI(1, 2) SLP_GCI(2, 4) SLP_GCI(3, 8) SLP_GCI(4, 16) SLP_GCI(5, 32)
+#undef SLP_GCI
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

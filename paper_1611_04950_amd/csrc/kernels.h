@@ -16,10 +16,31 @@ hipError_t build_row_tables(const FftGeom &g, cpx<R> *rt1, cpx<R> *rt2, hipStrea
 template <typename R>
 hipError_t build_col_table(const FftGeom &g, cpx<R> *tc, hipStream_t st);
 
+// U columns the fused inverse column pass stages (r padded to its matrix step)
+int colinv_corr_rp(int r, int mode);
 // LDS bytes of the fused inverse column pass (0 when not applicable).
 size_t colinv_corr_lds(int log1, int r, int mode);
 // whether the inverse column pass can carry the correction update (L1 <= 32, U tile <= 64 KB)
 bool colinv_corr_ok(int log1, int r, int mode);
+
+// ---- grouped launches over many plans (fft2.hip, corr_mfma.hip) ----
+// Workgroups each plan contributes to a grouped launch.
+int64_t group_blocks_single(const GroupPlan &P);
+int64_t group_blocks_colfwd(const GroupPlan &P);
+int64_t group_blocks_row(const GroupPlan &P);
+int64_t group_blocks_colinv(const GroupPlan &P);
+int64_t group_blocks_partial(const GroupPlan &P);
+int64_t group_blocks_reduce(const GroupPlan &P);
+// single-pass product with the FP32 correction, all plans of row length 2^log2
+hipError_t group_single(int log2, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
+// three-pass passes; all plans of the span share L1 = 2^log1 (columns) or L2 = 2^log2 (rows)
+hipError_t group_colfwd(int log1, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
+hipError_t group_row(int log2, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
+hipError_t group_colinv_corr(int log1, int mode, size_t lds, const GroupPlan *gp, const GroupSpan &sp,
+                             hipStream_t st);
+// C = U^T x partials and dC = d (.) C for every plan of the span
+hipError_t group_corr_partial(int mode, bool vec, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
+hipError_t group_corr_reduce(const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
 
 template <typename R>
 hipError_t conv_apply_v2(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, int64_t b, const FftGeom &g,
