@@ -172,7 +172,15 @@ struct slepian_group_s {
     int m = 0;
     int64_t blocks = 0;
   };
-  Span single[14], partial, reduce, colfwd[6], row, colinv[6];
+  // single_corr: single pass with the correction inside; single: without
+  // (the matrix-core partial / sum / apply launches carry it); colinv_corr /
+  // colinv: inverse column pass with / without the fused update.
+  // Alternatives chosen by timing at the first call (autotuning):
+  // partial[v]: 32 (2 - v) signals per wavefront; colinv_corr[l1][v]: 8 >> v
+  // wavefronts per workgroup.
+  Span single_corr[14], single[14], partial[2], reduce, colfwd[6], row, colinv_corr[6][2], colinv[6], apply;
+  int partial_var = 0, colinv_var[6] = {0, 0, 0, 0, 0, 0};
+  bool tuned = false;
   size_t colinv_lds[6] = {0, 0, 0, 0, 0, 0};
   std::vector<int> grouped, other;  // plan indices
   void *ws = nullptr;               // grouped workspace (Z, partials, dC per plan)
@@ -182,7 +190,7 @@ struct slepian_group_s {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int graph_vec = -1;
+  int graph_vec = -1;  // alignment class (bit 0: all x, bit 1: all y) the graph was captured for
   std::vector<const float *> lx;
   std::vector<float *> ly;
   ~slepian_group_s() {
@@ -207,8 +215,13 @@ typedef slepian_plan_s Plan;
 // Workspace layouts (shared by the size query and the calls)
 // ---------------------------------------------------------------------------
 
-bool fused_single(const Plan *P, const OpSet &op, int prec) {
-  return P->g32.single() && op.r <= kMaxRankSingle && prec == SLEPIAN_FP32;
+// The single-pass kernel with the correction inside reads U once per signal
+// pair; beyond a few pairs the matrix-core kernels, which read it once per 64
+// signals, win.
+constexpr int64_t kFusedSingleMaxBatch = 8;
+
+bool fused_single(const Plan *P, const OpSet &op, int prec, int64_t b) {
+  return P->g32.single() && op.r <= kMaxRankSingle && prec == SLEPIAN_FP32 && b <= kFusedSingleMaxBatch;
 }
 
 struct ProjWs {
@@ -219,7 +232,7 @@ struct ProjWs {
 
 ProjWs carve_project(const Plan *P, const OpSet &op, int64_t b, Carver &cv, int prec = SLEPIAN_FP32) {
   ProjWs w;
-  if (fused_single(P, op, prec)) return w;
+  if (fused_single(P, op, prec, b)) return w;
   const int64_t pairs = (b + 1) / 2;
   w.slice = (int64_t)conv_workspace_pairs(P->g32, pairs, sizeof(cpx<float>), slice_budget());
   if (!P->g32.single()) w.Z = cv.take<cpx<float>>((size_t)w.slice * (size_t)P->L);
@@ -323,7 +336,7 @@ void run_fast_op(const Plan *P, const OpSet &op, float beta, float gamma, const 
                  int64_t ldy, int64_t b, const ProjWs &w, hipStream_t st, int prec = SLEPIAN_FP32) {
   const int64_t N = P->N;
   const float *U = P->U32 + op.off * P->ldu;
-  if (fused_single(P, op, prec)) {
+  if (fused_single(P, op, prec, b)) {
     Corr<float> c;
     c.U = U;
     c.ldu = P->ldu;
@@ -1114,13 +1127,10 @@ int slepian_plan_load(const char *path, int device, slepian_plan_t *out) {
 namespace {
 
 // Plans whose three passes the grouped kernels cover: register-stage rows of
-// 8192 points, at most 32 columns, a correction that rides on the inverse
-// column pass.
-bool group_three_pass(const Plan *P, int prec) {
-  const int umode = prec == SLEPIAN_MIXED ? 1 : 0;
+// 8192 points and at most 32 columns.
+bool group_three_pass(const Plan *P) {
   const FftGeom &g = P->g32;
-  return g.v2 && !g.single() && g.log2 == 13 && g.log1 >= 1 && g.log1 <= 5 && P->proj.r > 0 &&
-         colinv_corr_ok(g.log1, (int)P->proj.r, umode);
+  return g.v2 && !g.single() && g.log2 == 13 && g.log1 >= 1 && g.log1 <= 5;
 }
 
 GroupSpan span_of(const slepian_group_s *G, const slepian_group_s::Span &sp) {
@@ -1134,17 +1144,79 @@ GroupSpan span_of(const slepian_group_s *G, const slepian_group_s::Span &sp) {
   return g;
 }
 
-// The grouped launches: single-pass plans on s2 (independent of the rest),
-// the three-pass chain on s1.
-void launch_grouped(const slepian_group_s *G, hipStream_t s1, hipStream_t s2, bool vec) {
+void group_partial(const slepian_group_s *G, int var, bool vec, hipStream_t st) {
   const int umode = G->prec == SLEPIAN_MIXED ? 1 : 0;
-  for (int l2 = 9; l2 <= 13; ++l2) HIPCHK(group_single(l2, G->gp_dev, span_of(G, G->single[l2]), s2));
-  HIPCHK(group_corr_partial(umode, vec, G->gp_dev, span_of(G, G->partial), s1));
+  HIPCHK(group_corr_partial(umode, 2 - var, vec, G->gp_dev, span_of(G, G->partial[var]), st));
+}
+
+void group_colinv_fused(const slepian_group_s *G, int l1, int var, hipStream_t st) {
+  const int umode = G->prec == SLEPIAN_MIXED ? 1 : 0;
+  HIPCHK(group_colinv_corr(l1, umode, 8 >> var, G->colinv_lds[l1], G->gp_dev, span_of(G, G->colinv_corr[l1][var]),
+                           st));
+}
+
+// The grouped launches, in the order of the single-plan path: plans whose
+// single-pass kernel carries the correction on s2 (independent of the rest),
+// everything else on s1.  vec: bit 0 all x, bit 1 all y 16-byte aligned rows.
+void launch_grouped(const slepian_group_s *G, hipStream_t s1, hipStream_t s2, int vec) {
+  for (int l2 = 9; l2 <= 13; ++l2) HIPCHK(group_single(l2, true, G->gp_dev, span_of(G, G->single_corr[l2]), s2));
+  group_partial(G, G->partial_var, vec & 1, s1);
   HIPCHK(group_corr_reduce(G->gp_dev, span_of(G, G->reduce), s1));
+  for (int l2 = 9; l2 <= 13; ++l2) HIPCHK(group_single(l2, false, G->gp_dev, span_of(G, G->single[l2]), s1));
   for (int l1 = 1; l1 <= 5; ++l1) HIPCHK(group_colfwd(l1, G->gp_dev, span_of(G, G->colfwd[l1]), s1));
   HIPCHK(group_row(13, G->gp_dev, span_of(G, G->row), s1));
-  for (int l1 = 1; l1 <= 5; ++l1)
-    HIPCHK(group_colinv_corr(l1, umode, G->colinv_lds[l1], G->gp_dev, span_of(G, G->colinv[l1]), s1));
+  for (int l1 = 1; l1 <= 5; ++l1) {
+    group_colinv_fused(G, l1, G->colinv_var[l1], s1);
+    HIPCHK(group_colinv(l1, G->gp_dev, span_of(G, G->colinv[l1]), s1));
+  }
+  HIPCHK(group_corr_apply((vec & 2) != 0, G->gp_dev, span_of(G, G->apply), s1));
+}
+
+// Autotuning: run the group once (so the intermediates hold this call's
+// data), then time each launch that has alternatives, best of two runs per
+// alternative, and keep the faster.  The alternatives differ only in how the
+// work is cut into workgroups, so every run writes the same results.
+void tune_group(slepian_group_s *G, hipStream_t st, int vec) {
+  launch_grouped(G, st, st, vec);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    throw Fail{SLEPIAN_EHIP};
+  }
+  auto timed = [&](auto &&fn) {
+    float best = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      HIPCHK(hipEventRecord(e0, st));
+      fn();
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      best = std::min(best, ms);
+    }
+    return best;
+  };
+  try {
+    if (G->partial[0].m) {
+      const float t0 = timed([&] { group_partial(G, 0, vec & 1, st); });
+      const float t1 = timed([&] { group_partial(G, 1, vec & 1, st); });
+      G->partial_var = t1 < t0 ? 1 : 0;
+    }
+    for (int l1 = 1; l1 <= 5; ++l1) {
+      if (!G->colinv_corr[l1][0].m) continue;
+      const float t0 = timed([&] { group_colinv_fused(G, l1, 0, st); });
+      const float t1 = timed([&] { group_colinv_fused(G, l1, 1, st); });
+      G->colinv_var[l1] = t1 < t0 ? 1 : 0;
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  G->tuned = true;
 }
 
 }  // namespace
@@ -1178,21 +1250,28 @@ int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batc
         return o;
       };
       std::vector<size_t> zoff(n, 0), poff(n, 0), doff(n, 0);
+      std::vector<char> fused(n, 0);  // single pass with the correction inside
       for (int i = 0; i < n; ++i) {
         const Plan *P = plans[i];
         const int64_t b = batch[i];
         if (b == 0) continue;
-        if (fused_single(P, P->proj, G->prec)) {
+        const int r = (int)P->proj.r;
+        const bool single = P->g32.single() && P->g32.v2;  // register-stage single pass
+        if (single && fused_single(P, P->proj, G->prec, b)) {
           G->grouped.push_back(i);
-        } else if (group_three_pass(P, G->prec)) {
-          G->grouped.push_back(i);
-          const int r = (int)P->proj.r;
-          zoff[i] = reserve((size_t)((b + 1) / 2) * (size_t)P->L * sizeof(cpx<float>));
-          poff[i] = reserve((size_t)corr_nchunks(P->N, b, r) * corr_rpad(r) * b * sizeof(float));
-          doff[i] = reserve((size_t)corr_rpad(r) * b * sizeof(float));
-        } else {
+          fused[i] = 1;
+          continue;
+        }
+        if (!single && !group_three_pass(P)) {
           G->other.push_back(i);
           G->ws_other_bytes = std::max(G->ws_other_bytes, op_workspace(P, SLEPIAN_OP_PROJECT, b));
+          continue;
+        }
+        G->grouped.push_back(i);
+        if (!single) zoff[i] = reserve((size_t)((b + 1) / 2) * (size_t)P->L * sizeof(cpx<float>));
+        if (r > 0) {
+          poff[i] = reserve((size_t)corr_nchunks(P->N, b, r) * corr_rpad(r) * b * sizeof(float));
+          doff[i] = reserve((size_t)corr_rpad(r) * b * sizeof(float));
         }
       }
       if (wsz) G->ws = dalloc<char>(wsz + 256);
@@ -1216,20 +1295,21 @@ int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batc
         g.corr.ldu = P->ldu;
         g.corr.r = (int)P->proj.r;
         g.corr.d = P->proj.d32;
-        if (!P->g32.single()) {
+        if (!fused[i]) {
           const int r = (int)P->proj.r;
           g.corr.mode = umode;
           g.rp = colinv_corr_rp(r, umode);
           g.rpad = corr_rpad(r);
           g.chunks = corr_nchunks(P->N, batch[i], r);
-          g.Z = reinterpret_cast<cpx<float> *>(ws + zoff[i]);
-          g.part = reinterpret_cast<float *>(ws + poff[i]);
-          g.corr.dC = reinterpret_cast<float *>(ws + doff[i]);
+          if (!P->g32.single()) g.Z = reinterpret_cast<cpx<float> *>(ws + zoff[i]);
+          if (r > 0) {
+            g.part = reinterpret_cast<float *>(ws + poff[i]);
+            g.corr.dC = reinterpret_cast<float *>(ws + doff[i]);
+          }
         }
       }
       // spans
-      auto add_span = [&](slepian_group_s::Span &sp, const std::vector<int> &ids,
-                          int64_t (*blocks)(const GroupPlan &)) {
+      auto add_span = [&](slepian_group_s::Span &sp, const std::vector<int> &ids, auto &&blocks) {
         std::vector<int> idx, start;
         int64_t tot = 0;
         for (int i : ids) {
@@ -1247,24 +1327,49 @@ int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batc
         G->span_host.insert(G->span_host.end(), idx.begin(), idx.end());
         G->span_host.insert(G->span_host.end(), start.begin(), start.end());
       };
-      std::vector<int> by_single[14], three, by_l1[6];
+      std::vector<int> by_single_corr[14], by_single[14], mfma, by_l1[6], by_l1_fused[6], by_l1_plain[6], apply;
       for (int i : G->grouped) {
         const Plan *P = plans[i];
+        const int r = (int)P->proj.r;
+        if (fused[i]) {
+          by_single_corr[P->g32.log2].push_back(i);
+          continue;
+        }
+        if (r > 0) mfma.push_back(i);
         if (P->g32.single()) {
           by_single[P->g32.log2].push_back(i);
+          if (r > 0) apply.push_back(i);
+          continue;
+        }
+        by_l1[P->g32.log1].push_back(i);
+        // the update rides on the inverse column pass exactly when the
+        // single-plan path fuses it there
+        if (r > 0 && colinv_corr_ok(P->g32.log1, r, umode)) {
+          by_l1_fused[P->g32.log1].push_back(i);
+          G->colinv_lds[P->g32.log1] = std::max(G->colinv_lds[P->g32.log1], colinv_corr_lds(P->g32.log1, r, umode));
         } else {
-          three.push_back(i);
-          by_l1[P->g32.log1].push_back(i);
-          G->colinv_lds[P->g32.log1] =
-              std::max(G->colinv_lds[P->g32.log1], colinv_corr_lds(P->g32.log1, (int)P->proj.r, umode));
+          by_l1_plain[P->g32.log1].push_back(i);
+          if (r > 0) apply.push_back(i);
         }
       }
-      for (int l2 = 9; l2 <= 13; ++l2) add_span(G->single[l2], by_single[l2], group_blocks_single);
-      add_span(G->partial, three, group_blocks_partial);
-      add_span(G->reduce, three, group_blocks_reduce);
+      std::vector<int> three;
+      for (int l1 = 1; l1 <= 5; ++l1) three.insert(three.end(), by_l1[l1].begin(), by_l1[l1].end());
+      for (int l2 = 9; l2 <= 13; ++l2) {
+        add_span(G->single_corr[l2], by_single_corr[l2], group_blocks_single);
+        add_span(G->single[l2], by_single[l2], group_blocks_single);
+      }
+      for (int v = 0; v < 2; ++v)
+        add_span(G->partial[v], mfma, [v](const GroupPlan &g) { return group_blocks_partial(g, 2 - v); });
+      add_span(G->reduce, mfma, group_blocks_reduce);
       for (int l1 = 1; l1 <= 5; ++l1) add_span(G->colfwd[l1], by_l1[l1], group_blocks_colfwd);
       add_span(G->row, three, group_blocks_row);
-      for (int l1 = 1; l1 <= 5; ++l1) add_span(G->colinv[l1], by_l1[l1], group_blocks_colinv);
+      for (int l1 = 1; l1 <= 5; ++l1) {
+        for (int v = 0; v < 2; ++v)
+          add_span(G->colinv_corr[l1][v], by_l1_fused[l1],
+                   [v](const GroupPlan &g) { return group_blocks_colinv(g, 8 >> v); });
+        add_span(G->colinv[l1], by_l1_plain[l1], group_blocks_colfwd);
+      }
+      add_span(G->apply, apply, group_blocks_apply);
       G->span_buf = dalloc<int>(G->span_host.size());
       HIPCHK(hipMemcpy(G->span_buf, G->span_host.data(), G->span_host.size() * sizeof(int), hipMemcpyHostToDevice));
       G->gp_dev = dalloc<GroupPlan>(n);
@@ -1292,7 +1397,7 @@ int slepian_group_project(slepian_group_t G, const float *const *x, float *const
     hipStream_t st = (hipStream_t)stream;
     bool same = G->lx.size() == (size_t)n;
     for (int i = 0; same && i < n; ++i) same = G->lx[i] == x[i] && G->ly[i] == y[i];
-    bool vec = true;
+    int vec = 3;
     if (!same) {
       for (int i : G->grouped) {
         G->gp[i].x = x[i];
@@ -1303,13 +1408,17 @@ int slepian_group_project(slepian_group_t G, const float *const *x, float *const
       G->lx.assign(x, x + n);
       G->ly.assign(y, y + n);
     }
-    for (int i : G->grouped) vec = vec && (reinterpret_cast<uintptr_t>(x[i]) & 15) == 0 && G->gp[i].ldx % 4 == 0;
+    for (int i : G->grouped) {
+      if ((reinterpret_cast<uintptr_t>(x[i]) & 15) != 0 || G->gp[i].ldx % 4 != 0) vec &= ~1;
+      if ((reinterpret_cast<uintptr_t>(y[i]) & 15) != 0 || G->gp[i].ldy % 4 != 0) vec &= ~2;
+    }
     if (!G->grouped.empty()) {
       if (trace_enabled()) {
         // per-kernel timing needs the launches themselves, not a graph
         launch_grouped(G, st, st, vec);
       } else {
-        if (!G->exec || G->graph_vec != (int)vec) {
+        if (!G->tuned) tune_group(G, st, vec);
+        if (!G->exec || G->graph_vec != vec) {
           if (G->exec) (void)hipGraphExecDestroy(G->exec);
           if (G->graph) (void)hipGraphDestroy(G->graph);
           G->exec = nullptr;
@@ -1329,7 +1438,7 @@ int slepian_group_project(slepian_group_t G, const float *const *x, float *const
           }
           HIPCHK(hipStreamEndCapture(G->cap, &G->graph));
           HIPCHK(hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0));
-          G->graph_vec = (int)vec;
+          G->graph_vec = vec;
         }
         HIPCHK(hipGraphLaunch(G->exec, st));
       }

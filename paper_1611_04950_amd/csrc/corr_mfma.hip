@@ -89,6 +89,33 @@ __device__ __forceinline__ void corr_partial_body(const float *__restrict__ X, i
         for (int e = 0; e < 8; ++e) xb[q][nb][e] = v ? xb[q][nb][e] : 0.f;
       }
     }
+  } else if (k_begin + KC <= N) {
+    // full chunk, rows not 16-byte aligned: unguarded dword loads from
+    // clamped rows, invalid lanes zeroed afterwards
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      const int kk = k_begin + 16 * q + 8 * kb;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ua[q][e] = Uj[kk + e];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int s = s_base + nb * 32 + i;
+        const float *xp = X + (int64_t)(s < b ? s : b - 1) * ldx + kk;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xb[q][nb][e] = xp[e];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ua[q][e] = jv ? ua[q][e] : 0.f;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const bool v = s_base + nb * 32 + i < b;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xb[q][nb][e] = v ? xb[q][nb][e] : 0.f;
+      }
+    }
   } else {
 #pragma unroll
     for (int q = 0; q < KS; ++q) {
@@ -201,15 +228,16 @@ __global__ __launch_bounds__(256) void k_corr_reduce2(const float *__restrict__ 
 // branch-free float4 accesses of Y (clamped addresses, selects for lanes past
 // the last signal); the tile crossing N takes the checked path.
 template <int NB, int JP, bool VEC>
-__global__ __launch_bounds__(256) void k_corr_apply_mfma(float *__restrict__ Y, int64_t ldy, int N, int b,
-                                                         const float *__restrict__ U, int64_t ldu, int r,
-                                                         const float *__restrict__ dC) {
+__device__ __forceinline__ void corr_apply_body(float *__restrict__ Y, int64_t ldy, int N, int b,
+                                                const float *__restrict__ U, int64_t ldu, int r,
+                                                const float *__restrict__ dC, int bx, int by) {
   const int lane = threadIdx.x & 63;
   const int i = lane & 31, kb = lane >> 5;
-  const int n0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+  const int n0 = (bx * 4 + (threadIdx.x >> 6)) * 32;
   if (n0 >= N) return;  // whole wavefront
-  const int s_base = blockIdx.y * 32 * NB;
+  const int s_base = by * 32 * NB;
   const bool full = VEC && n0 + 32 <= N;
+  const bool whole = n0 + 32 <= N;  // tile inside N: no per-element guards
   f32x16 acc[NB];
   float *Ys[NB];
 #pragma unroll
@@ -228,6 +256,13 @@ __global__ __launch_bounds__(256) void k_corr_apply_mfma(float *__restrict__ Y, 
         acc[nb][4 * q + 2] = t.z;
         acc[nb][4 * q + 3] = t.w;
       }
+  } else if (whole) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[nb][4 * q + e] = Ys[nb][n0 + 8 * q + 4 * kb + e];
   } else {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
@@ -277,6 +312,11 @@ __global__ __launch_bounds__(256) void k_corr_apply_mfma(float *__restrict__ Y, 
       for (int q = 0; q < 4; ++q)
         *reinterpret_cast<float4 *>(Ys[nb] + n0 + 8 * q + 4 * kb) =
             make_float4(acc[nb][4 * q + 0], acc[nb][4 * q + 1], acc[nb][4 * q + 2], acc[nb][4 * q + 3]);
+    } else if (whole) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Ys[nb][n0 + 8 * q + 4 * kb + e] = acc[nb][4 * q + e];
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -287,6 +327,13 @@ __global__ __launch_bounds__(256) void k_corr_apply_mfma(float *__restrict__ Y, 
         }
     }
   }
+}
+
+template <int NB, int JP, bool VEC>
+__global__ __launch_bounds__(256) void k_corr_apply_mfma(float *__restrict__ Y, int64_t ldy, int N, int b,
+                                                         const float *__restrict__ U, int64_t ldu, int r,
+                                                         const float *__restrict__ dC) {
+  corr_apply_body<NB, JP, VEC>(Y, ldy, N, b, U, ldu, r, dC, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -369,16 +416,16 @@ __device__ __forceinline__ int group_slot_c(const int *__restrict__ start, int m
   return lo;
 }
 
-template <int MODE, bool VEC>
+template <int MODE, int NB, bool VEC>
 __global__ __launch_bounds__(256) void k_corr_partial_group(const GroupPlan *__restrict__ gp,
                                                             const int *__restrict__ idx,
                                                             const int *__restrict__ start, int m) {
   const int q = group_slot_c(start, m, blockIdx.x);
   const GroupPlan &P = gp[idx[q]];
   const int w = (int)blockIdx.x - start[q];
-  const int gx = P.chunks, gy = (P.b + 32 * kPartNB - 1) / (32 * kPartNB);
-  corr_partial_body<MODE, kPartNB, kPartKS, VEC>(P.x, P.ldx, P.N, P.b, P.corr.U, P.corr.ldu, P.corr.r, P.part,
-                                                 P.rpad, w % gx, (w / gx) % gy, w / (gx * gy));
+  const int gx = P.chunks, gy = (P.b + 32 * NB - 1) / (32 * NB);
+  corr_partial_body<MODE, NB, kPartKS, VEC>(P.x, P.ldx, P.N, P.b, P.corr.U, P.corr.ldu, P.corr.r, P.part, P.rpad,
+                                            w % gx, (w / gx) % gy, w / (gx * gy));
 }
 
 __global__ __launch_bounds__(256) void k_corr_reduce_group(const GroupPlan *__restrict__ gp,
@@ -390,26 +437,56 @@ __global__ __launch_bounds__(256) void k_corr_reduce_group(const GroupPlan *__re
                    (int64_t)1, (int)blockIdx.x - start[q]);
 }
 
-int64_t group_blocks_partial(const GroupPlan &P) {
+int64_t group_blocks_partial(const GroupPlan &P, int nb) {
   if (P.corr.r == 0 || P.b == 0) return 0;
-  return (int64_t)P.chunks * ((P.b + 32 * kPartNB - 1) / (32 * kPartNB)) * ((P.corr.r + 31) / 32);
+  return (int64_t)P.chunks * ((P.b + 32 * nb - 1) / (32 * nb)) * ((P.corr.r + 31) / 32);
 }
 
 int64_t group_blocks_reduce(const GroupPlan &P) { return ((int64_t)P.corr.r * P.b + 15) / 16; }
 
-hipError_t group_corr_partial(int mode, bool vec, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_corr_apply_group(const GroupPlan *__restrict__ gp,
+                                                          const int *__restrict__ idx,
+                                                          const int *__restrict__ start, int m) {
+  const int q = group_slot_c(start, m, blockIdx.x);
+  const GroupPlan &P = gp[idx[q]];
+  const int w = (int)blockIdx.x - start[q];
+  const int gx = (P.N + 127) / 128;
+  corr_apply_body<kApplyNB, kApplyJP, VEC>(P.y, P.ldy, P.N, P.b, P.corr.U, P.corr.ldu, P.corr.r, P.corr.dC, w % gx,
+                                           w / gx);
+}
+
+int64_t group_blocks_apply(const GroupPlan &P) {
+  if (P.corr.r == 0 || P.b == 0) return 0;
+  return (int64_t)((P.N + 127) / 128) * ((P.b + 32 * kApplyNB - 1) / (32 * kApplyNB));
+}
+
+hipError_t group_corr_apply(bool vec, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
   if (sp.m == 0 || sp.blocks == 0) return hipSuccess;
   const dim3 grid((unsigned)sp.blocks);
+  if (vec) SLP_LAUNCH("corr_apply_group", k_corr_apply_group<true>, grid, dim3(256), 0, st, gp, sp.idx, sp.start, sp.m);
+  else SLP_LAUNCH("corr_apply_group", k_corr_apply_group<false>, grid, dim3(256), 0, st, gp, sp.idx, sp.start, sp.m);
+  return hipGetLastError();
+}
+
+template <int MODE, int NB>
+static void launch_partial_group(const char *name, bool vec, const GroupPlan *gp, const GroupSpan &sp,
+                                 hipStream_t st) {
+  const dim3 grid((unsigned)sp.blocks);
+  if (vec) SLP_LAUNCH(name, (k_corr_partial_group<MODE, NB, true>), grid, dim3(256), 0, st, gp, sp.idx, sp.start, sp.m);
+  else SLP_LAUNCH(name, (k_corr_partial_group<MODE, NB, false>), grid, dim3(256), 0, st, gp, sp.idx, sp.start, sp.m);
+}
+
+hipError_t group_corr_partial(int mode, int nb, bool vec, const GroupPlan *gp, const GroupSpan &sp,
+                              hipStream_t st) {
+  if (sp.m == 0 || sp.blocks == 0) return hipSuccess;
+  if (nb != 1 && nb != 2) return hipErrorInvalidValue;
   if (mode == kModeF32) {
-    if (vec) SLP_LAUNCH("corr_partial_group", (k_corr_partial_group<kModeF32, true>), grid, dim3(256), 0, st, gp,
-                        sp.idx, sp.start, sp.m);
-    else SLP_LAUNCH("corr_partial_group", (k_corr_partial_group<kModeF32, false>), grid, dim3(256), 0, st, gp,
-                    sp.idx, sp.start, sp.m);
+    if (nb == 2) launch_partial_group<kModeF32, 2>("corr_partial_group", vec, gp, sp, st);
+    else launch_partial_group<kModeF32, 1>("corr_partial_group", vec, gp, sp, st);
   } else if (mode == kModeBF16x3) {
-    if (vec) SLP_LAUNCH("corr_partial_bf16x3_group", (k_corr_partial_group<kModeBF16x3, true>), grid, dim3(256), 0,
-                        st, gp, sp.idx, sp.start, sp.m);
-    else SLP_LAUNCH("corr_partial_bf16x3_group", (k_corr_partial_group<kModeBF16x3, false>), grid, dim3(256), 0,
-                    st, gp, sp.idx, sp.start, sp.m);
+    if (nb == 2) launch_partial_group<kModeBF16x3, 2>("corr_partial_bf16x3_group", vec, gp, sp, st);
+    else launch_partial_group<kModeBF16x3, 1>("corr_partial_bf16x3_group", vec, gp, sp, st);
   } else {
     return hipErrorInvalidValue;
   }

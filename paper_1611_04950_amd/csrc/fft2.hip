@@ -330,11 +330,11 @@ __global__ __launch_bounds__(256) void k_colfwd2(const R *__restrict__ x, int64_
 // length-L1 DFT in registers, y1 = Re and y2 = Im for n = n2 + L2 n1 < N
 // (only n1 < L1/2 can hold such n because L >= 2N).
 template <typename R, int L1>
-__global__ __launch_bounds__(256) void k_colinv2(const cpx<R> *__restrict__ Z, int N, int b, int pair0, int logL,
-                                                 int log2, const cpx<R> *__restrict__ tcol, R *__restrict__ y,
-                                                 int64_t ldy) {
-  const int n2 = blockIdx.x * 256 + threadIdx.x;
-  const int pl = blockIdx.y, p = pair0 + pl;
+__device__ __forceinline__ void colinv_body(const cpx<R> *__restrict__ Z, int N, int b, int pair0, int logL,
+                                            int log2, const cpx<R> *__restrict__ tcol, R *__restrict__ y,
+                                            int64_t ldy, int bx, int pl) {
+  const int n2 = bx * 256 + threadIdx.x;
+  const int p = pair0 + pl;
   const int s0 = 2 * p, s1 = 2 * p + 1;
   const bool has1 = s1 < b;
   const cpx<R> *Zp = Z + ((int64_t)pl << logL) + n2;
@@ -353,6 +353,13 @@ __global__ __launch_bounds__(256) void k_colinv2(const cpx<R> *__restrict__ Z, i
       if (has1) y1[n] = a[n1].y;
     }
   }
+}
+
+template <typename R, int L1>
+__global__ __launch_bounds__(256) void k_colinv2(const cpx<R> *__restrict__ Z, int N, int b, int pair0, int logL,
+                                                 int log2, const cpx<R> *__restrict__ tcol, R *__restrict__ y,
+                                                 int64_t ldy) {
+  colinv_body<R, L1>(Z, N, b, pair0, logL, log2, tcol, y, ldy, blockIdx.x, blockIdx.y);
 }
 
 // Pass C fused with the correction update y += U dC (Corollary 2's U1 U2^T x
@@ -550,14 +557,23 @@ __device__ __forceinline__ int group_slot(const int *__restrict__ start, int m, 
   return lo;
 }
 
-template <int R1, int R2, int R3>
+template <int R1, int R2, int R3, bool CORR>
 __global__ __launch_bounds__(R2 *R3) void k_single2_group(const GroupPlan *__restrict__ gp,
                                                           const int *__restrict__ idx,
                                                           const int *__restrict__ start, int m) {
   const int q = group_slot(start, m, blockIdx.x);
   const GroupPlan &P = gp[idx[q]];
-  single_body<float, R1, R2, R3, true>(P.x, P.ldx, P.y, P.ldy, P.N, P.b, P.rt1, P.rt2, P.chat, P.beta, P.gl, P.corr,
+  single_body<float, R1, R2, R3, CORR>(P.x, P.ldx, P.y, P.ldy, P.N, P.b, P.rt1, P.rt2, P.chat, P.beta, P.gl, P.corr,
                                        (int)blockIdx.x - start[q]);
+}
+
+template <int L1>
+__global__ __launch_bounds__(256) void k_colinv2_group(const GroupPlan *__restrict__ gp, const int *__restrict__ idx,
+                                                       const int *__restrict__ start, int m) {
+  const int q = group_slot(start, m, blockIdx.x);
+  const GroupPlan &P = gp[idx[q]];
+  const int w = (int)blockIdx.x - start[q], sh = P.log2 - 8;  // 2^sh column blocks of 256
+  colinv_body<float, L1>(P.Z, P.N, P.b, 0, P.logL, P.log2, P.tcol, P.y, P.ldy, w & ((1 << sh) - 1), w >> sh);
 }
 
 template <int L1>
@@ -696,8 +712,8 @@ struct CicShape {
   int ppl = 1, cw = 8;
 };
 
-// the grouped launches use the default shape
-constexpr int kGroupCicPPL = 1, kGroupCicCW = 8;
+// the grouped launches use one pair per lane and 4 or 8 wavefronts (tuned)
+constexpr int kGroupCicPPL = 1;
 
 static CicShape cic_shape() {
   static const CicShape sh = [] {
@@ -722,8 +738,10 @@ size_t colinv_corr_lds(int log1, int r, int mode) {
   return mode == 0 ? rows * rp * 16 * sizeof(float) : rows * 16 * (rp + 8) * 2 * sizeof(__bf16);
 }
 
+// L1 = 32 keeps 64 complex inputs per lane on top of the accumulators; there
+// the plain pass plus the separate matrix-core update is faster.
 bool colinv_corr_ok(int log1, int r, int mode) {
-  return log1 >= 1 && log1 <= 5 && colinv_corr_lds(log1, r, mode) <= (size_t)64 * 1024;
+  return log1 >= 1 && log1 <= 4 && colinv_corr_lds(log1, r, mode) <= (size_t)64 * 1024;
 }
 
 template <int L1, int MODE, int CW, int PPL>
@@ -756,8 +774,7 @@ static bool launch_cic_mode(hipStream_t st, const cpx<float> *Z, int N, int b, i
     case 2: launch_cic_shape<4, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
     case 3: launch_cic_shape<8, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
     case 4: launch_cic_shape<16, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 5: launch_cic_shape<32, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    default: return false;  // L1 = 64 holds too many registers; the caller does the update separately
+    default: return false;  // larger L1: the caller does the update separately
   }
 }
 
@@ -836,19 +853,23 @@ hipError_t conv_apply_v2(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, 
 int64_t group_blocks_single(const GroupPlan &P) { return P.np; }
 int64_t group_blocks_colfwd(const GroupPlan &P) { return (int64_t)P.np << (P.log2 - 8); }
 int64_t group_blocks_row(const GroupPlan &P) { return (int64_t)P.np << P.log1; }
-int64_t group_blocks_colinv(const GroupPlan &P) {
-  constexpr int PW = 4 * kGroupCicPPL * kGroupCicCW;
-  return ((int64_t)(P.np + PW - 1) / PW) << (P.log2 - 4);
+int64_t group_blocks_colinv(const GroupPlan &P, int cw) {
+  const int pw = 4 * kGroupCicPPL * cw;
+  return ((int64_t)(P.np + pw - 1) / pw) << (P.log2 - 4);
 }
 
-hipError_t group_single(int log2, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
+hipError_t group_single(int log2, bool corr, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
   if (sp.m == 0) return hipSuccess;
   const dim3 grid((unsigned)sp.blocks);
   bool ok = false;
 #define SLP_GSINGLE(A, B, C)                                                                                  \
   if (!ok && A * B * C == (1 << log2)) {                                                                      \
-    SLP_LAUNCH("single_group", (k_single2_group<A, B, C>), grid, dim3(B * C), 0, st, gp, sp.idx, sp.start,   \
-               sp.m);                                                                                         \
+    if (corr)                                                                                                 \
+      SLP_LAUNCH("single_corr_group", (k_single2_group<A, B, C, true>), grid, dim3(B * C), 0, st, gp, sp.idx, \
+                 sp.start, sp.m);                                                                             \
+    else                                                                                                      \
+      SLP_LAUNCH("single_group", (k_single2_group<A, B, C, false>), grid, dim3(B * C), 0, st, gp, sp.idx,     \
+                 sp.start, sp.m);                                                                             \
     ok = true;                                                                                                \
   }
   SLP_ROW_SHAPES(SLP_GSINGLE)
@@ -860,10 +881,29 @@ hipError_t group_colfwd(int log1, const GroupPlan *gp, const GroupSpan &sp, hipS
   if (sp.m == 0) return hipSuccess;
   const dim3 grid((unsigned)sp.blocks);
   switch (log1) {
-#define SLP_GCF(LG, L1) \
-  case LG: SLP_LAUNCH("col_fwd_group", k_colfwd2_group<L1>, grid, dim3(256), 0, st, gp, sp.idx, sp.start, sp.m); break;
+#define SLP_GCF(LG, L1)                                                                                        \
+  case LG:                                                                                                    \
+    SLP_LAUNCH("col_fwd_group_L1_" #L1, k_colfwd2_group<L1>, grid, dim3(256), 0, st, gp, sp.idx, sp.start,  \
+               sp.m);                                                                                         \
+    break;
     SLP_GCF(1, 2) SLP_GCF(2, 4) SLP_GCF(3, 8) SLP_GCF(4, 16) SLP_GCF(5, 32)
 #undef SLP_GCF
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t group_colinv(int log1, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
+  if (sp.m == 0) return hipSuccess;
+  const dim3 grid((unsigned)sp.blocks);
+  switch (log1) {
+#define SLP_GCV(LG, L1)                                                                                        \
+  case LG:                                                                                                    \
+    SLP_LAUNCH("col_inv_group_L1_" #L1, k_colinv2_group<L1>, grid, dim3(256), 0, st, gp, sp.idx, sp.start,  \
+               sp.m);                                                                                         \
+    break;
+    SLP_GCV(1, 2) SLP_GCV(2, 4) SLP_GCV(3, 8) SLP_GCV(4, 16) SLP_GCV(5, 32)
+#undef SLP_GCV
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -877,26 +917,34 @@ hipError_t group_row(int log2, const GroupPlan *gp, const GroupSpan &sp, hipStre
   return hipGetLastError();
 }
 
-hipError_t group_colinv_corr(int log1, int mode, size_t lds, const GroupPlan *gp, const GroupSpan &sp,
-                             hipStream_t st) {
-  if (sp.m == 0) return hipSuccess;
-  const dim3 grid((unsigned)sp.blocks), block(64 * kGroupCicCW);
-  constexpr int CW = kGroupCicCW, PPL = kGroupCicPPL;
+template <int CW>
+static hipError_t group_colinv_cw(int log1, int mode, size_t lds, const GroupPlan *gp, const GroupSpan &sp,
+                                  hipStream_t st) {
+  const dim3 grid((unsigned)sp.blocks), block(64 * CW);
+  constexpr int PPL = kGroupCicPPL;
   switch (log1 * 2 + (mode ? 1 : 0)) {
 #define SLP_GCI(LG, L1)                                                                                            \
   case 2 * LG:                                                                                                    \
-    SLP_LAUNCH("col_inv_corr_group", (k_colinv_corr_group<L1, 0, CW, PPL>), grid, block, lds, st, gp, sp.idx,   \
-               sp.start, sp.m);                                                                                   \
+    SLP_LAUNCH("col_inv_corr_group_L1_" #L1, (k_colinv_corr_group<L1, 0, CW, PPL>), grid, block, lds, st, gp,   \
+               sp.idx, sp.start, sp.m);                                                                           \
     break;                                                                                                        \
   case 2 * LG + 1:                                                                                                \
-    SLP_LAUNCH("col_inv_corr_bf16x3_group", (k_colinv_corr_group<L1, 1, CW, PPL>), grid, block, lds, st, gp,    \
-               sp.idx, sp.start, sp.m);                                                                           \
+    SLP_LAUNCH("col_inv_corr_bf16x3_group_L1_" #L1, (k_colinv_corr_group<L1, 1, CW, PPL>), grid, block, lds, st, \
+               gp, sp.idx, sp.start, sp.m);                                                                       \
     break;
-    SLP_GCI(1, 2) SLP_GCI(2, 4) SLP_GCI(3, 8) SLP_GCI(4, 16) SLP_GCI(5, 32)
+    SLP_GCI(1, 2) SLP_GCI(2, 4) SLP_GCI(3, 8) SLP_GCI(4, 16)
 #undef SLP_GCI
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t group_colinv_corr(int log1, int mode, int cw, size_t lds, const GroupPlan *gp, const GroupSpan &sp,
+                             hipStream_t st) {
+  if (sp.m == 0) return hipSuccess;
+  if (cw == 8) return group_colinv_cw<8>(log1, mode, lds, gp, sp, st);
+  if (cw == 4) return group_colinv_cw<4>(log1, mode, lds, gp, sp, st);
+  return hipErrorInvalidValue;
 }
 
 template hipError_t build_row_tables<float>(const FftGeom &, cpx<float> *, cpx<float> *, hipStream_t);

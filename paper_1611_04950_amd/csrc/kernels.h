@@ -28,18 +28,24 @@ bool colinv_corr_ok(int log1, int r, int mode);
 int64_t group_blocks_single(const GroupPlan &P);
 int64_t group_blocks_colfwd(const GroupPlan &P);
 int64_t group_blocks_row(const GroupPlan &P);
-int64_t group_blocks_colinv(const GroupPlan &P);
-int64_t group_blocks_partial(const GroupPlan &P);
+int64_t group_blocks_colinv(const GroupPlan &P, int cw);  // cw: wavefronts per workgroup (4 or 8)
+int64_t group_blocks_partial(const GroupPlan &P, int nb);  // nb: 32-signal blocks per wavefront (1 or 2)
 int64_t group_blocks_reduce(const GroupPlan &P);
-// single-pass product with the FP32 correction, all plans of row length 2^log2
-hipError_t group_single(int log2, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
+// single-pass product (with the fused FP32 correction when `corr`), all plans of row length 2^log2
+hipError_t group_single(int log2, bool corr, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
+// plain inverse column pass (the correction update follows separately)
+hipError_t group_colinv(int log1, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
+// y += U dC on the matrix cores for every plan of the span
+int64_t group_blocks_apply(const GroupPlan &P);
+hipError_t group_corr_apply(bool vec, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
 // three-pass passes; all plans of the span share L1 = 2^log1 (columns) or L2 = 2^log2 (rows)
 hipError_t group_colfwd(int log1, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
 hipError_t group_row(int log2, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
-hipError_t group_colinv_corr(int log1, int mode, size_t lds, const GroupPlan *gp, const GroupSpan &sp,
+hipError_t group_colinv_corr(int log1, int mode, int cw, size_t lds, const GroupPlan *gp, const GroupSpan &sp,
                              hipStream_t st);
 // C = U^T x partials and dC = d (.) C for every plan of the span
-hipError_t group_corr_partial(int mode, bool vec, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
+hipError_t group_corr_partial(int mode, int nb, bool vec, const GroupPlan *gp, const GroupSpan &sp,
+                              hipStream_t st);
 hipError_t group_corr_reduce(const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
 
 template <typename R>

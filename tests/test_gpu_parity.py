@@ -246,6 +246,29 @@ def test_group_matches_single_plans(plans):
             assert torch.equal(y, ref), rep
 
 
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_group_paths_match_single_plans(prec):
+    """Every grouped path: single pass with and without the in-kernel
+    correction, three passes with the update fused into the inverse column
+    pass (L1 <= 16) or applied separately (L1 = 32), odd and unaligned
+    lengths; the grouped call reproduces the single-plan calls bit for bit,
+    on two calls in a row with different buffers."""
+    pr = S.SLEPIAN_FP32 if prec == "fp32" else S.SLEPIAN_MIXED
+    specs = [(1024, 0.05, 1e-3, 20), (3001, 0.2, 1e-6, 33), (700, 0.3, 1e-6, 3), (20000, 0.11, 1e-6, 9),
+             (70001, 0.05, 1e-6, 5), (5000, 0.03, 1e-6, 64), (100, 0.1, 1e-3, 6)]
+    ps = [S.slepian_plan(N, W, e, precision=pr) for N, W, e, _ in specs]
+    G = S.slepian_group_create(ps, [b for *_, b in specs])
+    for rep in range(2):
+        xs = [synth.gaussian(N, b, 700 + 10 * rep + i, device="cuda") for i, (N, _, _, b) in enumerate(specs)]
+        ys = [torch.full_like(x, float("nan")) for x in xs]
+        S.slepian_group_project(G, xs, ys)
+        torch.cuda.synchronize()
+        for p, x, y in zip(ps, xs, ys):
+            ref = S.slepian_project(p, x, precision=pr)
+            torch.cuda.synchronize()
+            assert torch.equal(y, ref), (rep, p.info["N"])
+
+
 @pytest.mark.parametrize("N,W,eps,b", [(1024, 1 / 16, 1e-6, 8), (65536, 1 / 8, 1e-6, 6), (3000, 0.2, 1e-6, 70)])
 def test_project_precision_modes(plans, N, W, eps, b):
     """MIXED (BF16 hi/lo matrix-core correction) meets the FP32 gate of 1e-5;
