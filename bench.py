@@ -202,6 +202,97 @@ def bench_batching(args, dev):
             "kernels_traced_ms": {k: round(v["total_ms"], 4) for k, v in st.items()}}
 
 
+def _time_calls(fn, steps, warmup, dev):
+    import torch
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_precision(args, dev):
+    """N = 262144, W = 0.05, eps = 1e-4, 1024 signals of 64 tones at 20 dB:
+    the mixed-precision projection (BF16 hi/lo correction) and the FP32 one.
+    Parity of sampled signals with the oracle at this size is a GPU test."""
+    import torch
+
+    from paper_1611_04950_amd import slepian as S
+    from paper_1611_04950_amd import synth
+    N, W, eps, b, cfg = WORKLOADS["precision N=262144 W=0.05 eps=1e-4 b=1024"]
+    log("bench: precision workload")
+    t0 = time.perf_counter()
+    plan = S.slepian_plan(N, W, eps)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    x = synth.config_signals(cfg, N, b, W, device=dev)
+    y = torch.empty_like(x)
+    out = {"workload": "precision N=262144 W=0.05 eps=1e-4 b=1024", "plan_setup_s": round(setup, 3),
+           "r": plan.info["r"], "L": plan.info["L"]}
+    for name, p in (("mixed", S.SLEPIAN_MIXED), ("fp32", S.SLEPIAN_FP32), ("bf16_raw", S.SLEPIAN_BF16_RAW)):
+        ms = _time_calls(lambda: S.slepian_project(plan, x, y, precision=p), max(3, args.steps // 4), 2, dev)
+        out[name] = {"ms_per_call": round(ms, 4), "value": round(N * b / (ms * 1e-3) / 1e9, 3), "unit": "GSamples/s"}
+    log(f"bench: precision workload mixed {out['mixed']['value']} GSamples/s, fp32 {out['fp32']['value']}")
+    del x, y
+    return out
+
+
+def bench_lsq(args, dev):
+    """N = 2^20, W = 0.02, eps = 1e-6, 64 signals of 200 tones at 10 dB:
+    Tikhonov (alpha = 1e-3) solve refined to a 1e-10 FP64 normal-equation
+    residual.  The residual is the library's own FP64 check; the CPU
+    recomputation and the comparison with the oracle's solve are GPU tests."""
+    import torch
+
+    from paper_1611_04950_amd import slepian as S
+    from paper_1611_04950_amd import synth
+    N, W, eps, b, alpha = 1 << 20, 0.02, 1e-6, 64, 1e-3
+    log("bench: least-squares workload")
+    t0 = time.perf_counter()
+    plan = S.slepian_plan(N, W, eps, alpha=alpha)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    yv = synth.config_signals(5, N, b, W, device=dev)
+    xs = torch.empty(yv.shape, dtype=torch.float64, device=dev)
+    wsz = S.slepian_workspace_size(plan, S.SLEPIAN_OP_LSQ, b)
+    work = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
+    rep = {}
+
+    def solve():
+        _, r = S.slepian_lsq(plan, yv, mode=S.SLEPIAN_TIKHONOV, alpha=alpha, tol=1e-10, max_iter=30, x=xs,
+                             work=work)
+        rep.update(r)
+
+    t0 = time.perf_counter()
+    solve()
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t0
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        solve()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    fast_ms = _time_calls(lambda: S.slepian_lsq(plan, yv, mode=S.SLEPIAN_TIKHONOV, alpha=alpha, tol=0.0,
+                                                max_iter=0, x=xs, work=work), 3, 1, dev)
+    log(f"bench: least squares {ms:.2f} ms per refined solve ({rep.get('iterations')} sweeps, "
+        f"residual {rep.get('rel_residual'):.2e})")
+    return {"workload": "least squares N=2^20 W=0.02 eps=1e-6 b=64 alpha=1e-3 tol=1e-10",
+            "plan_setup_s": round(setup, 3), "r": plan.info["r"], "r_tik": plan.info["r_tik"],
+            "ms_per_refined_solve": round(ms, 3), "first_call_ms": round(first * 1e3, 3),
+            "refinement_sweeps": rep.get("iterations"), "rel_residual": rep.get("rel_residual"),
+            "rel_residual_unrefined": rep.get("rel_residual_first"),
+            "ms_fast_operator_only": round(fast_ms, 3),
+            "value": round(N * b / (ms * 1e-3) / 1e9, 3), "unit": "GSamples/s solved (wall clock, synchronising)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +308,8 @@ def main():
                     help="correction arithmetic of the timed batched path (the FFT product is FP32 in both)")
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the many-plans workload (512 plans through one grouped call)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the precision (N=2^18, 1024 signals) and least-squares (N=2^20) workloads")
     args = ap.parse_args()
 
     if args.copy_only:
@@ -345,6 +438,8 @@ def main():
                  "speedup_batched": round(pms / ms_per_step, 2)}
 
     batching = None if args.no_batching else bench_batching(args, dev)
+    precision = None if args.no_extra else bench_precision(args, dev)
+    lsq = None if args.no_extra else bench_lsq(args, dev)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GSamples/s", "n_gpus": 1,
@@ -370,6 +465,8 @@ def main():
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
         "batching": batching,
+        "precision_workload": precision,
+        "least_squares_workload": lsq,
     }
     print(json.dumps(out), flush=True)
 

@@ -741,7 +741,12 @@ size_t colinv_corr_lds(int log1, int r, int mode) {
 // L1 = 32 keeps 64 complex inputs per lane on top of the accumulators; there
 // the plain pass plus the separate matrix-core update is faster.
 bool colinv_corr_ok(int log1, int r, int mode) {
-  return log1 >= 1 && log1 <= 4 && colinv_corr_lds(log1, r, mode) <= (size_t)64 * 1024;
+  // tuning override: SLEPIAN_CIC_MAXLOG1 (4 or 5), the largest L1 = 2^log1 fused
+  static const int maxlog1 = [] {
+    const char *e = std::getenv("SLEPIAN_CIC_MAXLOG1");
+    return e && std::atoi(e) == 5 ? 5 : 4;
+  }();
+  return log1 >= 1 && log1 <= maxlog1 && colinv_corr_lds(log1, r, mode) <= (size_t)64 * 1024;
 }
 
 template <int L1, int MODE, int CW, int PPL>
@@ -774,6 +779,7 @@ static bool launch_cic_mode(hipStream_t st, const cpx<float> *Z, int N, int b, i
     case 2: launch_cic_shape<4, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
     case 3: launch_cic_shape<8, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
     case 4: launch_cic_shape<16, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 5: launch_cic_shape<32, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
     default: return false;  // larger L1: the caller does the update separately
   }
 }
@@ -932,7 +938,7 @@ static hipError_t group_colinv_cw(int log1, int mode, size_t lds, const GroupPla
     SLP_LAUNCH("col_inv_corr_bf16x3_group_L1_" #L1, (k_colinv_corr_group<L1, 1, CW, PPL>), grid, block, lds, st, \
                gp, sp.idx, sp.start, sp.m);                                                                       \
     break;
-    SLP_GCI(1, 2) SLP_GCI(2, 4) SLP_GCI(3, 8) SLP_GCI(4, 16)
+    SLP_GCI(1, 2) SLP_GCI(2, 4) SLP_GCI(3, 8) SLP_GCI(4, 16) SLP_GCI(5, 32)
 #undef SLP_GCI
     default: return hipErrorInvalidValue;
   }
