@@ -424,7 +424,8 @@ FftGeom make_geom(int logL, int logE, bool allow_v2) {
     g.logT = g.log1 > g.log2 ? g.log1 : g.log2;
   }
   g.s = (logL + 1) / 2;
-  if (allow_v2 && g.log2 >= 9 && g.log2 <= 13 && g.log1 <= 6) {
+  // register-stage rows; columns in registers (L1 <= 32) or through LDS (64..512)
+  if (allow_v2 && g.log2 >= 9 && g.log2 <= 13 && g.log1 <= 9) {
     static const int shapes[5][3] = {{8, 8, 8}, {16, 8, 8}, {16, 16, 8}, {16, 16, 16}, {32, 16, 16}};
     const int *sh = shapes[g.log2 - 9];
     g.v2 = 1;

@@ -362,6 +362,121 @@ __global__ __launch_bounds__(256) void k_colinv2(const cpx<R> *__restrict__ Z, i
   colinv_body<R, L1>(Z, N, b, pair0, logL, log2, tcol, y, ldy, blockIdx.x, blockIdx.y);
 }
 
+// Column passes for long columns (L1 = A B = 64 .. 512), two stages through
+// LDS: with n1 = a + A n1b and k1 = k1b + B k1a, stage 1 is a length-B DFT
+// over n1b for each (column, a) times W_L1^{a k1b}, stage 2 a length-A DFT
+// over a for each (column, k1b).  A workgroup takes CB adjacent columns of one
+// pair; thread (c, a) = (t mod CB, t div CB) owns stage-1 job (c, a) and the
+// stage-2 jobs (c, a + A q), q < B / A.  LDS holds [k1b][a][c], so both
+// stages touch consecutive columns in consecutive lanes.  Only n1 < L1/2
+// carries samples (L >= 2N), so stage 1 reads half of its inputs.
+template <typename R, int A, int B, int CB>
+__global__ __launch_bounds__(CB *A) void k_colfwd_lds(const R *__restrict__ x, int64_t ldx, int N, int b, int pair0,
+                                                      int logL, int log2, const cpx<R> *__restrict__ tcol,
+                                                      cpx<R> *__restrict__ Z) {
+  constexpr int L1 = A * B, NT = CB * A, J = B / A;
+  static_assert(B % A == 0, "column stages");
+  __shared__ cpx<R> S[L1 * CB];
+  __shared__ cpx<R> tw[L1];  // W_L1^m
+  const int t = threadIdx.x, c = t % CB, a = t / CB;
+  const int n2 = blockIdx.x * CB + c;
+  const int pl = blockIdx.y, p = pair0 + pl;
+  const int s0 = 2 * p, s1 = 2 * p + 1;
+  const bool has1 = s1 < b;
+  const R *x0 = x + (int64_t)s0 * ldx;
+  const R *x1 = x + (int64_t)(has1 ? s1 : s0) * ldx;
+  for (int m = t; m < L1; m += NT) {
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)L1, &sn, &cs);
+    tw[m] = cpx<R>{(R)cs, (R)(-sn)};
+  }
+  cpx<R> u[B];
+#pragma unroll
+  for (int n1b = 0; n1b < B; ++n1b) {
+    R re = 0, im = 0;
+    if (n1b < B / 2) {
+      const int n = n2 + ((a + A * n1b) << log2);
+      if (n < N) {
+        re = x0[n];
+        if (has1) im = x1[n];
+      }
+    }
+    u[n1b] = cpx<R>{re, im};
+  }
+  reg::dft<B, -1>(u);
+  __syncthreads();
+#pragma unroll
+  for (int k1b = 0; k1b < B; ++k1b) S[(k1b * A + a) * CB + c] = k1b ? cmul(u[k1b], tw[a * k1b]) : u[k1b];
+  __syncthreads();
+  cpx<R> *Zp = Z + ((int64_t)pl << logL) + n2;
+#pragma unroll
+  for (int q = 0; q < J; ++q) {
+    const int k1b = a + A * q;
+    cpx<R> v[A];
+#pragma unroll
+    for (int i = 0; i < A; ++i) v[i] = S[(k1b * A + i) * CB + c];
+    reg::dft<A, -1>(v);
+#pragma unroll
+    for (int k1a = 0; k1a < A; ++k1a) {
+      const int k1 = k1b + B * k1a;
+      const int64_t o = (int64_t)k1 << log2;
+      Zp[o] = k1 ? cmul(v[k1a], tcol[o + n2]) : v[k1a];
+    }
+  }
+}
+
+template <typename R, int A, int B, int CB>
+__global__ __launch_bounds__(CB *A) void k_colinv_lds(const cpx<R> *__restrict__ Z, int N, int b, int pair0, int logL,
+                                                      int log2, const cpx<R> *__restrict__ tcol, R *__restrict__ y,
+                                                      int64_t ldy) {
+  constexpr int L1 = A * B, NT = CB * A, J = B / A;
+  __shared__ cpx<R> S[L1 * CB];
+  __shared__ cpx<R> tw[L1];
+  const int t = threadIdx.x, c = t % CB, a = t / CB;
+  const int n2 = blockIdx.x * CB + c;
+  const int pl = blockIdx.y, p = pair0 + pl;
+  const int s0 = 2 * p, s1 = 2 * p + 1;
+  const bool has1 = s1 < b;
+  for (int m = t; m < L1; m += NT) {
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)L1, &sn, &cs);
+    tw[m] = cpx<R>{(R)cs, (R)(-sn)};
+  }
+  const cpx<R> *Zp = Z + ((int64_t)pl << logL) + n2;
+#pragma unroll
+  for (int q = 0; q < J; ++q) {
+    const int k1b = a + A * q;
+    cpx<R> v[A];
+#pragma unroll
+    for (int k1a = 0; k1a < A; ++k1a) {
+      const int k1 = k1b + B * k1a;
+      const int64_t o = (int64_t)k1 << log2;
+      v[k1a] = k1 ? cmulc(Zp[o], tcol[o + n2]) : Zp[o];
+    }
+    reg::dft<A, +1>(v);
+#pragma unroll
+    for (int i = 0; i < A; ++i) S[(k1b * A + i) * CB + c] = v[i];
+  }
+  __syncthreads();
+  cpx<R> u[B];
+#pragma unroll
+  for (int k1b = 0; k1b < B; ++k1b) {
+    const cpx<R> w = S[(k1b * A + a) * CB + c];
+    u[k1b] = k1b ? cmulc(w, tw[a * k1b]) : w;
+  }
+  reg::dft<B, +1>(u);
+  R *y0 = y + (int64_t)s0 * ldy;
+  R *y1 = y + (int64_t)(has1 ? s1 : s0) * ldy;
+#pragma unroll
+  for (int n1b = 0; n1b < B / 2; ++n1b) {
+    const int n = n2 + ((a + A * n1b) << log2);
+    if (n < N) {
+      y0[n] = u[n1b].x;
+      if (has1) y1[n] = u[n1b].y;
+    }
+  }
+}
+
 // Pass C fused with the correction update y += U dC (Corollary 2's U1 U2^T x
 // term).  A workgroup of CW wavefronts owns 16 columns c0..c0+15 and
 // 4 PPL CW signal pairs; it stages U's rows n = c0 + col + L2 n1 (n1 < L1/2)
@@ -691,16 +806,44 @@ static void launch_cols(bool fwd, dim3 grid, hipStream_t st, const R *x, int64_t
   }
 }
 
+// Long columns: (A, B) and columns per workgroup CB with L1 CB elements of
+// LDS within 64 KB.
+template <typename R, int A, int B, int CB>
+static void launch_cols_lds(bool fwd, hipStream_t st, const R *x, int64_t ldx, R *y, int64_t ldy, int N, int b,
+                            int p0, int np, const FftGeom &g, const FftTables<R> &tb, cpx<R> *Z) {
+  const dim3 grid((1u << g.log2) / CB, (unsigned)np), block(CB * A);
+  if (fwd) {
+    SLP_LAUNCH(sizeof(R) == 4 ? "col_fwd" : "col_fwd_f64", (k_colfwd_lds<R, A, B, CB>), grid, block, 0, st, x, ldx,
+               N, b, p0, g.logL, g.log2, tb.col, Z);
+  } else {
+    SLP_LAUNCH(sizeof(R) == 4 ? "col_inv" : "col_inv_f64", (k_colinv_lds<R, A, B, CB>), grid, block, 0, st, Z, N, b,
+               p0, g.logL, g.log2, tb.col, y, ldy);
+  }
+}
+
 template <typename R>
 static bool dispatch_cols(bool fwd, dim3 grid, hipStream_t st, const R *x, int64_t ldx, R *y, int64_t ldy, int N,
                           int b, int p0, const FftGeom &g, const FftTables<R> &tb, cpx<R> *Z) {
+  const int np = (int)grid.y;
+  if (g.log1 >= 6) {
+    constexpr bool f32 = sizeof(R) == 4;
+    switch (g.log1) {
+      case 6: launch_cols_lds<R, 8, 8, 32>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z); return true;
+      case 7: launch_cols_lds<R, 8, 16, 32>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z); return true;
+      case 8: launch_cols_lds<R, 16, 16, 16>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z); return true;
+      case 9:
+        if (f32) launch_cols_lds<R, 16, 32, 16>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z);
+        else launch_cols_lds<R, 16, 32, 8>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z);
+        return true;
+      default: return false;
+    }
+  }
   switch (g.log1) {
     case 1: launch_cols<R, 2>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
     case 2: launch_cols<R, 4>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
     case 3: launch_cols<R, 8>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
     case 4: launch_cols<R, 16>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
     case 5: launch_cols<R, 32>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
-    case 6: launch_cols<R, 64>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
     default: return false;
   }
 }
