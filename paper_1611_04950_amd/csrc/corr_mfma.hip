@@ -199,14 +199,21 @@ __device__ __forceinline__ void corr_reduce_body(const float *__restrict__ part,
   const int64_t o = (int64_t)bx * 16 + og;  // o = j * b + s
   const bool valid = o < (int64_t)r * b;
   const int j = valid ? (int)(o / b) : 0, s = valid ? (int)(o % b) : 0;
-  float a0 = 0.f, a1 = 0.f;
-  int c = cg;
-  for (; c + 16 < chunks; c += 32) {
-    a0 += part[((int64_t)c * rpad + j) * b + s];
-    a1 += part[((int64_t)(c + 16) * rpad + j) * b + s];
+  // chunks cg, cg + 16, ...: eight independent loads in flight per round,
+  // summed in a fixed order
+  const int64_t stride = (int64_t)rpad * b;
+  const float *pp = part + (int64_t)j * b + s;
+  float acc = 0.f;
+  for (int c0 = cg; c0 < chunks; c0 += 128) {
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int c = c0 + 16 * e;
+      v[e] = c < chunks ? pp[(int64_t)c * stride] : 0.f;
+    }
+    acc += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
   }
-  if (c < chunks) a0 += part[((int64_t)c * rpad + j) * b + s];
-  red[cg][og] = a0 + a1;
+  red[cg][og] = acc;
   __syncthreads();
   if (cg == 0 && valid) {
     float t = 0.f;
