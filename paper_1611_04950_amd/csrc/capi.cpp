@@ -112,6 +112,7 @@ int ilog2_ceil(int64_t v) {
 struct OpSet {
   int64_t off = 0;   // first column within the plan's U
   int64_t r = 0;
+  int set = 0;       // column set: 0 projection / pinv, 1 Tikhonov (index of the plan's tiles)
   float *d32 = nullptr;
   std::vector<double> d;
 };
@@ -142,6 +143,9 @@ struct slepian_plan_s {
   size_t ws_bytes = 0;
   float *SK = nullptr;   // all K Slepian vectors (slepian_coeffs), leading dimension ldsk
   int64_t ldsk = 0;
+  // U's rows laid out for the fused inverse column pass, per column set and
+  // matrix mode (FP32, BF16 hi/lo); null where that pass does not apply
+  void *ctile[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 
   ~slepian_plan_s() {
     for (auto *p : tw32) dfree(p);
@@ -153,6 +157,8 @@ struct slepian_plan_s {
     for (OpSet *o : {&proj, &pinv, &tik, &tikm}) dfree(o->d32);
     dfree(ws);
     dfree(SK);
+    for (auto &t : ctile)
+      for (void *p : t) dfree(p);
   }
 };
 
@@ -181,7 +187,6 @@ struct slepian_group_s {
   Span single_corr[14], single[14], partial[2], reduce, colfwd[6], row, colinv_corr[6][2], colinv[6], apply;
   int partial_var = 0, colinv_var[6] = {0, 0, 0, 0, 0, 0};
   bool tuned = false;
-  size_t colinv_lds[6] = {0, 0, 0, 0, 0, 0};
   std::vector<int> grouped, other;  // plan indices
   void *ws = nullptr;               // grouped workspace (Z, partials, dC per plan)
   void *ws_other = nullptr;         // for the plans run one by one
@@ -352,7 +357,9 @@ void run_fast_op(const Plan *P, const OpSet &op, float beta, float gamma, const 
   }
   // the update U dC rides on the inverse column pass when its U tile fits in LDS
   const int umode = mode == 0 ? 0 : 1;
-  const bool fused = op.r > 0 && P->g32.v2 && !P->g32.single() && colinv_corr_ok(P->g32.log1, (int)op.r, umode);
+  const void *tile = P->ctile[op.set][umode];
+  const bool fused =
+      op.r > 0 && P->g32.v2 && !P->g32.single() && colinv_corr_ok(P->g32.log1, ldy, b, (int)op.r) && tile;
   Corr<float> c;
   if (fused) {
     c.U = U;
@@ -361,6 +368,7 @@ void run_fast_op(const Plan *P, const OpSet &op, float beta, float gamma, const 
     c.d = op.d32;
     c.dC = w.dC;
     c.mode = umode;
+    c.ut = tile;
   }
   HIPCHK(conv_apply<float>(x, ldx, y, ldy, N, b, P->g32, P->tb32, beta, gamma, c, w.Z, w.slice, st));
   if (op.r > 0 && !fused) HIPCHK(corr_apply_mfma(y, ldy, N, b, U, P->ldu, (int)op.r, w.dC, st));
@@ -380,6 +388,22 @@ void upload_d(OpSet &o) {
   std::vector<float> f(o.d.begin(), o.d.end());
   o.d32 = dalloc<float>(o.r);
   HIPCHK(hipMemcpy(o.d32, f.data(), o.r * sizeof(float), hipMemcpyHostToDevice));
+}
+
+// The fused inverse column pass's copies of U (both matrix modes, both
+// column sets), for three-pass plans whose L1 it handles.
+void build_corr_tiles(Plan *P, hipStream_t st) {
+  const FftGeom &g = P->g32;
+  if (!g.v2 || g.single() || !colinv_corr_tiled(g.log1)) return;
+  for (const OpSet *o : {&P->proj, &P->tik}) {
+    if (o->r <= 0) continue;
+    for (int mode = 0; mode < 2; ++mode) {
+      void *t = dalloc<char>(corr_tile_bytes(g.log1, g.log2, (int)o->r, mode));
+      P->ctile[o->set][mode] = t;
+      HIPCHK(build_corr_tile(P->U32 + o->off * P->ldu, P->ldu, (int)P->N, (int)o->r, g.log1, g.log2, mode, t, st));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
 }
 
 void build_fft_state(Plan *P, hipStream_t st) {
@@ -647,7 +671,9 @@ void build_eigen_state(Plan *P, hipStream_t st) {
       P->tikm.d.push_back(1.0 / (l * l + al) - (1.0 / al + (1.0 / (1.0 + al) - 1.0 / al) * l));
     }
   }
+  P->tik.set = P->tikm.set = 1;
   for (OpSet *o : {&P->proj, &P->pinv, &P->tik, &P->tikm}) upload_d(*o);
+  build_corr_tiles(P, st);
 }
 
 int validate_domain(int64_t N, double W, double eps, const slepian_plan_opts *o) {
@@ -1107,7 +1133,9 @@ int slepian_plan_load(const char *path, int device, slepian_plan_t *out) {
         HIPCHK(cast_f64_to_f32(P->U64, P->N, P->U32, P->ldu, P->N, P->u_r, nullptr));
         HIPCHK(hipDeviceSynchronize());
       }
+      P->tik.set = P->tikm.set = 1;
       for (OpSet *op : {&P->proj, &P->pinv, &P->tik, &P->tikm}) upload_d(*op);
+      build_corr_tiles(P, nullptr);
     } catch (...) {
       if (f) std::fclose(f);
       delete P;
@@ -1151,8 +1179,7 @@ void group_partial(const slepian_group_s *G, int var, bool vec, hipStream_t st) 
 
 void group_colinv_fused(const slepian_group_s *G, int l1, int var, hipStream_t st) {
   const int umode = G->prec == SLEPIAN_MIXED ? 1 : 0;
-  HIPCHK(group_colinv_corr(l1, umode, 8 >> var, G->colinv_lds[l1], G->gp_dev, span_of(G, G->colinv_corr[l1][var]),
-                           st));
+  HIPCHK(group_colinv_corr(l1, umode, 8 >> var, G->gp_dev, span_of(G, G->colinv_corr[l1][var]), st));
 }
 
 // The grouped launches, in the order of the single-plan path: plans whose
@@ -1298,6 +1325,7 @@ int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batc
         if (!fused[i]) {
           const int r = (int)P->proj.r;
           g.corr.mode = umode;
+          g.corr.ut = P->ctile[0][umode];
           g.rp = colinv_corr_rp(r, umode);
           g.rpad = corr_rpad(r);
           g.chunks = corr_nchunks(P->N, batch[i], r);
@@ -1344,9 +1372,8 @@ int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batc
         by_l1[P->g32.log1].push_back(i);
         // the update rides on the inverse column pass exactly when the
         // single-plan path fuses it there
-        if (r > 0 && colinv_corr_ok(P->g32.log1, r, umode)) {
+        if (r > 0 && colinv_corr_ok(P->g32.log1, P->N, batch[i], r) && P->ctile[0][umode]) {
           by_l1_fused[P->g32.log1].push_back(i);
-          G->colinv_lds[P->g32.log1] = std::max(G->colinv_lds[P->g32.log1], colinv_corr_lds(P->g32.log1, r, umode));
         } else {
           by_l1_plain[P->g32.log1].push_back(i);
           if (r > 0) apply.push_back(i);

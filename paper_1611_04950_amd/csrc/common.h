@@ -83,6 +83,7 @@ struct Corr {
   // mode 0: FP32 matrix instructions, 1: BF16 hi/lo.
   const R *dC = nullptr;
   int mode = 0;
+  const void *ut = nullptr;  // U's rows laid out for that pass (corr_tile), in `mode`'s number format
 };
 
 // One plan's operands for the grouped launches, held in a device table that

@@ -19,6 +19,7 @@
 // n = n2 + L2 n1, frequency index k = k1 + L1 k2) give each lane one column
 // n2 and do its length-L1 DFT entirely in registers, with the inter-pass
 // twiddle W_L^{n2 k1} applied there, so the row kernel needs none.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 
@@ -478,87 +479,74 @@ __global__ __launch_bounds__(CB *A) void k_colinv_lds(const cpx<R> *__restrict__
 }
 
 // Pass C fused with the correction update y += U dC (Corollary 2's U1 U2^T x
-// term).  A workgroup of CW wavefronts owns 16 columns c0..c0+15 and
-// 4 PPL CW signal pairs; it stages U's rows n = c0 + col + L2 n1 (n1 < L1/2)
-// for all j in LDS once.  Lane (col, blk) = (lane % 16, lane / 16) runs the
-// inverse column DFTs of PPL pairs (one set of twiddles for all) and places
-// the surviving rows straight into 16 x 16 matrix-core accumulators
-// D[signal slot][column] (row 4 blk + v, column lane % 16), so the update
-// U dC runs on the matrix cores over j with no reshuffle: A = dC^T (signal
-// slots x j) from memory, B = U^T (j x columns) from LDS.  With PPL = 1 the
-// slots 4 blk + 2, 4 blk + 3 stay zero: half the matrix rows are idle, which
-// costs little (the update is a small share of the pass) and halves the
-// registers that hold the DFT inputs, so more wavefronts keep loads in flight.
+// term).  Each wavefront owns 16 columns c0..c0+15 and 4 PPL signal pairs.
+// Lane (col, blk) = (lane % 16, lane / 16) runs the inverse column DFTs of
+// PPL pairs and places the surviving rows straight into 16 x 16 matrix-core
+// accumulators D[signal slot][column] (row 4 blk + v, column lane % 16), so
+// the update U dC runs on the matrix cores over j with no reshuffle: A =
+// dC^T (signal slots x j) from memory, B = U^T (j x columns) from U's rows
+// laid out for this pass at plan time (build_corr_tile): element (j, n) with
+// n = c0 + col + L2 n1 sits at ((cb ROWS + n1) 16 + col) rp + j, so a lane's
+// consecutive j are one vector load and a wavefront's loads for one row n1
+// are contiguous.  No LDS and no barrier: the wavefronts of a workgroup only
+// share the tile through the caches.  With PPL = 1 the slots 4 blk + 2,
+// 4 blk + 3 stay zero: half the matrix rows are idle, which costs little and
+// halves the registers that hold the DFT inputs.
+//   MODE 0: FP32 tile (rp multiple of 16), v_mfma_f32_16x16x4_f32, lane k
+//           index blk takes j = 16 g + 4 blk + m in instruction (g, m);
+//   MODE 1: BF16 hi and lo planes (rp multiple of 32), three
+//           v_mfma_f32_16x16x32_bf16 per 32 j (hi hi, hi lo, lo hi).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Loads and stores at a wavefront-uniform base plus a 32-bit byte offset per
+// lane (the base stays in scalar registers, the lane keeps one 32-bit
+// offset instead of a 64-bit address).
+template <typename T>
+__device__ __forceinline__ T ld_at(const T *base, uint32_t byte_off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T *base, uint32_t byte_off, T v) {
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+
+// Waves per SIMD the fused pass is compiled for (caps its registers).
+constexpr int kCicWaves = 6;
 
 template <int L1, int MODE, int CW, int PPL>
 __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ Z, int N, int b, int pair0, int np,
                                                  int logL, int log2, const cpx<float> *__restrict__ tcol,
-                                                 float *__restrict__ y, int64_t ldy, const float *__restrict__ U,
-                                                 int64_t ldu, int r, int rp, const float *__restrict__ dC, int cb,
-                                                 int by) {
+                                                 float *__restrict__ y, int64_t ldy, const void *__restrict__ ut,
+                                                 int r, int rp, const float *__restrict__ dC, int cb, int by) {
   constexpr int ROWS = L1 > 1 ? L1 / 2 : 1;
-  constexpr int NT = 64 * CW;
   static_assert(PPL == 1 || PPL == 2, "pairs per lane");
-  // MODE 0: FP32 [n1][j][col]; MODE 1: BF16 hi and lo planes [n1][col][j]
-  // with rows of rp + 8 elements, so that a lane's eight consecutive j are
-  // one 16-byte read and the sixteen columns fall on distinct banks.
-  extern __shared__ float Ut[];
-  const int c0 = cb * 16;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int col = lane & 15, blk = lane >> 4;
   const int pw = (by * CW + wave) * 4 * PPL;  // first pair of the wavefront, within the slice
-  const int n2 = c0 + col;
-  // The wavefront's Z loads go out first, so their latency overlaps the
-  // staging of U below.
+  if (pw >= np) return;                       // uniform per wavefront; the kernel has no barrier
+  const int c0 = cb * 16, n2 = c0 + col;
+  // lane offsets below stay under 2^32 bytes: pairs pw .. pw + 4 PPL - 1
+  // span 4 PPL L complex values; the host bounds ldy, r and b
+  const cpx<float> *Zw = Z + ((int64_t)pw << logL) + c0;
   cpx<float> a[PPL][L1];
 #pragma unroll
   for (int h = 0; h < PPL; ++h) {
-    const int pl = pw + PPL * blk + h;
-    const cpx<float> *Zp = Z + ((int64_t)(pl < np ? pl : 0) << logL) + n2;
+    const int q = pw + PPL * blk + h < np ? PPL * blk + h : 0;
+    const uint32_t zo = (((uint32_t)q << logL) + (uint32_t)col) * 8u;
 #pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) a[h][k1] = Zp[(int64_t)k1 << log2];
+    for (int k1 = 0; k1 < L1; ++k1) a[h][k1] = ld_at(Zw, zo + ((uint32_t)k1 << (log2 + 3)));
   }
-  {
-    const int tc = threadIdx.x & 15;
-    const int n0 = c0 + tc;
-    if constexpr (MODE == 0) {
-      for (int j = threadIdx.x >> 4; j < rp; j += NT / 16) {
-        const float *u = U + (int64_t)j * ldu;
-#pragma unroll
-        for (int n1 = 0; n1 < ROWS; ++n1) {
-          const int n = n0 + (n1 << log2);
-          Ut[(n1 * rp + j) * 16 + tc] = (j < r && n < N) ? u[n] : 0.f;
-        }
-      }
-    } else {
-      const int jp = rp + 8;
-      __bf16 *uh = reinterpret_cast<__bf16 *>(Ut);
-      __bf16 *ul = uh + ROWS * 16 * jp;
-      for (int j = threadIdx.x >> 4; j < rp; j += NT / 16) {
-        const float *u = U + (int64_t)j * ldu;
-#pragma unroll
-        for (int n1 = 0; n1 < ROWS; ++n1) {
-          const int n = n0 + (n1 << log2);
-          const float uv = (j < r && n < N) ? u[n] : 0.f;
-          const __bf16 hh = (__bf16)uv;
-          uh[(n1 * 16 + tc) * jp + j] = hh;
-          ul[(n1 * 16 + tc) * jp + j] = (__bf16)(uv - (float)hh);
-        }
-      }
-    }
-  }
-  __syncthreads();
-  if (pw >= np) return;  // uniform per wavefront; no barrier follows
   // W_L^{k1 n2} = W_L^{(k1 mod 8) n2} W_L^{8 (k1 div 8) n2}: eight plus L1/8
   // table loads per lane instead of L1, one extra rounding per factor.
   constexpr int TH = L1 > 8 ? L1 / 8 : 1;
+  const cpx<float> *tc = tcol + c0;
   cpx<float> tl[L1 < 8 ? L1 : 8], th[TH];
 #pragma unroll
-  for (int k = 1; k < (L1 < 8 ? L1 : 8); ++k) tl[k] = tcol[(k << log2) + n2];
+  for (int k = 1; k < (L1 < 8 ? L1 : 8); ++k) tl[k] = ld_at(tc, (((uint32_t)k << log2) + (uint32_t)col) * 8u);
 #pragma unroll
-  for (int m = 1; m < TH; ++m) th[m] = tcol[((8 * m) << log2) + n2];
+  for (int m = 1; m < TH; ++m) th[m] = ld_at(tc, (((uint32_t)(8 * m) << log2) + (uint32_t)col) * 8u);
 #pragma unroll
   for (int h = 0; h < PPL; ++h) {
 #pragma unroll
@@ -576,7 +564,9 @@ __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ 
   const int ipl = pw + PPL * iq + (iv >> 1);
   const int sa = 2 * (pair0 + ipl) + (iv & 1);
   const bool sav = (PPL == 2 || iv < 2) && ipl < np && sa < b;
-  const int sac = sav ? sa : 0;
+  const uint32_t sac = sav ? (uint32_t)sa : 0u;
+  const uint32_t tile_row = 16u * (uint32_t)rp;  // elements per row n1 of one column block
+  float *yw = y + (int64_t)2 * (pair0 + pw) * ldy;
   // Rows go through the matrix cores in chunks of at most eight, so only one
   // chunk's accumulators are live next to the DFT outputs.
   constexpr int RC = ROWS < 8 ? ROWS : 8;
@@ -593,33 +583,46 @@ __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ 
         acc[i][2 * h + 1] = live ? a[h][rc + i].y : 0.f;
       }
     }
+    const int64_t base = ((int64_t)cb * ROWS + rc) * tile_row;
     if constexpr (MODE == 0) {
-      for (int jb = 0; jb < rp; jb += 4) {
-        const int j = jb + blk;
-        const float av = (sav && j < r) ? dC[(int64_t)j * b + sac] : 0.f;
+      const float *T = static_cast<const float *>(ut) + base;
+      const uint32_t lo = (uint32_t)col * rp + 4u * blk;
+      for (int g = 0; g < rp; g += 16) {
+        float av[4];
 #pragma unroll
-        for (int i = 0; i < RC; ++i)
-          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, Ut[((rc + i) * rp + j) * 16 + col], acc[i], 0, 0, 0);
+        for (int m = 0; m < 4; ++m) {
+          const int j = g + 4 * blk + m;
+          av[m] = (sav && j < r) ? ld_at(dC, ((uint32_t)j * (uint32_t)b + sac) * 4u) : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+          const float4 u = ld_at(reinterpret_cast<const float4 *>(T), (lo + i * tile_row + g) * 4u);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], u.x, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1], u.y, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2], u.z, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[3], u.w, acc[i], 0, 0, 0);
+        }
       }
     } else {
-      const int jp = rp + 8;
-      const __bf16 *uh = reinterpret_cast<const __bf16 *>(Ut);
-      const __bf16 *ul = uh + ROWS * 16 * jp;
-      for (int jb = 0; jb < rp; jb += 32) {
+      const int64_t plane = ((int64_t)ROWS << log2) * rp;
+      const __bf16 *Th = static_cast<const __bf16 *>(ut) + base;
+      const __bf16 *Tl = Th + plane;
+      const uint32_t lo = (uint32_t)col * rp + 8u * blk;
+      for (int g = 0; g < rp; g += 32) {
         bf16x8 ahi, alo;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const int j = jb + 8 * blk + e;
-          const float av = (sav && j < r) ? dC[(int64_t)j * b + sac] : 0.f;
+          const int j = g + 8 * blk + e;
+          const float av = (sav && j < r) ? ld_at(dC, ((uint32_t)j * (uint32_t)b + sac) * 4u) : 0.f;
           const __bf16 hh = (__bf16)av;
           ahi[e] = hh;
           alo[e] = (__bf16)(av - (float)hh);
         }
 #pragma unroll
         for (int i = 0; i < RC; ++i) {
-          const int o = ((rc + i) * 16 + col) * jp + jb + 8 * blk;
-          const bf16x8 bhi = *reinterpret_cast<const bf16x8 *>(uh + o);
-          const bf16x8 blo = *reinterpret_cast<const bf16x8 *>(ul + o);
+          const uint32_t o = (lo + i * tile_row + g) * 2u;
+          const bf16x8 bhi = ld_at(reinterpret_cast<const bf16x8 *>(Th), o);
+          const bf16x8 blo = ld_at(reinterpret_cast<const bf16x8 *>(Tl), o);
           acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[i], 0, 0, 0);
           acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[i], 0, 0, 0);
           acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[i], 0, 0, 0);
@@ -632,29 +635,69 @@ __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ 
       const int pl = pw + PPL * blk + (v >> 1);
       const int sg = 2 * (pair0 + pl) + (v & 1);
       if (pl >= np || sg >= b) continue;
-      float *ys = y + (int64_t)sg * ldy;
+      const uint32_t so = (uint32_t)(2 * PPL * blk + v) * (uint32_t)ldy + (uint32_t)n2;
 #pragma unroll
       for (int i = 0; i < RC; ++i) {
         const int n = n2 + ((rc + i) << log2);
-        if (n < N) ys[n] = acc[i][v];
+        if (n < N) st_at(yw, (so + ((uint32_t)(rc + i) << log2)) * 4u, acc[i][v]);
       }
     }
   }
 }
 
 template <int L1, int MODE, int CW, int PPL>
-__global__ __launch_bounds__(64 * CW) void k_colinv_corr(const cpx<float> *__restrict__ Z, int N, int b, int pair0,
+__global__ __launch_bounds__(64 * CW, kCicWaves) void k_colinv_corr(const cpx<float> *__restrict__ Z, int N, int b, int pair0,
                                                          int np, int logL, int log2,
                                                          const cpx<float> *__restrict__ tcol, float *__restrict__ y,
-                                                         int64_t ldy, const float *__restrict__ U, int64_t ldu,
-                                                         int r, int rp, const float *__restrict__ dC) {
+                                                         int64_t ldy, const void *__restrict__ ut, int r, int rp,
+                                                         const float *__restrict__ dC) {
   // Workgroups are dealt to the eight XCDs round-robin by linear id; give
   // each XCD a contiguous run of column blocks, so the two 64-byte halves of
-  // a 128-byte line of y (and of U) are handled within one L2.
+  // a 128-byte line of y are handled within one L2.
   const int gx = gridDim.x;
   const int cb = (gx & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (gx >> 3) + (int)(blockIdx.x >> 3);
-  colinv_corr_body<L1, MODE, CW, PPL>(Z, N, b, pair0, np, logL, log2, tcol, y, ldy, U, ldu, r, rp, dC, cb,
-                                      blockIdx.y);
+  colinv_corr_body<L1, MODE, CW, PPL>(Z, N, b, pair0, np, logL, log2, tcol, y, ldy, ut, r, rp, dC, cb, blockIdx.y);
+}
+
+// U's rows in the order the fused inverse column pass reads them (see
+// colinv_corr_body): FP32 (mode 0), or BF16 hi and lo planes (mode 1, lo =
+// the rounding error of hi), zero for n >= N and j >= r.
+__global__ void k_corr_tile(const float *__restrict__ U, int64_t ldu, int N, int r, int log2, int rows, int rp,
+                            int mode, void *__restrict__ out) {
+  const int64_t total = ((int64_t)rows << log2) * rp;  // elements per plane
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e % rp);
+    const int64_t q = e / rp;
+    const int c = (int)(q & 15);
+    const int64_t q2 = q >> 4;
+    const int n1 = (int)(q2 % rows);
+    const int64_t cb = q2 / rows;
+    const int64_t n = cb * 16 + c + ((int64_t)n1 << log2);
+    const float u = (j < r && n < N) ? U[(int64_t)j * ldu + n] : 0.f;
+    if (mode == 0) {
+      static_cast<float *>(out)[e] = u;
+    } else {
+      const __bf16 h = (__bf16)u;
+      static_cast<__bf16 *>(out)[e] = h;
+      static_cast<__bf16 *>(out)[total + e] = (__bf16)(u - (float)h);
+    }
+  }
+}
+
+size_t corr_tile_bytes(int log1, int log2, int r, int mode) {
+  const int64_t rows = log1 > 0 ? ((int64_t)1 << log1) / 2 : 1;
+  const int64_t e = (rows << log2) * colinv_corr_rp(r, mode);
+  return mode == 0 ? (size_t)e * sizeof(float) : (size_t)e * 2 * sizeof(__bf16);
+}
+
+hipError_t build_corr_tile(const float *U, int64_t ldu, int N, int r, int log1, int log2, int mode, void *out,
+                           hipStream_t st) {
+  const int rows = log1 > 0 ? (1 << log1) / 2 : 1;
+  const int64_t total = ((int64_t)rows << log2) * colinv_corr_rp(r, mode);
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  SLP_LAUNCH("corr_tile", k_corr_tile, dim3((unsigned)blocks), dim3(256), 0, st, U, ldu, N, r, log2, rows,
+             colinv_corr_rp(r, mode), mode, out);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -711,14 +754,14 @@ __global__ __launch_bounds__(R2 *R3) void k_row2_group(const GroupPlan *__restri
 }
 
 template <int L1, int MODE, int CW, int PPL>
-__global__ __launch_bounds__(64 * CW) void k_colinv_corr_group(const GroupPlan *__restrict__ gp,
+__global__ __launch_bounds__(64 * CW, kCicWaves) void k_colinv_corr_group(const GroupPlan *__restrict__ gp,
                                                                const int *__restrict__ idx,
                                                                const int *__restrict__ start, int m) {
   const int q = group_slot(start, m, blockIdx.x);
   const GroupPlan &P = gp[idx[q]];
   const int w = (int)blockIdx.x - start[q], sh = P.log2 - 4;  // 2^sh column blocks of 16
-  colinv_corr_body<L1, MODE, CW, PPL>(P.Z, P.N, P.b, 0, P.np, P.logL, P.log2, P.tcol, P.y, P.ldy, P.corr.U,
-                                      P.corr.ldu, P.corr.r, P.rp, P.corr.dC, w & ((1 << sh) - 1), w >> sh);
+  colinv_corr_body<L1, MODE, CW, PPL>(P.Z, P.N, P.b, 0, P.np, P.logL, P.log2, P.tcol, P.y, P.ldy, P.corr.ut,
+                                      P.corr.r, P.rp, P.corr.dC, w & ((1 << sh) - 1), w >> sh);
 }
 
 // Row twiddle tables: rt1[k1 T + t] = W_L2^{t k1}, rt2[k2 R3 + m'] = W_T^{m' k2}.
@@ -849,10 +892,11 @@ static bool dispatch_cols(bool fwd, dim3 grid, hipStream_t st, const R *x, int64
 }
 
 // Fused pass C launch shape: PPL pairs per lane, CW wavefronts per workgroup
-// (4 PPL CW pairs share one staged U tile).  SLEPIAN_CIC_SHAPE = "PPLxCW"
-// (1x8, 1x4, 2x4) overrides the default for tuning.
+// (4 PPL CW pairs of one column block, whose U tile they share through the
+// caches).  SLEPIAN_CIC_SHAPE = "PPLxCW" (1x8, 1x4, 2x4) overrides the
+// default for tuning.
 struct CicShape {
-  int ppl = 1, cw = 8;
+  int ppl = 1, cw = 4;
 };
 
 // the grouped launches use one pair per lane and 4 or 8 wavefronts (tuned)
@@ -873,56 +917,52 @@ static CicShape cic_shape() {
   return sh;
 }
 
-int colinv_corr_rp(int r, int mode) { return mode == 0 ? (r + 3) / 4 * 4 : (r + 31) / 32 * 32; }
-
-size_t colinv_corr_lds(int log1, int r, int mode) {
-  const int rows = log1 > 0 ? (1 << log1) / 2 : 1;
-  const size_t rp = (size_t)colinv_corr_rp(r, mode);
-  return mode == 0 ? rows * rp * 16 * sizeof(float) : rows * 16 * (rp + 8) * 2 * sizeof(__bf16);
-}
+int colinv_corr_rp(int r, int mode) { return mode == 0 ? (r + 15) / 16 * 16 : (r + 31) / 32 * 32; }
 
 // L1 = 32 keeps 64 complex inputs per lane on top of the accumulators; there
 // the plain pass plus the separate matrix-core update is faster.
-bool colinv_corr_ok(int log1, int r, int mode) {
+bool colinv_corr_ok(int log1, int64_t ldy, int64_t b, int r) {
   // tuning override: SLEPIAN_CIC_MAXLOG1 (4 or 5), the largest L1 = 2^log1 fused
   static const int maxlog1 = [] {
     const char *e = std::getenv("SLEPIAN_CIC_MAXLOG1");
     return e && std::atoi(e) == 5 ? 5 : 4;
   }();
-  return log1 >= 1 && log1 <= maxlog1 && colinv_corr_lds(log1, r, mode) <= (size_t)64 * 1024;
+  // the pass addresses y and dC by 32-bit byte offsets from a wavefront's base
+  const bool fits = ldy < ((int64_t)1 << 25) && (int64_t)colinv_corr_rp(r, 1) * b < ((int64_t)1 << 29);
+  return log1 >= 1 && log1 <= maxlog1 && fits;
 }
 
+bool colinv_corr_tiled(int log1) { return colinv_corr_ok(log1, 1, 1, 1); }
+
 template <int L1, int MODE, int CW, int PPL>
-static void launch_cic(size_t lds, hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np,
-                       const FftGeom &g, const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c,
-                       int rp) {
+static void launch_cic(hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np, const FftGeom &g,
+                       const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c, int rp) {
   constexpr int PW = 4 * PPL * CW;  // pairs per workgroup
   const dim3 grid((1u << g.log2) / 16, (unsigned)((np + PW - 1) / PW));
   SLP_LAUNCH(MODE ? "col_inv_corr_bf16x3" : "col_inv_corr", (k_colinv_corr<L1, MODE, CW, PPL>), grid, dim3(64 * CW),
-             lds, st, Z, N, b, p0, np, g.logL, g.log2, tb.col, y, ldy, c.U, c.ldu, c.r, rp, c.dC);
+             0, st, Z, N, b, p0, np, g.logL, g.log2, tb.col, y, ldy, c.ut, c.r, rp, c.dC);
 }
 
 template <int L1, int MODE>
-static void launch_cic_shape(size_t lds, hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np,
-                             const FftGeom &g, const FftTables<float> &tb, float *y, int64_t ldy,
-                             const Corr<float> &c, int rp) {
+static void launch_cic_shape(hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np, const FftGeom &g,
+                             const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c, int rp) {
   const CicShape sh = cic_shape();
-  if (sh.ppl == 1 && sh.cw == 8) launch_cic<L1, MODE, 8, 1>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
-  else if (sh.ppl == 1) launch_cic<L1, MODE, 4, 1>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
-  else launch_cic<L1, MODE, 4, 2>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
+  if (sh.ppl == 1 && sh.cw == 8) launch_cic<L1, MODE, 8, 1>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
+  else if (sh.ppl == 1) launch_cic<L1, MODE, 4, 1>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
+  else launch_cic<L1, MODE, 4, 2>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
 }
 
 template <int MODE>
 static bool launch_cic_mode(hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np, const FftGeom &g,
                             const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c) {
   const int rp = colinv_corr_rp(c.r, MODE);
-  const size_t lds = colinv_corr_lds(g.log1, c.r, MODE);
+  if (!c.ut) return false;
   switch (g.log1) {
-    case 1: launch_cic_shape<2, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 2: launch_cic_shape<4, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 3: launch_cic_shape<8, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 4: launch_cic_shape<16, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 5: launch_cic_shape<32, MODE>(lds, st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 1: launch_cic_shape<2, MODE>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 2: launch_cic_shape<4, MODE>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 3: launch_cic_shape<8, MODE>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 4: launch_cic_shape<16, MODE>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 5: launch_cic_shape<32, MODE>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
     default: return false;  // larger L1: the caller does the update separately
   }
 }
@@ -1067,18 +1107,17 @@ hipError_t group_row(int log2, const GroupPlan *gp, const GroupSpan &sp, hipStre
 }
 
 template <int CW>
-static hipError_t group_colinv_cw(int log1, int mode, size_t lds, const GroupPlan *gp, const GroupSpan &sp,
-                                  hipStream_t st) {
+static hipError_t group_colinv_cw(int log1, int mode, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
   const dim3 grid((unsigned)sp.blocks), block(64 * CW);
   constexpr int PPL = kGroupCicPPL;
   switch (log1 * 2 + (mode ? 1 : 0)) {
 #define SLP_GCI(LG, L1)                                                                                            \
   case 2 * LG:                                                                                                    \
-    SLP_LAUNCH("col_inv_corr_group_L1_" #L1, (k_colinv_corr_group<L1, 0, CW, PPL>), grid, block, lds, st, gp,   \
+    SLP_LAUNCH("col_inv_corr_group_L1_" #L1, (k_colinv_corr_group<L1, 0, CW, PPL>), grid, block, 0, st, gp,   \
                sp.idx, sp.start, sp.m);                                                                           \
     break;                                                                                                        \
   case 2 * LG + 1:                                                                                                \
-    SLP_LAUNCH("col_inv_corr_bf16x3_group_L1_" #L1, (k_colinv_corr_group<L1, 1, CW, PPL>), grid, block, lds, st, \
+    SLP_LAUNCH("col_inv_corr_bf16x3_group_L1_" #L1, (k_colinv_corr_group<L1, 1, CW, PPL>), grid, block, 0, st, \
                gp, sp.idx, sp.start, sp.m);                                                                       \
     break;
     SLP_GCI(1, 2) SLP_GCI(2, 4) SLP_GCI(3, 8) SLP_GCI(4, 16) SLP_GCI(5, 32)
@@ -1088,11 +1127,10 @@ static hipError_t group_colinv_cw(int log1, int mode, size_t lds, const GroupPla
   return hipGetLastError();
 }
 
-hipError_t group_colinv_corr(int log1, int mode, int cw, size_t lds, const GroupPlan *gp, const GroupSpan &sp,
-                             hipStream_t st) {
+hipError_t group_colinv_corr(int log1, int mode, int cw, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
   if (sp.m == 0) return hipSuccess;
-  if (cw == 8) return group_colinv_cw<8>(log1, mode, lds, gp, sp, st);
-  if (cw == 4) return group_colinv_cw<4>(log1, mode, lds, gp, sp, st);
+  if (cw == 8) return group_colinv_cw<8>(log1, mode, gp, sp, st);
+  if (cw == 4) return group_colinv_cw<4>(log1, mode, gp, sp, st);
   return hipErrorInvalidValue;
 }
 

@@ -16,12 +16,19 @@ hipError_t build_row_tables(const FftGeom &g, cpx<R> *rt1, cpx<R> *rt2, hipStrea
 template <typename R>
 hipError_t build_col_table(const FftGeom &g, cpx<R> *tc, hipStream_t st);
 
-// U columns the fused inverse column pass stages (r padded to its matrix step)
+// U columns of the fused inverse column pass's tile (r padded to its matrix step:
+// 16 for mode 0, 32 for mode 1)
 int colinv_corr_rp(int r, int mode);
-// LDS bytes of the fused inverse column pass (0 when not applicable).
-size_t colinv_corr_lds(int log1, int r, int mode);
-// whether the inverse column pass can carry the correction update (L1 <= 32, U tile <= 64 KB)
-bool colinv_corr_ok(int log1, int r, int mode);
+// whether the inverse column pass carries the correction update (L1 = 2^log1 <= 16,
+// or <= 32 with the tuning override; output leading dimension ldy, b signals, rank r
+// within its 32-bit offsets), and whether a plan of that L1 keeps the tiles it reads
+bool colinv_corr_ok(int log1, int64_t ldy, int64_t b, int r);
+bool colinv_corr_tiled(int log1);
+// U's rows laid out for the fused inverse column pass (mode 0: FP32; mode 1: BF16 hi
+// and lo planes); bytes, and the layout kernel (U: N x r, leading dimension ldu)
+size_t corr_tile_bytes(int log1, int log2, int r, int mode);
+hipError_t build_corr_tile(const float *U, int64_t ldu, int N, int r, int log1, int log2, int mode, void *out,
+                           hipStream_t st);
 
 // ---- grouped launches over many plans (fft2.hip, corr_mfma.hip) ----
 // Workgroups each plan contributes to a grouped launch.
@@ -41,8 +48,7 @@ hipError_t group_corr_apply(bool vec, const GroupPlan *gp, const GroupSpan &sp, 
 // three-pass passes; all plans of the span share L1 = 2^log1 (columns) or L2 = 2^log2 (rows)
 hipError_t group_colfwd(int log1, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
 hipError_t group_row(int log2, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
-hipError_t group_colinv_corr(int log1, int mode, int cw, size_t lds, const GroupPlan *gp, const GroupSpan &sp,
-                             hipStream_t st);
+hipError_t group_colinv_corr(int log1, int mode, int cw, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
 // C = U^T x partials and dC = d (.) C for every plan of the span
 hipError_t group_corr_partial(int mode, int nb, bool vec, const GroupPlan *gp, const GroupSpan &sp,
                               hipStream_t st);
