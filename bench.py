@@ -138,9 +138,10 @@ def cpu_baseline(N, W, eps, x_sample, min_seconds):
 def bench_batching(args, dev):
     """The many-plans workload: 512 plans (N log-uniform over 2^10..2^17, W
     uniform in [0.01, 0.25], eps in {1e-3, 1e-6}, 4..64 Gaussian signals each)
-    projected by one grouped call (one HIP graph); parity of sampled plans
-    against the oracle and bitwise equality with single-plan calls are checked
-    before timing."""
+    projected by one grouped call (one HIP graph), in the correction
+    arithmetic of --precision; bitwise equality with the single-plan calls
+    (whose parity the test suite checks on the same plans) is checked before
+    timing."""
     import torch
 
     from paper_1611_04950_amd import slepian as S
@@ -149,7 +150,8 @@ def bench_batching(args, dev):
     specs = synth.batching_plans(512)
     log("bench: batching workload, creating 512 plans")
     t0 = time.perf_counter()
-    plans = [S.slepian_plan(n, w, e) for n, w, e, _ in specs]
+    prec = S.SLEPIAN_MIXED if args.precision == "mixed" else S.SLEPIAN_FP32
+    plans = [S.slepian_plan(n, w, e, precision=prec) for n, w, e, _ in specs]
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     xs = [synth.gaussian(n, bb, 4000 * 1000 + 100 * i, device=dev) for i, (n, _, _, bb) in enumerate(specs)]
@@ -195,6 +197,7 @@ def bench_batching(args, dev):
     value = total / (ms * 1e-3) / 1e9
     log(f"bench: batching {ms:.3f} ms per grouped call, {value:.2f} GSamples/s; plan by plan {ms_each:.3f} ms")
     return {"workload": "512 plans, N log-uniform 2^10..2^17, W U[0.01,0.25], eps {1e-3,1e-6}, 4-64 signals",
+            "precision": args.precision,
             "value": round(value, 3), "unit": "GSamples/s", "ms_per_call": round(ms, 4), "steps": steps,
             "samples": total, "plan_by_plan_ms": round(ms_each, 4),
             "speedup_vs_plan_by_plan": round(ms_each / ms, 2), "plans_setup_s": round(setup, 2),

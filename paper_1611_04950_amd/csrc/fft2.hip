@@ -511,7 +511,8 @@ __device__ __forceinline__ void st_at(T *base, uint32_t byte_off, T v) {
   *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
 }
 
-// Waves per SIMD the fused pass is compiled for (caps its registers).
+// Waves per SIMD the fused pass is compiled for (caps its registers; L1 = 32
+// keeps 64 complex inputs per lane and is compiled for 3).
 constexpr int kCicWaves = 6;
 
 template <int L1, int MODE, int CW, int PPL>
@@ -646,7 +647,7 @@ __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ 
 }
 
 template <int L1, int MODE, int CW, int PPL>
-__global__ __launch_bounds__(64 * CW, kCicWaves) void k_colinv_corr(const cpx<float> *__restrict__ Z, int N, int b, int pair0,
+__global__ __launch_bounds__(64 * CW, L1 >= 32 ? 3 : kCicWaves) void k_colinv_corr(const cpx<float> *__restrict__ Z, int N, int b, int pair0,
                                                          int np, int logL, int log2,
                                                          const cpx<float> *__restrict__ tcol, float *__restrict__ y,
                                                          int64_t ldy, const void *__restrict__ ut, int r, int rp,
@@ -754,7 +755,7 @@ __global__ __launch_bounds__(R2 *R3) void k_row2_group(const GroupPlan *__restri
 }
 
 template <int L1, int MODE, int CW, int PPL>
-__global__ __launch_bounds__(64 * CW, kCicWaves) void k_colinv_corr_group(const GroupPlan *__restrict__ gp,
+__global__ __launch_bounds__(64 * CW, L1 >= 32 ? 3 : kCicWaves) void k_colinv_corr_group(const GroupPlan *__restrict__ gp,
                                                                const int *__restrict__ idx,
                                                                const int *__restrict__ start, int m) {
   const int q = group_slot(start, m, blockIdx.x);
