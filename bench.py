@@ -247,6 +247,56 @@ def bench_precision(args, dev):
     return out
 
 
+def bench_fourier_extension(args, dev):
+    """The Fourier-extension experiment at its largest size (Section 4.3):
+    M = 2560 (N = 5121, W = 1/3, T = 1.5), the right-hand side by a
+    2^24-point quadrature, solved with the fast pseudoinverse (eps = 1e-5,
+    rank K = #{lambda >= 1e-4}) and the fast Tikhonov operator (alpha =
+    1e-8); relative RMS errors of the extensions and of the truncated Fourier
+    series with as many terms.  The comparison with the exact operators runs
+    in the GPU tests at smaller M (a dense eigendecomposition at N = 5121 is
+    left out here)."""
+    import numpy as np
+    import torch
+
+    from paper_1611_04950_amd import fourier_ext as fe
+    from paper_1611_04950_amd import slepian as S
+    from paper_1611_04950_amd import synth
+    M, T, eps, thr, alpha = 2560, 1.5, 1e-5, 1e-4, 1e-8
+    N, W = 2 * M + 1, 1.0 / (2 * T)
+    log("bench: Fourier-extension workload")
+    fp = synth.fe_function()
+    Q = synth.fe_grid(M)
+    yh = synth.fe_coefficients(fp, M, T, Q, device=dev)
+    t0 = time.perf_counter()
+    Pp = fe.truncated_plan(M, T, eps, thr)
+    torch.cuda.synchronize()
+    setup_p = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Pt = S.slepian_plan(N, W, eps, alpha=alpha)
+    torch.cuda.synchronize()
+    setup_t = time.perf_counter() - t0
+    y = torch.tensor(np.stack([yh.real, yh.imag]), dtype=torch.float32, device=dev)
+    xs = torch.empty(y.shape, dtype=torch.float64, device=dev)
+    ms_p = _time_calls(lambda: S.slepian_lsq(Pp, y, mode=S.SLEPIAN_PINV, tol=0.0, max_iter=0, x=xs), 20, 3, dev)
+    ms_t = _time_calls(lambda: S.slepian_lsq(Pt, y, mode=S.SLEPIAN_TIKHONOV, alpha=alpha, tol=0.0, max_iter=0,
+                                             x=xs), 20, 3, dev)
+    gp = fe.solve(Pp, yh, S.SLEPIAN_PINV, device=dev)
+    gt = fe.solve(Pt, yh, S.SLEPIAN_TIKHONOV, alpha=alpha, device=dev)
+    e_fs = synth.fe_rel_rms(fp, synth.fe_coefficients(fp, M, 1.0, Q, device=dev), 1.0, Q, device=dev)
+    e_p = synth.fe_rel_rms(fp, gp, T, Q, device=dev)
+    e_t = synth.fe_rel_rms(fp, gt, T, Q, device=dev)
+    log(f"bench: Fourier extension M={M}: series {e_fs:.3e}, fast pinv {e_p:.3e} ({ms_p:.3f} ms), "
+        f"fast Tikhonov {e_t:.3e} ({ms_t:.3f} ms)")
+    return {"workload": f"Fourier extension M={M} (N={N}, W=1/3, T=1.5), quadrature 2^{Q.bit_length() - 1}",
+            "K": Pp.info["K"], "r_pinv": Pp.info["r"], "r_tik": Pt.info["r_tik"],
+            "plan_setup_s": {"pinv": round(setup_p, 3), "tikhonov": round(setup_t, 3)},
+            "ms_per_solve": {"pinv": round(ms_p, 4), "tikhonov": round(ms_t, 4)},
+            "rel_rms_error": {"fourier_series": e_fs, "extension_fast_pinv": e_p,
+                              "extension_fast_tikhonov": e_t},
+            "series_over_extension": round(e_fs / e_p, 1)}
+
+
 def bench_lsq(args, dev):
     """N = 2^20, W = 0.02, eps = 1e-6, 64 signals of 200 tones at 10 dB:
     Tikhonov (alpha = 1e-3) solve refined to a 1e-10 FP64 normal-equation
@@ -443,6 +493,7 @@ def main():
     batching = None if args.no_batching else bench_batching(args, dev)
     precision = None if args.no_extra else bench_precision(args, dev)
     lsq = None if args.no_extra else bench_lsq(args, dev)
+    fext = None if args.no_extra else bench_fourier_extension(args, dev)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GSamples/s", "n_gpus": 1,
@@ -470,6 +521,7 @@ def main():
         "batching": batching,
         "precision_workload": precision,
         "least_squares_workload": lsq,
+        "fourier_extension_workload": fext,
     }
     print(json.dumps(out), flush=True)
 

@@ -171,10 +171,16 @@ int slepian_coeffs(slepian_plan_t plan, const float *x, int64_t ldx, float *c, i
 /* Least squares with the prolate matrix (Section 2.3):
  *   SLEPIAN_PINV:      x = B_K^+ y ~= B y + U diag(1/lambda - lambda | -lambda) U^T y
  *                      (Corollary 3, error <= 3 eps ||y||); single pass, tol and
- *                      max_iter ignored.
+ *                      max_iter ignored.  B y is the FP32 product; the
+ *                      correction runs in FP64 (its weights 1/lambda, up to
+ *                      1/eps, would amplify FP32 rounding of U^T y).  K is
+ *                      the plan's (round(2NW) or the override of
+ *                      slepian_plan_ex, e.g. #{lambda >= threshold}).
  *   SLEPIAN_TIKHONOV:  x ~= (B^2 + alpha I)^{-1} B y, starting from the fast
  *                      operator B y/(1+alpha) + U5 U5^T y (Corollary 4, error
- *                      <= eps ||y||), then refined: with the FP64 residual
+ *                      <= eps ||y||; with max_iter = 0 the correction runs in
+ *                      FP64, as its weights reach 1/(2 sqrt(alpha))), then
+ *                      refined: with the FP64 residual
  *                      rho = B y - (B^2 + alpha I) x, x += M rho, where M is an
  *                      FP32 fast approximation of (B^2 + alpha I)^{-1}, until
  *                      max_s ||rho_s|| / ||B y_s|| <= tol or max_iter sweeps.

@@ -44,7 +44,7 @@ __all__ = [
     "kernel_spectrum", "apply_prolate", "apply_prolate_dense",
     "dense_eig", "slepian_tridiagonal", "slepian_vectors",
     "transition_plan", "partition", "projection_d", "pinv_d", "tikhonov_g",
-    "project_exact", "project_fast", "pinv_exact", "pinv_fast",
+    "project_exact", "project_fast", "pinv_exact", "pinv_threshold", "pinv_fast",
     "tikhonov_exact", "tikhonov_fast", "tikhonov_cg", "coeffs_exact",
     "cor1_bound", "zhu_wakin_bound", "asymptotic_count", "sign_fix",
 ]
@@ -337,6 +337,15 @@ def pinv_exact(N: int, W: float, y: np.ndarray, K: int | None = None) -> np.ndar
     C = SK.T @ np.asarray(y, dtype=np.float64)
     C = C / lam[:K, None] if C.ndim == 2 else C / lam[:K]
     return SK @ C
+
+
+def pinv_threshold(N: int, W: float, y: np.ndarray, thr: float) -> tuple[np.ndarray, int]:
+    """The truncated pseudoinverse that drops the eigenvalues below thr (the
+    Fourier-extension experiment of Section 4.3): rank K = #{lambda >= thr},
+    B_K^+ y = S_K Lambda_K^-1 S_K^T y.  Returns (B_K^+ y, K)."""
+    lam, _ = dense_eig(N, W)
+    K = int((lam >= thr).sum())
+    return pinv_exact(N, W, y, K), K
 
 
 def tikhonov_exact(N: int, W: float, alpha: float, y: np.ndarray) -> np.ndarray:

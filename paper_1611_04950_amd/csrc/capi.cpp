@@ -114,6 +114,7 @@ struct OpSet {
   int64_t r = 0;
   int set = 0;       // column set: 0 projection / pinv, 1 Tikhonov (index of the plan's tiles)
   float *d32 = nullptr;
+  double *d64 = nullptr;
   std::vector<double> d;
 };
 
@@ -154,7 +155,10 @@ struct slepian_plan_s {
     dfree(chat64);
     dfree(U64);
     dfree(U32);
-    for (OpSet *o : {&proj, &pinv, &tik, &tikm}) dfree(o->d32);
+    for (OpSet *o : {&proj, &pinv, &tik, &tikm}) {
+      dfree(o->d32);
+      dfree(o->d64);
+    }
     dfree(ws);
     dfree(SK);
     for (auto &t : ctile)
@@ -265,6 +269,7 @@ B64Ws carve_b64(const Plan *P, int64_t b, Carver &cv) {
 struct TikWs {
   float *x32, *rho32, *e32;
   double *y64, *By, *t, *u, *rho, *nBy, *nr;
+  double *part64 = nullptr, *dC64 = nullptr;  // FP64 correction of the starting point
   ProjWs pw;
   B64Ws bw;
 };
@@ -282,10 +287,36 @@ TikWs carve_tik(const Plan *P, int64_t b, Carver &cv) {
   w.rho = cv.take<double>(nb);
   w.nBy = cv.take<double>(b);
   w.nr = cv.take<double>(b);
+  if (P->tik.r > 0) {
+    const int r = (int)P->tik.r;
+    w.part64 = cv.take<double>(corr64_workspace_doubles(P->N, b, r) - (size_t)r * b);
+    w.dC64 = cv.take<double>((size_t)r * b);
+  }
   // the fast operators of the solve use the Tikhonov column set
   w.pw = carve_project(P, P->tikm.r > P->tik.r ? P->tikm : P->tik, b, cv);
   w.bw = carve_b64(P, b, cv);
   return w;
+}
+
+// The pseudoinverse: B y through the FP32 product into t, and the correction
+// in FP64 (corr64) on top of it.
+struct PinvWs {
+  float *t = nullptr;
+  ProjWs w;
+  double *part = nullptr, *dC = nullptr;
+};
+
+PinvWs carve_pinv(const Plan *P, int64_t b, Carver &cv) {
+  static const OpSet none;
+  PinvWs p;
+  p.t = cv.take<float>((size_t)P->N * b);
+  p.w = carve_project(P, none, b, cv);
+  const int r = (int)P->pinv.r;
+  if (r > 0) {
+    p.part = cv.take<double>(corr64_workspace_doubles(P->N, b, r) - (size_t)r * b);
+    p.dC = cv.take<double>((size_t)r * b);
+  }
+  return p;
 }
 
 size_t op_workspace(const Plan *P, int op, int64_t b) {
@@ -303,8 +334,7 @@ size_t op_workspace(const Plan *P, int op, int64_t b) {
       break;
     case SLEPIAN_OP_LSQ: {
       Carver c1(nullptr), c2(nullptr);
-      c1.take<float>((size_t)P->N * b);
-      carve_project(P, P->pinv, b, c1);
+      carve_pinv(P, b, c1);
       carve_tik(P, b, c2);
       return std::max(c1.off, c2.off) + 256;
     }
@@ -388,6 +418,8 @@ void upload_d(OpSet &o) {
   std::vector<float> f(o.d.begin(), o.d.end());
   o.d32 = dalloc<float>(o.r);
   HIPCHK(hipMemcpy(o.d32, f.data(), o.r * sizeof(float), hipMemcpyHostToDevice));
+  o.d64 = dalloc<double>(o.r);
+  HIPCHK(hipMemcpy(o.d64, o.d.data(), o.r * sizeof(double), hipMemcpyHostToDevice));
 }
 
 // The fused inverse column pass's copies of U (both matrix modes, both
@@ -896,11 +928,13 @@ int slepian_lsq(slepian_plan_t P, int mode, double alpha, const float *y, int64_
     const int64_t N = P->N, b = batch;
     void *ws = get_ws(P, work, work_bytes, op_workspace(P, SLEPIAN_OP_LSQ, b));
     if (mode == SLEPIAN_PINV) {
+      static const OpSet none;
       Carver cv(ws);
-      float *t = cv.take<float>((size_t)N * b);
-      ProjWs w = carve_project(P, P->pinv, b, cv);
-      run_fast_op(P, P->pinv, 1.0f, 0.0f, y, ldy, t, N, b, w, st);
-      HIPCHK(cast_f32_to_f64(t, N, x, ldx, N, b, st));
+      PinvWs w = carve_pinv(P, b, cv);
+      run_fast_op(P, none, 1.0f, 0.0f, y, ldy, w.t, N, b, w.w, st);
+      HIPCHK(cast_f32_to_f64(w.t, N, x, ldx, N, b, st));
+      HIPCHK(corr64(y, ldy, x, ldx, N, b, P->U64 + P->pinv.off * N, N, (int)P->pinv.r, P->pinv.d64, w.part, w.dC,
+                    st));
       if (rep) {
         rep->converged = 1;
         HIPCHK(hipStreamSynchronize(st));
@@ -909,10 +943,20 @@ int slepian_lsq(slepian_plan_t P, int mode, double alpha, const float *y, int64_
     }
     Carver cv(ws);
     TikWs w = carve_tik(P, b, cv);
-    const float a = (float)alpha;
-    run_fast_op(P, P->tik, (float)(1.0 / (1.0 + alpha)), 0.0f, y, ldy, w.x32, N, b, w.pw, st);
-    HIPCHK(cast_f32_to_f64(w.x32, N, x, ldx, N, b, st));
-    (void)a;
+    // starting point B y / (1 + alpha) + U5 U5^T y.  As the result itself
+    // (max_iter = 0) its correction runs in FP64 (the weights reach
+    // 1/(2 sqrt(alpha)) and would amplify FP32 rounding); as the start of the
+    // refinement, which removes that rounding, in FP32 on the matrix cores.
+    if (max_iter == 0) {
+      static const OpSet none;
+      run_fast_op(P, none, (float)(1.0 / (1.0 + alpha)), 0.0f, y, ldy, w.x32, N, b, w.pw, st);
+      HIPCHK(cast_f32_to_f64(w.x32, N, x, ldx, N, b, st));
+      HIPCHK(corr64(y, ldy, x, ldx, N, b, P->U64 + P->tik.off * N, N, (int)P->tik.r, P->tik.d64, w.part64,
+                    w.dC64, st));
+    } else {
+      run_fast_op(P, P->tik, (float)(1.0 / (1.0 + alpha)), 0.0f, y, ldy, w.x32, N, b, w.pw, st);
+      HIPCHK(cast_f32_to_f64(w.x32, N, x, ldx, N, b, st));
+    }
     if (max_iter == 0 && !rep) return SLEPIAN_OK;
     HIPCHK(cast_f32_to_f64(y, ldy, w.y64, N, N, b, st));
     run_b64(P, w.y64, N, w.By, N, b, w.bw, st);

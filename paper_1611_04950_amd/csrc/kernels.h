@@ -98,19 +98,13 @@ hipError_t tridiag_inviter(const double *a, const double *off, int64_t N, const 
 hipError_t rayleigh(const double *V, const double *BV, int64_t N, int64_t count, double *lam, double *res,
                     hipStream_t st);
 
-// ---- Low-rank correction (corr.hip) ----
-// part[chunk][j][s] = sum over rows of the chunk of U[n,j] x_s[n].
-int corr_chunks(int64_t N);
-int corr_rpad(int r);
-hipError_t corr_partial(const float *x, int64_t ldx, int64_t N, int64_t b, const float *U, int64_t ldu, int r,
-                        float *part, hipStream_t st);
-// dC[s][j] = d[j] * sum_chunk part[chunk][j][s]
-hipError_t corr_reduce(const float *part, int64_t N, int64_t b, int r, const float *d, float *dC, hipStream_t st);
-// c[s*ldc + j] = sum_chunk part[chunk][j][s]
-hipError_t corr_sum(const float *part, int64_t N, int64_t b, int r, float *c, int64_t ldc, hipStream_t st);
-// y[s][n] += sum_j U[n,j] dC[s][j]
-hipError_t corr_apply(float *y, int64_t ldy, int64_t N, int64_t b, const float *U, int64_t ldu, int r,
-                      const float *dC, hipStream_t st);
+// ---- Low-rank correction of the pseudoinverse in FP64 (corr.hip) ----
+int corr_rpad(int r);  // r rounded up to the 32-column matrix tiles
+// x += U diag(d) U^T y for the FP32 signals y (FP64 products and sums, x FP64);
+// U: N x r FP64, leading dimension ldu; part and dC: corr64_workspace_doubles.
+hipError_t corr64(const float *y, int64_t ldy, double *x, int64_t ldx, int64_t N, int64_t b, const double *U,
+                  int64_t ldu, int r, const double *d, double *part, double *dC, hipStream_t st);
+size_t corr64_workspace_doubles(int64_t N, int64_t b, int r);
 
 // ---- Small elementwise helpers (eig.hip) ----
 hipError_t cast_f64_to_f32(const double *src, int64_t ld_src, float *dst, int64_t ld_dst, int64_t rows,
