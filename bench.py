@@ -297,6 +297,37 @@ def bench_fourier_extension(args, dev):
             "series_over_extension": round(e_fs / e_p, 1)}
 
 
+def bench_eigen_gap(args, dev):
+    """Figure 1's study from the GPU plans: #{eps < lambda < 1 - eps} for
+    W = 1/4, N = 2^4 .. 2^16, and for N = 2^16, W = 2^-14 .. 2^-2, with eps
+    in {1e-3, 1e-6, 1e-9, 1e-12}, beside the asymptotic count
+    (2/pi^2) log N log(1/eps - 1) (Section 2.2) and Corollary 1's bound."""
+    import torch
+
+    from paper_1611_04950_amd import slepian as S
+    log("bench: eigenvalue-gap study")
+    t0 = time.perf_counter()
+    epss = (1e-3, 1e-6, 1e-9, 1e-12)
+
+    def count(N, W, eps):
+        return int(S.slepian_plan(N, W, eps).info["r"])
+
+    vs_n = {f"{e:g}": [count(1 << lg, 0.25, e) for lg in range(4, 17)] for e in epss}
+    vs_w = {f"{e:g}": [count(1 << 16, 2.0 ** -k, e) for k in range(14, 1, -1)] for e in epss}
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    asym = {f"{e:g}": [round(2.0 / math.pi ** 2 * math.log(1 << lg) * math.log(1.0 / e - 1.0), 1)
+                       for lg in range(4, 17)] for e in epss}
+    cor1 = {f"{e:g}": round((8.0 / math.pi ** 2 * math.log(8 * (1 << 16)) + 12.0) * math.log(15.0 / e), 1)
+            for e in epss}
+    log(f"bench: eigenvalue gap, {2 * 13 * len(epss)} plans in {el:.1f} s; N = 2^16, W = 1/4: "
+        + ", ".join(f"eps {k}: {v[-1]}" for k, v in vs_n.items()))
+    return {"workload": "eigenvalue gap: W=1/4, N=2^4..2^16; N=2^16, W=2^-14..2^-2; eps 1e-3..1e-12",
+            "log2_N": list(range(4, 17)), "count_vs_N": vs_n, "asymptotic_vs_N": asym,
+            "log2_W": list(range(-14, -1)), "count_vs_W_at_N_2_16": vs_w,
+            "corollary1_bound_at_N_2_16": cor1, "plans": 2 * 13 * len(epss), "seconds": round(el, 2)}
+
+
 def bench_lsq(args, dev):
     """N = 2^20, W = 0.02, eps = 1e-6, 64 signals of 200 tones at 10 dB:
     Tikhonov (alpha = 1e-3) solve refined to a 1e-10 FP64 normal-equation
@@ -494,6 +525,7 @@ def main():
     precision = None if args.no_extra else bench_precision(args, dev)
     lsq = None if args.no_extra else bench_lsq(args, dev)
     fext = None if args.no_extra else bench_fourier_extension(args, dev)
+    egap = None if args.no_extra else bench_eigen_gap(args, dev)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GSamples/s", "n_gpus": 1,
@@ -522,6 +554,7 @@ def main():
         "precision_workload": precision,
         "least_squares_workload": lsq,
         "fourier_extension_workload": fext,
+        "eigenvalue_gap_study": egap,
     }
     print(json.dumps(out), flush=True)
 
