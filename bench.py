@@ -151,7 +151,7 @@ def bench_batching(args, dev):
     log("bench: batching workload, creating 512 plans")
     t0 = time.perf_counter()
     prec = S.SLEPIAN_MIXED if args.precision == "mixed" else S.SLEPIAN_FP32
-    plans = [S.slepian_plan(n, w, e, precision=prec) for n, w, e, _ in specs]
+    plans = S.slepian_plan_batch([(n, w, e) for n, w, e, _ in specs], precision=prec)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     xs = [synth.gaussian(n, bb, 4000 * 1000 + 100 * i, device=dev) for i, (n, _, _, bb) in enumerate(specs)]

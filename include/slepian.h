@@ -118,6 +118,18 @@ int slepian_plan(int64_t N, double W, double eps, slepian_plan_t *out);
 int slepian_plan_ex(int64_t N, double W, double eps, const slepian_plan_opts *opts,
                     slepian_plan_t *out);
 
+/* Many plans at once (Section 4.1 setup for each): plan i for N[i], W[i],
+ * eps[i] with options opts[i] (opts NULL: defaults for all; every plan on one
+ * device).  The same plans as n calls of slepian_plan_ex, with the
+ * eigensolves of all plans run together (one bisection, one inverse
+ * iteration and one normalisation launch per memory batch), which keeps the
+ * GPU busy where one plan's few hundred eigenvalues cannot.  Synchronous.
+ * out: n handles, written only on success; on any error no plan is created
+ * and the first failing status is returned (EINVAL, EGAP, ENOCONV, ENOMEM,
+ * EHIP). */
+int slepian_plan_batch(int n, const int64_t *N, const double *W, const double *eps, const slepian_plan_opts *opts,
+                       slepian_plan_t *out);
+
 /* Plan sizes and eigen-structure; info is host memory. */
 int slepian_plan_info_get(slepian_plan_t plan, slepian_plan_info *info);
 

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "slepian.h"
@@ -576,57 +577,74 @@ double asymptotic_width(int64_t N, double e) {
   return 2.0 / (M_PI * M_PI) * std::log((double)std::max<int64_t>(N, 2)) * std::log(1.0 / e - 1.0);
 }
 
-void build_eigen_state(Plan *P, hipStream_t st) {
-  const int64_t N = P->N, K = P->K;
-  double thr_lo = P->eps, thr_hi = 1.0 - P->eps;
-  if (P->alpha > 0) {
-    thr_lo = std::min(thr_lo, P->alpha * (1.0 + P->alpha) * P->eps);
-    thr_hi = std::max(thr_hi, 1.0 - P->eps / 3.0);
-  }
+// One plan's eigensolve in progress: the tridiagonal matrix, the index
+// window [lo, hi] (grown until its edge eigenvalues leave the thresholds),
+// and the window's vectors and eigenvalues once solved.
+struct EigState {
   Tridiag T;
-  build_tridiag(P, T, st);
-  int64_t h = (int64_t)(2.0 * asymptotic_width(N, std::min(thr_lo, 1.0 - thr_hi)) + 30.0);
-  int64_t lo = std::max<int64_t>(0, K - h), hi = std::min<int64_t>(N - 1, K + h);
-  double *V = nullptr;
-  std::vector<double> lam, res;
-  for (int attempt = 0;; ++attempt) {
-    const int64_t nv = hi - lo + 1;
-    dfree(V);
-    V = dalloc<double>((size_t)N * nv);
-    solve_vectors(P, T, lo, hi, V, st);
-    B64Ws bw;
-    {
-      Carver c0(nullptr);
-      carve_b64(P, nv, c0);
-      DBuf<char> ws(c0.off + 256);
-      Carver cv(ws.p);
-      bw = carve_b64(P, nv, cv);
-      DBuf<double> BV((size_t)N * nv), dl(nv), dr(nv);
-      run_b64(P, V, N, BV.p, N, nv, bw, st);
-      HIPCHK(rayleigh(V, BV.p, N, nv, dl.p, dr.p, st));
-      lam.assign(nv, 0.0);
-      res.assign(nv, 0.0);
-      HIPCHK(hipMemcpyAsync(lam.data(), dl.p, nv * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(res.data(), dr.p, nv * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-    }
-    for (int64_t c = 0; c < nv; ++c) {
-      if (!std::isfinite(lam[c]) || !(res[c] <= 1e-7)) {
-        dfree(V);
-        throw Fail{SLEPIAN_ENOCONV};
-      }
-    }
-    const bool ok_lo = lo == 0 || lam[0] >= thr_hi;
-    const bool ok_hi = hi == N - 1 || lam[nv - 1] <= thr_lo;
-    if (ok_lo && ok_hi) break;
-    if (attempt > 12) {
-      dfree(V);
-      throw Fail{SLEPIAN_ENOCONV};
-    }
-    h *= 2;
-    if (!ok_lo) lo = std::max<int64_t>(0, K - h);
-    if (!ok_hi) hi = std::min<int64_t>(N - 1, K + h);
+  double thr_lo = 0, thr_hi = 0;
+  int64_t h = 0, lo = 0, hi = 0;
+  double *V = nullptr;  // N x (hi - lo + 1)
+  std::vector<double> lam;
+  int attempt = 0;
+  bool done = false;
+  ~EigState() { dfree(V); }
+};
+
+void eig_init(const Plan *P, EigState &E, hipStream_t st) {
+  const int64_t N = P->N, K = P->K;
+  E.thr_lo = P->eps;
+  E.thr_hi = 1.0 - P->eps;
+  if (P->alpha > 0) {
+    E.thr_lo = std::min(E.thr_lo, P->alpha * (1.0 + P->alpha) * P->eps);
+    E.thr_hi = std::max(E.thr_hi, 1.0 - P->eps / 3.0);
   }
+  build_tridiag(P, E.T, st);
+  E.h = (int64_t)(2.0 * asymptotic_width(N, std::min(E.thr_lo, 1.0 - E.thr_hi)) + 30.0);
+  E.lo = std::max<int64_t>(0, K - E.h);
+  E.hi = std::min<int64_t>(N - 1, K + E.h);
+}
+
+// B's eigenvalues over the solved window (FP64 Rayleigh quotients, residual
+// check); true when the window brackets the thresholds, else the window is
+// widened and the vectors dropped for another solve.
+bool eig_check(const Plan *P, EigState &E, hipStream_t st) {
+  const int64_t N = P->N, K = P->K;
+  const int64_t nv = E.hi - E.lo + 1;
+  std::vector<double> res(nv);
+  {
+    Carver c0(nullptr);
+    carve_b64(P, nv, c0);
+    DBuf<char> ws(c0.off + 256);
+    Carver cv(ws.p);
+    B64Ws bw = carve_b64(P, nv, cv);
+    DBuf<double> BV((size_t)N * nv), dl(nv), dr(nv);
+    run_b64(P, E.V, N, BV.p, N, nv, bw, st);
+    HIPCHK(rayleigh(E.V, BV.p, N, nv, dl.p, dr.p, st));
+    E.lam.assign(nv, 0.0);
+    HIPCHK(hipMemcpyAsync(E.lam.data(), dl.p, nv * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(res.data(), dr.p, nv * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  for (int64_t c = 0; c < nv; ++c)
+    if (!std::isfinite(E.lam[c]) || !(res[c] <= 1e-7)) throw Fail{SLEPIAN_ENOCONV};
+  const bool ok_lo = E.lo == 0 || E.lam[0] >= E.thr_hi;
+  const bool ok_hi = E.hi == N - 1 || E.lam[nv - 1] <= E.thr_lo;
+  if (ok_lo && ok_hi) return E.done = true;
+  if (++E.attempt > 12) throw Fail{SLEPIAN_ENOCONV};
+  E.h *= 2;
+  if (!ok_lo) E.lo = std::max<int64_t>(0, K - E.h);
+  if (!ok_hi) E.hi = std::min<int64_t>(N - 1, K + E.h);
+  dfree(E.V);
+  E.V = nullptr;
+  return false;
+}
+
+void eig_finalize(Plan *P, EigState &E, hipStream_t st) {
+  const int64_t N = P->N, K = P->K;
+  const int64_t lo = E.lo, hi = E.hi;
+  const std::vector<double> &lam = E.lam;
+  const double *V = E.V;
   const int64_t nv = hi - lo + 1;
   P->win_lo = lo;
   P->win_hi = hi;
@@ -634,10 +652,7 @@ void build_eigen_state(Plan *P, hipStream_t st) {
   // K's gap condition (Corollary 2): lambda_{K-1} > eps, lambda_K < 1 - eps
   P->lam_Km1 = lam[K - 1 - lo];
   P->lam_K = lam[K - lo];
-  if (!(P->lam_Km1 > P->eps && P->lam_K < 1.0 - P->eps)) {
-    dfree(V);
-    throw Fail{SLEPIAN_EGAP};
-  }
+  if (!(P->lam_Km1 > P->eps && P->lam_K < 1.0 - P->eps)) throw Fail{SLEPIAN_EGAP};
   auto range = [&](double a, double b, int64_t &c0, int64_t &c1) {
     c0 = -1;
     c1 = -1;
@@ -681,7 +696,8 @@ void build_eigen_state(Plan *P, hipStream_t st) {
     HIPCHK(cast_f64_to_f32(P->U64, N, P->U32, P->ldu, N, P->u_r, st));
   }
   HIPCHK(hipStreamSynchronize(st));
-  dfree(V);
+  dfree(E.V);
+  E.V = nullptr;
   // weights of the low-rank corrections (Lemmas 5, 6, 7)
   const double al = P->alpha;
   P->proj.off = P->pinv.off = p0 - u0;
@@ -706,6 +722,85 @@ void build_eigen_state(Plan *P, hipStream_t st) {
   P->tik.set = P->tikm.set = 1;
   for (OpSet *o : {&P->proj, &P->pinv, &P->tik, &P->tikm}) upload_d(*o);
   build_corr_tiles(P, st);
+}
+
+void build_eigen_state(Plan *P, hipStream_t st) {
+  EigState E;
+  eig_init(P, E, st);
+  for (;;) {
+    const int64_t nv = E.hi - E.lo + 1;
+    E.V = dalloc<double>((size_t)P->N * nv);
+    solve_vectors(P, E.T, E.lo, E.hi, E.V, st);
+    if (eig_check(P, E, st)) break;
+  }
+  eig_finalize(P, E, st);
+}
+
+// Many plans' eigensolves together: the windows of all unfinished plans go
+// through one batched bisection / inverse iteration / normalisation
+// (eig_solve_many) per batch, batches filled up to the inverse-iteration
+// memory budget; each plan's arithmetic is that of build_eigen_state.
+void build_eigen_states(const std::vector<Plan *> &Ps, hipStream_t st) {
+  const size_t n = Ps.size();
+  std::vector<std::unique_ptr<EigState>> E(n);
+  for (size_t i = 0; i < n; ++i) {
+    E[i].reset(new EigState());
+    eig_init(Ps[i], *E[i], st);
+  }
+  const size_t budget = inviter_budget();
+  for (;;) {
+    std::vector<size_t> pend;
+    for (size_t i = 0; i < n; ++i)
+      if (!E[i]->done) pend.push_back(i);
+    if (pend.empty()) break;
+    size_t k = 0;
+    while (k < pend.size()) {
+      std::vector<size_t> grp;
+      size_t bytes = 0;
+      for (; k < pend.size(); ++k) {
+        const EigState &e = *E[pend[k]];
+        const size_t sb = inviter_scratch_bytes(Ps[pend[k]]->N, e.hi - e.lo + 1);
+        if (!grp.empty() && bytes + sb > budget) break;
+        grp.push_back(pend[k]);
+        bytes += sb;
+      }
+      if (grp.size() == 1 && bytes > budget) {
+        // one window larger than the budget: the chunked one-plan solve
+        const size_t i = grp[0];
+        EigState &e = *E[i];
+        e.V = dalloc<double>((size_t)Ps[i]->N * (e.hi - e.lo + 1));
+        solve_vectors(Ps[i], e.T, e.lo, e.hi, e.V, st);
+      } else {
+        std::vector<EigJob> jobs(grp.size());
+        std::vector<std::unique_ptr<DBuf<double>>> th;
+        std::vector<std::unique_ptr<DBuf<char>>> scr;
+        for (size_t g = 0; g < grp.size(); ++g) {
+          const Plan *P = Ps[grp[g]];
+          EigState &e = *E[grp[g]];
+          const int64_t nv = e.hi - e.lo + 1;
+          e.V = dalloc<double>((size_t)P->N * nv);
+          th.emplace_back(new DBuf<double>(nv));
+          scr.emplace_back(new DBuf<char>(inviter_scratch_bytes(P->N, nv)));
+          EigJob &J = jobs[g];
+          J.a = e.T.a;
+          J.e2 = e.T.e2;
+          J.off = e.T.off;
+          J.N = P->N;
+          J.t0 = P->N - 1 - e.hi;  // ascending index of l = hi
+          J.count = nv;
+          J.gl = e.T.gl;
+          J.gu = e.T.gu;
+          J.pivmin = e.T.pivmin;
+          J.theta = th.back()->p;
+          J.V = e.V;
+          J.scratch = scr.back()->p;
+        }
+        HIPCHK(eig_solve_many(jobs.data(), (int)jobs.size(), 3, st));
+      }
+      for (size_t i : grp) eig_check(Ps[i], *E[i], st);
+    }
+  }
+  for (size_t i = 0; i < n; ++i) eig_finalize(Ps[i], *E[i], st);
 }
 
 int validate_domain(int64_t N, double W, double eps, const slepian_plan_opts *o) {
@@ -798,6 +893,54 @@ int slepian_plan_ex(int64_t N, double W, double eps, const slepian_plan_opts *op
       throw;
     }
     *out = P;
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_plan_batch(int n, const int64_t *N, const double *W, const double *eps, const slepian_plan_opts *opts,
+                       slepian_plan_t *out) {
+  if (n < 0 || (n > 0 && (!N || !W || !eps || !out))) return SLEPIAN_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    const int v = validate_domain(N[i], W[i], eps[i], opts ? &opts[i] : nullptr);
+    if (v != SLEPIAN_OK) return v;
+  }
+  if (n == 0) return SLEPIAN_OK;
+  return guarded([&]() -> int {
+    int dev = opts && opts[0].device >= 0 ? opts[0].device : -1;
+    if (dev < 0) HIPCHK(hipGetDevice(&dev));
+    for (int i = 1; i < n; ++i)
+      if (opts && opts[i].device >= 0 && opts[i].device != dev) return SLEPIAN_EINVAL;
+    DeviceGuard dg(dev);
+    std::vector<Plan *> Ps;
+    hipStream_t st = nullptr;
+    try {
+      for (int i = 0; i < n; ++i) {
+        Plan *P = new Plan();
+        Ps.push_back(P);
+        const slepian_plan_opts *o = opts ? &opts[i] : nullptr;
+        P->device = dev;
+        P->N = N[i];
+        P->W = W[i];
+        P->eps = eps[i];
+        P->alpha = o ? o->alpha : 0.0;
+        P->precision = o ? o->precision : SLEPIAN_FP32;
+        P->K = (o && o->K > 0) ? o->K : (int64_t)std::floor(2.0 * (double)N[i] * W[i] + 0.5);
+        if (P->K < 1 || P->K > N[i] - 1) throw Fail{SLEPIAN_EGAP};
+      }
+      HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      for (Plan *P : Ps) build_fft_state(P, st);
+      build_eigen_states(Ps, st);
+      HIPCHK(hipStreamSynchronize(st));
+      (void)hipStreamDestroy(st);
+    } catch (...) {
+      if (st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+      }
+      for (Plan *P : Ps) delete P;
+      throw;
+    }
+    for (int i = 0; i < n; ++i) out[i] = Ps[i];
     return SLEPIAN_OK;
   });
 }

@@ -15,6 +15,7 @@
 // lambda = s^T B s with B applied in FP64 by the FFT product.
 #include <cfloat>
 #include <cmath>
+#include <vector>
 
 #include "common.h"
 #include "kernels.h"
@@ -82,11 +83,10 @@ __device__ __forceinline__ int sturm_count(const double *__restrict__ a, const d
 // One workgroup per eigenvalue theta_t (ascending index t): keep
 // [lo, hi) with count(lo) <= t < count(hi) and split it at blockDim.x points
 // per round until it is as narrow as FP64 allows.
-__global__ __launch_bounds__(256) void k_bisect(const double *__restrict__ a, const double *__restrict__ e2,
-                                                int64_t N, double gl, double gu, double pivmin, double atol,
-                                                int64_t t0, double *__restrict__ theta) {
+__device__ __forceinline__ void bisect_body(const double *__restrict__ a, const double *__restrict__ e2, int64_t N,
+                                            double gl, double gu, double pivmin, double atol, int64_t t,
+                                            double *__restrict__ theta_t) {
   __shared__ int first;
-  const int64_t t = t0 + blockIdx.x;
   const int P = blockDim.x;
   double lo = gl, hi = gu;
   for (int round = 0; round < 24; ++round) {
@@ -105,7 +105,13 @@ __global__ __launch_bounds__(256) void k_bisect(const double *__restrict__ a, co
     hi = nhi;
     __syncthreads();
   }
-  if (threadIdx.x == 0) theta[blockIdx.x] = 0.5 * (lo + hi);
+  if (threadIdx.x == 0) *theta_t = 0.5 * (lo + hi);
+}
+
+__global__ __launch_bounds__(256) void k_bisect(const double *__restrict__ a, const double *__restrict__ e2,
+                                                int64_t N, double gl, double gu, double pivmin, double atol,
+                                                int64_t t0, double *__restrict__ theta) {
+  bisect_body(a, e2, N, gl, gu, pivmin, atol, t0 + blockIdx.x, theta + blockIdx.x);
 }
 
 hipError_t tridiag_bisect(const double *a, const double *e2, int64_t N, double gl, double gu, double pivmin,
@@ -179,10 +185,9 @@ __device__ __forceinline__ void bst(double v, __amdgpu_buffer_rsrc_t r, int vo, 
 // (unnormalised) iterate is left in s.x.  Rows of the scratch arrays are
 // addressed from a base that moves with the block, so no offset exceeds a
 // block's span.
-__global__ __launch_bounds__(64) void k_inviter(const double *__restrict__ a, const double *__restrict__ off,
-                                                int64_t N, const double *__restrict__ theta, int64_t count,
-                                                InvScratch s, double tiny, int iters) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void inviter_body(const double *__restrict__ a, const double *__restrict__ off,
+                                             int64_t N, const double *__restrict__ theta, int64_t count,
+                                             InvScratch s, double tiny, int iters, int64_t j) {
   if (j >= count) return;
   const double th = theta[j];
   const int64_t C = count;
@@ -323,12 +328,18 @@ __global__ __launch_bounds__(64) void k_inviter(const double *__restrict__ a, co
   }
 }
 
+__global__ __launch_bounds__(64) void k_inviter(const double *__restrict__ a, const double *__restrict__ off,
+                                                int64_t N, const double *__restrict__ theta, int64_t count,
+                                                InvScratch s, double tiny, int iters) {
+  inviter_body(a, off, N, theta, count, s, tiny, iters, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // Normalise to unit 2-norm, sign so that the first entry of magnitude
 // >= 1e-3 max|v| is positive, and write column count-1-j of V.
-__global__ __launch_bounds__(256) void k_normalize(InvScratch s, int64_t N, int64_t count, double *__restrict__ V) {
+__device__ __forceinline__ void normalize_body(InvScratch s, int64_t N, int64_t count, double *__restrict__ V,
+                                               int64_t j) {
   __shared__ double red[256];
   __shared__ int64_t redi[256];
-  const int64_t j = blockIdx.x;
   const int64_t C = count;
   double ss = 0.0, mx = 0.0;
   for (int64_t k = threadIdx.x; k < N; k += blockDim.x) {
@@ -371,6 +382,10 @@ __global__ __launch_bounds__(256) void k_normalize(InvScratch s, int64_t N, int6
   for (int64_t k = threadIdx.x; k < N; k += blockDim.x) out[k] = s.x[k * C + j] * sc;
 }
 
+__global__ __launch_bounds__(256) void k_normalize(InvScratch s, int64_t N, int64_t count, double *__restrict__ V) {
+  normalize_body(s, N, count, V, blockIdx.x);
+}
+
 hipError_t tridiag_inviter(const double *a, const double *off, int64_t N, const double *theta, int64_t count,
                            double *V, void *scratch, int iters, hipStream_t st) {
   InvScratch s = carve(scratch, N, count);
@@ -380,6 +395,102 @@ hipError_t tridiag_inviter(const double *a, const double *off, int64_t N, const 
                      tiny, iters);
   hipLaunchKernelGGL(k_normalize, dim3((unsigned)count), dim3(256), 0, st, s, N, count, V);
   return hipGetLastError();
+}
+
+// ---- many plans in one launch ----
+// Workgroup w belongs to job q with start[q] <= w < start[q + 1] (binary
+// search), and runs the same body as the one-plan kernels on that job's
+// operands, so a plan's vectors do not depend on the company it is solved in.
+
+struct EigJobDev {
+  const double *a, *e2, *off;
+  int64_t N, t0, count;
+  double gl, gu, pivmin, atol, tiny;
+  double *theta, *V;
+  InvScratch s;
+};
+
+__device__ __forceinline__ int job_of(const int *__restrict__ start, int m, int w) {
+  int lo = 0, hi = m;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= w) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_bisect_many(const EigJobDev *__restrict__ jobs, const int *__restrict__ start,
+                                                     int m) {
+  const int q = job_of(start, m, blockIdx.x);
+  const EigJobDev &J = jobs[q];
+  const int64_t i = (int64_t)blockIdx.x - start[q];
+  bisect_body(J.a, J.e2, J.N, J.gl, J.gu, J.pivmin, J.atol, J.t0 + i, J.theta + i);
+}
+
+__global__ __launch_bounds__(64) void k_inviter_many(const EigJobDev *__restrict__ jobs, const int *__restrict__ start,
+                                                     int m, int iters) {
+  const int q = job_of(start, m, blockIdx.x);
+  const EigJobDev &J = jobs[q];
+  const int64_t j = ((int64_t)blockIdx.x - start[q]) * 64 + threadIdx.x;
+  inviter_body(J.a, J.off, J.N, J.theta, J.count, J.s, J.tiny, iters, j);
+}
+
+__global__ __launch_bounds__(256) void k_normalize_many(const EigJobDev *__restrict__ jobs,
+                                                        const int *__restrict__ start, int m) {
+  const int q = job_of(start, m, blockIdx.x);
+  const EigJobDev &J = jobs[q];
+  normalize_body(J.s, J.N, J.count, J.V, (int64_t)blockIdx.x - start[q]);
+}
+
+hipError_t eig_solve_many(const EigJob *jobs, int m, int iters, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  std::vector<EigJobDev> dj(m);
+  std::vector<int> sb(m + 1), si(m + 1);
+  sb[0] = si[0] = 0;
+  for (int q = 0; q < m; ++q) {
+    const EigJob &J = jobs[q];
+    EigJobDev &d = dj[q];
+    d.a = J.a;
+    d.e2 = J.e2;
+    d.off = J.off;
+    d.N = J.N;
+    d.t0 = J.t0;
+    d.count = J.count;
+    d.gl = J.gl;
+    d.gu = J.gu;
+    d.pivmin = J.pivmin;
+    d.atol = DBL_EPSILON * fmax(fabs(J.gl), fabs(J.gu));
+    d.tiny = DBL_EPSILON * 0.25 * (double)J.N * (double)J.N;
+    d.theta = J.theta;
+    d.V = J.V;
+    d.s = carve(J.scratch, J.N, J.count);
+    if ((int64_t)sb[q] + J.count > 0x7fffffff) return hipErrorInvalidValue;
+    sb[q + 1] = sb[q] + (int)J.count;
+    si[q + 1] = si[q] + (int)((J.count + 63) / 64);
+  }
+  EigJobDev *djd = nullptr;
+  int *sd = nullptr;
+  hipError_t e = hipMalloc(&djd, m * sizeof(EigJobDev));
+  if (e != hipSuccess) return e;
+  e = hipMalloc(&sd, 2 * (m + 1) * sizeof(int));
+  if (e != hipSuccess) {
+    (void)hipFree(djd);
+    return e;
+  }
+  e = hipMemcpyAsync(djd, dj.data(), m * sizeof(EigJobDev), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(sd, sb.data(), (m + 1) * sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(sd + m + 1, si.data(), (m + 1) * sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_bisect_many, dim3((unsigned)sb[m]), dim3(256), 0, st, djd, sd, m);
+    hipLaunchKernelGGL(k_inviter_many, dim3((unsigned)si[m]), dim3(64), 0, st, djd, sd + m + 1, m, iters);
+    hipLaunchKernelGGL(k_normalize_many, dim3((unsigned)sb[m]), dim3(256), 0, st, djd, sd, m);
+    e = hipGetLastError();
+  }
+  const hipError_t e2 = hipStreamSynchronize(st);
+  (void)hipFree(djd);
+  (void)hipFree(sd);
+  return e != hipSuccess ? e : e2;
 }
 
 __global__ __launch_bounds__(256) void k_rayleigh(const double *__restrict__ V, const double *__restrict__ BV,

@@ -95,6 +95,20 @@ hipError_t tridiag_inviter(const double *a, const double *off, int64_t N, const 
                            double *V, void *scratch, int iters, hipStream_t st);
 
 // lam[j] = v_j^T (B v_j), res[j] = ||B v_j - lam_j v_j|| for unit v_j.
+// Many plans' eigensolves in three launches (bisection, inverse iteration,
+// normalisation), each job solving `count` eigenvalues of its tridiagonal
+// matrix from ascending index t0 into theta and the vectors into V (N x count,
+// the same order as tridiag_inviter), with inviter_scratch_bytes(N, count)
+// bytes of scratch.  Synchronous.
+struct EigJob {
+  const double *a, *e2, *off;
+  int64_t N, t0, count;
+  double gl, gu, pivmin;
+  double *theta, *V;
+  void *scratch;
+};
+hipError_t eig_solve_many(const EigJob *jobs, int m, int iters, hipStream_t st);
+
 hipError_t rayleigh(const double *V, const double *BV, int64_t N, int64_t count, double *lam, double *res,
                     hipStream_t st);
 

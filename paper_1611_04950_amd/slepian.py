@@ -35,7 +35,7 @@ SLEPIAN_PINV, SLEPIAN_TIKHONOV = 0, 1
 SLEPIAN_OP_PROJECT, SLEPIAN_OP_COEFFS, SLEPIAN_OP_LSQ = 0, 1, 2
 
 EXPORTED = [
-    "slepian_plan", "slepian_plan_ex", "slepian_plan_info_get", "slepian_plan_eigenpairs",
+    "slepian_plan", "slepian_plan_ex", "slepian_plan_batch", "slepian_plan_info_get", "slepian_plan_eigenpairs",
     "slepian_plan_save", "slepian_plan_load", "slepian_plan_destroy", "slepian_workspace_size",
     "slepian_project", "slepian_project_ex", "slepian_coeffs", "slepian_lsq", "slepian_apply_b64",
     "slepian_group_create", "slepian_group_project", "slepian_group_destroy", "slepian_status_string",
@@ -75,6 +75,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     sig = {
         "slepian_plan": [i64, dbl, dbl, C.POINTER(vp)],
         "slepian_plan_ex": [i64, dbl, dbl, C.POINTER(PlanOpts), C.POINTER(vp)],
+        "slepian_plan_batch": [i32, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl), C.POINTER(PlanOpts),
+                               C.POINTER(vp)],
         "slepian_plan_info_get": [vp, C.POINTER(PlanInfo)],
         "slepian_plan_eigenpairs": [vp, C.POINTER(i64), C.POINTER(i64), vp, vp, i64, i64],
         "slepian_plan_save": [vp, C.c_char_p],
@@ -164,6 +166,22 @@ def slepian_plan(N: int, W: float, eps: float, alpha: float = 0.0, K: int = 0,
     opts = PlanOpts(alpha, K, precision, device)
     _check(_lib.slepian_plan_ex(N, W, eps, C.byref(opts), C.byref(h)), "slepian_plan")
     return Plan(h.value)
+
+
+def slepian_plan_batch(specs, alpha: float = 0.0, K: int = 0, precision: int = SLEPIAN_FP32,
+                       device: int = -1) -> list:
+    """Plans for (N, W, eps) triples in one call (the eigensolves run
+    together); the options apply to every plan."""
+    n = len(specs)
+    if n == 0:
+        return []
+    Ns = (C.c_int64 * n)(*[int(sp[0]) for sp in specs])
+    Ws = (C.c_double * n)(*[float(sp[1]) for sp in specs])
+    Es = (C.c_double * n)(*[float(sp[2]) for sp in specs])
+    opts = (PlanOpts * n)(*[PlanOpts(alpha, K, precision, device) for _ in range(n)])
+    hs = (C.c_void_p * n)()
+    _check(_lib.slepian_plan_batch(n, Ns, Ws, Es, opts, hs), "slepian_plan_batch")
+    return [Plan(h) for h in hs]
 
 
 def slepian_plan_info_get(plan: Plan) -> dict:

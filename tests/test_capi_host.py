@@ -56,6 +56,20 @@ def test_plan_options_checked():
         assert S._lib.slepian_plan_ex(100, 0.1, 1e-6, C.byref(opts), C.byref(h)) == S.SLEPIAN_EINVAL
 
 
+def test_plan_batch_checked_before_any_device_work():
+    """A bad triple anywhere in the batch fails the whole call before any
+    device work, and no handle is written."""
+    n = 3
+    Ns = (C.c_int64 * n)(100, 200, 1)
+    Ws = (C.c_double * n)(0.1, 0.1, 0.1)
+    Es = (C.c_double * n)(1e-6, 1e-6, 1e-6)
+    hs = (C.c_void_p * n)()
+    assert S._lib.slepian_plan_batch(n, Ns, Ws, Es, None, hs) == S.SLEPIAN_EINVAL
+    assert all(h is None for h in hs)
+    assert S._lib.slepian_plan_batch(-1, Ns, Ws, Es, None, hs) == S.SLEPIAN_EINVAL
+    assert S._lib.slepian_plan_batch(0, None, None, None, None, None) == S.SLEPIAN_OK
+
+
 def test_null_handles():
     lib = S._lib
     assert lib.slepian_plan_destroy(None) == S.SLEPIAN_OK
