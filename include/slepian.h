@@ -70,7 +70,8 @@ enum slepian_lsq_mode {
 enum slepian_op {
   SLEPIAN_OP_PROJECT = 0,
   SLEPIAN_OP_COEFFS = 1,
-  SLEPIAN_OP_LSQ = 2
+  SLEPIAN_OP_LSQ = 2,
+  SLEPIAN_OP_MULTIBAND = 3  /* batch argument of slepian_workspace_size = bands x signals */
 };
 
 typedef struct {
@@ -171,6 +172,21 @@ int slepian_project(slepian_plan_t plan, const float *x, int64_t ldx, float *y, 
 int slepian_project_ex(slepian_plan_t plan, int precision, const float *x, int64_t ldx,
                        float *y, int64_t ldy, int64_t batch, void *work, size_t work_bytes,
                        void *stream);
+
+/* Projection onto a multiband (modulated Slepian) dictionary (Section 2.3:
+ * the Slepian basis modulated to several frequency bands and merged): for
+ * band centres freqs[i] (cycles/sample; 0 for the baseband band, otherwise
+ * W <= f <= 1/2 - W; centres at least 2W apart, so the bands [f - W, f + W]
+ * do not overlap)
+ *     y = sum_i w_i Re(E_i P~ E_i^* x),  E_i = diag(exp(2 pi i f_i n)),
+ * w_i = 2 for f_i > 0 (the band pair +-f_i of a real signal), 1 for f_i = 0,
+ * P~ the plan's fast projection (Corollary 2) in the plan's precision.  The
+ * sum is the projection onto the union of the modulated subspaces up to the
+ * bands' mutual leakage.  x, y: N x batch FP32 real (y may equal x, no other
+ * overlap); 1 <= nbands <= 64; EINVAL on bad bands.  Workspace:
+ * slepian_workspace_size(plan, SLEPIAN_OP_MULTIBAND, nbands * batch). */
+int slepian_project_multiband(slepian_plan_t plan, int nbands, const double *freqs, const float *x, int64_t ldx,
+                              float *y, int64_t ldy, int64_t batch, void *work, size_t work_bytes, void *stream);
 
 /* Slepian coefficients c = S_K^T x (Section 2.3, "A fast factorization":
  * the K numbers that represent x), exact (dense) semantics.  The first call

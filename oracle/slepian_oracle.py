@@ -45,7 +45,8 @@ __all__ = [
     "dense_eig", "slepian_tridiagonal", "slepian_vectors",
     "transition_plan", "partition", "projection_d", "pinv_d", "tikhonov_g",
     "project_exact", "project_fast", "pinv_exact", "pinv_threshold", "pinv_fast",
-    "tikhonov_exact", "tikhonov_fast", "tikhonov_cg", "coeffs_exact",
+    "tikhonov_exact", "tikhonov_fast", "tikhonov_cg", "coeffs_exact", "multiband_fast", "multiband_exact",
+    "multiband_sum_exact",
     "cor1_bound", "zhu_wakin_bound", "asymptotic_count", "sign_fix",
 ]
 
@@ -424,3 +425,65 @@ def tikhonov_fast(N: int, W: float, eps: float, alpha: float, y: np.ndarray,
         tp = transition_plan(N, W, alpha * (1 + alpha) * eps, 1 - eps / 3.0)
     g, sel = tikhonov_g(tp["lam"], alpha, eps)
     return apply_prolate(N, W, y) / (1 + alpha) + _lowrank(tp["S"][:, sel], g[sel], y)
+
+
+# ---------------------------------------------------------------------------
+# Multiband (modulated Slepian) dictionaries (Section 2.3)
+# ---------------------------------------------------------------------------
+
+def _band_weight(f: float) -> float:
+    return 2.0 if f > 0 else 1.0
+
+
+def multiband_fast(N: int, W: float, eps: float, freqs, x: np.ndarray, tp: dict | None = None) -> np.ndarray:
+    """Sum over bands of the modulated fast projections for a real signal x:
+    y = sum_i w_i Re(E_i P~ E_i^* x), E_i = diag(exp(2 pi i f_i n)), w_i = 2
+    for f_i > 0 (the pair +-f_i) and 1 for f_i = 0, P~ = B + U diag(d) U^T
+    (Corollary 2) applied to the real and imaginary parts (B is real)."""
+    if tp is None:
+        tp = transition_plan(N, W, eps, 1 - eps)
+    x = np.asarray(x, dtype=np.float64)
+    n = np.arange(N)
+    y = np.zeros_like(x)
+    for f in freqs:
+        e = np.exp(2j * np.pi * f * n)
+        z = (np.conj(e)[:, None] * x) if x.ndim == 2 else np.conj(e) * x
+        pz = project_fast(N, W, eps, z.real, tp=tp) + 1j * project_fast(N, W, eps, z.imag, tp=tp)
+        y += _band_weight(f) * ((e[:, None] * pz).real if x.ndim == 2 else (e * pz).real)
+    return y
+
+
+def multiband_exact(N: int, W: float, freqs, x: np.ndarray, K: int | None = None) -> np.ndarray:
+    """Orthogonal projection of a real x onto the span of the modulated
+    Slepian bases E_f S_K, f in {+-f_i} (dense; Section 2.3's merged
+    dictionary)."""
+    if K is None:
+        K = choose_K(N, W)
+    _, S = dense_eig(N, W)
+    SK = S[:, :K]
+    n = np.arange(N)
+    cols = []
+    for f in freqs:
+        e = np.exp(2j * np.pi * f * n)
+        cols.append(e[:, None] * SK)
+        if f > 0:
+            cols.append(np.conj(e)[:, None] * SK)
+    Q, _ = np.linalg.qr(np.hstack(cols))
+    x = np.asarray(x, dtype=np.float64)
+    return (Q @ (Q.conj().T @ x)).real
+
+
+def multiband_sum_exact(N: int, W: float, freqs, x: np.ndarray, K: int | None = None) -> np.ndarray:
+    """sum_i w_i Re(E_i S_K S_K^T E_i^* x) with the dense S_K: what the fast
+    sum approximates band by band (Corollary 2 per band)."""
+    if K is None:
+        K = choose_K(N, W)
+    _, S = dense_eig(N, W)
+    SK = S[:, :K]
+    n = np.arange(N)
+    x = np.asarray(x, dtype=np.float64)
+    y = np.zeros_like(x)
+    for f in freqs:
+        e = np.exp(2j * np.pi * f * n)[:, None]
+        y += _band_weight(f) * (e * (SK @ (SK.T @ (np.conj(e) * x)))).real
+    return y

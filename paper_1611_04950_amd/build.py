@@ -21,7 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libslepian.so")
 
-SOURCES = ["fft.hip", "fft2.hip", "eig.hip", "corr.hip", "corr_mfma.hip", "lsq.hip", "capi.cpp", "trace.cpp"]
+SOURCES = ["fft.hip", "fft2.hip", "eig.hip", "corr.hip", "corr_mfma.hip", "lsq.hip", "multiband.hip", "capi.cpp",
+           "trace.cpp"]
 ARCH = os.environ.get("SLEPIAN_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -339,6 +339,11 @@ size_t op_workspace(const Plan *P, int op, int64_t b) {
       carve_tik(P, b, c2);
       return std::max(c1.off, c2.off) + 256;
     }
+    case SLEPIAN_OP_MULTIBAND:  // b = bands x signals
+      cv.take<float>((size_t)P->N * 2 * b);
+      cv.take<float>((size_t)P->N * 2 * b);
+      carve_project(P, P->proj, 2 * b, cv, P->precision);
+      break;
     default:
       return 0;
   }
@@ -1003,7 +1008,7 @@ int slepian_plan_eigenpairs(slepian_plan_t P, int64_t *l_first, int64_t *count, 
 }
 
 int slepian_workspace_size(slepian_plan_t P, int op, int64_t batch, size_t *bytes) {
-  if (!P || !bytes || batch < 0 || op < SLEPIAN_OP_PROJECT || op > SLEPIAN_OP_LSQ) return SLEPIAN_EINVAL;
+  if (!P || !bytes || batch < 0 || op < SLEPIAN_OP_PROJECT || op > SLEPIAN_OP_MULTIBAND) return SLEPIAN_EINVAL;
   *bytes = op_workspace(P, op, batch);
   return SLEPIAN_OK;
 }
@@ -1027,6 +1032,43 @@ int slepian_project_ex(slepian_plan_t P, int precision, const float *x, int64_t 
     Carver cv(ws);
     ProjWs w = carve_project(P, P->proj, batch, cv, precision);
     run_fast_op(P, P->proj, 1.0f, 0.0f, x, ldx, y, ldy, batch, w, st, precision);
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_project_multiband(slepian_plan_t P, int nbands, const double *freqs, const float *x, int64_t ldx,
+                              float *y, int64_t ldy, int64_t batch, void *work, size_t work_bytes, void *stream) {
+  if (bad_signal_args(P, x, ldx, y, ldy, batch)) return SLEPIAN_EINVAL;
+  if (nbands < 1 || nbands > kMaxBands || !freqs) return SLEPIAN_EINVAL;
+  BandSet bs;
+  bs.J = nbands;
+  for (int i = 0; i < nbands; ++i) {
+    const double f = freqs[i];
+    // a band [f - W, f + W] inside (0, 1/2), or the baseband band f = 0
+    if (!(f == 0.0 || (f >= P->W && f <= 0.5 - P->W))) return SLEPIAN_EINVAL;
+    for (int k = 0; k < i; ++k)
+      if (std::fabs(f - freqs[k]) < 2.0 * P->W) return SLEPIAN_EINVAL;  // bands overlap
+    bs.f[i] = f;
+  }
+  if (2 * (int64_t)nbands * batch > 32 * 65535) return SLEPIAN_EINVAL;
+  if (batch == 0) return SLEPIAN_OK;
+  if (x != y) {
+    const char *xa = (const char *)x, *xe = (const char *)(x + (batch - 1) * ldx + P->N);
+    const char *ya = (const char *)y, *ye = (const char *)(y + (batch - 1) * ldy + P->N);
+    if (xa < ye && ya < xe) return SLEPIAN_EINVAL;
+  }
+  return guarded([&]() -> int {
+    DeviceGuard dg(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = P->N, nb = (int64_t)nbands * batch;
+    void *ws = get_ws(P, work, work_bytes, op_workspace(P, SLEPIAN_OP_MULTIBAND, nb));
+    Carver cv(ws);
+    float *z = cv.take<float>((size_t)N * 2 * nb);
+    float *pz = cv.take<float>((size_t)N * 2 * nb);
+    ProjWs w = carve_project(P, P->proj, 2 * nb, cv, P->precision);
+    HIPCHK(band_demod(x, ldx, N, batch, bs, z, N, st));
+    run_fast_op(P, P->proj, 1.0f, 0.0f, z, N, pz, N, 2 * nb, w, st, P->precision);
+    HIPCHK(band_remod(pz, N, N, batch, bs, y, ldy, st));
     return SLEPIAN_OK;
   });
 }

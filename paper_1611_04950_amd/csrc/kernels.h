@@ -109,6 +109,20 @@ struct EigJob {
 };
 hipError_t eig_solve_many(const EigJob *jobs, int m, int iters, hipStream_t st);
 
+// ---- Multiband dictionaries (multiband.hip) ----
+constexpr int kMaxBands = 64;
+struct BandSet {  // band centres (cycles/sample), passed by value to the kernels
+  int J = 0;
+  double f[kMaxBands];
+};
+// z: 2 J b signals (leading dimension ldz): the real and imaginary parts of
+// E_{f_i}^* x_s at 2 (i b + s) and 2 (i b + s) + 1
+hipError_t band_demod(const float *x, int64_t ldx, int64_t N, int64_t b, const BandSet &bs, float *z, int64_t ldz,
+                      hipStream_t st);
+// y_s = sum_i w_i Re(E_{f_i} (p_{2(ib+s)} + i p_{2(ib+s)+1})), w_i = 2 (f_i > 0) or 1 (f_i = 0)
+hipError_t band_remod(const float *p, int64_t ldp, int64_t N, int64_t b, const BandSet &bs, float *y, int64_t ldy,
+                      hipStream_t st);
+
 hipError_t rayleigh(const double *V, const double *BV, int64_t N, int64_t count, double *lam, double *res,
                     hipStream_t st);
 

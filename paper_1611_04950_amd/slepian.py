@@ -32,12 +32,13 @@ SLEPIAN_EIO = -8
 
 SLEPIAN_FP32, SLEPIAN_MIXED, SLEPIAN_BF16_RAW = 0, 1, 2
 SLEPIAN_PINV, SLEPIAN_TIKHONOV = 0, 1
-SLEPIAN_OP_PROJECT, SLEPIAN_OP_COEFFS, SLEPIAN_OP_LSQ = 0, 1, 2
+SLEPIAN_OP_PROJECT, SLEPIAN_OP_COEFFS, SLEPIAN_OP_LSQ, SLEPIAN_OP_MULTIBAND = 0, 1, 2, 3
 
 EXPORTED = [
     "slepian_plan", "slepian_plan_ex", "slepian_plan_batch", "slepian_plan_info_get", "slepian_plan_eigenpairs",
     "slepian_plan_save", "slepian_plan_load", "slepian_plan_destroy", "slepian_workspace_size",
-    "slepian_project", "slepian_project_ex", "slepian_coeffs", "slepian_lsq", "slepian_apply_b64",
+    "slepian_project", "slepian_project_ex", "slepian_project_multiband", "slepian_coeffs", "slepian_lsq",
+    "slepian_apply_b64",
     "slepian_group_create", "slepian_group_project", "slepian_group_destroy", "slepian_status_string",
     "slepian_trace_enable", "slepian_trace_read",
 ]
@@ -85,6 +86,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "slepian_workspace_size": [vp, i32, i64, C.POINTER(sz)],
         "slepian_project": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_project_ex": [vp, i32, vp, i64, vp, i64, i64, vp, sz, vp],
+        "slepian_project_multiband": [vp, i32, C.POINTER(dbl), vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_coeffs": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_lsq": [vp, i32, dbl, vp, i64, vp, i64, i64, dbl, i32, vp, sz, vp, C.POINTER(LsqReport)],
         "slepian_apply_b64": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
@@ -231,6 +233,21 @@ def slepian_project(plan: Plan, x: torch.Tensor, y: torch.Tensor | None = None,
     prec = plan.info["precision"] if precision is None else precision
     _check(_lib.slepian_project_ex(plan.handle, prec, _ptr(x), ldx, _ptr(y), ldy, x.shape[0], _ptr(work), wb,
                                    _stream(x)), "slepian_project")
+    return y
+
+
+def slepian_project_multiband(plan: Plan, freqs, x: torch.Tensor, y: torch.Tensor | None = None,
+                              work: torch.Tensor | None = None) -> torch.Tensor:
+    """Projection onto the union of the Slepian subspaces modulated to the
+    band centres `freqs` (see include/slepian.h)."""
+    x, ldx = _signals(x, plan.N, torch.float32, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    y, ldy = _signals(y, plan.N, torch.float32, "y")
+    f = (C.c_double * len(freqs))(*[float(v) for v in freqs])
+    wb = 0 if work is None else work.numel() * work.element_size()
+    _check(_lib.slepian_project_multiband(plan.handle, len(freqs), f, _ptr(x), ldx, _ptr(y), ldy, x.shape[0],
+                                          _ptr(work), wb, _stream(x)), "slepian_project_multiband")
     return y
 
 
