@@ -40,6 +40,7 @@ extern "C" {
 
 typedef struct slepian_plan_s *slepian_plan_t;
 typedef struct slepian_group_s *slepian_group_t;
+typedef struct slepian_bands_s *slepian_bands_t;
 
 enum slepian_status {
   SLEPIAN_OK = 0,
@@ -187,6 +188,28 @@ int slepian_project_ex(slepian_plan_t plan, int precision, const float *x, int64
  * slepian_workspace_size(plan, SLEPIAN_OP_MULTIBAND, nbands * batch). */
 int slepian_project_multiband(slepian_plan_t plan, int nbands, const double *freqs, const float *x, int64_t ldx,
                               float *y, int64_t ldy, int64_t batch, void *work, size_t work_bytes, void *stream);
+
+/* Prepared band set for the same multiband projection (Section 2.3), computed
+ * with one FFT product instead of one per band.  For real x,
+ * Re(E_f B E_f^* x) is the Toeplitz product with the kernel
+ * cos(2 pi f m) sin(2 pi W m)/(pi m), so the bands' B parts add up to one real
+ * symmetric Toeplitz product, whose circulant spectrum (FP64 transform, stored
+ * FP32) and a table of cos(2 pi f_i n), -sin(2 pi f_i n) (2 nbands x N FP32)
+ * are built here; the correction parts form one correction of rank
+ * 2 nbands r (r = the plan's transition count, at most 128, else ENOTSUP),
+ * in the plan's precision (FP32, or BF16 hi/lo operands for MIXED and
+ * BF16_RAW).  The result equals slepian_project_multiband's up to FP32
+ * rounding.  The band rules and errors are slepian_project_multiband's; the
+ * plan must outlive the band set.  Setup is synchronous. */
+int slepian_bands_create(slepian_plan_t plan, int nbands, const double *freqs, slepian_bands_t *out);
+int slepian_bands_destroy(slepian_bands_t bands);
+/* Workspace bytes of slepian_project_bands on `batch` signals. */
+int slepian_bands_workspace_size(slepian_bands_t bands, int64_t batch, size_t *bytes);
+/* y = sum_i w_i Re(E_i P~ E_i^* x) for the prepared bands; x, y: N x batch
+ * FP32 real (y may equal x, no other overlap); batch == 0 is a no-op;
+ * ENOTSUP when the batch exceeds the launch limits of the correction. */
+int slepian_project_bands(slepian_bands_t bands, const float *x, int64_t ldx, float *y, int64_t ldy,
+                          int64_t batch, void *work, size_t work_bytes, void *stream);
 
 /* Slepian coefficients c = S_K^T x (Section 2.3, "A fast factorization":
  * the K numbers that represent x), exact (dense) semantics.  The first call

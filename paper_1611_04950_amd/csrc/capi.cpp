@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "slepian.h"
@@ -148,6 +149,10 @@ struct slepian_plan_s {
   // U's rows laid out for the fused inverse column pass, per column set and
   // matrix mode (FP32, BF16 hi/lo); null where that pass does not apply
   void *ctile[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  // U's layouts for prepared band sets, built by the first band set of each
+  // matrix mode (0: FP32 U^T; 1: BF16 hi/lo planes of U and U^T)
+  void *mbu[2] = {nullptr, nullptr};
+  std::mutex mbu_mu;
 
   ~slepian_plan_s() {
     for (auto *p : tw32) dfree(p);
@@ -164,6 +169,24 @@ struct slepian_plan_s {
     dfree(SK);
     for (auto &t : ctile)
       for (void *p : t) dfree(p);
+    for (void *p : mbu) dfree(p);
+  }
+};
+
+// A prepared band set: the band-sum kernel's spectrum in the FP32 product's
+// layout and the modulation table; U, d and the FFT tables stay the plan's.
+struct slepian_bands_s {
+  slepian_plan_s *P = nullptr;
+  int device = 0;
+  BandSet bs;
+  float *chat32 = nullptr;  // spectrum of the band-sum kernel's circulant embedding / L
+  float *M = nullptr;       // band_table_rows(J) rows of ldm floats
+  int64_t ldm = 0;
+  int mode = 0;             // matrix mode of the correction (plan precision FP32: 0, else 1)
+  MbU u;                    // U's layouts, owned by the plan
+  ~slepian_bands_s() {
+    dfree(chat32);
+    dfree(M);
   }
 };
 
@@ -831,6 +854,88 @@ int guarded(F &&f) {
   }
 }
 
+// Bands [f - W, f + W] inside [0, 1/2] (f = 0: the baseband band), centres
+// at least 2W apart, 1..kMaxBands of them.
+bool parse_bands(const Plan *P, int nbands, const double *freqs, BandSet &bs) {
+  if (!P || nbands < 1 || nbands > kMaxBands || !freqs) return false;
+  bs.J = nbands;
+  for (int i = 0; i < nbands; ++i) {
+    const double f = freqs[i];
+    if (!(f == 0.0 || (f >= P->W && f <= 0.5 - P->W))) return false;
+    for (int k = 0; k < i; ++k)
+      if (std::fabs(f - freqs[k]) < 2.0 * P->W) return false;  // bands overlap
+    bs.f[i] = f;
+  }
+  return true;
+}
+
+bool overlapping(const float *x, int64_t ldx, const float *y, int64_t ldy, int64_t N, int64_t b) {
+  if (x == y || b == 0) return false;  // in place is allowed; any other overlap is not
+  const char *xa = (const char *)x, *xe = (const char *)(x + (b - 1) * ldx + N);
+  const char *ya = (const char *)y, *ye = (const char *)(y + (b - 1) * ldy + N);
+  return xa < ye && ya < xe;
+}
+
+// U's layouts for the modulated correction in matrix mode `mode`, built on
+// first use (synchronous) and kept by the plan.
+MbU mb_layout(Plan *P, int mode) {
+  const int r = (int)P->proj.r;
+  const int64_t N = P->N, rpad = (r + 31) / 32 * 32, ldm = mb_ldm(N);
+  MbU u;
+  if (r == 0) return u;
+  std::lock_guard<std::mutex> lock(P->mbu_mu);
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  // mode 1: Uh, Ul (blocked, BF16) then Th, Tl; mode 0: U32b (blocked) then T32
+  const size_t esz = mode == 0 ? sizeof(float) : sizeof(__bf16);
+  const size_t blk = al((size_t)rpad * ldm * esz), tr = al((size_t)N * rpad * esz);
+  if (!P->mbu[mode]) {
+    const size_t bytes = mode == 0 ? blk + tr : 2 * blk + 2 * tr;
+    char *base = dalloc<char>(bytes);
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+      const float *U = P->U32 + P->proj.off * P->ldu;
+      if (mode == 0)
+        e = mb_ulayout(0, U, P->ldu, N, r, ldm, nullptr, nullptr, reinterpret_cast<float *>(base), nullptr, nullptr,
+                       reinterpret_cast<float *>(base + blk), st);
+      else
+        e = mb_ulayout(1, U, P->ldu, N, r, ldm, reinterpret_cast<__bf16 *>(base),
+                       reinterpret_cast<__bf16 *>(base + blk), nullptr, reinterpret_cast<__bf16 *>(base + 2 * blk),
+                       reinterpret_cast<__bf16 *>(base + 2 * blk + tr), nullptr, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+    if (e != hipSuccess) {
+      dfree(base);
+      throw Fail{hip_status(e)};
+    }
+    P->mbu[mode] = base;
+  }
+  char *base = static_cast<char *>(P->mbu[mode]);
+  if (mode == 0) {
+    u.U32b = reinterpret_cast<const float *>(base);
+    u.T32 = reinterpret_cast<const float *>(base + blk);
+  } else {
+    u.Uh = reinterpret_cast<const __bf16 *>(base);
+    u.Ul = reinterpret_cast<const __bf16 *>(base + blk);
+    u.Th = reinterpret_cast<const __bf16 *>(base + 2 * blk);
+    u.Tl = reinterpret_cast<const __bf16 *>(base + 2 * blk + tr);
+  }
+  return u;
+}
+
+// Workspace of a prepared band-set projection of b signals: the FFT product's
+// and the modulated correction's.
+size_t bands_workspace(const slepian_bands_s *B, int64_t b) {
+  const Plan *P = B->P;
+  Carver cv(nullptr);
+  const int64_t pairs = (b + 1) / 2;
+  const int64_t slice = (int64_t)conv_workspace_pairs(P->g32, pairs, sizeof(cpx<float>), slice_budget());
+  if (!P->g32.single()) cv.take<cpx<float>>((size_t)slice * (size_t)P->L);
+  if (P->proj.r > 0) cv.take<char>(mb_workspace_bytes(mb_shape(P->N, b, (int)P->proj.r, B->bs.J), b));
+  return cv.off + 256;
+}
+
 bool bad_signal_args(const Plan *P, const void *x, int64_t ldx, const void *y, int64_t ldy, int64_t b) {
   if (!P || b < 0) return true;
   if (b == 0) return false;
@@ -1018,12 +1123,7 @@ int slepian_project_ex(slepian_plan_t P, int precision, const float *x, int64_t 
   if (bad_signal_args(P, x, ldx, y, ldy, batch)) return SLEPIAN_EINVAL;
   if (precision < SLEPIAN_FP32 || precision > SLEPIAN_BF16_RAW) return SLEPIAN_EINVAL;
   if (batch == 0) return SLEPIAN_OK;
-  if (x != y) {
-    // in place is allowed; any other overlap is not
-    const char *xa = (const char *)x, *xe = (const char *)(x + (batch - 1) * ldx + P->N);
-    const char *ya = (const char *)y, *ye = (const char *)(y + (batch - 1) * ldy + P->N);
-    if (xa < ye && ya < xe) return SLEPIAN_EINVAL;
-  }
+  if (overlapping(x, ldx, y, ldy, P->N, batch)) return SLEPIAN_EINVAL;
   return guarded([&]() -> int {
     DeviceGuard dg(P->device);
     hipStream_t st = (hipStream_t)stream;
@@ -1039,24 +1139,11 @@ int slepian_project_ex(slepian_plan_t P, int precision, const float *x, int64_t 
 int slepian_project_multiband(slepian_plan_t P, int nbands, const double *freqs, const float *x, int64_t ldx,
                               float *y, int64_t ldy, int64_t batch, void *work, size_t work_bytes, void *stream) {
   if (bad_signal_args(P, x, ldx, y, ldy, batch)) return SLEPIAN_EINVAL;
-  if (nbands < 1 || nbands > kMaxBands || !freqs) return SLEPIAN_EINVAL;
   BandSet bs;
-  bs.J = nbands;
-  for (int i = 0; i < nbands; ++i) {
-    const double f = freqs[i];
-    // a band [f - W, f + W] inside (0, 1/2), or the baseband band f = 0
-    if (!(f == 0.0 || (f >= P->W && f <= 0.5 - P->W))) return SLEPIAN_EINVAL;
-    for (int k = 0; k < i; ++k)
-      if (std::fabs(f - freqs[k]) < 2.0 * P->W) return SLEPIAN_EINVAL;  // bands overlap
-    bs.f[i] = f;
-  }
+  if (!parse_bands(P, nbands, freqs, bs)) return SLEPIAN_EINVAL;
   if (2 * (int64_t)nbands * batch > 32 * 65535) return SLEPIAN_EINVAL;
   if (batch == 0) return SLEPIAN_OK;
-  if (x != y) {
-    const char *xa = (const char *)x, *xe = (const char *)(x + (batch - 1) * ldx + P->N);
-    const char *ya = (const char *)y, *ye = (const char *)(y + (batch - 1) * ldy + P->N);
-    if (xa < ye && ya < xe) return SLEPIAN_EINVAL;
-  }
+  if (overlapping(x, ldx, y, ldy, P->N, batch)) return SLEPIAN_EINVAL;
   return guarded([&]() -> int {
     DeviceGuard dg(P->device);
     hipStream_t st = (hipStream_t)stream;
@@ -1069,6 +1156,100 @@ int slepian_project_multiband(slepian_plan_t P, int nbands, const double *freqs,
     HIPCHK(band_demod(x, ldx, N, batch, bs, z, N, st));
     run_fast_op(P, P->proj, 1.0f, 0.0f, z, N, pz, N, 2 * nb, w, st, P->precision);
     HIPCHK(band_remod(pz, N, N, batch, bs, y, ldy, st));
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_bands_create(slepian_plan_t P, int nbands, const double *freqs, slepian_bands_t *out) {
+  if (!out) return SLEPIAN_EINVAL;
+  *out = nullptr;
+  BandSet bs;
+  if (!parse_bands(P, nbands, freqs, bs)) return SLEPIAN_EINVAL;
+  if (P->proj.r > kMbMaxRank) return SLEPIAN_ENOTSUP;
+  return guarded([&]() -> int {
+    DeviceGuard dg(P->device);
+    auto *B = new slepian_bands_s;
+    B->P = P;
+    B->device = P->device;
+    B->bs = bs;
+    hipStream_t st = nullptr;
+    try {
+      HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      const int64_t L = P->L, N = P->N;
+      // spectrum of the band-sum kernel's circulant embedding, as the plan's own (FP64 transform)
+      const FftGeom gen64 = generic_twin(P->g64);
+      {
+        DBuf<double> c(L);
+        DBuf<cpx<double>> spec(L);
+        HIPCHK(band_embed(c.p, L, N, P->W, bs, st));
+        HIPCHK(fft_forward_real64(c.p, gen64, P->tb64, spec.p, st));
+        B->chat32 = dalloc<float>(L);
+        HIPCHK(spectrum_relayout<float>(spec.p, gen64, B->chat32, P->g32, st));
+        HIPCHK(hipStreamSynchronize(st));
+      }
+      B->ldm = mb_ldm(N);
+      B->M = dalloc<float>((size_t)band_table_rows(bs.J) * B->ldm);
+      HIPCHK(band_table(B->M, B->ldm, N, bs, st));
+      HIPCHK(hipStreamSynchronize(st));
+      B->mode = P->precision == SLEPIAN_FP32 ? 0 : 1;
+      B->u = mb_layout(P, B->mode);
+      (void)hipStreamDestroy(st);
+    } catch (...) {
+      if (st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+      }
+      delete B;
+      throw;
+    }
+    *out = B;
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_bands_destroy(slepian_bands_t B) {
+  if (!B) return SLEPIAN_OK;
+  return guarded([&]() -> int {
+    DeviceGuard dg(B->device);
+    (void)hipDeviceSynchronize();
+    delete B;
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_bands_workspace_size(slepian_bands_t B, int64_t batch, size_t *bytes) {
+  if (!B || !bytes || batch < 0) return SLEPIAN_EINVAL;
+  *bytes = bands_workspace(B, batch);
+  return SLEPIAN_OK;
+}
+
+int slepian_project_bands(slepian_bands_t B, const float *x, int64_t ldx, float *y, int64_t ldy, int64_t batch,
+                          void *work, size_t work_bytes, void *stream) {
+  if (!B) return SLEPIAN_EINVAL;
+  Plan *P = B->P;
+  if (bad_signal_args(P, x, ldx, y, ldy, batch)) return SLEPIAN_EINVAL;
+  if (batch == 0) return SLEPIAN_OK;
+  if (overlapping(x, ldx, y, ldy, P->N, batch)) return SLEPIAN_EINVAL;
+  const int r = (int)P->proj.r;
+  const MbShape sh = mb_shape(P->N, batch, r, B->bs.J);
+  if (r > 0 && !mb_ok(sh, P->N, batch, r)) return SLEPIAN_ENOTSUP;
+  return guarded([&]() -> int {
+    DeviceGuard dg(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = P->N;
+    void *ws = get_ws(P, work, work_bytes, bands_workspace(B, batch));
+    Carver cv(ws);
+    const int64_t pairs = (batch + 1) / 2;
+    const int64_t slice = (int64_t)conv_workspace_pairs(P->g32, pairs, sizeof(cpx<float>), slice_budget());
+    cpx<float> *Z = P->g32.single() ? nullptr : cv.take<cpx<float>>((size_t)slice * (size_t)P->L);
+    MbWs mw;
+    if (r > 0) mw = mb_carve(sh, batch, cv.take<char>(mb_workspace_bytes(sh, batch)));
+    // the coefficients read x before the product writes y (which may be x)
+    HIPCHK(mb_coeffs(B->mode, x, ldx, N, batch, B->u, r, P->proj.d32, B->M, B->ldm, B->bs, sh, mw, st));
+    FftTables<float> tb = P->tb32;
+    tb.chat = B->chat32;
+    HIPCHK(conv_apply<float>(x, ldx, y, ldy, N, batch, P->g32, tb, 1.0f, 0.0f, Corr<float>(), Z, slice, st));
+    HIPCHK(mb_apply(B->mode, y, ldy, N, batch, B->u, r, B->M, B->ldm, sh, mw, st));
     return SLEPIAN_OK;
   });
 }

@@ -122,6 +122,46 @@ hipError_t band_demod(const float *x, int64_t ldx, int64_t N, int64_t b, const B
 // y_s = sum_i w_i Re(E_{f_i} (p_{2(ib+s)} + i p_{2(ib+s)+1})), w_i = 2 (f_i > 0) or 1 (f_i = 0)
 hipError_t band_remod(const float *p, int64_t ldp, int64_t N, int64_t b, const BandSet &bs, float *y, int64_t ldy,
                       hipStream_t st);
+// Prepared band sets: circulant embedding (length L, FP64) of the band-sum kernel
+// b(m) sum_i w_i cos(2 pi f_i m), and the modulation table M[(2 i + c) ldm + n]
+// (c = 0: cos(2 pi f_i n), c = 1: -sin(2 pi f_i n); zero for N <= n < ldm, ldm a
+// multiple of 64) with band_table_rows(J) = 2 J + 1 rows, the last one zero
+hipError_t band_embed(double *c, int64_t L, int64_t N, double W, const BandSet &bs, hipStream_t st);
+int64_t band_table_rows(int J);
+int64_t mb_ldm(int64_t N);  // leading dimension of the table and of U's [j][n] planes
+hipError_t band_table(float *M, int64_t ldm, int64_t N, const BandSet &bs, hipStream_t st);
+// The modulated correction of rank 2 J r: coefficients dC' from x (before the
+// product, so that y may alias x), then y += the update.  mode 0 FP32, 1 BF16 hi/lo.
+constexpr int kMbMaxRank = 128;
+struct MbShape {
+  int ncmb = 0, logG = 0, nsg = 0, nbw = 0, nw = 0, ncg = 0, nz = 0, rpad = 0, jp = 0, steps = 0, chunks = 0;
+  int tiles = 0, cu = 0;  // apply: 16-sample tiles per wavefront, modulations per iteration
+};
+struct MbWs {
+  float *part = nullptr, *D = nullptr;
+  __bf16 *H = nullptr, *Lo = nullptr;
+};
+// U's columns for the modulated correction (the plan's proj set), laid out by
+// mb_ulayout once per plan and matrix mode: a copy blocked by 8 samples,
+// [(n / 8) rpad + j] 8 + n % 8 with rpad = 32 ceil(r / 32) rows and n < ldm (BF16
+// hi/lo planes Uh, Ul for mode 1, U32b in FP32 for mode 0), and U^T planes
+// [n][rpad] (Th, Tl in BF16 for mode 1, T32 in FP32 for mode 0).  The table's
+// blocking is the same: [(n / 8) (2J + 1) + row] 8 + n % 8.
+struct MbU {
+  const __bf16 *Uh = nullptr, *Ul = nullptr, *Th = nullptr, *Tl = nullptr;
+  const float *U32b = nullptr, *T32 = nullptr;
+};
+hipError_t mb_ulayout(int mode, const float *U, int64_t ldu, int64_t N, int r, int64_t ldm, __bf16 *Uh, __bf16 *Ul,
+                      float *U32b, __bf16 *Th, __bf16 *Tl, float *T32, hipStream_t st);
+MbShape mb_shape(int64_t N, int64_t b, int r, int J);
+bool mb_ok(const MbShape &sh, int64_t N, int64_t b, int r);
+size_t mb_workspace_bytes(const MbShape &sh, int64_t b);
+MbWs mb_carve(const MbShape &sh, int64_t b, void *ws);
+hipError_t mb_coeffs(int mode, const float *x, int64_t ldx, int64_t N, int64_t b, const MbU &u, int r,
+                     const float *d, const float *M, int64_t ldm, const BandSet &bs, const MbShape &sh, const MbWs &w,
+                     hipStream_t st);
+hipError_t mb_apply(int mode, float *y, int64_t ldy, int64_t N, int64_t b, const MbU &u, int r, const float *M,
+                    int64_t ldm, const MbShape &sh, const MbWs &w, hipStream_t st);
 
 hipError_t rayleigh(const double *V, const double *BV, int64_t N, int64_t count, double *lam, double *res,
                     hipStream_t st);

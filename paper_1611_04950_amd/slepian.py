@@ -37,7 +37,8 @@ SLEPIAN_OP_PROJECT, SLEPIAN_OP_COEFFS, SLEPIAN_OP_LSQ, SLEPIAN_OP_MULTIBAND = 0,
 EXPORTED = [
     "slepian_plan", "slepian_plan_ex", "slepian_plan_batch", "slepian_plan_info_get", "slepian_plan_eigenpairs",
     "slepian_plan_save", "slepian_plan_load", "slepian_plan_destroy", "slepian_workspace_size",
-    "slepian_project", "slepian_project_ex", "slepian_project_multiband", "slepian_coeffs", "slepian_lsq",
+    "slepian_project", "slepian_project_ex", "slepian_project_multiband", "slepian_bands_create",
+    "slepian_bands_destroy", "slepian_bands_workspace_size", "slepian_project_bands", "slepian_coeffs", "slepian_lsq",
     "slepian_apply_b64",
     "slepian_group_create", "slepian_group_project", "slepian_group_destroy", "slepian_status_string",
     "slepian_trace_enable", "slepian_trace_read",
@@ -87,6 +88,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "slepian_project": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_project_ex": [vp, i32, vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_project_multiband": [vp, i32, C.POINTER(dbl), vp, i64, vp, i64, i64, vp, sz, vp],
+        "slepian_bands_create": [vp, i32, C.POINTER(dbl), C.POINTER(vp)],
+        "slepian_bands_destroy": [vp],
+        "slepian_bands_workspace_size": [vp, i64, C.POINTER(sz)],
+        "slepian_project_bands": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_coeffs": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_lsq": [vp, i32, dbl, vp, i64, vp, i64, i64, dbl, i32, vp, sz, vp, C.POINTER(LsqReport)],
         "slepian_apply_b64": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
@@ -248,6 +253,48 @@ def slepian_project_multiband(plan: Plan, freqs, x: torch.Tensor, y: torch.Tenso
     wb = 0 if work is None else work.numel() * work.element_size()
     _check(_lib.slepian_project_multiband(plan.handle, len(freqs), f, _ptr(x), ldx, _ptr(y), ldy, x.shape[0],
                                           _ptr(work), wb, _stream(x)), "slepian_project_multiband")
+    return y
+
+
+class Bands:
+    """Owns a slepian_bands_t; keeps its plan alive."""
+
+    def __init__(self, handle: int, plan: Plan, freqs):
+        self.handle = C.c_void_p(handle)
+        self.plan = plan
+        self.freqs = list(freqs)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.slepian_bands_destroy(h)
+            self.handle = C.c_void_p(0)
+
+
+def slepian_bands_create(plan: Plan, freqs) -> Bands:
+    """Prepared band set for slepian_project_bands (see include/slepian.h)."""
+    f = (C.c_double * len(freqs))(*[float(v) for v in freqs])
+    h = C.c_void_p()
+    _check(_lib.slepian_bands_create(plan.handle, len(freqs), f, C.byref(h)), "slepian_bands_create")
+    return Bands(h.value, plan, freqs)
+
+
+def slepian_bands_workspace_size(bands: Bands, batch: int) -> int:
+    n = C.c_size_t()
+    _check(_lib.slepian_bands_workspace_size(bands.handle, batch, C.byref(n)), "slepian_bands_workspace_size")
+    return n.value
+
+
+def slepian_project_bands(bands: Bands, x: torch.Tensor, y: torch.Tensor | None = None,
+                          work: torch.Tensor | None = None) -> torch.Tensor:
+    N = bands.plan.N
+    x, ldx = _signals(x, N, torch.float32, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    y, ldy = _signals(y, N, torch.float32, "y")
+    wb = 0 if work is None else work.numel() * work.element_size()
+    _check(_lib.slepian_project_bands(bands.handle, _ptr(x), ldx, _ptr(y), ldy, x.shape[0], _ptr(work), wb,
+                                      _stream(x)), "slepian_project_bands")
     return y
 
 

@@ -4,7 +4,10 @@ baseband band alone and matches the dense per-band sum within the bands'
 eps; the dense union projection is an orthogonal projector that keeps the
 dictionary's span; the sum differs from the union projection by the
 subspaces' mutual coherence, measured and bounded here.  Also the host
-checks of the C entry point's band validation."""
+checks of the C entry point's band validation, and the two identities the
+prepared band sets compute with (dense, in FP64): the bands' B parts add up
+to one Toeplitz product, and the bands' corrections to one correction with
+modulated columns."""
 
 import ctypes as C
 
@@ -70,3 +73,44 @@ def test_bad_bands_rejected_before_device_work():
         assert lib.slepian_project_multiband(None, len(freqs), f, None, 0, None, 0, 1, None, 0, None) == \
             S.SLEPIAN_EINVAL
     assert lib.slepian_project_multiband(None, 0, None, None, 0, None, 0, 0, None, 0, None) == S.SLEPIAN_EINVAL
+
+
+def test_band_sum_of_B_is_one_toeplitz_product():
+    """sum_i w_i Re(E_i B E_i^* x) = T x for real x, T the symmetric Toeplitz
+    matrix of k(m) = b(m) sum_i w_i cos(2 pi f_i m), b(m) = sin(2 pi W m)/(pi m)
+    (b(0) = 2W).  It holds band by band, whatever the weights; a sine in place
+    of the cosine, or a phase of f m instead of 2 pi f m, breaks it."""
+    n = 200
+    x = np.random.default_rng(4).standard_normal((n, 3))
+    B = o.prolate_matrix(n, W)
+    t = np.arange(n)
+    lhs = np.zeros_like(x)
+    for f in BANDS:
+        e = np.exp(2j * np.pi * f * t)
+        lhs += (2.0 if f > 0 else 1.0) * (e[:, None] * (B @ (np.conj(e)[:, None] * x))).real
+    m = np.abs(t[:, None] - t[None, :])
+    bm = np.where(m == 0, 2 * W, np.sin(2 * np.pi * W * m) / (np.pi * np.maximum(m, 1)))
+    k = bm * sum((2.0 if f > 0 else 1.0) * np.cos(2 * np.pi * f * m) for f in BANDS)
+    np.testing.assert_allclose(k @ x, lhs, rtol=0, atol=1e-12 * np.abs(lhs).max())
+
+
+def test_band_sum_of_corrections_is_one_modulated_correction():
+    """sum_i w_i Re(E_i U D U^T E_i^* x) = sum_(i,c) w_i V_ic D V_ic^T x with
+    V_i0 = cos(2 pi f_i n) U and V_i1 = -sin(2 pi f_i n) U (rows scaled), for
+    real U, diagonal D and real x."""
+    n, r = 150, 7
+    rng = np.random.default_rng(6)
+    U = rng.standard_normal((n, r))
+    D = np.diag(rng.standard_normal(r))
+    x = rng.standard_normal((n, 2))
+    t = np.arange(n)
+    lhs = np.zeros_like(x)
+    rhs = np.zeros_like(x)
+    for f in BANDS:
+        w = 2.0 if f > 0 else 1.0
+        e = np.exp(2j * np.pi * f * t)
+        lhs += w * (e[:, None] * (U @ D @ U.T @ (np.conj(e)[:, None] * x))).real
+        for m in (np.cos(2 * np.pi * f * t), -np.sin(2 * np.pi * f * t)):
+            V = m[:, None] * U
+            rhs += w * (V @ D @ V.T @ x)
+    np.testing.assert_allclose(rhs, lhs, rtol=0, atol=1e-12 * np.abs(lhs).max())
