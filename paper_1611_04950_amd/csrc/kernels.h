@@ -136,6 +136,7 @@ constexpr int kMbMaxRank = 128;
 struct MbShape {
   int ncmb = 0, logG = 0, nsg = 0, nbw = 0, nw = 0, ncg = 0, nz = 0, rpad = 0, jp = 0, steps = 0, chunks = 0;
   int tiles = 0, cu = 0;  // apply: 16-sample tiles per wavefront, modulations per iteration
+  int ss = 0, lds_bytes = 0;  // coefficients: samples per LDS stage, dynamic LDS bytes
 };
 struct MbWs {
   float *part = nullptr, *D = nullptr;

@@ -247,42 +247,48 @@ hipError_t mb_ulayout(int mode, const float *U, int64_t ldu, int64_t N, int r, i
   return hipGetLastError();
 }
 
-// C' partials.  Workgroup = up to 4 wavefronts on one chunk of 32 * steps
+// C' partials.  Workgroup = nw (up to 4) wavefronts on one chunk of 32 * steps
 // samples (blockIdx.x); wavefront w holds NBW 32 x 32 accumulators, the column
-// blocks (4 cg + w) NBW + nb of the 32-column blocks of C'.  Rows are
+// blocks (nw cg + w) NBW + nb of the 32-column blocks of C'.  Rows are
 // j = 32 blockIdx.z + lane % 32 (U columns); columns are packed as G = 2^logG
 // signals times 32 / G modulations, so lane i serves signal s = G sg + i % G
 // (the same in every accumulator) and modulation cmb = blk 32/G + i / G
-// (blockIdx.y = cg nsg + sg).  U and x are read once per step and shared by
-// the accumulators; the B operand x_s(n) m_cmb(n) is formed in registers.
-// U comes from its blocked copy (BF16 hi/lo for MODE 1, FP32 for MODE 0; zero
-// rows past r, zero beyond N), the table in the same blocking.  Lanes past the last signal or U column read a valid
-// clamped address; their accumulator columns and rows are never stored, so
-// their values need no masking.  Each wavefront stores its own columns of the
-// chunk's partial, part[(chunk rpad + j) ncol + cmb b + s]; no barrier.
+// (blockIdx.y = cg nsg + sg).  The chunk is processed in stages of SS samples:
+// the workgroup first copies the R = nw NBW 32/G table rows of its
+// modulations (rows past the last one read the table's zero row) and its G
+// signals for the stage into LDS with coalesced loads, then every wavefront
+// reads its operands from LDS, where lanes that share a value are served by
+// one broadcast.  U comes from its blocked copy (BF16 hi/lo for MODE 1, FP32
+// for MODE 0; zero rows past r, zero beyond N).  Lanes past the last signal or
+// U column compute columns and rows that are never stored.  Each wavefront
+// stores its own columns of the chunk's partial,
+// part[(chunk rpad + j) ncol + cmb b + s].
 template <int MODE, int NBW, bool VEC>
 __global__ __launch_bounds__(256) void k_mb_partial(const float *__restrict__ X, int64_t ldx, int N, int b,
                                                     const float *__restrict__ U32b, const __bf16 *__restrict__ Uh,
                                                     const __bf16 *__restrict__ Ul, int r,
                                                     const float *__restrict__ M, int ncmb, int logG, int nsg, int nw,
-                                                    int steps, float *__restrict__ part, int rpad) {
+                                                    int steps, int SS, float *__restrict__ part, int rpad) {
+  extern __shared__ float lds[];
+  const int nthr = 64 * nw;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = lane & 31, kb = lane >> 5;
   const int G = 1 << logG, cpb = 32 >> logG;
   const int sg = blockIdx.y % nsg, cg = blockIdx.y / nsg;
+  const int R = nw * NBW * cpb;        // table rows staged by this workgroup
+  const int cmb0 = cg * R;             // its first modulation
   const int blk0 = (cg * nw + wave) * NBW;
-  if (blk0 * cpb >= ncmb) return;  // whole wavefront: no modulation left
+  const bool active = blk0 * cpb < ncmb;  // wave-uniform
+  const int XS = SS + 4;               // padded LDS row of a signal
+  float *tabL = lds;                   // [SS / 8][R][8]
+  float *xL = lds + SS * R;            // [G][XS]
   const int s = sg * G + (i & (G - 1));
   const bool sv = s < b;
-  const float *xs = X + (int64_t)(sv ? s : b - 1) * ldx;
   const int j = blockIdx.z * 32 + i;  // < rpad
   const int mrows = ncmb + 1;
-  int mc[NBW];
+  int rl[NBW];
 #pragma unroll
-  for (int nb = 0; nb < NBW; ++nb) {
-    const int cmb = (blk0 + nb) * cpb + (i >> logG);
-    mc[nb] = cmb < ncmb ? cmb : ncmb;  // row ncmb is zero
-  }
+  for (int nb = 0; nb < NBW; ++nb) rl[nb] = (wave * NBW + nb) * cpb + (i >> logG);  // row within tabL
   f32x16 acc[NBW];
 #pragma unroll
   for (int nb = 0; nb < NBW; ++nb)
@@ -290,54 +296,88 @@ __global__ __launch_bounds__(256) void k_mb_partial(const float *__restrict__ X,
     for (int v = 0; v < 16; ++v) acc[nb][v] = 0.f;
   const int k_begin = blockIdx.x * steps * 32;
   const int k_end = min(N, k_begin + steps * 32);
-  for (int k0 = k_begin; k0 < k_end; k0 += 32) {
-    float ua[MODE == 0 ? 2 : 1][8], xv[2][8];
-    bf16x8 ah[2], al[2];
-    const bool whole = k0 + 32 <= N;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int kk = k0 + 16 * q + 8 * kb;
-      // the blocked copies are zero-padded to ldm >= N rounded up to 64: no guard
-      const int64_t ub = ((int64_t)(kk >> 3) * rpad + j) * 8;
-      if constexpr (MODE == 0) {
-        mb_load8<true>(U32b + ub, ua[q]);
+  for (int st0 = k_begin; st0 < k_end; st0 += SS) {
+    __syncthreads();  // the previous stage has been read
+    // stage the table rows: (SS / 8) blocks x R rows x two float4
+    const int tunits = (SS / 8) * R * 2;
+    for (int u = threadIdx.x; u < tunits; u += nthr) {
+      const int n8 = u / (2 * R), rem = u - n8 * 2 * R, row = rem >> 1, half = rem & 1;
+      const int g = min(cmb0 + row, ncmb);
+      // blocks at or past N lie beyond the table's padded length for the last stage: zero
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (st0 + 8 * n8 < N) v = *reinterpret_cast<const float4 *>(M + (((int64_t)(st0 >> 3) + n8) * mrows + g) * 8 + 4 * half);
+      *reinterpret_cast<float4 *>(tabL + (n8 * R + row) * 8 + 4 * half) = v;
+    }
+    // stage the signals: G rows x SS samples (zero beyond N)
+    const int xunits = G * (SS / 4);
+    for (int u = threadIdx.x; u < xunits; u += nthr) {
+      const int row = u / (SS / 4), c4 = u - row * (SS / 4);
+      const int sr = min(sg * G + row, b - 1);
+      const int n = st0 + 4 * c4;
+      const float *xp = X + (int64_t)sr * ldx + n;
+      float4 v;
+      if (VEC && n + 4 <= N) {
+        v = *reinterpret_cast<const float4 *>(xp);
       } else {
-        ah[q] = *reinterpret_cast<const bf16x8 *>(Uh + ub);
-        al[q] = *reinterpret_cast<const bf16x8 *>(Ul + ub);
+        v.x = n < N ? xp[0] : 0.f;
+        v.y = n + 1 < N ? xp[1] : 0.f;
+        v.z = n + 2 < N ? xp[2] : 0.f;
+        v.w = n + 3 < N ? xp[3] : 0.f;
       }
-      if (whole) mb_load8<VEC>(xs + kk, xv[q]);
-      else
-#pragma unroll
-        for (int e = 0; e < 8; ++e) xv[q][e] = kk + e < N ? xs[kk + e] : 0.f;
+      *reinterpret_cast<float4 *>(xL + row * XS + 4 * c4) = v;
     }
-    float m[2][NBW][8];
+    __syncthreads();
+    if (active) {
+      const int st1 = min(k_end, st0 + SS);
+      for (int k0 = st0; k0 < st1; k0 += 32) {
+        const int kl = k0 - st0;
+        float ua[MODE == 0 ? 2 : 1][8], xv[2][8];
+        bf16x8 ah[2], al[2];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int64_t mb = (int64_t)((k0 + 16 * q + 8 * kb) >> 3) * mrows;
+        for (int q = 0; q < 2; ++q) {
+          const int kk = k0 + 16 * q + 8 * kb;
+          // the blocked copies are zero-padded to ldm >= N rounded up to 64: no guard
+          const int64_t ub = ((int64_t)(kk >> 3) * rpad + j) * 8;
+          if constexpr (MODE == 0) {
+            mb_load8<true>(U32b + ub, ua[q]);
+          } else {
+            ah[q] = *reinterpret_cast<const bf16x8 *>(Uh + ub);
+            al[q] = *reinterpret_cast<const bf16x8 *>(Ul + ub);
+          }
+          const float *xr = xL + (i & (G - 1)) * XS + kl + 16 * q + 8 * kb;
+          const float4 x0 = *reinterpret_cast<const float4 *>(xr);
+          const float4 x1 = *reinterpret_cast<const float4 *>(xr + 4);
+          xv[q][0] = x0.x; xv[q][1] = x0.y; xv[q][2] = x0.z; xv[q][3] = x0.w;
+          xv[q][4] = x1.x; xv[q][5] = x1.y; xv[q][6] = x1.z; xv[q][7] = x1.w;
+        }
 #pragma unroll
-      for (int nb = 0; nb < NBW; ++nb) mb_load8<true>(M + (mb + mc[nb]) * 8, m[q][nb]);
-    }
+        for (int q = 0; q < 2; ++q) {
+          const int n8 = (kl + 16 * q + 8 * kb) >> 3;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+          for (int nb = 0; nb < NBW; ++nb) {
+            const float *mr = tabL + (n8 * R + rl[nb]) * 8;
+            const float4 m0 = *reinterpret_cast<const float4 *>(mr);
+            const float4 m1 = *reinterpret_cast<const float4 *>(mr + 4);
+            float bv[8];
+            bv[0] = xv[q][0] * m0.x; bv[1] = xv[q][1] * m0.y; bv[2] = xv[q][2] * m0.z; bv[3] = xv[q][3] * m0.w;
+            bv[4] = xv[q][4] * m1.x; bv[5] = xv[q][5] * m1.y; bv[6] = xv[q][6] * m1.z; bv[7] = xv[q][7] * m1.w;
+            if constexpr (MODE == 0) {
 #pragma unroll
-      for (int nb = 0; nb < NBW; ++nb) {
-        float bv[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) bv[e] = xv[q][e] * m[q][nb][e];
-        if constexpr (MODE == 0) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ua[q][e], bv[e], acc[nb], 0, 0, 0);
-        } else {
-          bf16x8 bhi, blo;
-          mb_split(bv, bhi, blo);
-          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[q], bhi, acc[nb], 0, 0, 0);
-          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[q], blo, acc[nb], 0, 0, 0);
-          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[q], bhi, acc[nb], 0, 0, 0);
+              for (int e = 0; e < 8; ++e)
+                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ua[q][e], bv[e], acc[nb], 0, 0, 0);
+            } else {
+              bf16x8 bhi, blo;
+              mb_split(bv, bhi, blo);
+              acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[q], bhi, acc[nb], 0, 0, 0);
+              acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[q], blo, acc[nb], 0, 0, 0);
+              acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[q], bhi, acc[nb], 0, 0, 0);
+            }
+          }
         }
       }
     }
   }
-  if (!sv) return;
+  if (!active || !sv) return;
   const int ncol = ncmb * b;
   float *pc = part + (int64_t)blockIdx.x * rpad * ncol;
 #pragma unroll
@@ -398,14 +438,17 @@ __global__ __launch_bounds__(256) void k_mb_reduce(const float *__restrict__ par
 }
 
 // y += the modulated update.  A wavefront owns 16 signals (s0 = 16 blockIdx.y)
-// and T consecutive 16-sample tiles; lane (c, q) = (lane % 16, lane / 16).
-// A = dC'^T (row c: signal s0 + c; k: j) is loaded for CU modulations at a
-// time and reused for the T tiles; B = U^T (k: j; column c: sample
-// n0 + 16 t + c) comes from the plan's [n][jp] layout of U, one vector load
-// per 8 (BF16) or 4 (FP32) consecutive j, once per tile.  Per modulation and
-// tile, a product over j into tt, then acc += m_cmb(n) tt.  D[4 q + v][c] is
-// signal s0 + 4 q + v at the sample of column c.  Lanes past the last signal
-// read a clamped row of dC' and are not stored.
+// and T consecutive 16-sample tiles; lane (c, q) = (lane % 16, lane / 16);
+// the workgroup's 4 wavefronts cover 64 T consecutive samples.  The table
+// rows of up to 64 / T modulations at a time are first copied into LDS
+// (coalesced, zero past N and past the last modulation).  A = dC'^T (row c:
+// signal s0 + c; k: j) is loaded for CU modulations at a time and reused for
+// the T tiles; B = U^T (k: j; column c: sample n0 + 16 t + c) comes from the
+// plan's [n][jp] layout of U, one vector load per 8 (BF16) or 4 (FP32)
+// consecutive j, once per tile.  Per modulation and tile, a product over j
+// into tt, then acc += m_cmb(n) tt.  D[4 q + v][c] is signal s0 + 4 q + v at
+// the sample of column c.  Lanes past the last signal read a clamped row of
+// dC' and are not stored.
 template <int MODE, int RK, int T, int CU>
 __global__ __launch_bounds__(256) void k_mb_apply(float *__restrict__ Y, int64_t ldy, int N, int b,
                                                   const float *__restrict__ T32, const __bf16 *__restrict__ Th,
@@ -413,12 +456,17 @@ __global__ __launch_bounds__(256) void k_mb_apply(float *__restrict__ Y, int64_t
                                                   int ncmb, const float *__restrict__ D,
                                                   const __bf16 *__restrict__ H, const __bf16 *__restrict__ Lo) {
   constexpr int JP = 32 * RK;
-  const int lane = threadIdx.x & 63, c = lane & 15, q = lane >> 4;
-  const int n0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * T;
-  if (n0 >= N) return;  // whole wavefront
+  constexpr int WS = 64 * T;        // samples per workgroup
+  constexpr int CCM = 4096 / WS;    // modulations per LDS stage (a multiple of CU)
+  __shared__ float tabA[WS / 8][CCM][8];
+  const int lane = threadIdx.x & 63, c = lane & 15, q = lane >> 4, wave = threadIdx.x >> 6;
+  const int nW = blockIdx.x * WS;
+  const int n0 = nW + wave * 16 * T;
+  const bool active = n0 < N;  // wave-uniform
   const int s0 = blockIdx.y * 16;
   const int sa = s0 + c;
   const int sac = sa < b ? sa : b - 1;
+  const int mrows = ncmb + 1;
   int nc[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) {
@@ -428,89 +476,107 @@ __global__ __launch_bounds__(256) void k_mb_apply(float *__restrict__ Y, int64_t
   // B operand: U[j][n] for this lane's j, every tile
   float4 uf[MODE == 0 ? T : 1][MODE == 0 ? JP / 16 : 1];
   bf16x8 uh[MODE == 0 ? 1 : T][MODE == 0 ? 1 : RK], ul[MODE == 0 ? 1 : T][MODE == 0 ? 1 : RK];
-#pragma unroll
-  for (int t = 0; t < T; ++t) {
-    const int64_t row = (int64_t)nc[t] * JP;
-    if constexpr (MODE == 0) {
-#pragma unroll
-      for (int g = 0; g < JP / 16; ++g) uf[t][g] = *reinterpret_cast<const float4 *>(T32 + row + 16 * g + 4 * q);
-    } else {
-#pragma unroll
-      for (int k = 0; k < RK; ++k) {
-        uh[t][k] = *reinterpret_cast<const bf16x8 *>(Th + row + 32 * k + 8 * q);
-        ul[t][k] = *reinterpret_cast<const bf16x8 *>(Tl + row + 32 * k + 8 * q);
-      }
-    }
-  }
   f32x4 acc[T];
+  if (active) {
 #pragma unroll
-  for (int t = 0; t < T; ++t)
+    for (int t = 0; t < T; ++t) {
+      const int64_t row = (int64_t)nc[t] * JP;
+      if constexpr (MODE == 0) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int sg = s0 + 4 * q + v;
-      const int n = n0 + 16 * t + c;
-      acc[t][v] = (sg < b && n < N) ? Y[(int64_t)sg * ldy + n] : 0.f;
-    }
-  // CU modulations per iteration: all their loads are issued before the
-  // first product (modulations past ncmb read the zero row of the table)
-  for (int cb = 0; cb < ncmb; cb += CU) {
-    float mv[CU][T];
-    if constexpr (MODE == 0) {
-      float4 a[CU][JP / 16];
-#pragma unroll
-      for (int u = 0; u < CU; ++u) {
-        const int cmb = cb + u < ncmb ? cb + u : ncmb;
-#pragma unroll
-        for (int t = 0; t < T; ++t) mv[u][t] = M[(((int64_t)(nc[t] >> 3) * (ncmb + 1)) + cmb) * 8 + (nc[t] & 7)];
-        const int64_t arow = ((int64_t)(cmb < ncmb ? cmb : ncmb - 1) * b + sac) * JP;
-#pragma unroll
-        for (int g = 0; g < JP / 16; ++g) a[u][g] = *reinterpret_cast<const float4 *>(D + arow + 16 * g + 4 * q);
-      }
-#pragma unroll
-      for (int u = 0; u < CU; ++u)
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-          f32x4 tt = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int g = 0; g < JP / 16; ++g) {
-            tt = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][g].x, uf[t][g].x, tt, 0, 0, 0);
-            tt = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][g].y, uf[t][g].y, tt, 0, 0, 0);
-            tt = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][g].z, uf[t][g].z, tt, 0, 0, 0);
-            tt = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][g].w, uf[t][g].w, tt, 0, 0, 0);
-          }
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[t][v] += mv[u][t] * tt[v];
-        }
-    } else {
-      bf16x8 ah[CU][RK], al[CU][RK];
-#pragma unroll
-      for (int u = 0; u < CU; ++u) {
-        const int cmb = cb + u < ncmb ? cb + u : ncmb;
-#pragma unroll
-        for (int t = 0; t < T; ++t) mv[u][t] = M[(((int64_t)(nc[t] >> 3) * (ncmb + 1)) + cmb) * 8 + (nc[t] & 7)];
-        const int64_t arow = ((int64_t)(cmb < ncmb ? cmb : ncmb - 1) * b + sac) * JP;
+        for (int g = 0; g < JP / 16; ++g) uf[t][g] = *reinterpret_cast<const float4 *>(T32 + row + 16 * g + 4 * q);
+      } else {
 #pragma unroll
         for (int k = 0; k < RK; ++k) {
-          ah[u][k] = *reinterpret_cast<const bf16x8 *>(H + arow + 32 * k + 8 * q);
-          al[u][k] = *reinterpret_cast<const bf16x8 *>(Lo + arow + 32 * k + 8 * q);
+          uh[t][k] = *reinterpret_cast<const bf16x8 *>(Th + row + 32 * k + 8 * q);
+          ul[t][k] = *reinterpret_cast<const bf16x8 *>(Tl + row + 32 * k + 8 * q);
         }
       }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int sg = s0 + 4 * q + v;
+        const int n = n0 + 16 * t + c;
+        acc[t][v] = (sg < b && n < N) ? Y[(int64_t)sg * ldy + n] : 0.f;
+      }
+  }
+  for (int c0 = 0; c0 < ncmb; c0 += CCM) {
+    __syncthreads();  // the previous stage has been read
+    for (int u = threadIdx.x; u < (WS / 8) * CCM * 2; u += 256) {
+      const int n8 = u / (2 * CCM), rem = u - n8 * 2 * CCM, row = rem >> 1, half = rem & 1;
+      const int cmb = c0 + row;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (cmb < ncmb && nW + 8 * n8 < N)
+        v = *reinterpret_cast<const float4 *>(M + (((int64_t)(nW >> 3) + n8) * mrows + cmb) * 8 + 4 * half);
+      *reinterpret_cast<float4 *>(&tabA[n8][row][4 * half]) = v;
+    }
+    __syncthreads();
+    if (!active) continue;
+    const int c1 = min(ncmb, c0 + CCM);
+    for (int cb = c0; cb < c1; cb += CU) {
+      float mv[CU][T];
 #pragma unroll
       for (int u = 0; u < CU; ++u)
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-          f32x4 tt = {0.f, 0.f, 0.f, 0.f};
+          const int nl = wave * 16 * T + 16 * t + c;
+          mv[u][t] = tabA[nl >> 3][cb - c0 + u][nl & 7];  // zero past the last modulation
+        }
+      if constexpr (MODE == 0) {
+        float4 a[CU][JP / 16];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+          const int cmb = cb + u < ncmb ? cb + u : ncmb - 1;
+          const int64_t arow = ((int64_t)cmb * b + sac) * JP;
+#pragma unroll
+          for (int g = 0; g < JP / 16; ++g) a[u][g] = *reinterpret_cast<const float4 *>(D + arow + 16 * g + 4 * q);
+        }
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            f32x4 tt = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int g = 0; g < JP / 16; ++g) {
+              tt = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][g].x, uf[t][g].x, tt, 0, 0, 0);
+              tt = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][g].y, uf[t][g].y, tt, 0, 0, 0);
+              tt = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][g].z, uf[t][g].z, tt, 0, 0, 0);
+              tt = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][g].w, uf[t][g].w, tt, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[t][v] += mv[u][t] * tt[v];
+          }
+      } else {
+        bf16x8 ah[CU][RK], al[CU][RK];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+          const int cmb = cb + u < ncmb ? cb + u : ncmb - 1;
+          const int64_t arow = ((int64_t)cmb * b + sac) * JP;
 #pragma unroll
           for (int k = 0; k < RK; ++k) {
-            tt = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][k], uh[t][k], tt, 0, 0, 0);
-            tt = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][k], ul[t][k], tt, 0, 0, 0);
-            tt = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[u][k], uh[t][k], tt, 0, 0, 0);
+            ah[u][k] = *reinterpret_cast<const bf16x8 *>(H + arow + 32 * k + 8 * q);
+            al[u][k] = *reinterpret_cast<const bf16x8 *>(Lo + arow + 32 * k + 8 * q);
           }
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[t][v] += mv[u][t] * tt[v];
         }
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            f32x4 tt = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < RK; ++k) {
+              tt = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][k], uh[t][k], tt, 0, 0, 0);
+              tt = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][k], ul[t][k], tt, 0, 0, 0);
+              tt = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[u][k], uh[t][k], tt, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[t][v] += mv[u][t] * tt[v];
+          }
+      }
     }
   }
+  if (!active) return;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int n = n0 + 16 * t + c;
@@ -549,23 +615,30 @@ MbShape mb_shape(int64_t N, int64_t b, int r, int J) {
   sh.nz = (r + 31) / 32;
   sh.rpad = 32 * sh.nz;
   sh.jp = 32 * sh.nz;
-  // about 2048 wavefronts in the partial pass (tuning override SLEPIAN_MB_PWAVES)
-  int64_t waves = env_int("SLEPIAN_MB_PWAVES", 2048);
-  if (waves < 256 || waves > 65536) waves = 2048;
+  // about 4096 wavefronts in the partial pass (tuning override SLEPIAN_MB_PWAVES)
+  int64_t waves = env_int("SLEPIAN_MB_PWAVES", 4096);
+  if (waves < 256 || waves > 65536) waves = 4096;
   const int64_t per_chunk = (int64_t)sh.nw * sh.ncg * sh.nsg * sh.nz;
   const int64_t want = per_chunk >= waves ? 1 : waves / per_chunk;
   int64_t steps = (N + 32 * want - 1) / (32 * want);
   if (steps < 1) steps = 1;
   if (steps > 1024) steps = 1024;
+  // LDS stage: R table rows and G signal rows of SS samples, SS R <= 4096 floats
+  const int R = sh.nw * sh.nbw * cpb;
+  int ss = 256;
+  while (ss > 32 && ss * R > 4096) ss >>= 1;
+  sh.ss = ss;
+  if (steps % (ss / 32) != 0) steps = (steps + ss / 32 - 1) / (ss / 32) * (ss / 32);
+  sh.lds_bytes = (ss * R + G * (ss + 4)) * (int)sizeof(float);
   sh.steps = (int)steps;
   sh.chunks = (int)((N + 32 * steps - 1) / (32 * steps));
   // apply: 16-sample tiles per wavefront and modulations per iteration
   // (tuning overrides SLEPIAN_MB_T, SLEPIAN_MB_CU for one 32-row block)
   const int rk = sh.nz;
-  sh.tiles = rk == 1 ? 8 : (rk == 2 ? 4 : 2);
-  sh.cu = 1;
+  sh.tiles = rk == 1 ? 4 : (rk == 2 ? 4 : 2);
+  sh.cu = rk == 1 ? 4 : 1;
   if (rk == 1) {
-    const int t = env_int("SLEPIAN_MB_T", 8), cu = env_int("SLEPIAN_MB_CU", 1);
+    const int t = env_int("SLEPIAN_MB_T", 4), cu = env_int("SLEPIAN_MB_CU", 4);
     if (t == 4 || t == 8) sh.tiles = t;
     if (cu == 1 || cu == 4) sh.cu = cu;
   }
@@ -612,11 +685,11 @@ static void launch_mb_partial(bool vec, dim3 grid, dim3 block, hipStream_t st, c
   const char *name = MODE == 0 ? "mb_partial" : "mb_partial_bf16x3";
   (void)ldm;
   if (vec)
-    SLP_LAUNCH(name, (k_mb_partial<MODE, NBW, true>), grid, block, 0, st, x, ldx, N, b, u.U32b, u.Uh, u.Ul, r, M,
-               sh.ncmb, sh.logG, sh.nsg, sh.nw, sh.steps, part, sh.rpad);
+    SLP_LAUNCH(name, (k_mb_partial<MODE, NBW, true>), grid, block, sh.lds_bytes, st, x, ldx, N, b, u.U32b, u.Uh,
+               u.Ul, r, M, sh.ncmb, sh.logG, sh.nsg, sh.nw, sh.steps, sh.ss, part, sh.rpad);
   else
-    SLP_LAUNCH(name, (k_mb_partial<MODE, NBW, false>), grid, block, 0, st, x, ldx, N, b, u.U32b, u.Uh, u.Ul, r, M,
-               sh.ncmb, sh.logG, sh.nsg, sh.nw, sh.steps, part, sh.rpad);
+    SLP_LAUNCH(name, (k_mb_partial<MODE, NBW, false>), grid, block, sh.lds_bytes, st, x, ldx, N, b, u.U32b, u.Uh,
+               u.Ul, r, M, sh.ncmb, sh.logG, sh.nsg, sh.nw, sh.steps, sh.ss, part, sh.rpad);
 }
 
 template <int MODE, int RK, int T, int CU>
