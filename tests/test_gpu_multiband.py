@@ -89,7 +89,8 @@ def test_workspace_size_and_explicit_workspace():
 # correction of rank 2 J r.  Batches and band counts below cover every column
 # packing of the correction (G = 1, 4, 8, 16 and 32 signals per 32-column
 # block, one and several column groups), a rank above one 32-row block
-# (N = 4096, W = 1/8, eps = 1e-12: r = 46) and unaligned rows (odd N).
+# (N = 4096, W = 1/8, eps = 1e-12: r = 46), unaligned rows (odd N) and a
+# plan whose product runs in three passes (N = 5000).
 BAND_CASES = [
     (512, 1 / 32, 1e-6, [0.0, 0.125, 0.25, 0.375], 5),
     (4096, 1 / 64, 1e-6, [0.05, 0.2, 0.41], 16),
@@ -97,6 +98,7 @@ BAND_CASES = [
     (2048, 1 / 128, 1e-6, [0.0] + [k / 40 for k in range(1, 20)], 16),
     (4096, 1 / 8, 1e-12, [0.0, 0.25], 70),
     (777, 0.01, 1e-6, [0.03], 3),
+    (5000, 1 / 40, 1e-6, [0.0, 0.2, 0.35], 7),  # L = 16384: the three-pass product
 ]
 
 
