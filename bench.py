@@ -377,6 +377,41 @@ def bench_multiband(args, dev):
             "kernels_traced_ms": {k: round(v["total_ms"], 4) for k, v in st.items()}}
 
 
+def bench_coeffs(args, dev):
+    """Slepian coefficients c = S_K^T x (Section 2.3, the compression to K
+    numbers) at the paper-scale size N = 65536, W = 1/8 (K = 16384), 256
+    signals: a plain GEMM on the matrix cores (hipBLASLt), FP32 for an FP32
+    plan and three BF16 products of hi/lo halves for a mixed plan.  The first
+    call computes all K Slepian vectors; the timed calls reuse them."""
+    import torch
+
+    from paper_1611_04950_amd import slepian as S
+    from paper_1611_04950_amd import synth
+    N, W, eps, b = 65536, 1.0 / 8, 1e-6, 256
+    log("bench: coefficients workload")
+    x = synth.gaussian(N, b, 6100, device=dev)
+    out = {"workload": f"slepian_coeffs N={N}, W=1/8, K=16384, {b} signals",
+           "flops_per_call": 2.0 * 16384 * b * N}
+    for name, prec, peak in (("fp32", S.SLEPIAN_FP32, 157.3), ("mixed", S.SLEPIAN_MIXED, 2500.0)):
+        P = S.slepian_plan(N, W, eps, precision=prec)
+        K = P.info["K"]
+        t0 = time.perf_counter()
+        c = S.slepian_coeffs(P, x)
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t0
+        ms = _time_calls(lambda: S.slepian_coeffs(P, x, c), 5, 1, dev)
+        tf = 2.0 * K * b * N / (ms * 1e-3) / 1e12
+        mfma = tf * (3 if prec != S.SLEPIAN_FP32 else 1)
+        out[name] = {"ms_per_call": round(ms, 3), "TFLOP_s": round(tf, 1), "first_call_s": round(first, 2),
+                     "matrix_TFLOP_s": round(mfma, 1), "frac_of_peak": round(mfma / peak, 3),
+                     "peak_TFLOP_s": peak}
+        log(f"bench: coefficients {name}: {ms:.3f} ms per call, {tf:.1f} TFLOP/s "
+            f"({mfma:.0f} TFLOP/s on the matrix cores, {100 * mfma / peak:.1f}% of peak)")
+        del P, c
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_lsq(args, dev):
     """N = 2^20, W = 0.02, eps = 1e-6, 64 signals of 200 tones at 10 dB:
     Tikhonov (alpha = 1e-3) solve refined to a 1e-10 FP64 normal-equation
@@ -576,6 +611,7 @@ def main():
     fext = None if args.no_extra else bench_fourier_extension(args, dev)
     egap = None if args.no_extra else bench_eigen_gap(args, dev)
     mband = None if args.no_extra else bench_multiband(args, dev)
+    coeffs = None if args.no_extra else bench_coeffs(args, dev)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GSamples/s", "n_gpus": 1,
@@ -606,6 +642,7 @@ def main():
         "fourier_extension_workload": fext,
         "eigenvalue_gap_study": egap,
         "multiband_workload": mband,
+        "coefficients_workload": coeffs,
     }
     print(json.dumps(out), flush=True)
 

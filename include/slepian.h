@@ -214,8 +214,13 @@ int slepian_project_bands(slepian_bands_t bands, const float *x, int64_t ldx, fl
 /* Slepian coefficients c = S_K^T x (Section 2.3, "A fast factorization":
  * the K numbers that represent x), exact (dense) semantics.  The first call
  * computes all K Slepian vectors on the GPU and keeps them in the plan
- * (N*K*4 bytes); ENOTSUP if that exceeds 16 GiB.  Vector signs follow the
- * convention of slepian_plan_eigenpairs.  c: K x batch FP32, ldc >= K. */
+ * (N*K*4 bytes, plus as many again for their BF16 hi/lo halves in plans of
+ * MIXED or BF16_RAW precision); ENOTSUP if N*K*4 bytes exceed 16 GiB.  The
+ * product is a library GEMM (hipBLASLt) on the matrix cores: FP32 for FP32
+ * plans, otherwise three BF16 products of the hi/lo halves (hi*hi + hi*lo +
+ * lo*hi) accumulated in FP32.  Vector signs follow the convention of
+ * slepian_plan_eigenpairs.  c: K x batch FP32, ldc >= K; EHIP if the library
+ * fails, ENOTSUP if it has no algorithm for the shape. */
 int slepian_coeffs(slepian_plan_t plan, const float *x, int64_t ldx, float *c, int64_t ldc,
                    int64_t batch, void *work, size_t work_bytes, void *stream);
 

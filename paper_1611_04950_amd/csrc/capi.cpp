@@ -122,6 +122,8 @@ struct OpSet {
 
 }  // namespace
 
+constexpr size_t kCoeffsGemmWs = (size_t)64 << 20;  // the library GEMM's workspace
+
 struct slepian_plan_s {
   int device = 0;
   int64_t N = 0, K = 0, L = 0;
@@ -146,6 +148,9 @@ struct slepian_plan_s {
   size_t ws_bytes = 0;
   float *SK = nullptr;   // all K Slepian vectors (slepian_coeffs), leading dimension ldsk
   int64_t ldsk = 0;
+  __bf16 *SKh = nullptr, *SKl = nullptr;  // their BF16 hi/lo planes (plans of MIXED or BF16_RAW precision)
+  GemmCache coeffs_cache;                 // the library's algorithm for the last coefficient GEMM shape
+  std::mutex coeffs_mu;
   // U's rows laid out for the fused inverse column pass, per column set and
   // matrix mode (FP32, BF16 hi/lo); null where that pass does not apply
   void *ctile[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
@@ -167,6 +172,8 @@ struct slepian_plan_s {
     }
     dfree(ws);
     dfree(SK);
+    dfree(SKh);
+    dfree(SKl);
     for (auto &t : ctile)
       for (void *p : t) dfree(p);
     for (void *p : mbu) dfree(p);
@@ -353,9 +360,15 @@ size_t op_workspace(const Plan *P, int op, int64_t b) {
       carve_project(P, P->proj, b, c2, SLEPIAN_MIXED);
       return std::max(cv.off, c2.off) + 256;
     }
-    case SLEPIAN_OP_COEFFS:
-      cv.take<float>((size_t)corr_nchunks(P->N, b, (int)P->K) * corr_rpad((int)P->K) * b);
+    case SLEPIAN_OP_COEFFS: {
+      // staged x (FP32, or BF16 hi and lo), the product, the library's workspace
+      const size_t ldxb = (size_t)(P->N + 7) / 8 * 8, ldcb = (size_t)(P->K + 3) / 4 * 4;
+      if (P->precision == SLEPIAN_FP32) cv.take<float>(ldxb * b);
+      else cv.take<__bf16>(2 * ldxb * b);
+      cv.take<float>(ldcb * b);
+      cv.take<char>(kCoeffsGemmWs);
       break;
+    }
     case SLEPIAN_OP_LSQ: {
       Carver c1(nullptr), c2(nullptr);
       carve_pinv(P, b, c1);
@@ -1410,12 +1423,60 @@ int slepian_coeffs(slepian_plan_t P, const float *x, int64_t ldx, float *c, int6
       P->SK = SK;
       P->ldsk = (N + 3) / 4 * 4;
     }
+    const int mode = P->precision == SLEPIAN_FP32 ? 0 : 1;
+    if (mode == 1 && !P->SKh) {
+      // BF16 hi/lo planes of the Slepian vectors, built once
+      __bf16 *h = dalloc<__bf16>((size_t)P->ldsk * K), *l = nullptr;
+      try {
+        l = dalloc<__bf16>((size_t)P->ldsk * K);
+        for (int64_t j0 = 0; j0 < K; j0 += 32768) {
+          const int64_t cc = std::min<int64_t>(32768, K - j0);
+          HIPCHK(split_bf16(P->SK + j0 * P->ldsk, P->ldsk, N, cc, h + j0 * P->ldsk, l + j0 * P->ldsk, P->ldsk, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+      } catch (...) {
+        dfree(h);
+        dfree(l);
+        throw;
+      }
+      P->SKh = h;
+      P->SKl = l;
+    }
     const size_t need = op_workspace(P, SLEPIAN_OP_COEFFS, batch);
     void *ws = get_ws(P, work, work_bytes, need);
     Carver cv(ws);
-    float *part = cv.take<float>((size_t)corr_nchunks(N, batch, (int)K) * corr_rpad((int)K) * batch);
-    HIPCHK(corr_partial_mfma(0, x, ldx, N, batch, P->SK, P->ldsk, (int)K, part, st));
-    HIPCHK(corr_sum_mfma(part, N, batch, (int)K, c, ldc, st));
+    const int64_t ldxb = (N + 7) / 8 * 8, ldcb = (K + 3) / 4 * 4;
+    float *x32 = nullptr;
+    __bf16 *xh = nullptr, *xl = nullptr;
+    if (mode == 0) {
+      x32 = cv.take<float>((size_t)ldxb * batch);
+    } else {
+      xh = cv.take<__bf16>((size_t)ldxb * batch);
+      xl = xh + (size_t)ldxb * batch;
+      cv.off += (size_t)ldxb * batch * sizeof(__bf16);
+    }
+    float *cw = cv.take<float>((size_t)ldcb * batch);
+    void *gws = cv.take<char>(kCoeffsGemmWs);
+    // x staged into aligned planes, the product into an aligned buffer, then c
+    for (int64_t s0 = 0; s0 < batch; s0 += 65535) {
+      const int64_t bb = std::min<int64_t>(65535, batch - s0);
+      if (mode == 0) HIPCHK(copy_f32(x + s0 * ldx, ldx, x32 + s0 * ldxb, ldxb, N, bb, st));
+      else HIPCHK(split_bf16(x + s0 * ldx, ldx, N, bb, xh + s0 * ldxb, xl + s0 * ldxb, ldxb, st));
+    }
+    int g;
+    {
+      std::lock_guard<std::mutex> lock(P->coeffs_mu);
+      g = mode == 0 ? coeffs_gemm(P->device, 0, P->SK, nullptr, P->ldsk, x32, nullptr, ldxb, cw, ldcb, N, K, batch,
+                                  gws, kCoeffsGemmWs, P->coeffs_cache, st)
+                    : coeffs_gemm(P->device, 1, P->SKh, P->SKl, P->ldsk, xh, xl, ldxb, cw, ldcb, N, K, batch, gws,
+                                  kCoeffsGemmWs, P->coeffs_cache, st);
+    }
+    if (g == -2) return SLEPIAN_ENOTSUP;
+    if (g != 0) return SLEPIAN_EHIP;
+    for (int64_t s0 = 0; s0 < batch; s0 += 65535) {
+      const int64_t bb = std::min<int64_t>(65535, batch - s0);
+      HIPCHK(copy_f32(cw + s0 * ldcb, ldcb, c + s0 * ldc, ldc, K, bb, st));
+    }
     return SLEPIAN_OK;
   });
 }

@@ -193,6 +193,28 @@ hipError_t corr_sum_mfma(const float *part, int64_t N, int64_t b, int r, float *
 hipError_t corr_apply_mfma(float *y, int64_t ldy, int64_t N, int64_t b, const float *U, int64_t ldu, int r,
                            const float *dC, hipStream_t st);
 
+// ---- Slepian coefficients as a library GEMM (gemm.hip) ----
+// hi/lo BF16 halves of an N x b FP32 matrix into planes with leading dimension ld
+hipError_t split_bf16(const float *x, int64_t ldx, int64_t N, int64_t b, __bf16 *hi, __bf16 *lo, int64_t ld,
+                      hipStream_t st);
+// dst (rows x cols, ldd) = src (lds), FP32
+hipError_t copy_f32(const float *src, int64_t lds, float *dst, int64_t ldd, int64_t rows, int64_t cols,
+                    hipStream_t st);
+// The algorithm chosen for one GEMM shape (kept per plan and mode).
+struct GemmCache {
+  bool valid = false;
+  int mode = -1;
+  int64_t N = 0, K = 0, b = 0, lds = 0, ldx = 0, ldc = 0;
+  size_t ws_max = 0, ws = 0;
+  alignas(16) unsigned char algo[128];  // hipblasLtMatmulAlgo_t, opaque here
+};
+// c (K x b, ldc) = S^T X with S: N x K (lds) and X: N x b (ldx); mode 0 FP32 operands
+// (S, X), mode 1 BF16 hi (S, X) and lo (Slo, Xlo) planes, three products.  Returns 0,
+// -1 (library error) or -2 (no algorithm for the shape).
+int coeffs_gemm(int device, int mode, const void *S, const void *Slo, int64_t lds, const void *X, const void *Xlo,
+                int64_t ldx, float *c, int64_t ldc, int64_t N, int64_t K, int64_t b, void *ws, size_t ws_bytes,
+                GemmCache &cache, hipStream_t st);
+
 // ---- Least-squares refinement helpers (lsq.hip) ----
 // rho = By - u - alpha x (all FP64, N x b with leading dimension N except x: ldx)
 hipError_t lsq_residual(const double *By, const double *u, const double *x, int64_t ldx, double alpha, double *rho,

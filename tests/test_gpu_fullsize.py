@@ -175,3 +175,26 @@ def test_batching_workload():
         e = rel_err(ys[i].cpu().numpy(), ref)
         _log(f"plan {i} N={N} W={W:.4f} eps={eps} b={b}: max rel err {e.max():.3e}")
         assert e.max() <= 1e-5
+
+
+def test_coeffs_paper_scale_energy():
+    """c = S_K^T x at N = 65536, W = 1/8 (K = 16384), 8 signals: ||c||^2 =
+    x^T S_K S_K^T x, which the fast projection approximates within
+    Corollary 2's eps (x^T P~ x, eps = 1e-6 relative to ||x||^2); and the
+    mixed-precision coefficients (three BF16 products) agree with the FP32 ones."""
+    N, W, eps = 65536, 1 / 8, 1e-6
+    x = synth.gaussian(N, 8, 5151, device="cuda")
+    P = S.slepian_plan(N, W, eps)
+    c = S.slepian_coeffs(P, x)
+    y = S.slepian_project(P, x)
+    torch.cuda.synchronize()
+    e_c = (c.double() ** 2).sum(1)
+    e_p = (x.double() * y.double()).sum(1)
+    xx = (x.double() ** 2).sum(1)
+    assert ((e_c - e_p).abs() / xx).max().item() <= 3e-6
+    del P
+    Q = S.slepian_plan(N, W, eps, precision=S.SLEPIAN_MIXED)
+    cm = S.slepian_coeffs(Q, x)
+    torch.cuda.synchronize()
+    d = (torch.linalg.vector_norm((cm - c).double(), dim=1) / torch.linalg.vector_norm(c.double(), dim=1)).max()
+    assert d.item() <= 1e-5, d.item()

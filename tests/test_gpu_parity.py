@@ -205,14 +205,23 @@ def test_tikhonov_fast_and_refined(plans, N, W, eps, alpha):
 
 
 @pytest.mark.parametrize("N,W", [(256, 1 / 8), (1024, 1 / 16), (777, 0.21)])
-def test_coeffs_match_oracle(plans, N, W):
-    P = plans(N, W, 1e-6)
-    x = synth.gaussian(N, 4, 3, device="cuda")
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_coeffs_match_oracle(plans, N, W, prec):
+    P = plans(N, W, 1e-6) if prec == "fp32" else S.slepian_plan(N, W, 1e-6, precision=S.SLEPIAN_MIXED)
+    x = synth.gaussian(N, 5, 3, device="cuda")
     c = S.slepian_coeffs(P, x)
     torch.cuda.synchronize()
     ref = o.coeffs_exact(N, W, x.double().cpu().numpy().T).T
     e = rel_err(c.cpu().numpy(), ref)
     assert e.max() <= 1e-5, e
+    # rows of x that are slices with an odd leading dimension, and a strided c
+    xb = torch.zeros((5, N + 3), device="cuda")
+    xb[:, :N] = x
+    cb = torch.full((5, P.K + 5), float("nan"), device="cuda")
+    S.slepian_coeffs(P, xb[:, :N], cb[:, :P.K])
+    torch.cuda.synchronize()
+    assert torch.equal(cb[:, :P.K], c)
+    assert torch.isnan(cb[:, P.K:]).all()
 
 
 def test_save_load_roundtrip(plans, tmp_path):
