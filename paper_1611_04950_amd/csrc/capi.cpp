@@ -300,6 +300,7 @@ B64Ws carve_b64(const Plan *P, int64_t b, Carver &cv) {
 struct TikWs {
   float *x32, *rho32, *e32;
   double *y64, *By, *t, *u, *rho, *nBy, *nr;
+  double *npart = nullptr;                    // column-norm partial sums
   double *part64 = nullptr, *dC64 = nullptr;  // FP64 correction of the starting point
   ProjWs pw;
   B64Ws bw;
@@ -318,6 +319,7 @@ TikWs carve_tik(const Plan *P, int64_t b, Carver &cv) {
   w.rho = cv.take<double>(nb);
   w.nBy = cv.take<double>(b);
   w.nr = cv.take<double>(b);
+  w.npart = cv.take<double>((size_t)b * kNormParts);
   if (P->tik.r > 0) {
     const int r = (int)P->tik.r;
     w.part64 = cv.take<double>(corr64_workspace_doubles(P->N, b, r) - (size_t)r * b);
@@ -1339,7 +1341,7 @@ int slepian_lsq(slepian_plan_t P, int mode, double alpha, const float *y, int64_
     if (max_iter == 0 && !rep) return SLEPIAN_OK;
     HIPCHK(cast_f32_to_f64(y, ldy, w.y64, N, N, b, st));
     run_b64(P, w.y64, N, w.By, N, b, w.bw, st);
-    HIPCHK(col_norms(w.By, N, N, b, w.nBy, st));
+    HIPCHK(col_norms(w.By, N, N, b, w.nBy, w.npart, st));
     std::vector<double> nBy(b), nr(b);
     HIPCHK(hipMemcpyAsync(nBy.data(), w.nBy, b * sizeof(double), hipMemcpyDeviceToHost, st));
     const float betaM = (float)(1.0 / (1.0 + alpha) - 1.0 / alpha);
@@ -1351,7 +1353,7 @@ int slepian_lsq(slepian_plan_t P, int mode, double alpha, const float *y, int64_
       run_b64(P, x, ldx, w.t, N, b, w.bw, st);
       run_b64(P, w.t, N, w.u, N, b, w.bw, st);
       HIPCHK(lsq_residual(w.By, w.u, x, ldx, alpha, w.rho, N, b, st));
-      HIPCHK(col_norms(w.rho, N, N, b, w.nr, st));
+      HIPCHK(col_norms(w.rho, N, N, b, w.nr, w.npart, st));
       HIPCHK(hipMemcpyAsync(nr.data(), w.nr, b * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       rel = 0.0;

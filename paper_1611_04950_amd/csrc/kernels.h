@@ -219,8 +219,10 @@ int coeffs_gemm(int device, int mode, const void *S, const void *Slo, int64_t ld
 // rho = By - u - alpha x (all FP64, N x b with leading dimension N except x: ldx)
 hipError_t lsq_residual(const double *By, const double *u, const double *x, int64_t ldx, double alpha, double *rho,
                         int64_t N, int64_t b, hipStream_t st);
-// norms[s] = ||v_s||_2 (FP64)
-hipError_t col_norms(const double *v, int64_t ldv, int64_t N, int64_t b, double *norms, hipStream_t st);
+// norms[s] = ||v_s||_2 (FP64, fixed summation order); part: b * kNormParts doubles of scratch
+constexpr int kNormParts = 256;
+hipError_t col_norms(const double *v, int64_t ldv, int64_t N, int64_t b, double *norms, double *part,
+                     hipStream_t st);
 // x (FP64, ldx) += e (FP32, lde)
 hipError_t add_f32_to_f64(const float *e, int64_t lde, double *x, int64_t ldx, int64_t N, int64_t b, hipStream_t st);
 

@@ -24,24 +24,73 @@ hipError_t lsq_residual(const double *By, const double *u, const double *x, int6
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_col_norms(const double *__restrict__ v, int64_t ldv, int64_t N,
-                                                   double *__restrict__ norms) {
+// Column norms in two passes with a fixed summation order: pass 1 gives each
+// of `parts` workgroups per column one contiguous segment (four independent
+// accumulators per thread, then a tree over the workgroup), pass 2 sums a
+// column's segment partials in order and takes the square root.
+__global__ __launch_bounds__(256) void k_col_norms_part(const double *__restrict__ v, int64_t ldv, int64_t N,
+                                                        int64_t seg, int parts, double *__restrict__ part) {
   __shared__ double red[256];
-  const double *c = v + (int64_t)blockIdx.x * ldv;
-  double acc = 0.0;
-  for (int64_t n = threadIdx.x; n < N; n += 256) acc += c[n] * c[n];
-  red[threadIdx.x] = acc;
+  const int p = blockIdx.x, s = blockIdx.y;
+  const double *c = v + (int64_t)s * ldv;
+  const int64_t n0 = (int64_t)p * seg, n1 = n0 + seg < N ? n0 + seg : N;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t n = n0 + threadIdx.x;
+  for (; n + 768 < n1; n += 1024) {
+    const double x0 = c[n], x1 = c[n + 256], x2 = c[n + 512], x3 = c[n + 768];
+    a0 += x0 * x0;
+    a1 += x1 * x1;
+    a2 += x2 * x2;
+    a3 += x3 * x3;
+  }
+  for (; n < n1; n += 256) a0 += c[n] * c[n];
+  red[threadIdx.x] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) norms[blockIdx.x] = sqrt(red[0]);
+  if (threadIdx.x == 0) part[(int64_t)s * parts + p] = red[0];
 }
 
-hipError_t col_norms(const double *v, int64_t ldv, int64_t N, int64_t b, double *norms, hipStream_t st) {
+__global__ __launch_bounds__(256) void k_col_norms_sum(const double *__restrict__ part, int parts,
+                                                       double *__restrict__ norms) {
+  __shared__ double red[256];
+  const int s = blockIdx.x;
+  red[threadIdx.x] = (int)threadIdx.x < parts ? part[(int64_t)s * parts + threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) norms[s] = sqrt(red[0]);
+}
+
+hipError_t col_norms(const double *v, int64_t ldv, int64_t N, int64_t b, double *norms, double *part,
+                     hipStream_t st) {
   if (b == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_col_norms, dim3((unsigned)b), dim3(256), 0, st, v, ldv, N, norms);
+  if (b > 65535) {
+    for (int64_t s0 = 0; s0 < b; s0 += 65535) {
+      const int64_t bb = b - s0 < 65535 ? b - s0 : 65535;
+      const hipError_t e = col_norms(v + s0 * ldv, ldv, N, bb, norms + s0, part + s0 * kNormParts, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  // about 2048 workgroups over the whole batch, at most kNormParts per column,
+  // segments of whole 1024-sample rounds
+  int64_t parts = 2048 / b;
+  if (parts < 1) parts = 1;
+  if (parts > kNormParts) parts = kNormParts;
+  int64_t seg = (N + parts - 1) / parts;
+  seg = (seg + 1023) / 1024 * 1024;
+  parts = (N + seg - 1) / seg;
+  if (parts < 1) parts = 1;
+  hipLaunchKernelGGL(k_col_norms_part, dim3((unsigned)parts, (unsigned)b), dim3(256), 0, st, v, ldv, N, seg,
+                     (int)parts, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_norms_sum, dim3((unsigned)b), dim3(256), 0, st, part, (int)parts, norms);
   return hipGetLastError();
 }
 
