@@ -4,7 +4,7 @@
 // rounding in U^T y is amplified by up to that factor; the product runs in
 // FP64 from the plan's FP64 vectors (the FFT product B y stays FP32, its
 // rounding is not amplified).  C = U^T Y is split over chunks of samples,
-// each workgroup forming 64 j x 8 signals of one chunk from LDS tiles, and
+// each workgroup forming 64 j x 32 signals of one chunk from LDS tiles, and
 // the chunk partials are summed in a fixed order (deterministic).
 #include "common.h"
 #include "kernels.h"
@@ -16,12 +16,12 @@ int corr_rpad(int r) { return (r + 31) / 32 * 32; }
 
 constexpr int kC64Chunk = 1024;  // samples per workgroup
 constexpr int kC64Sub = 64;      // samples staged in LDS at a time
-constexpr int kC64Sig = 8;       // signals per workgroup
+constexpr int kC64Sig = 32;      // signals per workgroup
 
 int corr64_chunks(int64_t N) { return (int)((N + kC64Chunk - 1) / kC64Chunk); }
 
-// grid (chunks, ceil(b / 8)), 256 threads: thread t owns U column j0 + t % 64
-// and signals 2 (t / 64) and 2 (t / 64) + 1 of the workgroup's eight.
+// grid (chunks, ceil(b / 32)), 256 threads: thread t owns U column j0 + t % 64
+// and signals 8 (t / 64) .. 8 (t / 64) + 7 of the workgroup's 32.
 __global__ __launch_bounds__(256) void k_corr64_partial(const float *__restrict__ y, int64_t ldy, int N, int b,
                                                         const double *__restrict__ U, int64_t ldu, int r,
                                                         double *__restrict__ part) {
@@ -31,7 +31,9 @@ __global__ __launch_bounds__(256) void k_corr64_partial(const float *__restrict_
   const int s_base = blockIdx.y * kC64Sig;
   const int n_chunk = blockIdx.x * kC64Chunk;
   for (int j0 = 0; j0 < r; j0 += 64) {
-    double a0 = 0.0, a1 = 0.0;
+    double a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = 0.0;
     for (int sub = 0; sub < kC64Chunk; sub += kC64Sub) {
       const int n0 = n_chunk + sub;
       if (n0 >= N) break;
@@ -45,32 +47,49 @@ __global__ __launch_bounds__(256) void k_corr64_partial(const float *__restrict_
         Yt[s][nn] = (n < N && s_base + s < b) ? (double)y[(int64_t)(s_base + s) * ldy + n] : 0.0;
       }
       __syncthreads();
-#pragma unroll 8
+#pragma unroll 4
       for (int nn = 0; nn < kC64Sub; ++nn) {
         const double u = Ut[jj][nn];
-        a0 += u * Yt[2 * sp][nn];
-        a1 += u * Yt[2 * sp + 1][nn];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] += u * Yt[8 * sp + q][nn];
       }
     }
-    const int j = j0 + jj, s0 = s_base + 2 * sp;
+    const int j = j0 + jj;
     if (j < r) {
-      if (s0 < b) part[((int64_t)blockIdx.x * r + j) * b + s0] = a0;
-      if (s0 + 1 < b) part[((int64_t)blockIdx.x * r + j) * b + s0 + 1] = a1;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int s = s_base + 8 * sp + q;
+        if (s < b) part[((int64_t)blockIdx.x * r + j) * b + s] = a[q];
+      }
     }
   }
 }
 
-// dC[j][s] = d[j] * sum over chunks of part[chunk][j][s], chunks in order.
-__global__ void k_corr64_reduce(const double *__restrict__ part, int chunks, int b, int r,
-                                const double *__restrict__ d, double *__restrict__ dC) {
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= (int64_t)r * b) return;
+// dC[j][s] = d[j] * sum over chunks of part[chunk][j][s]: 16 outputs per
+// workgroup, 16 lanes per output each summing every 16th chunk, then a
+// fixed-order sum of the 16 through LDS.
+__global__ __launch_bounds__(256) void k_corr64_reduce(const double *__restrict__ part, int chunks, int b, int r,
+                                                       const double *__restrict__ d, double *__restrict__ dC) {
+  __shared__ double red[16][17];
+  const int og = threadIdx.x & 15, cg = threadIdx.x >> 4;
+  const int64_t o = (int64_t)blockIdx.x * 16 + og;  // o = j b + s
+  const bool valid = o < (int64_t)r * b;
   double acc = 0.0;
-  for (int c = 0; c < chunks; ++c) acc += part[(int64_t)c * r * b + o];
-  dC[o] = d[o / b] * acc;
+  if (valid) {
+    const int64_t stride = (int64_t)r * b;
+    for (int c = cg; c < chunks; c += 16) acc += part[(int64_t)c * stride + o];
+  }
+  red[cg][og] = acc;
+  __syncthreads();
+  if (cg == 0 && valid) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += red[q][og];
+    dC[o] = d[o / b] * t;
+  }
 }
 
-// x[s][n] += sum_j U[n][j] dC[j][s]: one sample per lane, eight signals per
+// x[s][n] += sum_j U[n][j] dC[j][s]: one sample per lane, 32 signals per
 // workgroup, dC staged in LDS 64 columns at a time.
 __global__ __launch_bounds__(256) void k_corr64_apply(double *__restrict__ x, int64_t ldx, int N, int b,
                                                       const double *__restrict__ U, int64_t ldu, int r,
@@ -113,7 +132,7 @@ hipError_t corr64(const float *y, int64_t ldy, double *x, int64_t ldx, int64_t N
   SLP_LAUNCH("corr64_partial", k_corr64_partial, dim3((unsigned)chunks, gy), dim3(256), 0, st, y, ldy, (int)N,
              (int)b, U, ldu, r, part);
   const int64_t outs = (int64_t)r * b;
-  SLP_LAUNCH("corr64_reduce", k_corr64_reduce, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, st, part, chunks,
+  SLP_LAUNCH("corr64_reduce", k_corr64_reduce, dim3((unsigned)((outs + 15) / 16)), dim3(256), 0, st, part, chunks,
              (int)b, r, d, dC);
   SLP_LAUNCH("corr64_apply", k_corr64_apply, dim3((unsigned)((N + 255) / 256), gy), dim3(256), 0, st, x, ldx,
              (int)N, (int)b, U, ldu, r, dC);
