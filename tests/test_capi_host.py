@@ -84,6 +84,15 @@ def test_null_handles():
     h = C.c_void_p()
     assert lib.slepian_plan_load(b"/nonexistent/plan.bin", -1, C.byref(h)) == S.SLEPIAN_EIO
     assert lib.slepian_group_create(None, 0, None, C.byref(h)) == S.SLEPIAN_EINVAL
+    # multiband entry points: no plan, no band set
+    f = (C.c_double * 2)(0.0, 0.25)
+    assert lib.slepian_project_multiband(None, 2, f, None, 0, None, 0, 1, None, 0, None) == S.SLEPIAN_EINVAL
+    assert lib.slepian_bands_create(None, 2, f, C.byref(h)) == S.SLEPIAN_EINVAL
+    assert h.value is None
+    assert lib.slepian_bands_create(None, 2, f, None) == S.SLEPIAN_EINVAL
+    assert lib.slepian_bands_destroy(None) == S.SLEPIAN_OK
+    assert lib.slepian_bands_workspace_size(None, 4, C.byref(n)) == S.SLEPIAN_EINVAL
+    assert lib.slepian_project_bands(None, None, 0, None, 0, 1, None, 0, None) == S.SLEPIAN_EINVAL
 
 
 def test_plan_load_rejects_garbage(tmp_path):
