@@ -108,9 +108,9 @@ def copy_bandwidth(dev, mib=256, reps=10):
 
 def cpu_baseline(N, W, eps, x_sample, min_seconds):
     """The oracle's FP64 fast projection timed on this host (1 thread), on a
-    sample of the workload's signals.  Returns the timing record and the
+    sample of the workload's signals.  Returns the timing record, the
     oracle's outputs for the sample, against which the GPU's outputs for the
-    same signals are checked."""
+    same signals are checked, and the sample's exact projection."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -129,10 +129,15 @@ def cpu_baseline(N, W, eps, x_sample, min_seconds):
             if el >= min_seconds:
                 break
     samples = reps * xs.shape[0] * xs.shape[1]
+    # the exact projection S_K S_K^T x of the sample, for which the oracle's
+    # fast projection at eps = 1e-13 stands in (Corollary 2 puts it within
+    # 1e-13 ||x||); outside the timed loop
+    with threadpool_limits(limits=1):
+        exact = o.project_fast(N, W, 1e-13, xs)
     return {"value": samples / el / 1e6, "unit": "MSamples/s", "cores": 1, "kind": "oracle",
             "sample": f"{xs.shape[1]} signals of the workload, projected {reps} times ({el:.1f} s); "
                       f"oracle setup (transition vectors) {setup:.1f} s not included",
-            "setup_s": setup}, ref.T
+            "setup_s": setup}, ref.T, exact.T
 
 
 def bench_batching(args, dev):
@@ -520,10 +525,11 @@ def main():
     prec = S.SLEPIAN_MIXED if args.precision == "mixed" else S.SLEPIAN_FP32
     cpu = None
     err = err_sel = None
+    extra_err = None
     if not args.no_cpu:
         ns = min(b, 32)
         log(f"bench: timing the CPU oracle on {ns} signals")
-        cpu, ref = cpu_baseline(N, W, eps, x[:ns].double().cpu().numpy(), args.cpu_seconds)
+        cpu, ref, exact = cpu_baseline(N, W, eps, x[:ns].double().cpu().numpy(), args.cpu_seconds)
         errs = {}
         for p in (S.SLEPIAN_FP32, prec):
             S.slepian_project(plan, x, y, work=work, precision=p)
@@ -535,6 +541,21 @@ def main():
         if not (err <= 1e-5 and err_sel <= 1e-5):
             log("bench: parity gate failed; no throughput reported")
             sys.exit(1)
+        # the BF16 correction without its lo terms, and the distance of the
+        # selected precision's result from the exact projection
+        S.slepian_project(plan, x, y, work=work, precision=S.SLEPIAN_BF16_RAW)
+        torch.cuda.synchronize()
+        ys = y[:ns].double().cpu().numpy()
+        err_raw = float((np.linalg.norm(ys - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
+        S.slepian_project(plan, x, y, work=work, precision=prec)
+        torch.cuda.synchronize()
+        ys = y[:ns].double().cpu().numpy()
+        xn = np.linalg.norm(x[:ns].double().cpu().numpy(), axis=1)
+        err_exact = float((np.linalg.norm(ys - exact, axis=1) / xn).max())
+        log(f"bench: bf16 without lo terms {err_raw:.3e} vs the oracle; {args.precision} vs the exact projection "
+            f"{err_exact:.3e} of ||x|| (Corollary 2 bound eps = {eps:g})")
+        extra_err = {"bf16_raw_vs_oracle": err_raw, "vs_exact_projection_rel_to_x": err_exact,
+                     "corollary2_bound_rel_to_x": eps}
 
     stream = torch.cuda.current_stream(dev)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -626,6 +647,7 @@ def main():
                    "L": info["L"], "r": info["r"]},
         "parity_max_rel_err": err_sel,
         "parity_max_rel_err_fp32": err,
+        "errors": extra_err,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_fp32_per_signal": plain,
