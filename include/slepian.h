@@ -18,8 +18,10 @@
  *     the caller; host pointers are marked "host".
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     Calls enqueue work on `stream` and return without synchronising unless
- *     stated otherwise.  A plan is read-only after creation; concurrent calls
- *     on different streams need separate workspaces.
+ *     stated otherwise.  A plan does not change after creation except for
+ *     buffers built on first use and then kept (the Slepian vectors of
+ *     slepian_coeffs, U's layouts for band sets), which are built under a
+ *     lock; concurrent calls on different streams need separate workspaces.
  *   - Workspace: pass work = NULL, work_bytes = 0 to let the plan use an
  *     internal buffer (grown on demand; then calls on one plan must not run
  *     concurrently), or pass a buffer of at least slepian_workspace_size()

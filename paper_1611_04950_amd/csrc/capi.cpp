@@ -1392,6 +1392,9 @@ int slepian_coeffs(slepian_plan_t P, const float *x, int64_t ldx, float *c, int6
     DeviceGuard dg(P->device);
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = P->N, K = P->K;
+    // the vectors, their BF16 halves and the library's algorithm are built on
+    // first use and kept by the plan; one call at a time builds or reads them
+    std::lock_guard<std::mutex> lock(P->coeffs_mu);
     if (!P->SK) {
       // all K Slepian vectors, l = 0..K-1 (column l), FP64 then FP32
       Tridiag T;
@@ -1465,14 +1468,10 @@ int slepian_coeffs(slepian_plan_t P, const float *x, int64_t ldx, float *c, int6
       if (mode == 0) HIPCHK(copy_f32(x + s0 * ldx, ldx, x32 + s0 * ldxb, ldxb, N, bb, st));
       else HIPCHK(split_bf16(x + s0 * ldx, ldx, N, bb, xh + s0 * ldxb, xl + s0 * ldxb, ldxb, st));
     }
-    int g;
-    {
-      std::lock_guard<std::mutex> lock(P->coeffs_mu);
-      g = mode == 0 ? coeffs_gemm(P->device, 0, P->SK, nullptr, P->ldsk, x32, nullptr, ldxb, cw, ldcb, N, K, batch,
-                                  gws, kCoeffsGemmWs, P->coeffs_cache, st)
-                    : coeffs_gemm(P->device, 1, P->SKh, P->SKl, P->ldsk, xh, xl, ldxb, cw, ldcb, N, K, batch, gws,
-                                  kCoeffsGemmWs, P->coeffs_cache, st);
-    }
+    const int g = mode == 0 ? coeffs_gemm(P->device, 0, P->SK, nullptr, P->ldsk, x32, nullptr, ldxb, cw, ldcb, N, K,
+                                          batch, gws, kCoeffsGemmWs, P->coeffs_cache, st)
+                            : coeffs_gemm(P->device, 1, P->SKh, P->SKl, P->ldsk, xh, xl, ldxb, cw, ldcb, N, K, batch,
+                                          gws, kCoeffsGemmWs, P->coeffs_cache, st);
     if (g == -2) return SLEPIAN_ENOTSUP;
     if (g != 0) return SLEPIAN_EHIP;
     for (int64_t s0 = 0; s0 < batch; s0 += 65535) {

@@ -600,6 +600,18 @@ static int env_int(const char *name, int dflt) {
   return e ? std::atoi(e) : dflt;
 }
 
+// tuning overrides, read once per process
+struct MbTuning {
+  int nbw1, pwaves, tiles, cu;
+  MbTuning()
+      : nbw1(env_int("SLEPIAN_MB_NBW", 0) == 1), pwaves(env_int("SLEPIAN_MB_PWAVES", 4096)),
+        tiles(env_int("SLEPIAN_MB_T", 4)), cu(env_int("SLEPIAN_MB_CU", 4)) {}
+};
+static const MbTuning &mb_tuning() {
+  static const MbTuning t;
+  return t;
+}
+
 MbShape mb_shape(int64_t N, int64_t b, int r, int J) {
   MbShape sh;
   sh.ncmb = 2 * J;
@@ -608,7 +620,7 @@ MbShape mb_shape(int64_t N, int64_t b, int r, int J) {
   sh.nsg = (int)((b + G - 1) / G);
   const int nblk = (sh.ncmb + cpb - 1) / cpb;
   sh.nbw = nblk >= 8 ? 2 : 1;
-  if (env_int("SLEPIAN_MB_NBW", 0) == 1) sh.nbw = 1;  // tuning override
+  if (mb_tuning().nbw1) sh.nbw = 1;  // tuning override
   const int per = (nblk + sh.nbw - 1) / sh.nbw;  // wavefronts needed for all blocks
   sh.nw = per < 4 ? per : 4;
   sh.ncg = (nblk + sh.nw * sh.nbw - 1) / (sh.nw * sh.nbw);
@@ -616,7 +628,7 @@ MbShape mb_shape(int64_t N, int64_t b, int r, int J) {
   sh.rpad = 32 * sh.nz;
   sh.jp = 32 * sh.nz;
   // about 4096 wavefronts in the partial pass (tuning override SLEPIAN_MB_PWAVES)
-  int64_t waves = env_int("SLEPIAN_MB_PWAVES", 4096);
+  int64_t waves = mb_tuning().pwaves;
   if (waves < 256 || waves > 65536) waves = 4096;
   const int64_t per_chunk = (int64_t)sh.nw * sh.ncg * sh.nsg * sh.nz;
   const int64_t want = per_chunk >= waves ? 1 : waves / per_chunk;
@@ -638,7 +650,7 @@ MbShape mb_shape(int64_t N, int64_t b, int r, int J) {
   sh.tiles = rk == 1 ? 4 : (rk == 2 ? 4 : 2);
   sh.cu = rk == 1 ? 4 : 1;
   if (rk == 1) {
-    const int t = env_int("SLEPIAN_MB_T", 4), cu = env_int("SLEPIAN_MB_CU", 4);
+    const int t = mb_tuning().tiles, cu = mb_tuning().cu;
     if (t == 4 || t == 8) sh.tiles = t;
     if (cu == 1 || cu == 4) sh.cu = cu;
   }
