@@ -13,7 +13,7 @@ tolerance of the fast approximations), K (number of leading Slepian vectors),
 B (the N x N prolate matrix), lambda (its eigenvalues, sorted descending),
 S (its eigenvectors, the Slepian basis).
 
-Readings of points the paper leaves open (all listed in the design doc too):
+Readings of points the paper leaves open:
   * B's diagonal is 2W, the limit of sin(2 pi W k)/(pi k) as k -> 0.
   * K = round(2NW) rounds halves away from zero (Section 4.1 uses "round").
   * The FFT length for B x is the smallest power of two >= 2N (Section 4.1).
