@@ -53,7 +53,7 @@ enum slepian_status {
   SLEPIAN_ENOMEM = -3,     /* device or host allocation failed, or workspace too small */
   SLEPIAN_EHIP = -4,       /* a HIP runtime call failed */
   SLEPIAN_ENOCONV = -5,    /* eigensolver check or iterative refinement did not converge */
-  SLEPIAN_ENOTSUP = -6,    /* size or mode not supported by this build */
+  SLEPIAN_ENOTSUP = -6,    /* size or mode the library does not support  */
   SLEPIAN_ENONFINITE = -7, /* NaN or Inf found where finite values are required */
   SLEPIAN_EIO = -8         /* plan file could not be read or written, or is malformed */
 };
