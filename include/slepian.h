@@ -213,6 +213,54 @@ int slepian_bands_workspace_size(slepian_bands_t bands, int64_t batch, size_t *b
 int slepian_project_bands(slepian_bands_t bands, const float *x, int64_t ldx, float *y, int64_t ldy,
                           int64_t batch, void *work, size_t work_bytes, void *stream);
 
+/* Fast factorization S_K S_K^T ~= T1 T2^T (Section 2.3, "A fast
+ * factorization", with Theorem 1):
+ *     T1 = [F, V diag(mu), U diag(d)],   T2 = [F, V, U],
+ * F the partial DFT matrix of the 2NW' lowest length-N frequencies (2NW' =
+ * kf, the odd integer nearest to 2NW; ties upward), V diag(mu) V^T the
+ * eigenpairs of the symmetric Toeplitz matrix B - F F^* with |mu| > eps (the
+ * least-rank factor within eps, so r1 is at most Theorem 1's rank), and
+ * U diag(d) U^T the plan's transition correction of Corollary 2.
+ * ||S_K S_K^T - T1 T2^T|| <= 2 eps.  For real signals F is used in its real
+ * form F_r (same F F^*): columns 1/sqrt(N), sqrt(2/N) cos(2 pi k n / N),
+ * -sqrt(2/N) sin(2 pi k n / N) for k = 1 .. (kf - 1)/2, in that interleaved
+ * order.  A compressed signal holds kprime = kf + r1 + r FP32 numbers:
+ * [F_r^T x; V^T x; U^T x].
+ * Requires N a power of two (the plan's FFT length is then exactly 2N) with
+ * 256 <= N <= 2^20, else ENOTSUP.  Setup (synchronous, FP64 on the GPU):
+ * subspace iteration on a random +-1 block with the FFT-applied B - F F^*,
+ * Householder QR and a Rayleigh-Ritz step (rocSOLVER), widening the block
+ * until it resolves every |mu| > eps; ENOCONV if it cannot.  The plan must
+ * outlive the factorization. */
+typedef struct slepian_factor_s *slepian_factor_t;
+typedef struct {
+  int64_t kf;         /* 2NW': rows of the F part of a compressed signal */
+  int64_t r1;         /* columns of V */
+  int64_t r;          /* columns of U (the plan's projection transition set) */
+  int64_t kprime;     /* kf + r1 + r */
+  int64_t subspace;   /* block size the setup converged with */
+  double mu_dropped;  /* largest |Ritz value| of B - F F^* left out (<= eps) */
+} slepian_factor_info_t;
+int slepian_factor_create(slepian_plan_t plan, slepian_factor_t *out);
+int slepian_factor_destroy(slepian_factor_t f);
+int slepian_factor_info(slepian_factor_t f, slepian_factor_info_t *info);
+/* mu (r1 values, decreasing |mu|) to host memory of n >= r1 doubles. */
+int slepian_factor_mu(slepian_factor_t f, double *mu, int64_t n);
+/* Workspace bytes of compress or recover on `batch` signals. */
+int slepian_factor_workspace_size(slepian_factor_t f, int64_t batch, size_t *bytes);
+/* c = T2^T x.  x: N x batch FP32 (device, ldx >= N); c: kprime x batch FP32
+ * (device, ldc >= kprime), no overlap with x.  F_r^T x runs through the
+ * plan's FP32 FFT passes; V^T x and U^T x as one product on the matrix cores
+ * in the plan's precision (FP32, or BF16 hi/lo operands).  batch == 0 is a
+ * no-op; batch <= 32 * 65535. */
+int slepian_factor_compress(slepian_factor_t f, const float *x, int64_t ldx, float *c, int64_t ldc, int64_t batch,
+                            void *work, size_t work_bytes, void *stream);
+/* y = T1 c.  c: kprime x batch FP32 (ldc >= kprime); y: N x batch FP32
+ * (ldy >= N), no overlap with c.  F_r c_F through the plan's FP32 inverse FFT
+ * passes, then y += [V U] ([mu d] . c_rest) on the matrix cores (FP32). */
+int slepian_factor_recover(slepian_factor_t f, const float *c, int64_t ldc, float *y, int64_t ldy, int64_t batch,
+                           void *work, size_t work_bytes, void *stream);
+
 /* Slepian coefficients c = S_K^T x (Section 2.3, "A fast factorization":
  * the K numbers that represent x), exact (dense) semantics.  The first call
  * computes all K Slepian vectors on the GPU and keeps them in the plan

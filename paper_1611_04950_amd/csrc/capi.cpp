@@ -2,6 +2,7 @@
 // coefficients, groups and plan files.  Declarations and argument contracts
 // are in include/slepian.h.
 #include <hip/hip_runtime.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <cfloat>
@@ -1265,6 +1266,327 @@ int slepian_project_bands(slepian_bands_t B, const float *x, int64_t ldx, float 
     tb.chat = B->chat32;
     HIPCHK(conv_apply<float>(x, ldx, y, ldy, N, batch, P->g32, tb, 1.0f, 0.0f, Corr<float>(), Z, slice, st));
     HIPCHK(mb_apply(B->mode, y, ldy, N, batch, B->u, r, B->M, B->ldm, sh, mw, st));
+    return SLEPIAN_OK;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Fast factorization S_K S_K^T ~= T1 T2^T (Section 2.3, Theorem 1)
+// ---------------------------------------------------------------------------
+
+struct slepian_factor_s {
+  slepian_plan_s *P = nullptr;
+  int device = 0;
+  int kf = 0;                 // 2NW', the odd integer nearest to 2NW
+  int64_t r1 = 0, r = 0;      // columns of the Theorem 1 factor and of the transition set
+  int64_t p = 0;              // subspace size the setup converged with
+  double mu_drop = 0;         // largest |Ritz value| left out (<= eps)
+  float *U = nullptr;         // N x (r1 + r), leading dimension ldu: [V | U_T]
+  int64_t ldu = 0;
+  float *w = nullptr;         // r1 + r weights [mu | d]
+  int mode = 0;               // matrix mode of the coefficient products
+  std::vector<double> mu;
+  ~slepian_factor_s() {
+    dfree(U);
+    dfree(w);
+  }
+};
+
+namespace {
+
+// 2NW': nearest odd integer to 2NW, ties (2NW an even integer) upward.
+int factor_kf(int64_t N, double W) {
+  const double v = 2.0 * (double)N * W;
+  int64_t lo = (int64_t)std::floor(v);
+  if (lo % 2 == 0) lo -= 1;
+  const int64_t hi = lo + 2;
+  return (int)((v - (double)lo) < ((double)hi - v) ? lo : hi);
+}
+
+struct RocHandle {
+  rocblas_handle h = nullptr;
+  explicit RocHandle(hipStream_t st) {
+    if (rocblas_create_handle(&h) != rocblas_status_success) throw Fail{SLEPIAN_EHIP};
+    if (rocblas_set_stream(h, st) != rocblas_status_success) throw Fail{SLEPIAN_EHIP};
+  }
+  ~RocHandle() {
+    if (h) (void)rocblas_destroy_handle(h);
+  }
+};
+
+#define ROCCHK(call)                                             \
+  do {                                                           \
+    if ((call) != rocblas_status_success) throw Fail{SLEPIAN_EHIP}; \
+  } while (0)
+
+size_t factor_workspace(const slepian_factor_s *F, int64_t b) {
+  const Plan *P = F->P;
+  Carver cv(nullptr);
+  const int64_t pairs = (b + 1) / 2;
+  cv.take<cpx<float>>((size_t)pairs * F->kf);
+  const int64_t slice = (int64_t)conv_workspace_pairs(P->g32, pairs, sizeof(cpx<float>), slice_budget());
+  if (!P->g32.single()) cv.take<cpx<float>>((size_t)slice * (size_t)P->L);
+  const int rt = (int)(F->r1 + F->r);
+  if (rt > 0) {
+    cv.take<float>((size_t)corr_nchunks(P->N, b, rt) * corr_rpad(rt) * b);
+    cv.take<float>((size_t)b * corr_rpad(rt));
+  }
+  return cv.off;
+}
+
+struct FactorWs {
+  cpx<float> *Zb = nullptr, *Z = nullptr;
+  int64_t slice = 0;
+  float *part = nullptr, *dC = nullptr;
+};
+
+FactorWs carve_factor(const slepian_factor_s *F, int64_t b, void *base) {
+  const Plan *P = F->P;
+  Carver cv(base);
+  FactorWs w;
+  const int64_t pairs = (b + 1) / 2;
+  w.Zb = cv.take<cpx<float>>((size_t)pairs * F->kf);
+  w.slice = (int64_t)conv_workspace_pairs(P->g32, pairs, sizeof(cpx<float>), slice_budget());
+  if (!P->g32.single()) w.Z = cv.take<cpx<float>>((size_t)w.slice * (size_t)P->L);
+  const int rt = (int)(F->r1 + F->r);
+  if (rt > 0) {
+    w.part = cv.take<float>((size_t)corr_nchunks(P->N, b, rt) * corr_rpad(rt) * b);
+    w.dC = cv.take<float>((size_t)b * corr_rpad(rt));
+  }
+  return w;
+}
+
+// V, mu with B - F F^* ~= V diag(mu) V^T over the eigenpairs with |mu| > eps:
+// subspace iteration on a +-1 start block of p columns with the FP64 product
+// (Toeplitz kernel t of B - F F^*), Householder QR after every product, then
+// a Rayleigh-Ritz step.  p doubles until at least 24 Ritz values fall at or
+// below eps, so every kept pair is resolved far beyond eps.
+void factor_setup(slepian_factor_s *F, hipStream_t st) {
+  Plan *P = F->P;
+  const int64_t N = P->N, L = P->L;
+  // spectrum of t's circulant embedding in the FP64 product's layout
+  const FftGeom gen64 = generic_twin(P->g64);
+  DBuf<double> chat(L);
+  {
+    DBuf<double> c(L);
+    DBuf<cpx<double>> spec(L);
+    HIPCHK(diff_embed(c.p, L, N, P->W, F->kf, st));
+    HIPCHK(fft_forward_real64(c.p, gen64, P->tb64, spec.p, st));
+    HIPCHK(spectrum_relayout<double>(spec.p, gen64, chat.p, P->g64, st));
+  }
+  FftTables<double> tbt = P->tb64;
+  tbt.chat = chat.p;
+  RocHandle rh(st);
+  constexpr int kIters = 6, kMargin = 24;
+  int64_t p = std::min<int64_t>(96, N - 1);
+  for (;;) {
+    DBuf<double> Q((size_t)N * p), Y((size_t)N * p), tau(p), H((size_t)p * p), D(p), E(p);
+    DBuf<int> info(1);
+    Carver mc(nullptr);
+    carve_b64(P, p, mc);
+    DBuf<char> ws(std::max<size_t>(mc.off, 256));
+    Carver cv(ws.p);
+    const B64Ws bw = carve_b64(P, p, cv);
+    HIPCHK(rademacher(Q.p, N, N, p, 0x5eed5eedull, st));
+    for (int it = 0; it <= kIters; ++it) {
+      HIPCHK(conv_apply<double>(Q.p, N, Y.p, N, N, p, P->g64, tbt, 1.0, 0.0, Corr<double>(), bw.Z, bw.slice, st));
+      if (it == kIters) break;
+      ROCCHK(rocsolver_dgeqrf(rh.h, (rocblas_int)N, (rocblas_int)p, Y.p, (rocblas_int)N, tau.p));
+      ROCCHK(rocsolver_dorgqr(rh.h, (rocblas_int)N, (rocblas_int)p, (rocblas_int)p, Y.p, (rocblas_int)N, tau.p));
+      std::swap(Q.p, Y.p);
+    }
+    // H = Q^T (T Q), its eigenpairs (ascending), Ritz vectors Q Z
+    const double one = 1.0, zero = 0.0;
+    ROCCHK(rocblas_dgemm(rh.h, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)p, (rocblas_int)p,
+                         (rocblas_int)N, &one, Q.p, (rocblas_int)N, Y.p, (rocblas_int)N, &zero, H.p,
+                         (rocblas_int)p));
+    ROCCHK(rocsolver_dsyevd(rh.h, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)p, H.p, (rocblas_int)p,
+                            D.p, E.p, info.p));
+    std::vector<double> d(p), z((size_t)p * p);
+    int inf = 0;
+    HIPCHK(hipMemcpyAsync(d.data(), D.p, p * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(z.data(), H.p, (size_t)p * p * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&inf, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (inf != 0) throw Fail{SLEPIAN_ENOCONV};
+    std::vector<int64_t> keep;
+    double drop = 0;
+    for (int64_t i = 0; i < p; ++i) {
+      if (std::fabs(d[i]) > P->eps) keep.push_back(i);
+      else drop = std::max(drop, std::fabs(d[i]));
+    }
+    if (p - (int64_t)keep.size() < kMargin) {
+      if (p >= std::min<int64_t>(1024, N - 1)) throw Fail{SLEPIAN_ENOCONV};
+      p = std::min<int64_t>(2 * p, std::min<int64_t>(1024, N - 1));
+      continue;
+    }
+    std::stable_sort(keep.begin(), keep.end(), [&](int64_t a, int64_t b) { return std::fabs(d[a]) > std::fabs(d[b]); });
+    const int64_t r1 = (int64_t)keep.size();
+    F->r1 = r1;
+    F->p = p;
+    F->mu_drop = drop;
+    F->mu.resize(r1);
+    std::vector<double> zs((size_t)p * std::max<int64_t>(r1, 1));
+    for (int64_t j = 0; j < r1; ++j) {
+      F->mu[j] = d[keep[j]];
+      std::copy(z.begin() + keep[j] * p, z.begin() + (keep[j] + 1) * p, zs.begin() + j * p);
+    }
+    const int64_t rt = r1 + F->r;
+    F->ldu = (N + 3) / 4 * 4;
+    F->U = dalloc<float>((size_t)F->ldu * std::max<int64_t>(rt, 1));
+    if (r1 > 0) {
+      DBuf<double> Zs((size_t)p * r1), V((size_t)N * r1);
+      HIPCHK(hipMemcpyAsync(Zs.p, zs.data(), (size_t)p * r1 * sizeof(double), hipMemcpyHostToDevice, st));
+      ROCCHK(rocblas_dgemm(rh.h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)N, (rocblas_int)r1,
+                           (rocblas_int)p, &one, Q.p, (rocblas_int)N, Zs.p, (rocblas_int)p, &zero, V.p,
+                           (rocblas_int)N));
+      HIPCHK(sign_fix_cols(V.p, N, N, r1, st));
+      HIPCHK(cast_f64_to_f32(V.p, N, F->U, F->ldu, N, r1, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    if (F->r > 0)
+      HIPCHK(copy_f32(P->U32 + P->proj.off * P->ldu, P->ldu, F->U + r1 * F->ldu, F->ldu, N, F->r, st));
+    std::vector<float> w32(std::max<int64_t>(rt, 1));
+    for (int64_t j = 0; j < r1; ++j) w32[j] = (float)F->mu[j];
+    for (int64_t j = 0; j < F->r; ++j) w32[r1 + j] = (float)P->proj.d[j];
+    F->w = dalloc<float>(w32.size());
+    HIPCHK(hipMemcpyAsync(F->w, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return;
+  }
+}
+
+bool bad_factor_args(const slepian_factor_s *F, const void *in, int64_t ldin, int64_t rows_in, const void *out,
+                     int64_t ldout, int64_t rows_out, int64_t batch) {
+  if (!F || batch < 0 || batch > 32 * (int64_t)65535) return true;
+  if (batch == 0) return false;
+  return !in || !out || ldin < rows_in || ldout < rows_out;
+}
+
+bool factor_overlap(const void *a, int64_t lda, int64_t rows_a, const void *b, int64_t ldb, int64_t rows_b,
+                    int64_t batch) {
+  const char *a0 = static_cast<const char *>(a), *b0 = static_cast<const char *>(b);
+  const char *a1 = a0 + ((batch - 1) * lda + rows_a) * (int64_t)sizeof(float);
+  const char *b1 = b0 + ((batch - 1) * ldb + rows_b) * (int64_t)sizeof(float);
+  return a0 < b1 && b0 < a1;
+}
+
+}  // namespace
+
+int slepian_factor_create(slepian_plan_t P, slepian_factor_t *out) {
+  if (!out) return SLEPIAN_EINVAL;
+  *out = nullptr;
+  if (!P) return SLEPIAN_EINVAL;
+  if (!dft_bins_ok(P->g32, P->N) || P->N > ((int64_t)1 << 20)) return SLEPIAN_ENOTSUP;
+  return guarded([&]() -> int {
+    DeviceGuard dg(P->device);
+    auto *F = new slepian_factor_s;
+    F->P = P;
+    F->device = P->device;
+    F->kf = factor_kf(P->N, P->W);
+    F->r = P->proj.r;
+    F->mode = P->precision == SLEPIAN_FP32 ? 0 : 1;
+    hipStream_t st = nullptr;
+    try {
+      HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      factor_setup(F, st);
+      (void)hipStreamDestroy(st);
+    } catch (...) {
+      if (st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+      }
+      delete F;
+      throw;
+    }
+    *out = F;
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_factor_destroy(slepian_factor_t F) {
+  if (!F) return SLEPIAN_OK;
+  return guarded([&]() -> int {
+    DeviceGuard dg(F->device);
+    (void)hipDeviceSynchronize();
+    delete F;
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_factor_info(slepian_factor_t F, slepian_factor_info_t *info) {
+  if (!F || !info) return SLEPIAN_EINVAL;
+  info->kf = F->kf;
+  info->r1 = F->r1;
+  info->r = F->r;
+  info->kprime = F->kf + F->r1 + F->r;
+  info->subspace = F->p;
+  info->mu_dropped = F->mu_drop;
+  return SLEPIAN_OK;
+}
+
+int slepian_factor_mu(slepian_factor_t F, double *mu, int64_t n) {
+  if (!F || (n > 0 && !mu) || n < F->r1) return SLEPIAN_EINVAL;
+  std::copy(F->mu.begin(), F->mu.end(), mu);
+  return SLEPIAN_OK;
+}
+
+int slepian_factor_workspace_size(slepian_factor_t F, int64_t batch, size_t *bytes) {
+  if (!F || !bytes || batch < 0) return SLEPIAN_EINVAL;
+  *bytes = factor_workspace(F, batch);
+  return SLEPIAN_OK;
+}
+
+int slepian_factor_compress(slepian_factor_t F, const float *x, int64_t ldx, float *c, int64_t ldc, int64_t batch,
+                            void *work, size_t work_bytes, void *stream) {
+  if (!F) return SLEPIAN_EINVAL;
+  Plan *P = F->P;
+  const int64_t kp = F->kf + F->r1 + F->r;
+  if (bad_factor_args(F, x, ldx, P->N, c, ldc, kp, batch)) return SLEPIAN_EINVAL;
+  if (batch == 0) return SLEPIAN_OK;
+  if (factor_overlap(x, ldx, P->N, c, ldc, kp, batch)) return SLEPIAN_EINVAL;
+  return guarded([&]() -> int {
+    DeviceGuard dg(F->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = P->N;
+    void *ws = get_ws(P, work, work_bytes, factor_workspace(F, batch));
+    const FactorWs w = carve_factor(F, batch, ws);
+    // F_r^T x: length-N DFT bins of signal pairs, then the real coefficients
+    HIPCHK(dft_bins_fwd(x, ldx, N, batch, P->g32, P->tb32, w.Z, w.slice, w.Zb, F->kf, st));
+    HIPCHK(bins_unpack(w.Zb, F->kf, N, batch, c, ldc, st));
+    // [V U_T]^T x on the matrix cores, chunk partials summed in a fixed order
+    const int rt = (int)(F->r1 + F->r);
+    if (rt > 0) {
+      HIPCHK(corr_partial_mfma(F->mode, x, ldx, N, batch, F->U, F->ldu, rt, w.part, st));
+      HIPCHK(corr_sum_mfma(w.part, N, batch, rt, c + F->kf, ldc, st));
+    }
+    return SLEPIAN_OK;
+  });
+}
+
+int slepian_factor_recover(slepian_factor_t F, const float *c, int64_t ldc, float *y, int64_t ldy, int64_t batch,
+                           void *work, size_t work_bytes, void *stream) {
+  if (!F) return SLEPIAN_EINVAL;
+  Plan *P = F->P;
+  const int64_t kp = F->kf + F->r1 + F->r;
+  if (bad_factor_args(F, c, ldc, kp, y, ldy, P->N, batch)) return SLEPIAN_EINVAL;
+  if (batch == 0) return SLEPIAN_OK;
+  if (factor_overlap(c, ldc, kp, y, ldy, P->N, batch)) return SLEPIAN_EINVAL;
+  return guarded([&]() -> int {
+    DeviceGuard dg(F->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = P->N;
+    void *ws = get_ws(P, work, work_bytes, factor_workspace(F, batch));
+    const FactorWs w = carve_factor(F, batch, ws);
+    // F_r c_F: bins of the pairs, inverse length-2N transform, rows n < N
+    HIPCHK(bins_pack(c, ldc, F->kf, N, batch, w.Zb, st));
+    HIPCHK(dft_bins_inv(w.Zb, F->kf, y, ldy, N, batch, P->g32, P->tb32, w.Z, w.slice, st));
+    // y += [V U_T] ([mu d] . c_rest)
+    const int rt = (int)(F->r1 + F->r);
+    if (rt > 0) {
+      HIPCHK(scale_rows(c, ldc, F->kf, rt, batch, F->w, w.dC, st));
+      HIPCHK(corr_apply_mfma(y, ldy, N, batch, F->U, F->ldu, rt, w.dC, st));
+    }
     return SLEPIAN_OK;
   });
 }

@@ -49,19 +49,26 @@ struct RowShape {
 // result out.  tw1: the lane's W_L2^{t k1} (k1 < R1); rt2: W_T^{m' k2} in LDS,
 // rows k2 of R3 + 1 elements (the padding keeps the stage-3 reads, whose lanes
 // differ in k2, free of bank conflicts).
-template <typename R, int R1, int R2, int R3, typename Spec>
+//
+// DIR = 1 stops after the spectrum callback (forward transform only; v is
+// left undefined); DIR = 2 skips the forward stages and the callback must
+// fill all R3 values of each job (inverse transform only; v need not be set).
+template <typename R, int R1, int R2, int R3, int DIR = 0, typename Spec>
 __device__ __forceinline__ void row_conv_core(cpx<R> (&v)[R1], cpx<R> *S, const cpx<R> (&tw1)[R1],
                                               const cpx<R> *__restrict__ rt2, Spec spec) {
   using RS = RowShape<R1, R2, R3>;
   constexpr int T = RS::T;
   const int t = threadIdx.x;
+  cpx<R> w[RS::J2][R2];
+  if constexpr (DIR == 2) {
+    __syncthreads();  // rt2 staged by the caller
+  } else {
   reg::dft<R1, -1>(v);
 #pragma unroll
   for (int k1 = 1; k1 < R1; ++k1) v[k1] = cmul(v[k1], tw1[k1]);
 #pragma unroll
   for (int k1 = 0; k1 < R1; ++k1) S[k1 * RS::S1 + t] = v[k1];
   __syncthreads();
-  cpx<R> w[RS::J2][R2];
 #pragma unroll
   for (int q = 0; q < RS::J2; ++q) {
     const int g = t + T * q, mp = g % R3, k1 = g / R3;
@@ -79,18 +86,25 @@ __device__ __forceinline__ void row_conv_core(cpx<R> (&v)[R1], cpx<R> *S, const 
     for (int k2 = 0; k2 < R2; ++k2) S[k1 * RS::S2K + k2 * RS::S2 + mp] = w[q][k2];
   }
   __syncthreads();
+  }
   cpx<R> z[RS::J3][R3];
 #pragma unroll
   for (int q = 0; q < RS::J3; ++q) {
-    const int g = t + T * q, k2 = g % R2, k1 = g / R2;
+    const int g = t + T * q, k2 = g % R2;
+    if constexpr (DIR != 2) {
+      const int k1 = g / R2;
 #pragma unroll
-    for (int m = 0; m < R3; ++m) z[q][m] = S[k1 * RS::S2K + k2 * RS::S2 + m];
-    reg::dft<R3, -1>(z[q]);
+      for (int m = 0; m < R3; ++m) z[q][m] = S[k1 * RS::S2K + k2 * RS::S2 + m];
+      reg::dft<R3, -1>(z[q]);
+    }
     spec(z[q], q);
-    reg::dft<R3, +1>(z[q]);
+    if constexpr (DIR != 1) {
+      reg::dft<R3, +1>(z[q]);
 #pragma unroll
-    for (int m = 1; m < R3; ++m) z[q][m] = cmulc(z[q][m], rt2[k2 * (R3 + 1) + m]);
+      for (int m = 1; m < R3; ++m) z[q][m] = cmulc(z[q][m], rt2[k2 * (R3 + 1) + m]);
+    }
   }
+  if constexpr (DIR == 1) return;
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < RS::J3; ++q) {
@@ -1033,6 +1047,258 @@ hipError_t conv_apply_v2(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, 
       }
     }
     if (!dispatch_cols<R>(false, gcol, st, x, ldx, y, ldy, (int)N, (int)b, (int)p0, g, tb, Z))
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---- length-N DFT bins for the fast factorization (Section 2.3) ----
+//
+// With L = 2N, bin K = 2k of the length-L transform of the zero-padded pair
+// z = x1 + i x2 is bin k of its length-N transform.  The bins kept are
+// |k| <= M = (kf - 1)/2, stored per pair at slot M + k (k < 0 wraps to
+// K = L + 2k).  Within a row the stage-3 value m of job q sits at row
+// frequency kr = d1 + R1 d2 + R1 R2 m (q -> g = t + T q, d1 = g / R2,
+// d2 = g % R2), full frequency K = k1c + L1 kr.
+
+// slot of full frequency K (even), or -1 if the bin is not kept
+__device__ __forceinline__ int bin_slot(int64_t K, int64_t N, int M) {
+  const int64_t k = K >> 1;
+  if (k <= M) return (int)(M + k);
+  if (k >= N - M) return (int)(M - (N - k));
+  return -1;
+}
+
+template <int R1, int R2, int R3>
+__device__ __forceinline__ int64_t row_freq(int q, int m) {
+  constexpr int T = R2 * R3;
+  const int g = threadIdx.x + T * q;
+  return (int64_t)(g / R2) + (int64_t)R1 * (g % R2) + (int64_t)R1 * R2 * m;
+}
+
+// Forward row transforms of the even rows k1c = 2 blockIdx.x of pair pl,
+// kept bins written to Zb[pl][slot].
+template <int R1, int R2, int R3>
+__global__ __launch_bounds__(R2 *R3) void k_row_bins(const cpx<float> *__restrict__ Z, int logL, int log1, int log2,
+                                                    const cpx<float> *__restrict__ rt1,
+                                                    const cpx<float> *__restrict__ rt2, cpx<float> *__restrict__ Zb,
+                                                    int kf) {
+  using RS = RowShape<R1, R2, R3>;
+  __shared__ cpx<float> S[RS::LDS];
+  __shared__ cpx<float> rt2s[R2 * (R3 + 1)];
+  const int k1c = 2 * blockIdx.x, pl = blockIdx.y;
+  const cpx<float> *row = Z + ((int64_t)pl << logL) + ((int64_t)k1c << log2);
+  const int t = threadIdx.x;
+  cpx<float> v[R1];
+#pragma unroll
+  for (int n1 = 0; n1 < R1; ++n1) v[n1] = row[t + RS::T * n1];
+  cpx<float> tw1[R1];
+  load_tw1<float, R1, R2, R3>(tw1, rt1);
+  stage_rt2<float, R1, R2, R3>(rt2s, rt2);
+  const int64_t N = (int64_t)1 << (logL - 1);
+  const int M = (kf - 1) / 2;
+  cpx<float> *out = Zb + (int64_t)pl * kf;
+  row_conv_core<float, R1, R2, R3, 1>(v, S, tw1, rt2s, [&](cpx<float> *z, int q) {
+#pragma unroll
+    for (int m = 0; m < R3; ++m) {
+      const int sl = bin_slot(k1c + (row_freq<R1, R2, R3>(q, m) << log1), N, M);
+      if (sl >= 0) out[sl] = z[m];
+    }
+  });
+}
+
+// Inverse row transforms of every row k1c of pair pl from the kept bins
+// (zero elsewhere; odd rows hold no even frequency and are zeroed).
+template <int R1, int R2, int R3>
+__global__ __launch_bounds__(R2 *R3) void k_row_from_bins(const cpx<float> *__restrict__ Zb, int kf, int logL,
+                                                         int log1, int log2, const cpx<float> *__restrict__ rt1,
+                                                         const cpx<float> *__restrict__ rt2,
+                                                         cpx<float> *__restrict__ Z) {
+  using RS = RowShape<R1, R2, R3>;
+  __shared__ cpx<float> S[RS::LDS];
+  __shared__ cpx<float> rt2s[R2 * (R3 + 1)];
+  const int k1c = blockIdx.x, pl = blockIdx.y;
+  cpx<float> *row = Z + ((int64_t)pl << logL) + ((int64_t)k1c << log2);
+  const int t = threadIdx.x;
+  cpx<float> v[R1];
+  if (k1c & 1) {
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) row[t + RS::T * n1] = cpx<float>{0.f, 0.f};
+    return;
+  }
+  cpx<float> tw1[R1];
+  load_tw1<float, R1, R2, R3>(tw1, rt1);
+  stage_rt2<float, R1, R2, R3>(rt2s, rt2);
+  const int64_t N = (int64_t)1 << (logL - 1);
+  const int M = (kf - 1) / 2;
+  const cpx<float> *in = Zb + (int64_t)pl * kf;
+  row_conv_core<float, R1, R2, R3, 2>(v, S, tw1, rt2s, [&](cpx<float> *z, int q) {
+#pragma unroll
+    for (int m = 0; m < R3; ++m) {
+      const int sl = bin_slot(k1c + (row_freq<R1, R2, R3>(q, m) << log1), N, M);
+      z[m] = sl >= 0 ? in[sl] : cpx<float>{0.f, 0.f};
+    }
+  });
+#pragma unroll
+  for (int n1 = 0; n1 < R1; ++n1) row[t + RS::T * n1] = v[n1];
+}
+
+// Single pass (L = R1 R2 R3): forward transform of pair blockIdx.x of x,
+// kept bins to Zb.
+template <int R1, int R2, int R3>
+__global__ __launch_bounds__(R2 *R3) void k_single_bins(const float *__restrict__ x, int64_t ldx, int N, int b,
+                                                       const cpx<float> *__restrict__ rt1,
+                                                       const cpx<float> *__restrict__ rt2, cpx<float> *__restrict__ Zb,
+                                                       int kf) {
+  using RS = RowShape<R1, R2, R3>;
+  constexpr int T = RS::T;
+  __shared__ cpx<float> S[RS::LDS];
+  __shared__ cpx<float> rt2s[R2 * (R3 + 1)];
+  const int t = threadIdx.x, p = blockIdx.x;
+  const int s0 = 2 * p, s1 = 2 * p + 1;
+  const bool has1 = s1 < b;
+  const float *x0 = x + (int64_t)s0 * ldx;
+  const float *x1 = x + (int64_t)(has1 ? s1 : s0) * ldx;
+  cpx<float> v[R1];
+#pragma unroll
+  for (int n1 = 0; n1 < R1; ++n1) {
+    const int n = t + T * n1;
+    float a = 0.f, c = 0.f;
+    if (n < N) {
+      a = x0[n];
+      if (has1) c = x1[n];
+    }
+    v[n1] = cpx<float>{a, c};
+  }
+  cpx<float> tw1[R1];
+  load_tw1<float, R1, R2, R3>(tw1, rt1);
+  stage_rt2<float, R1, R2, R3>(rt2s, rt2);
+  const int M = (kf - 1) / 2;
+  cpx<float> *out = Zb + (int64_t)p * kf;
+  row_conv_core<float, R1, R2, R3, 1>(v, S, tw1, rt2s, [&](cpx<float> *z, int q) {
+#pragma unroll
+    for (int m = 0; m < R3; ++m) {
+      const int64_t K = row_freq<R1, R2, R3>(q, m);
+      const int sl = (K & 1) ? -1 : bin_slot(K, N, M);
+      if (sl >= 0) out[sl] = z[m];
+    }
+  });
+}
+
+// Single pass: inverse transform of pair blockIdx.x from its kept bins,
+// samples n < N to y.
+template <int R1, int R2, int R3>
+__global__ __launch_bounds__(R2 *R3) void k_single_from_bins(const cpx<float> *__restrict__ Zb, int kf,
+                                                            float *__restrict__ y, int64_t ldy, int N, int b,
+                                                            const cpx<float> *__restrict__ rt1,
+                                                            const cpx<float> *__restrict__ rt2) {
+  using RS = RowShape<R1, R2, R3>;
+  constexpr int T = RS::T;
+  __shared__ cpx<float> S[RS::LDS];
+  __shared__ cpx<float> rt2s[R2 * (R3 + 1)];
+  const int t = threadIdx.x, p = blockIdx.x;
+  const int s0 = 2 * p, s1 = 2 * p + 1;
+  const bool has1 = s1 < b;
+  cpx<float> tw1[R1];
+  load_tw1<float, R1, R2, R3>(tw1, rt1);
+  stage_rt2<float, R1, R2, R3>(rt2s, rt2);
+  const int M = (kf - 1) / 2;
+  const cpx<float> *in = Zb + (int64_t)p * kf;
+  cpx<float> v[R1];
+  row_conv_core<float, R1, R2, R3, 2>(v, S, tw1, rt2s, [&](cpx<float> *z, int q) {
+#pragma unroll
+    for (int m = 0; m < R3; ++m) {
+      const int64_t K = row_freq<R1, R2, R3>(q, m);
+      const int sl = (K & 1) ? -1 : bin_slot(K, N, M);
+      z[m] = sl >= 0 ? in[sl] : cpx<float>{0.f, 0.f};
+    }
+  });
+  float *y0 = y + (int64_t)s0 * ldy;
+  float *y1 = y + (int64_t)s1 * ldy;
+#pragma unroll
+  for (int n1 = 0; n1 < R1; ++n1) {
+    const int n = t + T * n1;
+    if (n < N) {
+      y0[n] = v[n1].x;
+      if (has1) y1[n] = v[n1].y;
+    }
+  }
+}
+
+bool dft_bins_ok(const FftGeom &g, int64_t N) {
+  if (!g.v2 || ((int64_t)1 << g.logL) != 2 * N) return false;
+  bool ok = false;
+#define SLP_BOK(A, B, C) ok = ok || (g.R1 == A && g.R2 == B && g.R3 == C);
+  SLP_ROW_SHAPES(SLP_BOK)
+#undef SLP_BOK
+  return ok && (g.single() || g.log1 <= 9);
+}
+
+hipError_t dft_bins_fwd(const float *x, int64_t ldx, int64_t N, int64_t b, const FftGeom &g,
+                        const FftTables<float> &tb, cpx<float> *Z, int64_t slice_pairs, cpx<float> *Zb, int kf,
+                        hipStream_t st) {
+  const int64_t pairs = (b + 1) / 2;
+  if (pairs == 0) return hipSuccess;
+  if (!dft_bins_ok(g, N)) return hipErrorInvalidValue;
+  if (g.single()) {
+    for (int64_t p0 = 0; p0 < pairs; p0 += 65535) {
+      const int64_t np = std::min<int64_t>(65535, pairs - p0);
+      const int bs = (int)std::min<int64_t>(b - 2 * p0, 2 * np);
+#define SLP_SB(A, B, C)                                                                                        \
+  if (g.R1 == A && g.R2 == B && g.R3 == C)                                                                      \
+    SLP_LAUNCH("dft_bins_single", (k_single_bins<A, B, C>), dim3((unsigned)np), dim3(B * C), 0, st,           \
+               x + 2 * p0 * ldx, ldx, (int)N, bs, tb.row1, tb.row2, Zb + p0 * kf, kf);
+      SLP_ROW_SHAPES(SLP_SB)
+#undef SLP_SB
+    }
+    return hipGetLastError();
+  }
+  for (int64_t p0 = 0; p0 < pairs; p0 += slice_pairs) {
+    const int64_t np = std::min<int64_t>(slice_pairs, pairs - p0);
+    const dim3 gcol((1u << g.log2) / 256, (unsigned)np);
+    if (!dispatch_cols<float>(true, gcol, st, x, ldx, nullptr, 0, (int)N, (int)b, (int)p0, g, tb, Z))
+      return hipErrorInvalidValue;
+    const dim3 grow(1u << (g.log1 - 1), (unsigned)np);
+#define SLP_RB(A, B, C)                                                                                         \
+  if (g.R1 == A && g.R2 == B && g.R3 == C)                                                                       \
+    SLP_LAUNCH("dft_bins_row", (k_row_bins<A, B, C>), grow, dim3(B * C), 0, st, Z, g.logL, g.log1, g.log2,     \
+               tb.row1, tb.row2, Zb + p0 * kf, kf);
+    SLP_ROW_SHAPES(SLP_RB)
+#undef SLP_RB
+  }
+  return hipGetLastError();
+}
+
+hipError_t dft_bins_inv(const cpx<float> *Zb, int kf, float *y, int64_t ldy, int64_t N, int64_t b,
+                        const FftGeom &g, const FftTables<float> &tb, cpx<float> *Z, int64_t slice_pairs,
+                        hipStream_t st) {
+  const int64_t pairs = (b + 1) / 2;
+  if (pairs == 0) return hipSuccess;
+  if (!dft_bins_ok(g, N)) return hipErrorInvalidValue;
+  if (g.single()) {
+    for (int64_t p0 = 0; p0 < pairs; p0 += 65535) {
+      const int64_t np = std::min<int64_t>(65535, pairs - p0);
+      const int bs = (int)std::min<int64_t>(b - 2 * p0, 2 * np);
+#define SLP_SI(A, B, C)                                                                                        \
+  if (g.R1 == A && g.R2 == B && g.R3 == C)                                                                      \
+    SLP_LAUNCH("dft_from_bins_single", (k_single_from_bins<A, B, C>), dim3((unsigned)np), dim3(B * C), 0, st, \
+               Zb + p0 * kf, kf, y + 2 * p0 * ldy, ldy, (int)N, bs, tb.row1, tb.row2);
+      SLP_ROW_SHAPES(SLP_SI)
+#undef SLP_SI
+    }
+    return hipGetLastError();
+  }
+  for (int64_t p0 = 0; p0 < pairs; p0 += slice_pairs) {
+    const int64_t np = std::min<int64_t>(slice_pairs, pairs - p0);
+    const dim3 grow(1u << g.log1, (unsigned)np);
+#define SLP_RI(A, B, C)                                                                                         \
+  if (g.R1 == A && g.R2 == B && g.R3 == C)                                                                       \
+    SLP_LAUNCH("dft_from_bins_row", (k_row_from_bins<A, B, C>), grow, dim3(B * C), 0, st, Zb + p0 * kf, kf,    \
+               g.logL, g.log1, g.log2, tb.row1, tb.row2, Z);
+    SLP_ROW_SHAPES(SLP_RI)
+#undef SLP_RI
+    const dim3 gcol((1u << g.log2) / 256, (unsigned)np);
+    if (!dispatch_cols<float>(false, gcol, st, nullptr, 0, y, ldy, (int)N, (int)b, (int)p0, g, tb, Z))
       return hipErrorInvalidValue;
   }
   return hipGetLastError();

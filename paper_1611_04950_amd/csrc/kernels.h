@@ -215,6 +215,31 @@ int coeffs_gemm(int device, int mode, const void *S, const void *Slo, int64_t ld
                 int64_t ldx, float *c, int64_t ldc, int64_t N, int64_t K, int64_t b, void *ws, size_t ws_bytes,
                 GemmCache &cache, hipStream_t st);
 
+// ---- Fast factorization T1 T2^T (fft2.hip, factor.hip) ----
+// Length-N DFT bins |k| <= M = (kf - 1)/2 of signal pairs through the FP32
+// product's geometry g (L = 2N): forward from x into Zb (kf bins per pair,
+// slot M + k), and inverse from Zb into y (rows n < N).  dft_bins_ok: whether
+// g supports them (register-stage row shape, L = 2N).
+bool dft_bins_ok(const FftGeom &g, int64_t N);
+hipError_t dft_bins_fwd(const float *x, int64_t ldx, int64_t N, int64_t b, const FftGeom &g,
+                        const FftTables<float> &tb, cpx<float> *Z, int64_t slice_pairs, cpx<float> *Zb, int kf,
+                        hipStream_t st);
+hipError_t dft_bins_inv(const cpx<float> *Zb, int kf, float *y, int64_t ldy, int64_t N, int64_t b,
+                        const FftGeom &g, const FftTables<float> &tb, cpx<float> *Z, int64_t slice_pairs,
+                        hipStream_t st);
+// first column of B - F F^* embedded in a length-L circulant (FP64)
+hipError_t diff_embed(double *c, int64_t L, int64_t N, double W, int kf, hipStream_t st);
+// N x p block of +-1 (FP64, leading dimension ld) from a counter-based generator
+hipError_t rademacher(double *O, int64_t ld, int64_t N, int64_t p, uint64_t seed, hipStream_t st);
+// sign convention of each column: first entry of magnitude >= 1e-3 max positive
+hipError_t sign_fix_cols(double *V, int64_t ld, int64_t N, int64_t cols, hipStream_t st);
+// pair bins <-> the real coefficients F_r^T x (rows 0 .. kf-1 of c, leading dimension ldc)
+hipError_t bins_unpack(const cpx<float> *Zb, int kf, int64_t N, int64_t b, float *c, int64_t ldc, hipStream_t st);
+hipError_t bins_pack(const float *c, int64_t ldc, int kf, int64_t N, int64_t b, cpx<float> *Zb, hipStream_t st);
+// dC[j b + s] = w[j] c[row0 + j + s ldc]
+hipError_t scale_rows(const float *c, int64_t ldc, int64_t row0, int r, int64_t b, const float *w, float *dC,
+                      hipStream_t st);
+
 // ---- Least-squares refinement helpers (lsq.hip) ----
 // rho = By - u - alpha x (all FP64, N x b with leading dimension N except x: ldx)
 hipError_t lsq_residual(const double *By, const double *u, const double *x, int64_t ldx, double alpha, double *rho,

@@ -39,6 +39,8 @@ EXPORTED = [
     "slepian_plan_save", "slepian_plan_load", "slepian_plan_destroy", "slepian_workspace_size",
     "slepian_project", "slepian_project_ex", "slepian_project_multiband", "slepian_bands_create",
     "slepian_bands_destroy", "slepian_bands_workspace_size", "slepian_project_bands", "slepian_coeffs", "slepian_lsq",
+    "slepian_factor_create", "slepian_factor_destroy", "slepian_factor_info", "slepian_factor_mu",
+    "slepian_factor_workspace_size", "slepian_factor_compress", "slepian_factor_recover",
     "slepian_apply_b64",
     "slepian_group_create", "slepian_group_project", "slepian_group_destroy", "slepian_status_string",
     "slepian_trace_enable", "slepian_trace_read",
@@ -47,6 +49,11 @@ EXPORTED = [
 
 class PlanOpts(C.Structure):
     _fields_ = [("alpha", C.c_double), ("K", C.c_int64), ("precision", C.c_int), ("device", C.c_int)]
+
+
+class FactorInfo(C.Structure):
+    _fields_ = [("kf", C.c_int64), ("r1", C.c_int64), ("r", C.c_int64), ("kprime", C.c_int64),
+                ("subspace", C.c_int64), ("mu_dropped", C.c_double)]
 
 
 class PlanInfo(C.Structure):
@@ -93,6 +100,13 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "slepian_bands_workspace_size": [vp, i64, C.POINTER(sz)],
         "slepian_project_bands": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_coeffs": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
+        "slepian_factor_create": [vp, C.POINTER(vp)],
+        "slepian_factor_destroy": [vp],
+        "slepian_factor_info": [vp, C.POINTER(FactorInfo)],
+        "slepian_factor_mu": [vp, C.POINTER(dbl), i64],
+        "slepian_factor_workspace_size": [vp, i64, C.POINTER(sz)],
+        "slepian_factor_compress": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
+        "slepian_factor_recover": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_lsq": [vp, i32, dbl, vp, i64, vp, i64, i64, dbl, i32, vp, sz, vp, C.POINTER(LsqReport)],
         "slepian_apply_b64": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_group_create": [C.POINTER(vp), i32, C.POINTER(i64), C.POINTER(vp)],
@@ -283,6 +297,68 @@ def slepian_bands_workspace_size(bands: Bands, batch: int) -> int:
     n = C.c_size_t()
     _check(_lib.slepian_bands_workspace_size(bands.handle, batch, C.byref(n)), "slepian_bands_workspace_size")
     return n.value
+
+
+class Factor:
+    """Owns a slepian_factor_t (fast factorization T1 T2^T); keeps its plan alive."""
+
+    def __init__(self, handle: int, plan: Plan):
+        self.handle = C.c_void_p(handle)
+        self.plan = plan
+        inf = FactorInfo()
+        _check(_lib.slepian_factor_info(self.handle, C.byref(inf)), "slepian_factor_info")
+        self.info = {f: getattr(inf, f) for f, _ in FactorInfo._fields_}
+        n = max(self.info["r1"], 1)
+        mu = (C.c_double * n)()
+        _check(_lib.slepian_factor_mu(self.handle, mu, n), "slepian_factor_mu")
+        self.mu = [mu[i] for i in range(self.info["r1"])]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.slepian_factor_destroy(h)
+            self.handle = C.c_void_p(0)
+
+
+def slepian_factor_create(plan: Plan) -> Factor:
+    """Fast factorization S_K S_K^T ~= T1 T2^T of the plan (see include/slepian.h)."""
+    h = C.c_void_p()
+    _check(_lib.slepian_factor_create(plan.handle, C.byref(h)), "slepian_factor_create")
+    return Factor(h.value, plan)
+
+
+def slepian_factor_workspace_size(f: Factor, batch: int) -> int:
+    n = C.c_size_t()
+    _check(_lib.slepian_factor_workspace_size(f.handle, batch, C.byref(n)), "slepian_factor_workspace_size")
+    return n.value
+
+
+def slepian_factor_compress(f: Factor, x: torch.Tensor, c: torch.Tensor | None = None,
+                            work: torch.Tensor | None = None) -> torch.Tensor:
+    """c = T2^T x: (batch, N) -> (batch, kprime) FP32."""
+    x, ldx = _signals(x, f.plan.N, torch.float32, "x")
+    kp = f.info["kprime"]
+    if c is None:
+        c = torch.empty((x.shape[0], kp), dtype=torch.float32, device=x.device)
+    c, ldc = _signals(c, kp, torch.float32, "c")
+    wb = 0 if work is None else work.numel() * work.element_size()
+    _check(_lib.slepian_factor_compress(f.handle, _ptr(x), ldx, _ptr(c), ldc, x.shape[0], _ptr(work), wb,
+                                        _stream(x)), "slepian_factor_compress")
+    return c
+
+
+def slepian_factor_recover(f: Factor, c: torch.Tensor, y: torch.Tensor | None = None,
+                           work: torch.Tensor | None = None) -> torch.Tensor:
+    """y = T1 c: (batch, kprime) -> (batch, N) FP32."""
+    c, ldc = _signals(c, f.info["kprime"], torch.float32, "c")
+    N = f.plan.N
+    if y is None:
+        y = torch.empty((c.shape[0], N), dtype=torch.float32, device=c.device)
+    y, ldy = _signals(y, N, torch.float32, "y")
+    wb = 0 if work is None else work.numel() * work.element_size()
+    _check(_lib.slepian_factor_recover(f.handle, _ptr(c), ldc, _ptr(y), ldy, c.shape[0], _ptr(work), wb,
+                                       _stream(c)), "slepian_factor_recover")
+    return y
 
 
 def slepian_project_bands(bands: Bands, x: torch.Tensor, y: torch.Tensor | None = None,

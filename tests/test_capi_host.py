@@ -93,6 +93,17 @@ def test_null_handles():
     assert lib.slepian_bands_destroy(None) == S.SLEPIAN_OK
     assert lib.slepian_bands_workspace_size(None, 4, C.byref(n)) == S.SLEPIAN_EINVAL
     assert lib.slepian_project_bands(None, None, 0, None, 0, 1, None, 0, None) == S.SLEPIAN_EINVAL
+    # fast factorization: no plan, no factorization
+    h = C.c_void_p()
+    assert lib.slepian_factor_create(None, C.byref(h)) == S.SLEPIAN_EINVAL
+    assert h.value is None
+    assert lib.slepian_factor_create(None, None) == S.SLEPIAN_EINVAL
+    assert lib.slepian_factor_destroy(None) == S.SLEPIAN_OK
+    assert lib.slepian_factor_info(None, None) == S.SLEPIAN_EINVAL
+    assert lib.slepian_factor_mu(None, None, 0) == S.SLEPIAN_EINVAL
+    assert lib.slepian_factor_workspace_size(None, 4, C.byref(n)) == S.SLEPIAN_EINVAL
+    assert lib.slepian_factor_compress(None, None, 0, None, 0, 1, None, 0, None) == S.SLEPIAN_EINVAL
+    assert lib.slepian_factor_recover(None, None, 0, None, 0, 1, None, 0, None) == S.SLEPIAN_EINVAL
 
 
 def test_plan_load_rejects_garbage(tmp_path):
