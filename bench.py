@@ -382,6 +382,56 @@ def bench_multiband(args, dev):
             "kernels_traced_ms": {k: round(v["total_ms"], 4) for k, v in st.items()}}
 
 
+def bench_factorization(args, dev):
+    """Fast factorization S_K S_K^T ~= T1 T2^T (Section 2.3, Theorem 1) at the
+    paper-scale size N = 65536, W = 1/8, eps = 1e-6, 256 signals: compression
+    T2^T x (length-N DFT bins through the FFT passes plus [V U]^T x on the
+    matrix cores) and recovery T1 c, in the bench's correction precision.
+    Also reports the distance of the round trip from the plan's fast
+    projection (both within eps of S_K S_K^T, so at most 3 eps apart)."""
+    import torch
+
+    from paper_1611_04950_amd import slepian as S
+    from paper_1611_04950_amd import synth
+    N, W, eps, b = 65536, 1.0 / 8, 1e-6, 256
+    log("bench: factorization workload")
+    plan = S.slepian_plan(N, W, eps, precision=S.SLEPIAN_MIXED if args.precision == "mixed" else S.SLEPIAN_FP32)
+    t0 = time.perf_counter()
+    F = S.slepian_factor_create(plan)
+    setup = time.perf_counter() - t0
+    x = synth.gaussian(N, b, 6200, device=dev)
+    kp = F.info["kprime"]
+    c = torch.empty((b, kp), dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    work = torch.empty(S.slepian_factor_workspace_size(F, b), dtype=torch.uint8, device=dev)
+    ms_c = _time_calls(lambda: S.slepian_factor_compress(F, x, c, work=work), 20, 3, dev)
+    ms_r = _time_calls(lambda: S.slepian_factor_recover(F, c, y, work=work), 20, 3, dev)
+    S.slepian_trace_enable(True)
+    S.slepian_trace_read(reset=True)
+    S.slepian_factor_compress(F, x, c, work=work)
+    torch.cuda.synchronize()
+    st_c = S.slepian_trace_read(reset=True)
+    S.slepian_factor_recover(F, c, y, work=work)
+    torch.cuda.synchronize()
+    st_r = S.slepian_trace_read(reset=True)
+    S.slepian_trace_enable(False)
+    p = S.slepian_project(plan, x)
+    torch.cuda.synchronize()
+    dist = ((torch.linalg.vector_norm((y - p).double(), dim=1) / torch.linalg.vector_norm(x.double(), dim=1))
+            .max().item())
+    log(f"bench: factorization N={N}, K'={kp} (kf {F.info['kf']}, r1 {F.info['r1']}, r {F.info['r']}): "
+        f"compress {ms_c:.3f} ms, recover {ms_r:.3f} ms, setup {setup:.2f} s, |T1T2^T x - P~x|/|x| <= {dist:.1e}")
+    return {"workload": f"fast factorization N={N}, W=1/8, eps=1e-6, {b} signals",
+            "precision": args.precision, "K": plan.info["K"], "kf": F.info["kf"], "r1": F.info["r1"],
+            "r": F.info["r"], "kprime": kp, "setup_subspace": F.info["subspace"], "setup_s": round(setup, 3),
+            "compress_ms": round(ms_c, 4), "recover_ms": round(ms_r, 4),
+            "compress_GSamples_per_s": round(N * b / (ms_c * 1e-3) / 1e9, 3),
+            "recover_GSamples_per_s": round(N * b / (ms_r * 1e-3) / 1e9, 3),
+            "max_dist_to_fast_projection_rel_to_x": dist,
+            "compress_kernels_traced_ms": {k: round(v["total_ms"], 4) for k, v in st_c.items()},
+            "recover_kernels_traced_ms": {k: round(v["total_ms"], 4) for k, v in st_r.items()}}
+
+
 def bench_coeffs(args, dev):
     """Slepian coefficients c = S_K^T x (Section 2.3, the compression to K
     numbers) at the paper-scale size N = 65536, W = 1/8 (K = 16384), 256
@@ -633,6 +683,9 @@ def main():
     egap = None if args.no_extra else bench_eigen_gap(args, dev)
     mband = None if args.no_extra else bench_multiband(args, dev)
     coeffs = None if args.no_extra else bench_coeffs(args, dev)
+    factor = None if args.no_extra else bench_factorization(args, dev)
+    if factor and coeffs:
+        factor["speedup_compress_vs_dense_coeffs"] = round(coeffs[args.precision]["ms_per_call"] / factor["compress_ms"], 1)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GSamples/s", "n_gpus": 1,
@@ -665,6 +718,7 @@ def main():
         "eigenvalue_gap_study": egap,
         "multiband_workload": mband,
         "coefficients_workload": coeffs,
+        "factorization_workload": factor,
     }
     print(json.dumps(out), flush=True)
 
