@@ -1285,10 +1285,12 @@ struct slepian_factor_s {
   int64_t ldu = 0;
   float *w = nullptr;         // r1 + r weights [mu | d]
   int mode = 0;               // matrix mode of the coefficient products
+  void *ctile = nullptr;      // [V | U] laid out for the fused inverse column pass (or null)
   std::vector<double> mu;
   ~slepian_factor_s() {
     dfree(U);
     dfree(w);
+    dfree(ctile);
   }
 };
 
@@ -1451,6 +1453,11 @@ void factor_setup(slepian_factor_s *F, hipStream_t st) {
     for (int64_t j = 0; j < F->r; ++j) w32[r1 + j] = (float)P->proj.d[j];
     F->w = dalloc<float>(w32.size());
     HIPCHK(hipMemcpyAsync(F->w, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    const FftGeom &g = P->g32;
+    if (rt > 0 && !g.single() && colinv_corr_tiled(g.log1)) {
+      F->ctile = dalloc<char>(corr_tile_bytes(g.log1, g.log2, (int)rt, F->mode));
+      HIPCHK(build_corr_tile(F->U, F->ldu, (int)N, (int)rt, g.log1, g.log2, F->mode, F->ctile, st));
+    }
     HIPCHK(hipStreamSynchronize(st));
     return;
   }
@@ -1578,15 +1585,24 @@ int slepian_factor_recover(slepian_factor_t F, const float *c, int64_t ldc, floa
     const int64_t N = P->N;
     void *ws = get_ws(P, work, work_bytes, factor_workspace(F, batch));
     const FactorWs w = carve_factor(F, batch, ws);
-    // F_r c_F: bins of the pairs, inverse length-2N transform, rows n < N
-    HIPCHK(bins_pack(c, ldc, F->kf, N, batch, w.Zb, st));
-    HIPCHK(dft_bins_inv(w.Zb, F->kf, y, ldy, N, batch, P->g32, P->tb32, w.Z, w.slice, st));
-    // y += [V U_T] ([mu d] . c_rest)
+    // F_r c_F: bins of the pairs, inverse length-2N transform, rows n < N;
+    // y += [V U_T] ([mu d] . c_rest), inside the inverse column pass where it
+    // takes the update, else as a separate pass
     const int rt = (int)(F->r1 + F->r);
-    if (rt > 0) {
-      HIPCHK(scale_rows(c, ldc, F->kf, rt, batch, F->w, w.dC, st));
-      HIPCHK(corr_apply_mfma(y, ldy, N, batch, F->U, F->ldu, rt, w.dC, st));
+    if (rt > 0) HIPCHK(scale_rows(c, ldc, F->kf, rt, batch, F->w, w.dC, st));
+    HIPCHK(bins_pack(c, ldc, F->kf, N, batch, w.Zb, st));
+    Corr<float> corr;
+    const bool fused = rt > 0 && F->ctile && colinv_corr_ok(P->g32.log1, ldy, batch, rt);
+    if (fused) {
+      corr.U = F->U;
+      corr.ldu = F->ldu;
+      corr.r = rt;
+      corr.dC = w.dC;
+      corr.mode = F->mode;
+      corr.ut = F->ctile;
     }
+    HIPCHK(dft_bins_inv(w.Zb, F->kf, y, ldy, N, batch, P->g32, P->tb32, w.Z, w.slice, corr, st));
+    if (rt > 0 && !fused) HIPCHK(corr_apply_mfma(y, ldy, N, batch, F->U, F->ldu, rt, w.dC, st));
     return SLEPIAN_OK;
   });
 }

@@ -1271,7 +1271,7 @@ hipError_t dft_bins_fwd(const float *x, int64_t ldx, int64_t N, int64_t b, const
 
 hipError_t dft_bins_inv(const cpx<float> *Zb, int kf, float *y, int64_t ldy, int64_t N, int64_t b,
                         const FftGeom &g, const FftTables<float> &tb, cpx<float> *Z, int64_t slice_pairs,
-                        hipStream_t st) {
+                        const Corr<float> &corr, hipStream_t st) {
   const int64_t pairs = (b + 1) / 2;
   if (pairs == 0) return hipSuccess;
   if (!dft_bins_ok(g, N)) return hipErrorInvalidValue;
@@ -1297,6 +1297,11 @@ hipError_t dft_bins_inv(const cpx<float> *Zb, int kf, float *y, int64_t ldy, int
                g.logL, g.log1, g.log2, tb.row1, tb.row2, Z);
     SLP_ROW_SHAPES(SLP_RI)
 #undef SLP_RI
+    if (corr.dC) {
+      if (!launch_colinv_corr(st, Z, (int)N, (int)b, (int)p0, (int)np, g, tb, y, ldy, corr))
+        return hipErrorInvalidValue;
+      continue;
+    }
     const dim3 gcol((1u << g.log2) / 256, (unsigned)np);
     if (!dispatch_cols<float>(false, gcol, st, nullptr, 0, y, ldy, (int)N, (int)b, (int)p0, g, tb, Z))
       return hipErrorInvalidValue;

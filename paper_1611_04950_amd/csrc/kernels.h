@@ -218,15 +218,17 @@ int coeffs_gemm(int device, int mode, const void *S, const void *Slo, int64_t ld
 // ---- Fast factorization T1 T2^T (fft2.hip, factor.hip) ----
 // Length-N DFT bins |k| <= M = (kf - 1)/2 of signal pairs through the FP32
 // product's geometry g (L = 2N): forward from x into Zb (kf bins per pair,
-// slot M + k), and inverse from Zb into y (rows n < N).  dft_bins_ok: whether
-// g supports them (register-stage row shape, L = 2N).
+// slot M + k), and inverse from Zb into y (rows n < N), with y += U dC fused
+// into the inverse column pass when corr.dC is set (three-pass geometries the
+// fused pass handles; corr.ut from build_corr_tile).  dft_bins_ok: whether g
+// supports them (register-stage row shape, L = 2N).
 bool dft_bins_ok(const FftGeom &g, int64_t N);
 hipError_t dft_bins_fwd(const float *x, int64_t ldx, int64_t N, int64_t b, const FftGeom &g,
                         const FftTables<float> &tb, cpx<float> *Z, int64_t slice_pairs, cpx<float> *Zb, int kf,
                         hipStream_t st);
 hipError_t dft_bins_inv(const cpx<float> *Zb, int kf, float *y, int64_t ldy, int64_t N, int64_t b,
                         const FftGeom &g, const FftTables<float> &tb, cpx<float> *Z, int64_t slice_pairs,
-                        hipStream_t st);
+                        const Corr<float> &corr, hipStream_t st);
 // first column of B - F F^* embedded in a length-L circulant (FP64)
 hipError_t diff_embed(double *c, int64_t L, int64_t N, double W, int kf, hipStream_t st);
 // N x p block of +-1 (FP64, leading dimension ld) from a counter-based generator

@@ -29,7 +29,8 @@ pytestmark = pytest.mark.gpu
 if torch.cuda.is_available():
     from paper_1611_04950_amd import slepian as S
 
-# N, W, eps, batch, precision: single pass (L <= 8192) and three passes (L1 = 4, 16)
+# N, W, eps, batch, precision: single pass (L <= 8192) and three passes (L1 = 4, 16 with the
+# update fused into the inverse column pass, L1 = 32 without)
 CASES = [
     (256, 1 / 8, 1e-6, 5, "fp32"),
     (1024, 1 / 16, 1e-6, 8, "mixed"),
@@ -37,6 +38,7 @@ CASES = [
     (16384, 1 / 8, 1e-6, 6, "mixed"),
     (16384, 0.05, 1e-4, 7, "fp32"),
     (65536, 1 / 8, 1e-6, 4, "mixed"),
+    (131072, 1 / 16, 1e-6, 3, "fp32"),  # L1 = 32: update after the inverse column pass
 ]
 _FAC = {}
 
