@@ -306,7 +306,9 @@ __global__ __launch_bounds__(R2 *R3) void k_single2(const R *__restrict__ x, int
 // Pass A: lane = column n2 of pair pl; length-L1 DFT of z[n2 + L2 n1] =
 // x1 + i x2 (zero for n >= N) in registers, times W_L^{n2 k1}, stored at
 // Z[k1][n2].
-template <typename R, int L1>
+// EVEN: only the even frequency rows k1 are stored (the length-N DFT bins of
+// the fast factorization read no others).
+template <typename R, int L1, bool EVEN = false>
 __device__ __forceinline__ void colfwd_body(const R *__restrict__ x, int64_t ldx, int N, int b, int pair0, int logL,
                                             int log2, const cpx<R> *__restrict__ tcol, cpx<R> *__restrict__ Z,
                                             int bx, int pl) {
@@ -331,7 +333,8 @@ __device__ __forceinline__ void colfwd_body(const R *__restrict__ x, int64_t ldx
   cpx<R> *Zp = Z + ((int64_t)pl << logL) + n2;
   Zp[0] = a[0];
 #pragma unroll
-  for (int k1 = 1; k1 < L1; ++k1) Zp[(int64_t)k1 << log2] = cmul(a[k1], tcol[(k1 << log2) + n2]);
+  for (int k1 = 1; k1 < L1; ++k1)
+    if (!EVEN || (k1 & 1) == 0) Zp[(int64_t)k1 << log2] = cmul(a[k1], tcol[(k1 << log2) + n2]);
 }
 
 template <typename R, int L1>
@@ -341,10 +344,18 @@ __global__ __launch_bounds__(256) void k_colfwd2(const R *__restrict__ x, int64_
   colfwd_body<R, L1>(x, ldx, N, b, pair0, logL, log2, tcol, Z, blockIdx.x, blockIdx.y);
 }
 
+template <typename R, int L1>
+__global__ __launch_bounds__(256) void k_colfwd2_even(const R *__restrict__ x, int64_t ldx, int N, int b, int pair0,
+                                                      int logL, int log2, const cpx<R> *__restrict__ tcol,
+                                                      cpx<R> *__restrict__ Z) {
+  colfwd_body<R, L1, true>(x, ldx, N, b, pair0, logL, log2, tcol, Z, blockIdx.x, blockIdx.y);
+}
+
 // Pass C: lane = column n2 of pair pl; Z[k1][n2] times W_L^{-n2 k1}, inverse
 // length-L1 DFT in registers, y1 = Re and y2 = Im for n = n2 + L2 n1 < N
 // (only n1 < L1/2 can hold such n because L >= 2N).
-template <typename R, int L1>
+// EVEN: the odd frequency rows k1 are known to be zero and are not read.
+template <typename R, int L1, bool EVEN = false>
 __device__ __forceinline__ void colinv_body(const cpx<R> *__restrict__ Z, int N, int b, int pair0, int logL,
                                             int log2, const cpx<R> *__restrict__ tcol, R *__restrict__ y,
                                             int64_t ldy, int bx, int pl) {
@@ -356,7 +367,8 @@ __device__ __forceinline__ void colinv_body(const cpx<R> *__restrict__ Z, int N,
   cpx<R> a[L1];
   a[0] = Zp[0];
 #pragma unroll
-  for (int k1 = 1; k1 < L1; ++k1) a[k1] = cmulc(Zp[(int64_t)k1 << log2], tcol[(k1 << log2) + n2]);
+  for (int k1 = 1; k1 < L1; ++k1)
+    a[k1] = (EVEN && (k1 & 1)) ? cpx<R>{0, 0} : cmulc(Zp[(int64_t)k1 << log2], tcol[(k1 << log2) + n2]);
   reg::dft<L1, +1>(a);
   R *y0 = y + (int64_t)s0 * ldy;
   R *y1 = y + (int64_t)(has1 ? s1 : s0) * ldy;
@@ -377,6 +389,13 @@ __global__ __launch_bounds__(256) void k_colinv2(const cpx<R> *__restrict__ Z, i
   colinv_body<R, L1>(Z, N, b, pair0, logL, log2, tcol, y, ldy, blockIdx.x, blockIdx.y);
 }
 
+template <typename R, int L1>
+__global__ __launch_bounds__(256) void k_colinv2_even(const cpx<R> *__restrict__ Z, int N, int b, int pair0,
+                                                      int logL, int log2, const cpx<R> *__restrict__ tcol,
+                                                      R *__restrict__ y, int64_t ldy) {
+  colinv_body<R, L1, true>(Z, N, b, pair0, logL, log2, tcol, y, ldy, blockIdx.x, blockIdx.y);
+}
+
 // Column passes for long columns (L1 = A B = 64 .. 512), two stages through
 // LDS: with n1 = a + A n1b and k1 = k1b + B k1a, stage 1 is a length-B DFT
 // over n1b for each (column, a) times W_L1^{a k1b}, stage 2 a length-A DFT
@@ -385,7 +404,7 @@ __global__ __launch_bounds__(256) void k_colinv2(const cpx<R> *__restrict__ Z, i
 // stage-2 jobs (c, a + A q), q < B / A.  LDS holds [k1b][a][c], so both
 // stages touch consecutive columns in consecutive lanes.  Only n1 < L1/2
 // carries samples (L >= 2N), so stage 1 reads half of its inputs.
-template <typename R, int A, int B, int CB>
+template <typename R, int A, int B, int CB, bool EVEN = false>
 __global__ __launch_bounds__(CB *A) void k_colfwd_lds(const R *__restrict__ x, int64_t ldx, int N, int b, int pair0,
                                                       int logL, int log2, const cpx<R> *__restrict__ tcol,
                                                       cpx<R> *__restrict__ Z) {
@@ -435,12 +454,12 @@ __global__ __launch_bounds__(CB *A) void k_colfwd_lds(const R *__restrict__ x, i
     for (int k1a = 0; k1a < A; ++k1a) {
       const int k1 = k1b + B * k1a;
       const int64_t o = (int64_t)k1 << log2;
-      Zp[o] = k1 ? cmul(v[k1a], tcol[o + n2]) : v[k1a];
+      if (!EVEN || (k1 & 1) == 0) Zp[o] = k1 ? cmul(v[k1a], tcol[o + n2]) : v[k1a];
     }
   }
 }
 
-template <typename R, int A, int B, int CB>
+template <typename R, int A, int B, int CB, bool EVEN = false>
 __global__ __launch_bounds__(CB *A) void k_colinv_lds(const cpx<R> *__restrict__ Z, int N, int b, int pair0, int logL,
                                                       int log2, const cpx<R> *__restrict__ tcol, R *__restrict__ y,
                                                       int64_t ldy) {
@@ -466,7 +485,7 @@ __global__ __launch_bounds__(CB *A) void k_colinv_lds(const cpx<R> *__restrict__
     for (int k1a = 0; k1a < A; ++k1a) {
       const int k1 = k1b + B * k1a;
       const int64_t o = (int64_t)k1 << log2;
-      v[k1a] = k1 ? cmulc(Zp[o], tcol[o + n2]) : Zp[o];
+      v[k1a] = (EVEN && (k1 & 1)) ? cpx<R>{0, 0} : k1 ? cmulc(Zp[o], tcol[o + n2]) : Zp[o];
     }
     reg::dft<A, +1>(v);
 #pragma unroll
@@ -529,7 +548,7 @@ __device__ __forceinline__ void st_at(T *base, uint32_t byte_off, T v) {
 // keeps 64 complex inputs per lane and is compiled for 3).
 constexpr int kCicWaves = 6;
 
-template <int L1, int MODE, int CW, int PPL>
+template <int L1, int MODE, int CW, int PPL, bool EVEN = false>
 __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ Z, int N, int b, int pair0, int np,
                                                  int logL, int log2, const cpx<float> *__restrict__ tcol,
                                                  float *__restrict__ y, int64_t ldy, const void *__restrict__ ut,
@@ -551,7 +570,8 @@ __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ 
     const int q = pw + PPL * blk + h < np ? PPL * blk + h : 0;
     const uint32_t zo = (((uint32_t)q << logL) + (uint32_t)col) * 8u;
 #pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) a[h][k1] = ld_at(Zw, zo + ((uint32_t)k1 << (log2 + 3)));
+    for (int k1 = 0; k1 < L1; ++k1)
+      a[h][k1] = (EVEN && (k1 & 1)) ? cpx<float>{0.f, 0.f} : ld_at(Zw, zo + ((uint32_t)k1 << (log2 + 3)));
   }
   // W_L^{k1 n2} = W_L^{(k1 mod 8) n2} W_L^{8 (k1 div 8) n2}: eight plus L1/8
   // table loads per lane instead of L1, one extra rounding per factor.
@@ -660,7 +680,7 @@ __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ 
   }
 }
 
-template <int L1, int MODE, int CW, int PPL>
+template <int L1, int MODE, int CW, int PPL, bool EVEN = false>
 __global__ __launch_bounds__(64 * CW, L1 >= 32 ? 3 : kCicWaves) void k_colinv_corr(const cpx<float> *__restrict__ Z, int N, int b, int pair0,
                                                          int np, int logL, int log2,
                                                          const cpx<float> *__restrict__ tcol, float *__restrict__ y,
@@ -671,7 +691,8 @@ __global__ __launch_bounds__(64 * CW, L1 >= 32 ? 3 : kCicWaves) void k_colinv_co
   // a 128-byte line of y are handled within one L2.
   const int gx = gridDim.x;
   const int cb = (gx & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (gx >> 3) + (int)(blockIdx.x >> 3);
-  colinv_corr_body<L1, MODE, CW, PPL>(Z, N, b, pair0, np, logL, log2, tcol, y, ldy, ut, r, rp, dC, cb, blockIdx.y);
+  colinv_corr_body<L1, MODE, CW, PPL, EVEN>(Z, N, b, pair0, np, logL, log2, tcol, y, ldy, ut, r, rp, dC, cb,
+                                            blockIdx.y);
 }
 
 // U's rows in the order the fused inverse column pass reads them (see
@@ -852,12 +873,18 @@ static void launch_single(int64_t np, hipStream_t st, const R *x, int64_t ldx, R
   }
 }
 
-template <typename R, int L1>
+template <typename R, int L1, bool EVEN = false>
 static void launch_cols(bool fwd, dim3 grid, hipStream_t st, const R *x, int64_t ldx, R *y, int64_t ldy, int N,
                         int b, int p0, const FftGeom &g, const FftTables<R> &tb, cpx<R> *Z) {
-  if (fwd) {
+  if (fwd && EVEN) {
+    SLP_LAUNCH("col_fwd_even", (k_colfwd2_even<R, L1>), grid, dim3(256), 0, st, x, ldx, N, b, p0, g.logL, g.log2,
+               tb.col, Z);
+  } else if (fwd) {
     SLP_LAUNCH(sizeof(R) == 4 ? "col_fwd" : "col_fwd_f64", (k_colfwd2<R, L1>), grid, dim3(256), 0, st, x, ldx, N, b,
                p0, g.logL, g.log2, tb.col, Z);
+  } else if (EVEN) {
+    SLP_LAUNCH("col_inv_even", (k_colinv2_even<R, L1>), grid, dim3(256), 0, st, Z, N, b, p0, g.logL, g.log2, tb.col,
+               y, ldy);
   } else {
     SLP_LAUNCH(sizeof(R) == 4 ? "col_inv" : "col_inv_f64", (k_colinv2<R, L1>), grid, dim3(256), 0, st, Z, N, b, p0,
                g.logL, g.log2, tb.col, y, ldy);
@@ -866,42 +893,42 @@ static void launch_cols(bool fwd, dim3 grid, hipStream_t st, const R *x, int64_t
 
 // Long columns: (A, B) and columns per workgroup CB with L1 CB elements of
 // LDS within 64 KB.
-template <typename R, int A, int B, int CB>
+template <typename R, int A, int B, int CB, bool EVEN = false>
 static void launch_cols_lds(bool fwd, hipStream_t st, const R *x, int64_t ldx, R *y, int64_t ldy, int N, int b,
                             int p0, int np, const FftGeom &g, const FftTables<R> &tb, cpx<R> *Z) {
   const dim3 grid((1u << g.log2) / CB, (unsigned)np), block(CB * A);
   if (fwd) {
-    SLP_LAUNCH(sizeof(R) == 4 ? "col_fwd" : "col_fwd_f64", (k_colfwd_lds<R, A, B, CB>), grid, block, 0, st, x, ldx,
-               N, b, p0, g.logL, g.log2, tb.col, Z);
+    SLP_LAUNCH(EVEN ? "col_fwd_even" : sizeof(R) == 4 ? "col_fwd" : "col_fwd_f64", (k_colfwd_lds<R, A, B, CB, EVEN>),
+               grid, block, 0, st, x, ldx, N, b, p0, g.logL, g.log2, tb.col, Z);
   } else {
-    SLP_LAUNCH(sizeof(R) == 4 ? "col_inv" : "col_inv_f64", (k_colinv_lds<R, A, B, CB>), grid, block, 0, st, Z, N, b,
-               p0, g.logL, g.log2, tb.col, y, ldy);
+    SLP_LAUNCH(EVEN ? "col_inv_even" : sizeof(R) == 4 ? "col_inv" : "col_inv_f64", (k_colinv_lds<R, A, B, CB, EVEN>),
+               grid, block, 0, st, Z, N, b, p0, g.logL, g.log2, tb.col, y, ldy);
   }
 }
 
-template <typename R>
+template <typename R, bool EVEN = false>
 static bool dispatch_cols(bool fwd, dim3 grid, hipStream_t st, const R *x, int64_t ldx, R *y, int64_t ldy, int N,
                           int b, int p0, const FftGeom &g, const FftTables<R> &tb, cpx<R> *Z) {
   const int np = (int)grid.y;
   if (g.log1 >= 6) {
     constexpr bool f32 = sizeof(R) == 4;
     switch (g.log1) {
-      case 6: launch_cols_lds<R, 8, 8, 32>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z); return true;
-      case 7: launch_cols_lds<R, 8, 16, 32>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z); return true;
-      case 8: launch_cols_lds<R, 16, 16, 16>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z); return true;
+      case 6: launch_cols_lds<R, 8, 8, 32, EVEN>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z); return true;
+      case 7: launch_cols_lds<R, 8, 16, 32, EVEN>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z); return true;
+      case 8: launch_cols_lds<R, 16, 16, 16, EVEN>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z); return true;
       case 9:
-        if (f32) launch_cols_lds<R, 16, 32, 16>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z);
-        else launch_cols_lds<R, 16, 32, 8>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z);
+        if (f32) launch_cols_lds<R, 16, 32, 16, EVEN>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z);
+        else launch_cols_lds<R, 16, 32, 8, EVEN>(fwd, st, x, ldx, y, ldy, N, b, p0, np, g, tb, Z);
         return true;
       default: return false;
     }
   }
   switch (g.log1) {
-    case 1: launch_cols<R, 2>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
-    case 2: launch_cols<R, 4>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
-    case 3: launch_cols<R, 8>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
-    case 4: launch_cols<R, 16>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
-    case 5: launch_cols<R, 32>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
+    case 1: launch_cols<R, 2, EVEN>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
+    case 2: launch_cols<R, 4, EVEN>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
+    case 3: launch_cols<R, 8, EVEN>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
+    case 4: launch_cols<R, 16, EVEN>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
+    case 5: launch_cols<R, 32, EVEN>(fwd, grid, st, x, ldx, y, ldy, N, b, p0, g, tb, Z); return true;
     default: return false;
   }
 }
@@ -949,43 +976,45 @@ bool colinv_corr_ok(int log1, int64_t ldy, int64_t b, int r) {
 
 bool colinv_corr_tiled(int log1) { return colinv_corr_ok(log1, 1, 1, 1); }
 
-template <int L1, int MODE, int CW, int PPL>
+template <int L1, int MODE, int CW, int PPL, bool EVEN = false>
 static void launch_cic(hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np, const FftGeom &g,
                        const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c, int rp) {
   constexpr int PW = 4 * PPL * CW;  // pairs per workgroup
   const dim3 grid((1u << g.log2) / 16, (unsigned)((np + PW - 1) / PW));
-  SLP_LAUNCH(MODE ? "col_inv_corr_bf16x3" : "col_inv_corr", (k_colinv_corr<L1, MODE, CW, PPL>), grid, dim3(64 * CW),
+  SLP_LAUNCH(MODE ? (EVEN ? "col_inv_even_corr_bf16x3" : "col_inv_corr_bf16x3") : (EVEN ? "col_inv_even_corr" : "col_inv_corr"),
+             (k_colinv_corr<L1, MODE, CW, PPL, EVEN>), grid, dim3(64 * CW),
              0, st, Z, N, b, p0, np, g.logL, g.log2, tb.col, y, ldy, c.ut, c.r, rp, c.dC);
 }
 
-template <int L1, int MODE>
+template <int L1, int MODE, bool EVEN = false>
 static void launch_cic_shape(hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np, const FftGeom &g,
                              const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c, int rp) {
   const CicShape sh = cic_shape();
-  if (sh.ppl == 1 && sh.cw == 8) launch_cic<L1, MODE, 8, 1>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
-  else if (sh.ppl == 1) launch_cic<L1, MODE, 4, 1>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
-  else launch_cic<L1, MODE, 4, 2>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
+  if (sh.ppl == 1 && sh.cw == 8) launch_cic<L1, MODE, 8, 1, EVEN>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
+  else if (sh.ppl == 1) launch_cic<L1, MODE, 4, 1, EVEN>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
+  else launch_cic<L1, MODE, 4, 2, EVEN>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
 }
 
-template <int MODE>
+template <int MODE, bool EVEN = false>
 static bool launch_cic_mode(hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np, const FftGeom &g,
                             const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c) {
   const int rp = colinv_corr_rp(c.r, MODE);
   if (!c.ut) return false;
   switch (g.log1) {
-    case 1: launch_cic_shape<2, MODE>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 2: launch_cic_shape<4, MODE>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 3: launch_cic_shape<8, MODE>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 4: launch_cic_shape<16, MODE>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
-    case 5: launch_cic_shape<32, MODE>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 1: launch_cic_shape<2, MODE, EVEN>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 2: launch_cic_shape<4, MODE, EVEN>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 3: launch_cic_shape<8, MODE, EVEN>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 4: launch_cic_shape<16, MODE, EVEN>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
+    case 5: launch_cic_shape<32, MODE, EVEN>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp); return true;
     default: return false;  // larger L1: the caller does the update separately
   }
 }
 
+template <bool EVEN = false>
 static bool launch_colinv_corr(hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np, const FftGeom &g,
                                const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c) {
-  return c.mode == 0 ? launch_cic_mode<0>(st, Z, N, b, p0, np, g, tb, y, ldy, c)
-                     : launch_cic_mode<1>(st, Z, N, b, p0, np, g, tb, y, ldy, c);
+  return c.mode == 0 ? launch_cic_mode<0, EVEN>(st, Z, N, b, p0, np, g, tb, y, ldy, c)
+                     : launch_cic_mode<1, EVEN>(st, Z, N, b, p0, np, g, tb, y, ldy, c);
 }
 
 #define SLP_ROW_SHAPES(X) \
@@ -1107,8 +1136,9 @@ __global__ __launch_bounds__(R2 *R3) void k_row_bins(const cpx<float> *__restric
   });
 }
 
-// Inverse row transforms of every row k1c of pair pl from the kept bins
-// (zero elsewhere; odd rows hold no even frequency and are zeroed).
+// Inverse row transforms of the even rows k1c = 2 blockIdx.x of pair pl from
+// the kept bins (zero elsewhere).  Odd rows hold no even frequency; they are
+// neither written here nor read by the inverse column pass that follows.
 template <int R1, int R2, int R3>
 __global__ __launch_bounds__(R2 *R3) void k_row_from_bins(const cpx<float> *__restrict__ Zb, int kf, int logL,
                                                          int log1, int log2, const cpx<float> *__restrict__ rt1,
@@ -1117,15 +1147,10 @@ __global__ __launch_bounds__(R2 *R3) void k_row_from_bins(const cpx<float> *__re
   using RS = RowShape<R1, R2, R3>;
   __shared__ cpx<float> S[RS::LDS];
   __shared__ cpx<float> rt2s[R2 * (R3 + 1)];
-  const int k1c = blockIdx.x, pl = blockIdx.y;
+  const int k1c = 2 * blockIdx.x, pl = blockIdx.y;
   cpx<float> *row = Z + ((int64_t)pl << logL) + ((int64_t)k1c << log2);
   const int t = threadIdx.x;
   cpx<float> v[R1];
-  if (k1c & 1) {
-#pragma unroll
-    for (int n1 = 0; n1 < R1; ++n1) row[t + RS::T * n1] = cpx<float>{0.f, 0.f};
-    return;
-  }
   cpx<float> tw1[R1];
   load_tw1<float, R1, R2, R3>(tw1, rt1);
   stage_rt2<float, R1, R2, R3>(rt2s, rt2);
@@ -1256,7 +1281,7 @@ hipError_t dft_bins_fwd(const float *x, int64_t ldx, int64_t N, int64_t b, const
   for (int64_t p0 = 0; p0 < pairs; p0 += slice_pairs) {
     const int64_t np = std::min<int64_t>(slice_pairs, pairs - p0);
     const dim3 gcol((1u << g.log2) / 256, (unsigned)np);
-    if (!dispatch_cols<float>(true, gcol, st, x, ldx, nullptr, 0, (int)N, (int)b, (int)p0, g, tb, Z))
+    if (!dispatch_cols<float, true>(true, gcol, st, x, ldx, nullptr, 0, (int)N, (int)b, (int)p0, g, tb, Z))
       return hipErrorInvalidValue;
     const dim3 grow(1u << (g.log1 - 1), (unsigned)np);
 #define SLP_RB(A, B, C)                                                                                         \
@@ -1290,7 +1315,7 @@ hipError_t dft_bins_inv(const cpx<float> *Zb, int kf, float *y, int64_t ldy, int
   }
   for (int64_t p0 = 0; p0 < pairs; p0 += slice_pairs) {
     const int64_t np = std::min<int64_t>(slice_pairs, pairs - p0);
-    const dim3 grow(1u << g.log1, (unsigned)np);
+    const dim3 grow(1u << (g.log1 - 1), (unsigned)np);
 #define SLP_RI(A, B, C)                                                                                         \
   if (g.R1 == A && g.R2 == B && g.R3 == C)                                                                       \
     SLP_LAUNCH("dft_from_bins_row", (k_row_from_bins<A, B, C>), grow, dim3(B * C), 0, st, Zb + p0 * kf, kf,    \
@@ -1298,12 +1323,12 @@ hipError_t dft_bins_inv(const cpx<float> *Zb, int kf, float *y, int64_t ldy, int
     SLP_ROW_SHAPES(SLP_RI)
 #undef SLP_RI
     if (corr.dC) {
-      if (!launch_colinv_corr(st, Z, (int)N, (int)b, (int)p0, (int)np, g, tb, y, ldy, corr))
+      if (!launch_colinv_corr<true>(st, Z, (int)N, (int)b, (int)p0, (int)np, g, tb, y, ldy, corr))
         return hipErrorInvalidValue;
       continue;
     }
     const dim3 gcol((1u << g.log2) / 256, (unsigned)np);
-    if (!dispatch_cols<float>(false, gcol, st, nullptr, 0, y, ldy, (int)N, (int)b, (int)p0, g, tb, Z))
+    if (!dispatch_cols<float, true>(false, gcol, st, nullptr, 0, y, ldy, (int)N, (int)b, (int)p0, g, tb, Z))
       return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -39,6 +39,7 @@ CASES = [
     (16384, 0.05, 1e-4, 7, "fp32"),
     (65536, 1 / 8, 1e-6, 4, "mixed"),
     (131072, 1 / 16, 1e-6, 3, "fp32"),  # L1 = 32: update after the inverse column pass
+    (262144, 0.05, 1e-4, 2, "mixed"),  # L1 = 64: column passes through LDS
 ]
 _FAC = {}
 
