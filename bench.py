@@ -406,19 +406,48 @@ def bench_factorization(args, dev):
     work = torch.empty(S.slepian_factor_workspace_size(F, b), dtype=torch.uint8, device=dev)
     ms_c = _time_calls(lambda: S.slepian_factor_compress(F, x, c, work=work), 20, 3, dev)
     ms_r = _time_calls(lambda: S.slepian_factor_recover(F, c, y, work=work), 20, 3, dev)
+    # per-launch averages over ten traced calls of each direction (HIP events
+    # around each launch), against each kernel's algorithmic bytes: x and y
+    # once (4 B per sample), the even frequency rows of the pair intermediate
+    # once (8 B per complex value, L/2 per pair), the kept bins once (8 B,
+    # kf per pair), [V U] once (4 B per entry; BF16 hi + lo in the fused pass)
     S.slepian_trace_enable(True)
     S.slepian_trace_read(reset=True)
-    S.slepian_factor_compress(F, x, c, work=work)
+    for _ in range(10):
+        S.slepian_factor_compress(F, x, c, work=work)
     torch.cuda.synchronize()
     st_c = S.slepian_trace_read(reset=True)
-    S.slepian_factor_recover(F, c, y, work=work)
+    for _ in range(10):
+        S.slepian_factor_recover(F, c, y, work=work)
     torch.cuda.synchronize()
     st_r = S.slepian_trace_read(reset=True)
     S.slepian_trace_enable(False)
+    L, P, kf, rt = 2 * N, b // 2, F.info["kf"], F.info["r1"] + F.info["r"]
+    rp = (rt + 31) // 32 * 32
+    even_rows = P * (L // 2) * 8.0
+    alg = {"col_fwd_even": 4.0 * N * b + even_rows, "dft_bins_row": even_rows + P * kf * 8.0,
+           "corr_partial_bf16x3": 4.0 * N * b + 4.0 * N * rt, "corr_partial": 4.0 * N * b + 4.0 * N * rt,
+           "dft_from_bins_row": P * kf * 8.0 + even_rows,
+           "col_inv_even_corr_bf16x3": even_rows + 4.0 * N * b + 4.0 * N * rp + 4.0 * rt * b,
+           "col_inv_even_corr": even_rows + 4.0 * N * b + 4.0 * N * rp + 4.0 * rt * b}
+
+    def roof(st):
+        out = {}
+        for k, v in st.items():
+            us = 1000.0 * v["total_ms"] / max(v["launches"], 1)
+            e = {"avg_us": round(us, 2)}
+            if k in alg:
+                gbs = alg[k] / (us * 1e-6) / 1e9
+                e.update({"alg_bytes": alg[k], "alg_GBs": round(gbs, 1), "frac_of_8TBs": round(gbs / 8000.0, 3)})
+            out[k] = e
+        dom = max(out, key=lambda k: out[k]["avg_us"])
+        return out, dom
     p = S.slepian_project(plan, x)
     torch.cuda.synchronize()
     dist = ((torch.linalg.vector_norm((y - p).double(), dim=1) / torch.linalg.vector_norm(x.double(), dim=1))
             .max().item())
+    kc, dc = roof(st_c)
+    kr, dr = roof(st_r)
     log(f"bench: factorization N={N}, K'={kp} (kf {F.info['kf']}, r1 {F.info['r1']}, r {F.info['r']}): "
         f"compress {ms_c:.3f} ms, recover {ms_r:.3f} ms, setup {setup:.2f} s, |T1T2^T x - P~x|/|x| <= {dist:.1e}")
     return {"workload": f"fast factorization N={N}, W=1/8, eps=1e-6, {b} signals",
@@ -428,8 +457,7 @@ def bench_factorization(args, dev):
             "compress_GSamples_per_s": round(N * b / (ms_c * 1e-3) / 1e9, 3),
             "recover_GSamples_per_s": round(N * b / (ms_r * 1e-3) / 1e9, 3),
             "max_dist_to_fast_projection_rel_to_x": dist,
-            "compress_kernels_traced_ms": {k: round(v["total_ms"], 4) for k, v in st_c.items()},
-            "recover_kernels_traced_ms": {k: round(v["total_ms"], 4) for k, v in st_r.items()}}
+            "compress_kernels": kc, "compress_dominant": dc, "recover_kernels": kr, "recover_dominant": dr}
 
 
 def bench_coeffs(args, dev):
