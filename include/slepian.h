@@ -230,7 +230,8 @@ int slepian_project_bands(slepian_bands_t bands, const float *x, int64_t ldx, fl
  * 256 <= N <= 2^20, else ENOTSUP.  Setup (synchronous, FP64 on the GPU):
  * subspace iteration on a random +-1 block with the FFT-applied B - F F^*,
  * Householder QR and a Rayleigh-Ritz step (rocSOLVER), widening the block
- * until it resolves every |mu| > eps; ENOCONV if it cannot.  The plan must
+ * until it resolves every |mu| > eps with a residual of at most eps / 4
+ * (checked with one more product); ENOCONV if it cannot.  The plan must
  * outlive the factorization. */
 typedef struct slepian_factor_s *slepian_factor_t;
 typedef struct {
@@ -240,6 +241,7 @@ typedef struct {
   int64_t kprime;     /* kf + r1 + r */
   int64_t subspace;   /* block size the setup converged with */
   double mu_dropped;  /* largest |Ritz value| of B - F F^* left out (<= eps) */
+  double ritz_residual; /* largest ||(B - F F^*) v - mu v|| of the kept pairs (<= eps / 4) */
 } slepian_factor_info_t;
 int slepian_factor_create(slepian_plan_t plan, slepian_factor_t *out);
 int slepian_factor_destroy(slepian_factor_t f);

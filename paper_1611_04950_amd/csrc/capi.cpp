@@ -1281,6 +1281,7 @@ struct slepian_factor_s {
   int64_t r1 = 0, r = 0;      // columns of the Theorem 1 factor and of the transition set
   int64_t p = 0;              // subspace size the setup converged with
   double mu_drop = 0;         // largest |Ritz value| left out (<= eps)
+  double ritz_res = 0;        // largest ||T v_j - mu_j v_j|| of the kept pairs
   float *U = nullptr;         // N x (r1 + r), leading dimension ldu: [V | U_T]
   int64_t ldu = 0;
   float *w = nullptr;         // r1 + r weights [mu | d]
@@ -1362,7 +1363,7 @@ FactorWs carve_factor(const slepian_factor_s *F, int64_t b, void *base) {
 // subspace iteration on a +-1 start block of p columns with the FP64 product
 // (Toeplitz kernel t of B - F F^*), Householder QR after every product, then
 // a Rayleigh-Ritz step.  p doubles until at least 24 Ritz values fall at or
-// below eps, so every kept pair is resolved far beyond eps.
+// below eps and every kept pair's residual ||T v - mu v|| is at most eps / 4.
 void factor_setup(slepian_factor_s *F, hipStream_t st) {
   Plan *P = F->P;
   const int64_t N = P->N, L = P->L;
@@ -1424,26 +1425,47 @@ void factor_setup(slepian_factor_s *F, hipStream_t st) {
     }
     std::stable_sort(keep.begin(), keep.end(), [&](int64_t a, int64_t b) { return std::fabs(d[a]) > std::fabs(d[b]); });
     const int64_t r1 = (int64_t)keep.size();
+    std::vector<double> mu(r1), zs((size_t)p * std::max<int64_t>(r1, 1));
+    for (int64_t j = 0; j < r1; ++j) {
+      mu[j] = d[keep[j]];
+      std::copy(z.begin() + keep[j] * p, z.begin() + (keep[j] + 1) * p, zs.begin() + j * p);
+    }
+    // Ritz vectors V = Q Z, signed; their residuals ||T v_j - mu_j v_j||
+    // checked against eps / 4 (else a wider block)
+    std::unique_ptr<DBuf<double>> V;
+    double res = 0;
+    if (r1 > 0) {
+      V.reset(new DBuf<double>((size_t)N * r1));
+      DBuf<double> Zs((size_t)p * r1), R((size_t)N * r1), mud(r1), nrm(r1), part((size_t)r1 * kNormParts);
+      HIPCHK(hipMemcpyAsync(Zs.p, zs.data(), (size_t)p * r1 * sizeof(double), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(mud.p, mu.data(), (size_t)r1 * sizeof(double), hipMemcpyHostToDevice, st));
+      ROCCHK(rocblas_dgemm(rh.h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)N, (rocblas_int)r1,
+                           (rocblas_int)p, &one, Q.p, (rocblas_int)N, Zs.p, (rocblas_int)p, &zero, V->p,
+                           (rocblas_int)N));
+      HIPCHK(sign_fix_cols(V->p, N, N, r1, st));
+      HIPCHK(conv_apply<double>(V->p, N, R.p, N, N, r1, P->g64, tbt, 1.0, 0.0, Corr<double>(), bw.Z, bw.slice, st));
+      HIPCHK(ritz_residual(R.p, V->p, mud.p, N, N, r1, st));
+      HIPCHK(col_norms(R.p, N, N, r1, nrm.p, part.p, st));
+      std::vector<double> h(r1);
+      HIPCHK(hipMemcpyAsync(h.data(), nrm.p, (size_t)r1 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (double v : h) res = std::max(res, v);
+      if (!(res <= 0.25 * P->eps)) {
+        if (p >= std::min<int64_t>(1024, N - 1)) throw Fail{SLEPIAN_ENOCONV};
+        p = std::min<int64_t>(2 * p, std::min<int64_t>(1024, N - 1));
+        continue;
+      }
+    }
     F->r1 = r1;
     F->p = p;
     F->mu_drop = drop;
-    F->mu.resize(r1);
-    std::vector<double> zs((size_t)p * std::max<int64_t>(r1, 1));
-    for (int64_t j = 0; j < r1; ++j) {
-      F->mu[j] = d[keep[j]];
-      std::copy(z.begin() + keep[j] * p, z.begin() + (keep[j] + 1) * p, zs.begin() + j * p);
-    }
+    F->ritz_res = res;
+    F->mu = mu;
     const int64_t rt = r1 + F->r;
     F->ldu = (N + 3) / 4 * 4;
     F->U = dalloc<float>((size_t)F->ldu * std::max<int64_t>(rt, 1));
     if (r1 > 0) {
-      DBuf<double> Zs((size_t)p * r1), V((size_t)N * r1);
-      HIPCHK(hipMemcpyAsync(Zs.p, zs.data(), (size_t)p * r1 * sizeof(double), hipMemcpyHostToDevice, st));
-      ROCCHK(rocblas_dgemm(rh.h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)N, (rocblas_int)r1,
-                           (rocblas_int)p, &one, Q.p, (rocblas_int)N, Zs.p, (rocblas_int)p, &zero, V.p,
-                           (rocblas_int)N));
-      HIPCHK(sign_fix_cols(V.p, N, N, r1, st));
-      HIPCHK(cast_f64_to_f32(V.p, N, F->U, F->ldu, N, r1, st));
+      HIPCHK(cast_f64_to_f32(V->p, N, F->U, F->ldu, N, r1, st));
       HIPCHK(hipStreamSynchronize(st));
     }
     if (F->r > 0)
@@ -1529,6 +1551,7 @@ int slepian_factor_info(slepian_factor_t F, slepian_factor_info_t *info) {
   info->kprime = F->kf + F->r1 + F->r;
   info->subspace = F->p;
   info->mu_dropped = F->mu_drop;
+  info->ritz_residual = F->ritz_res;
   return SLEPIAN_OK;
 }
 

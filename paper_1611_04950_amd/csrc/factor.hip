@@ -99,6 +99,25 @@ hipError_t sign_fix_cols(double *V, int64_t ld, int64_t N, int64_t cols, hipStre
   return hipGetLastError();
 }
 
+// R[:, j] -= mu[j] V[:, j] (N x r, leading dimension ld): the Ritz residuals
+// T v_j - mu_j v_j once R holds T V.
+__global__ void k_ritz_residual(double *__restrict__ R, const double *__restrict__ V, const double *__restrict__ mu,
+                                int64_t ld, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= N) return;
+  R[j * ld + i] -= mu[j] * V[j * ld + i];
+}
+
+hipError_t ritz_residual(double *R, const double *V, const double *mu, int64_t ld, int64_t N, int64_t r,
+                         hipStream_t st) {
+  if (N == 0 || r == 0) return hipSuccess;
+  if (r > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ritz_residual, dim3((unsigned)((N + 255) / 256), (unsigned)r), dim3(256), 0, st, R, V, mu, ld,
+                     N);
+  return hipGetLastError();
+}
+
 // Pair bins -> real coefficients of both signals (rows 0 .. kf-1 of c):
 // X1(k) = (Z(k) + conj Z(-k)) / 2, X2(k) = (Z(k) - conj Z(-k)) / 2i.
 __global__ void k_bins_unpack(const cpx<float> *__restrict__ Zb, int kf, int64_t N, int b, int p0,

@@ -235,6 +235,9 @@ hipError_t diff_embed(double *c, int64_t L, int64_t N, double W, int kf, hipStre
 hipError_t rademacher(double *O, int64_t ld, int64_t N, int64_t p, uint64_t seed, hipStream_t st);
 // sign convention of each column: first entry of magnitude >= 1e-3 max positive
 hipError_t sign_fix_cols(double *V, int64_t ld, int64_t N, int64_t cols, hipStream_t st);
+// R[:, j] -= mu[j] V[:, j] (FP64, N x r, leading dimension ld; mu on the device)
+hipError_t ritz_residual(double *R, const double *V, const double *mu, int64_t ld, int64_t N, int64_t r,
+                         hipStream_t st);
 // pair bins <-> the real coefficients F_r^T x (rows 0 .. kf-1 of c, leading dimension ldc)
 hipError_t bins_unpack(const cpx<float> *Zb, int kf, int64_t N, int64_t b, float *c, int64_t ldc, hipStream_t st);
 hipError_t bins_pack(const float *c, int64_t ldc, int kf, int64_t N, int64_t b, cpx<float> *Zb, hipStream_t st);

@@ -53,7 +53,7 @@ class PlanOpts(C.Structure):
 
 class FactorInfo(C.Structure):
     _fields_ = [("kf", C.c_int64), ("r1", C.c_int64), ("r", C.c_int64), ("kprime", C.c_int64),
-                ("subspace", C.c_int64), ("mu_dropped", C.c_double)]
+                ("subspace", C.c_int64), ("mu_dropped", C.c_double), ("ritz_residual", C.c_double)]
 
 
 class PlanInfo(C.Structure):
