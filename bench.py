@@ -110,7 +110,9 @@ def cpu_baseline(N, W, eps, x_sample, min_seconds):
     """The oracle's FP64 fast projection timed on this host (1 thread), on a
     sample of the workload's signals.  Returns the timing record, the
     oracle's outputs for the sample, against which the GPU's outputs for the
-    same signals are checked, and the sample's exact projection."""
+    same signals are checked, the sample's exact projection, and the same
+    timing record and outputs of the oracle's fast factorization (compress,
+    then recover) on that sample."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -134,10 +136,29 @@ def cpu_baseline(N, W, eps, x_sample, min_seconds):
     # 1e-13 ||x||); outside the timed loop
     with threadpool_limits(limits=1):
         exact = o.project_fast(N, W, 1e-13, xs)
+    # the oracle's fast factorization (Section 2.3): compression T2^T x and
+    # recovery T1 c of the same sample, timed the same way after its setup
+    from oracle import factorization as fz
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        fac = fz.fast_factorization(N, W, eps)
+        fsetup = time.perf_counter() - t0
+        freps = 0
+        t0 = time.perf_counter()
+        while True:
+            fref = fz.recover(fac, fz.compress(fac, xs))
+            freps += 1
+            fel = time.perf_counter() - t0
+            if fel >= min_seconds / 2:
+                break
+    fcpu = {"value": freps * xs.shape[0] * xs.shape[1] / fel / 1e6, "unit": "MSamples/s (compress + recover)",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{xs.shape[1]} signals of the workload, compressed and recovered {freps} times ({fel:.1f} s); "
+                      f"oracle setup {fsetup:.1f} s not included", "setup_s": fsetup}
     return {"value": samples / el / 1e6, "unit": "MSamples/s", "cores": 1, "kind": "oracle",
             "sample": f"{xs.shape[1]} signals of the workload, projected {reps} times ({el:.1f} s); "
                       f"oracle setup (transition vectors) {setup:.1f} s not included",
-            "setup_s": setup}, ref.T, exact.T
+            "setup_s": setup}, ref.T, exact.T, fcpu, fref.T
 
 
 def bench_batching(args, dev):
@@ -382,13 +403,16 @@ def bench_multiband(args, dev):
             "kernels_traced_ms": {k: round(v["total_ms"], 4) for k, v in st.items()}}
 
 
-def bench_factorization(args, dev):
+def bench_factorization(args, dev, check=None):
     """Fast factorization S_K S_K^T ~= T1 T2^T (Section 2.3, Theorem 1) at the
     paper-scale size N = 65536, W = 1/8, eps = 1e-6, 256 signals: compression
     T2^T x (length-N DFT bins through the FFT passes plus [V U]^T x on the
     matrix cores) and recovery T1 c, in the bench's correction precision.
     Also reports the distance of the round trip from the plan's fast
-    projection (both within eps of S_K S_K^T, so at most 3 eps apart)."""
+    projection (both within eps of S_K S_K^T, so at most 3 eps apart) and,
+    given the CPU leg's `check`, the round trip of its signal sample against
+    the oracle's (per-signal relative error, gated at 1e-5) with the oracle's
+    timing beside it."""
     import torch
 
     from paper_1611_04950_amd import slepian as S
@@ -448,6 +472,17 @@ def bench_factorization(args, dev):
             .max().item())
     kc, dc = roof(st_c)
     kr, dr = roof(st_r)
+    vs_oracle = None
+    if check is not None:
+        import numpy as np
+        ys = S.slepian_factor_recover(F, S.slepian_factor_compress(F, check["sample"]))
+        torch.cuda.synchronize()
+        ys = ys.double().cpu().numpy()
+        ref = check["ref"]
+        vs_oracle = float((np.linalg.norm(ys - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
+        if not vs_oracle <= 1e-5:
+            log(f"bench: factorization parity gate failed ({vs_oracle:.2e})")
+            sys.exit(1)
     log(f"bench: factorization N={N}, K'={kp} (kf {F.info['kf']}, r1 {F.info['r1']}, r {F.info['r']}): "
         f"compress {ms_c:.3f} ms, recover {ms_r:.3f} ms, setup {setup:.2f} s, |T1T2^T x - P~x|/|x| <= {dist:.1e}")
     return {"workload": f"fast factorization N={N}, W=1/8, eps=1e-6, {b} signals",
@@ -457,6 +492,8 @@ def bench_factorization(args, dev):
             "compress_GSamples_per_s": round(N * b / (ms_c * 1e-3) / 1e9, 3),
             "recover_GSamples_per_s": round(N * b / (ms_r * 1e-3) / 1e9, 3),
             "max_dist_to_fast_projection_rel_to_x": dist,
+            "parity_max_rel_err_vs_oracle": vs_oracle,
+            "cpu_oracle": None if check is None else check["cpu"],
             "compress_kernels": kc, "compress_dominant": dc, "recover_kernels": kr, "recover_dominant": dr}
 
 
@@ -604,10 +641,12 @@ def main():
     cpu = None
     err = err_sel = None
     extra_err = None
+    fac_check = None
     if not args.no_cpu:
         ns = min(b, 32)
         log(f"bench: timing the CPU oracle on {ns} signals")
-        cpu, ref, exact = cpu_baseline(N, W, eps, x[:ns].double().cpu().numpy(), args.cpu_seconds)
+        cpu, ref, exact, fcpu, fref = cpu_baseline(N, W, eps, x[:ns].double().cpu().numpy(), args.cpu_seconds)
+        fac_check = {"sample": x[:ns].contiguous(), "ref": fref, "cpu": fcpu}
         errs = {}
         for p in (S.SLEPIAN_FP32, prec):
             S.slepian_project(plan, x, y, work=work, precision=p)
@@ -711,7 +750,7 @@ def main():
     egap = None if args.no_extra else bench_eigen_gap(args, dev)
     mband = None if args.no_extra else bench_multiband(args, dev)
     coeffs = None if args.no_extra else bench_coeffs(args, dev)
-    factor = None if args.no_extra else bench_factorization(args, dev)
+    factor = None if args.no_extra else bench_factorization(args, dev, fac_check)
     if factor and coeffs:
         factor["speedup_compress_vs_dense_coeffs"] = round(coeffs[args.precision]["ms_per_call"] / factor["compress_ms"], 1)
 
