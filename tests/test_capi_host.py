@@ -122,3 +122,17 @@ def test_synth_is_seeded_and_float32():
     assert (a == b).all()
     c = synth.config_signals(1, 100, 2, 0.1)
     assert abs(float(c.double().std()) - 1.0) < 0.2
+
+
+def test_header_is_plain_c():
+    """include/slepian.h is a C header (the boundary takes no C++ or torch
+    types): it compiles as C99 and as C++ with warnings as errors."""
+    import shutil
+    import subprocess
+    hdr = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "slepian.h")
+    for cc, args in (("gcc", ["-std=c99", "-x", "c"]), ("g++", ["-x", "c++"])):
+        if shutil.which(cc) is None:
+            pytest.skip(f"{cc} not available")
+        r = subprocess.run([cc, "-fsyntax-only", "-Wall", "-Wextra", "-Werror", *args, hdr], capture_output=True,
+                           text=True)
+        assert r.returncode == 0, r.stderr
