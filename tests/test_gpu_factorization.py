@@ -179,3 +179,27 @@ def test_factorization_errors():
                                        None) == S.SLEPIAN_EINVAL
     ws = C.c_size_t()
     assert lib.slepian_factor_workspace_size(F.handle, 4, C.byref(ws)) == S.SLEPIAN_OK and ws.value > 0
+
+
+def test_factorization_random_configs():
+    """Seeded random plans (N = 2^8 .. 2^14, W in [0.01, 0.45], eps in {1e-3,
+    1e-6, 1e-9}, 1..9 signals, FP32 or mixed): kf and r1 equal the oracle's
+    and the round trip matches the oracle's within 1e-5 per signal."""
+    rng = np.random.default_rng(1611)
+    for i in range(8):
+        N = int(2 ** rng.integers(8, 15))
+        W = float(rng.uniform(0.01, 0.45))
+        eps = float(rng.choice([1e-3, 1e-6, 1e-9]))
+        b = int(rng.integers(1, 10))
+        prec = str(rng.choice(["fp32", "mixed"]))
+        print(f"random factorization case {i}: N={N} W={W:.4f} eps={eps:g} b={b} {prec}", flush=True)
+        P, F = _setup(N, W, eps, prec)
+        fac = fz.fast_factorization(N, W, eps)
+        assert F.info["kf"] == fac["kf"]
+        _check_r1(F, fac, eps)
+        x = _x(N, b, 500 + i)
+        y = S.slepian_factor_recover(F, S.slepian_factor_compress(F, torch.from_numpy(x.T.copy()).cuda()))
+        y = y.cpu().numpy().astype(np.float64).T
+        ref = fz.recover(fac, fz.compress(fac, x.astype(np.float64)))
+        for s in range(b):
+            assert np.linalg.norm(y[:, s] - ref[:, s]) <= 1e-5 * np.linalg.norm(ref[:, s])
