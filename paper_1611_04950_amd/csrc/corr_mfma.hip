@@ -187,6 +187,128 @@ __global__ __launch_bounds__(256) void k_corr_partial_mfma(const float *__restri
   corr_partial_body<MODE, NB, KS, VEC>(X, ldx, N, b, U, ldu, r, part, rpad, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
+// The same partials for r > 32 in one pass over x: each workgroup loads its
+// chunk of x once (and, in the BF16 modes, splits it into hi/lo halves once)
+// and then runs the nz = ceil(r / 32) column tiles of U in turn, each with
+// the same matrix instructions, fixed-order wavefront sum through LDS and
+// partial layout as corr_partial_body.
+template <int MODE, int NB, int KS, bool VEC>
+__global__ __launch_bounds__(256) void k_corr_partial_tiles(const float *__restrict__ X, int64_t ldx, int N, int b,
+                                                            const float *__restrict__ U, int64_t ldu, int r,
+                                                            float *__restrict__ part, int rpad, int nz) {
+  __shared__ float red[3][NB][16][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = lane & 31, kb = lane >> 5;
+  const int bx = blockIdx.x, by = blockIdx.y;
+  const int s_base = by * 32 * NB;
+  constexpr int KC = KS * 16;
+  const int k_begin = (bx * 4 + wave) * KC;
+  const int k_end = min(N, k_begin + KC);
+  const bool full = k_begin + KC <= N;
+  float xb[KS][NB][8];
+#pragma unroll
+  for (int q = 0; q < KS; ++q) {
+    const int kk = k_begin + 16 * q + 8 * kb;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int s = s_base + nb * 32 + i;
+      const bool v = s < b;
+      const float *xp = X + (int64_t)(v ? s : b - 1) * ldx;
+      if (VEC && full) {
+        const float4 c0 = *reinterpret_cast<const float4 *>(xp + kk);
+        const float4 c1 = *reinterpret_cast<const float4 *>(xp + kk + 4);
+        xb[q][nb][0] = c0.x; xb[q][nb][1] = c0.y; xb[q][nb][2] = c0.z; xb[q][nb][3] = c0.w;
+        xb[q][nb][4] = c1.x; xb[q][nb][5] = c1.y; xb[q][nb][6] = c1.z; xb[q][nb][7] = c1.w;
+      } else if (full) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xb[q][nb][e] = xp[kk + e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xb[q][nb][e] = kk + e < k_end ? xp[kk + e] : 0.f;
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xb[q][nb][e] = v ? xb[q][nb][e] : 0.f;
+    }
+  }
+  bf16x8 xh[KS][NB], xl[KS][NB];
+  if constexpr (MODE != kModeF32) {
+#pragma unroll
+    for (int q = 0; q < KS; ++q)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) split_bf16(xb[q][nb], xh[q][nb], xl[q][nb]);
+  }
+  for (int bz = 0; bz < nz; ++bz) {
+    const int j = bz * 32 + i;
+    const bool jv = j < r;
+    const float *Uj = U + (int64_t)(jv ? j : r - 1) * ldu;
+    float ua[KS][8];
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      const int kk = k_begin + 16 * q + 8 * kb;
+      if (VEC && full) {
+        const float4 a0 = *reinterpret_cast<const float4 *>(Uj + kk);
+        const float4 a1 = *reinterpret_cast<const float4 *>(Uj + kk + 4);
+        ua[q][0] = a0.x; ua[q][1] = a0.y; ua[q][2] = a0.z; ua[q][3] = a0.w;
+        ua[q][4] = a1.x; ua[q][5] = a1.y; ua[q][6] = a1.z; ua[q][7] = a1.w;
+      } else if (full) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ua[q][e] = Uj[kk + e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ua[q][e] = kk + e < k_end ? Uj[kk + e] : 0.f;
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ua[q][e] = jv ? ua[q][e] : 0.f;
+    }
+    f32x16 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[nb][v] = 0.f;
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      if constexpr (MODE == kModeF32) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ua[q][e], xb[q][nb][e], acc[nb], 0, 0, 0);
+      } else {
+        bf16x8 ahi, alo;
+        split_bf16(ua[q], ahi, alo);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, xh[q][nb], acc[nb], 0, 0, 0);
+          if constexpr (MODE == kModeBF16x3) {
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, xl[q][nb], acc[nb], 0, 0, 0);
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, xh[q][nb], acc[nb], 0, 0, 0);
+          }
+        }
+      }
+    }
+    if (bz > 0) __syncthreads();  // wavefront 0 has read the previous tile's sums
+    if (wave > 0) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) red[wave - 1][nb][v][lane] = acc[nb][v];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int s = s_base + nb * 32 + i;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const float t = (acc[nb][v] + red[0][nb][v][lane]) + (red[1][nb][v][lane] + red[2][nb][v][lane]);
+          const int jj = bz * 32 + 8 * (v >> 2) + 4 * kb + (v & 3);
+          if (jj < r && s < b) part[((int64_t)bx * rpad + jj) * b + s] = t;
+        }
+      }
+    }
+  }
+}
+
 // out[j * ldo_j + s * ldo_s] = d[j] * sum over chunks of part[chunk][j][s]
 // (d == nullptr: no weights).  16 outputs per workgroup (consecutive s),
 // 16 lanes per output each summing every 16th chunk with two accumulators,
@@ -365,6 +487,12 @@ static bool aligned16(const void *p, int64_t ld) {
 template <int MODE, bool VEC>
 static void launch_partial(const char *name, dim3 grid, hipStream_t st, const float *x, int64_t ldx, int64_t N,
                            int64_t b, const float *U, int64_t ldu, int r, float *part, int rpad) {
+  if (grid.z > 1) {
+    const int nz = (int)grid.z;
+    SLP_LAUNCH(name, (k_corr_partial_tiles<MODE, kPartNB, kPartKS, VEC>), dim3(grid.x, grid.y, 1), dim3(256), 0, st,
+               x, ldx, (int)N, (int)b, U, ldu, r, part, rpad, nz);
+    return;
+  }
   SLP_LAUNCH(name, (k_corr_partial_mfma<MODE, kPartNB, kPartKS, VEC>), grid, dim3(256), 0, st, x, ldx, (int)N,
              (int)b, U, ldu, r, part, rpad);
 }
