@@ -939,6 +939,7 @@ static bool dispatch_cols(bool fwd, dim3 grid, hipStream_t st, const R *x, int64
 // default for tuning.
 struct CicShape {
   int ppl = 1, cw = 4;
+  bool set = false;  // from the override
 };
 
 // the grouped launches use one pair per lane and 4 or 8 wavefronts (tuned)
@@ -952,6 +953,7 @@ static CicShape cic_shape() {
       if (std::sscanf(e, "%dx%d", &p, &w) == 2 && ((p == 1 && (w == 4 || w == 8)) || (p == 2 && w == 4))) {
         c.ppl = p;
         c.cw = w;
+        c.set = true;
       }
     }
     return c;
@@ -989,7 +991,14 @@ static void launch_cic(hipStream_t st, const cpx<float> *Z, int N, int b, int p0
 template <int L1, int MODE, bool EVEN = false>
 static void launch_cic_shape(hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np, const FftGeom &g,
                              const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c, int rp) {
-  const CicShape sh = cic_shape();
+  // the even-row pass (fast factorization, update of rank r1 + r, about three
+  // times the projection's) re-reads a larger U tile per pair group; two pairs
+  // per lane halve the groups (measured 77 -> 53 us at rank 91)
+  CicShape sh = cic_shape();
+  if (EVEN && !sh.set) {
+    sh.ppl = 2;
+    sh.cw = 4;
+  }
   if (sh.ppl == 1 && sh.cw == 8) launch_cic<L1, MODE, 8, 1, EVEN>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
   else if (sh.ppl == 1) launch_cic<L1, MODE, 4, 1, EVEN>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
   else launch_cic<L1, MODE, 4, 2, EVEN>(st, Z, N, b, p0, np, g, tb, y, ldy, c, rp);
