@@ -1114,17 +1114,31 @@ __device__ __forceinline__ int64_t row_freq(int q, int m) {
   return (int64_t)(g / R2) + (int64_t)R1 * (g % R2) + (int64_t)R1 * R2 * m;
 }
 
-// Forward row transforms of the even rows k1c = 2 blockIdx.x of pair pl,
-// kept bins written to Zb[pl][slot].
+// Workgroup -> (even row h, pair pl) for the bins row passes.  Workgroups
+// are dealt to the 8 XCDs round robin by linear id; w = 8 (h + R g) + q with
+// pair pl = 8 g + q puts all R = L1/2 even rows of a pair on one XCD, so the
+// rows' interleaved bins (slots M + h + R kr) meet in one L2.  Workgroups
+// past the last pair exit at once (before any barrier).
+__device__ __forceinline__ bool bins_row_pair(int R, int np, int &h, int &pl) {
+  const int w = blockIdx.x, q = w & 7, rest = w >> 3;
+  h = rest % R;
+  pl = (rest / R) * 8 + q;
+  return pl < np;
+}
+
+// Forward row transforms of the even rows k1c = 2h of pair pl, kept bins
+// written to Zb[pl][slot].
 template <int R1, int R2, int R3>
 __global__ __launch_bounds__(R2 *R3) void k_row_bins(const cpx<float> *__restrict__ Z, int logL, int log1, int log2,
                                                     const cpx<float> *__restrict__ rt1,
                                                     const cpx<float> *__restrict__ rt2, cpx<float> *__restrict__ Zb,
-                                                    int kf) {
+                                                    int kf, int np) {
   using RS = RowShape<R1, R2, R3>;
   __shared__ cpx<float> S[RS::LDS];
   __shared__ cpx<float> rt2s[R2 * (R3 + 1)];
-  const int k1c = 2 * blockIdx.x, pl = blockIdx.y;
+  int h, pl;
+  if (!bins_row_pair(1 << (log1 - 1), np, h, pl)) return;
+  const int k1c = 2 * h;
   const cpx<float> *row = Z + ((int64_t)pl << logL) + ((int64_t)k1c << log2);
   const int t = threadIdx.x;
   cpx<float> v[R1];
@@ -1145,18 +1159,21 @@ __global__ __launch_bounds__(R2 *R3) void k_row_bins(const cpx<float> *__restric
   });
 }
 
-// Inverse row transforms of the even rows k1c = 2 blockIdx.x of pair pl from
-// the kept bins (zero elsewhere).  Odd rows hold no even frequency; they are
-// neither written here nor read by the inverse column pass that follows.
+// Inverse row transforms of the even rows k1c = 2h of pair pl from the kept
+// bins (zero elsewhere; workgroups mapped as in k_row_bins).  Odd rows hold
+// no even frequency; they are neither written here nor read by the inverse
+// column pass that follows.
 template <int R1, int R2, int R3>
 __global__ __launch_bounds__(R2 *R3) void k_row_from_bins(const cpx<float> *__restrict__ Zb, int kf, int logL,
                                                          int log1, int log2, const cpx<float> *__restrict__ rt1,
                                                          const cpx<float> *__restrict__ rt2,
-                                                         cpx<float> *__restrict__ Z) {
+                                                         cpx<float> *__restrict__ Z, int np) {
   using RS = RowShape<R1, R2, R3>;
   __shared__ cpx<float> S[RS::LDS];
   __shared__ cpx<float> rt2s[R2 * (R3 + 1)];
-  const int k1c = 2 * blockIdx.x, pl = blockIdx.y;
+  int h, pl;
+  if (!bins_row_pair(1 << (log1 - 1), np, h, pl)) return;
+  const int k1c = 2 * h;
   cpx<float> *row = Z + ((int64_t)pl << logL) + ((int64_t)k1c << log2);
   const int t = threadIdx.x;
   cpx<float> v[R1];
@@ -1292,11 +1309,11 @@ hipError_t dft_bins_fwd(const float *x, int64_t ldx, int64_t N, int64_t b, const
     const dim3 gcol((1u << g.log2) / 256, (unsigned)np);
     if (!dispatch_cols<float, true>(true, gcol, st, x, ldx, nullptr, 0, (int)N, (int)b, (int)p0, g, tb, Z))
       return hipErrorInvalidValue;
-    const dim3 grow(1u << (g.log1 - 1), (unsigned)np);
+    const dim3 grow((unsigned)(((np + 7) / 8) * 8 << (g.log1 - 1)));
 #define SLP_RB(A, B, C)                                                                                         \
   if (g.R1 == A && g.R2 == B && g.R3 == C)                                                                       \
     SLP_LAUNCH("dft_bins_row", (k_row_bins<A, B, C>), grow, dim3(B * C), 0, st, Z, g.logL, g.log1, g.log2,     \
-               tb.row1, tb.row2, Zb + p0 * kf, kf);
+               tb.row1, tb.row2, Zb + p0 * kf, kf, (int)np);
     SLP_ROW_SHAPES(SLP_RB)
 #undef SLP_RB
   }
@@ -1324,11 +1341,11 @@ hipError_t dft_bins_inv(const cpx<float> *Zb, int kf, float *y, int64_t ldy, int
   }
   for (int64_t p0 = 0; p0 < pairs; p0 += slice_pairs) {
     const int64_t np = std::min<int64_t>(slice_pairs, pairs - p0);
-    const dim3 grow(1u << (g.log1 - 1), (unsigned)np);
+    const dim3 grow((unsigned)(((np + 7) / 8) * 8 << (g.log1 - 1)));
 #define SLP_RI(A, B, C)                                                                                         \
   if (g.R1 == A && g.R2 == B && g.R3 == C)                                                                       \
     SLP_LAUNCH("dft_from_bins_row", (k_row_from_bins<A, B, C>), grow, dim3(B * C), 0, st, Zb + p0 * kf, kf,    \
-               g.logL, g.log1, g.log2, tb.row1, tb.row2, Z);
+               g.logL, g.log1, g.log2, tb.row1, tb.row2, Z, (int)np);
     SLP_ROW_SHAPES(SLP_RI)
 #undef SLP_RI
     if (corr.dC) {
