@@ -203,3 +203,27 @@ def test_factorization_random_configs():
         ref = fz.recover(fac, fz.compress(fac, x.astype(np.float64)))
         for s in range(b):
             assert np.linalg.norm(y[:, s] - ref[:, s]) <= 1e-5 * np.linalg.norm(ref[:, s])
+
+
+def test_factorization_batch_slices():
+    """A batch whose pair intermediate exceeds one 256 MiB slice (N = 2^18:
+    64 pairs per slice; 130 signals = 65 pairs, so two slices, the second
+    with one pair): signals on both sides of the slice boundary match the
+    oracle's round trip, and the F part of the compression matches F_r^T x."""
+    N, W, eps, b = 262144, 0.05, 1e-4, 130
+    P, F = _setup(N, W, eps, "mixed")
+    fac = _oracle(N, W, eps)
+    x = synth.gaussian(N, b, 77)
+    xd = x.cuda()
+    c = S.slepian_factor_compress(F, xd)
+    y = S.slepian_factor_recover(F, c)
+    torch.cuda.synchronize()
+    pick = [0, 1, 126, 127, 128, 129]
+    xs = x[pick].double().numpy().T
+    ref = fz.recover(fac, fz.compress(fac, xs))
+    ys = y[pick].double().cpu().numpy().T
+    cf = fz.fr_adjoint(xs, fac["kf"])
+    cs = c[pick, :fac["kf"]].double().cpu().numpy().T
+    for q in range(len(pick)):
+        assert np.linalg.norm(ys[:, q] - ref[:, q]) <= 1e-5 * np.linalg.norm(ref[:, q])
+        assert np.abs(cs[:, q] - cf[:, q]).max() <= 1e-5 * np.linalg.norm(cf[:, q])
