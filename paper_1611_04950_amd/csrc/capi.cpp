@@ -1612,8 +1612,7 @@ int slepian_factor_recover(slepian_factor_t F, const float *c, int64_t ldc, floa
     // y += [V U_T] ([mu d] . c_rest), inside the inverse column pass where it
     // takes the update, else as a separate pass
     const int rt = (int)(F->r1 + F->r);
-    if (rt > 0) HIPCHK(scale_rows(c, ldc, F->kf, rt, batch, F->w, w.dC, st));
-    HIPCHK(bins_pack(c, ldc, F->kf, N, batch, w.Zb, st));
+    HIPCHK(pack_scale(c, ldc, F->kf, N, batch, w.Zb, rt, F->w, w.dC, st));
     Corr<float> corr;
     const bool fused = rt > 0 && F->ctile && colinv_corr_ok(P->g32.log1, ldy, batch, rt);
     if (fused) {

@@ -155,58 +155,54 @@ hipError_t bins_unpack(const cpx<float> *Zb, int kf, int64_t N, int64_t b, float
   return hipGetLastError();
 }
 
-// Real coefficients of both signals -> pair bins scaled for an unnormalised
-// inverse transform of length 2N: with Y(0) = sqrt(N) c[0] and
-// Y(k) = sqrt(N/2) (c[2k-1] + i c[2k]), Z(k) = (Y1(k) + i Y2(k)) / N and
-// Z(-k) = (conj Y1(k) + i conj Y2(k)) / N.
-__global__ void k_bins_pack(const float *__restrict__ c, int64_t ldc, int kf, int64_t N, int b, int p0,
-                            cpx<float> *__restrict__ Zb) {
-  const int M = (kf - 1) / 2;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = p0 + blockIdx.y;
-  if (k > M) return;
-  const int s0 = 2 * p, s1 = 2 * p + 1;
-  const bool has1 = s1 < b;
-  const float *c0 = c + (int64_t)s0 * ldc, *c1 = c + (int64_t)(has1 ? s1 : s0) * ldc;
-  cpx<float> *z = Zb + (int64_t)p * kf;
-  if (k == 0) {
-    const float sc = (float)(1.0 / sqrt((double)N));
-    z[M] = cpx<float>{c0[0] * sc, has1 ? c1[0] * sc : 0.f};
+// Recovery's two reads of c in one launch.  Workgroups [0, nbp) (per_pair
+// workgroups of 256 bins per pair) turn the real coefficients of both
+// signals into pair bins scaled for an unnormalised inverse transform of
+// length 2N: with Y(0) = sqrt(N) c[0] and Y(k) = sqrt(N/2) (c[2k-1] + i c[2k]),
+// Z(k) = (Y1(k) + i Y2(k)) / N and Z(-k) = (conj Y1(k) + i conj Y2(k)) / N.
+// The rest form dC[j b + s] = w[j] c[kf + j + s ldc] for j < r, s < b.
+__global__ __launch_bounds__(256) void k_pack_scale(const float *__restrict__ c, int64_t ldc, int kf, int64_t N,
+                                                    int b, int per_pair, int64_t nbp, cpx<float> *__restrict__ Zb,
+                                                    int r, const float *__restrict__ w, float *__restrict__ dC) {
+  const int64_t bid = blockIdx.x;
+  if (bid < nbp) {
+    const int M = (kf - 1) / 2;
+    const int p = (int)(bid / per_pair);
+    const int k = (int)(bid % per_pair) * 256 + threadIdx.x;
+    if (k > M) return;
+    const int s0 = 2 * p, s1 = 2 * p + 1;
+    const bool has1 = s1 < b;
+    const float *c0 = c + (int64_t)s0 * ldc, *c1 = c + (int64_t)(has1 ? s1 : s0) * ldc;
+    cpx<float> *z = Zb + (int64_t)p * kf;
+    if (k == 0) {
+      const float sc = (float)(1.0 / sqrt((double)N));
+      z[M] = cpx<float>{c0[0] * sc, has1 ? c1[0] * sc : 0.f};
+      return;
+    }
+    const float f = (float)(1.0 / sqrt(2.0 * (double)N));
+    const float a1 = c0[2 * k - 1], b1 = c0[2 * k];
+    const float a2 = has1 ? c1[2 * k - 1] : 0.f, b2 = has1 ? c1[2 * k] : 0.f;
+    z[M + k] = cpx<float>{(a1 - b2) * f, (b1 + a2) * f};
+    z[M - k] = cpx<float>{(a1 + b2) * f, (a2 - b1) * f};
     return;
   }
-  const float f = (float)(1.0 / sqrt(2.0 * (double)N));
-  const float a1 = c0[2 * k - 1], b1 = c0[2 * k];
-  const float a2 = has1 ? c1[2 * k - 1] : 0.f, b2 = has1 ? c1[2 * k] : 0.f;
-  z[M + k] = cpx<float>{(a1 - b2) * f, (b1 + a2) * f};
-  z[M - k] = cpx<float>{(a1 + b2) * f, (a2 - b1) * f};
-}
-
-hipError_t bins_pack(const float *c, int64_t ldc, int kf, int64_t N, int64_t b, cpx<float> *Zb, hipStream_t st) {
-  const int64_t pairs = (b + 1) / 2;
-  const int M = (kf - 1) / 2;
-  for (int64_t p0 = 0; p0 < pairs; p0 += 65535) {
-    const int64_t np = pairs - p0 < 65535 ? pairs - p0 : 65535;
-    SLP_LAUNCH("bins_pack", k_bins_pack, dim3((unsigned)((M + 256) / 256), (unsigned)np), dim3(256), 0, st, c, ldc,
-               kf, N, (int)b, (int)p0, Zb);
-  }
-  return hipGetLastError();
-}
-
-// dC[j b + s] = w[j] c[row0 + j + s ldc] for j < r, s < b.
-__global__ void k_scale_rows(const float *__restrict__ c, int64_t ldc, int64_t row0, int r, int64_t b,
-                             const float *__restrict__ w, float *__restrict__ dC) {
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t o = (bid - nbp) * 256 + threadIdx.x;
   if (o >= (int64_t)r * b) return;
   const int64_t j = o / b, s = o % b;
-  dC[o] = w[j] * c[row0 + j + s * ldc];
+  dC[o] = w[j] * c[kf + j + s * ldc];
 }
 
-hipError_t scale_rows(const float *c, int64_t ldc, int64_t row0, int r, int64_t b, const float *w, float *dC,
-                      hipStream_t st) {
-  const int64_t n = (int64_t)r * b;
-  if (n == 0) return hipSuccess;
-  SLP_LAUNCH("scale_rows", k_scale_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c, ldc, row0, r, b, w,
-             dC);
+hipError_t pack_scale(const float *c, int64_t ldc, int kf, int64_t N, int64_t b, cpx<float> *Zb, int r,
+                      const float *w, float *dC, hipStream_t st) {
+  const int64_t pairs = (b + 1) / 2;
+  if (pairs == 0) return hipSuccess;
+  const int M = (kf - 1) / 2;
+  const int per_pair = (M + 256) / 256;
+  const int64_t nbp = (int64_t)per_pair * pairs;
+  const int64_t nbs = ((int64_t)r * b + 255) / 256;
+  if (nbp + nbs > 0x7fffffffLL) return hipErrorInvalidValue;
+  SLP_LAUNCH("pack_scale", k_pack_scale, dim3((unsigned)(nbp + nbs)), dim3(256), 0, st, c, ldc, kf, N, (int)b,
+             per_pair, nbp, Zb, r, w, dC);
   return hipGetLastError();
 }
 

@@ -238,12 +238,12 @@ hipError_t sign_fix_cols(double *V, int64_t ld, int64_t N, int64_t cols, hipStre
 // R[:, j] -= mu[j] V[:, j] (FP64, N x r, leading dimension ld; mu on the device)
 hipError_t ritz_residual(double *R, const double *V, const double *mu, int64_t ld, int64_t N, int64_t r,
                          hipStream_t st);
-// pair bins <-> the real coefficients F_r^T x (rows 0 .. kf-1 of c, leading dimension ldc)
+// pair bins -> the real coefficients F_r^T x (rows 0 .. kf-1 of c, leading dimension ldc)
 hipError_t bins_unpack(const cpx<float> *Zb, int kf, int64_t N, int64_t b, float *c, int64_t ldc, hipStream_t st);
-hipError_t bins_pack(const float *c, int64_t ldc, int kf, int64_t N, int64_t b, cpx<float> *Zb, hipStream_t st);
-// dC[j b + s] = w[j] c[row0 + j + s ldc]
-hipError_t scale_rows(const float *c, int64_t ldc, int64_t row0, int r, int64_t b, const float *w, float *dC,
-                      hipStream_t st);
+// recovery's reads of c: the real coefficients -> pair bins (Zb), and
+// dC[j b + s] = w[j] c[kf + j + s ldc] (j < r)
+hipError_t pack_scale(const float *c, int64_t ldc, int kf, int64_t N, int64_t b, cpx<float> *Zb, int r,
+                      const float *w, float *dC, hipStream_t st);
 
 // ---- Least-squares refinement helpers (lsq.hip) ----
 // rho = By - u - alpha x (all FP64, N x b with leading dimension N except x: ldx)
