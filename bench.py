@@ -596,6 +596,9 @@ def main():
                     help="correction arithmetic of the timed batched path (the FFT product is FP32 in both)")
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the many-plans workload (512 plans through one grouped call)")
+    ap.add_argument("--extra", default="all",
+                    help="comma-separated extra workloads to run (precision, lsq, fourier, eigengap, multiband, "
+                         "coeffs, factorization), or all")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the precision (N=2^18, 1024 signals) and least-squares (N=2^20) workloads")
     args = ap.parse_args()
@@ -744,13 +747,16 @@ def main():
                  "speedup_batched": round(pms / ms_per_step, 2)}
 
     batching = None if args.no_batching else bench_batching(args, dev)
-    precision = None if args.no_extra else bench_precision(args, dev)
-    lsq = None if args.no_extra else bench_lsq(args, dev)
-    fext = None if args.no_extra else bench_fourier_extension(args, dev)
-    egap = None if args.no_extra else bench_eigen_gap(args, dev)
-    mband = None if args.no_extra else bench_multiband(args, dev)
-    coeffs = None if args.no_extra else bench_coeffs(args, dev)
-    factor = None if args.no_extra else bench_factorization(args, dev, fac_check)
+    extras = set() if args.no_extra else (
+        {"precision", "lsq", "fourier", "eigengap", "multiband", "coeffs", "factorization"} if args.extra == "all"
+        else set(args.extra.split(",")))
+    precision = bench_precision(args, dev) if "precision" in extras else None
+    lsq = bench_lsq(args, dev) if "lsq" in extras else None
+    fext = bench_fourier_extension(args, dev) if "fourier" in extras else None
+    egap = bench_eigen_gap(args, dev) if "eigengap" in extras else None
+    mband = bench_multiband(args, dev) if "multiband" in extras else None
+    coeffs = bench_coeffs(args, dev) if "coeffs" in extras else None
+    factor = bench_factorization(args, dev, fac_check) if "factorization" in extras else None
     if factor and coeffs:
         factor["speedup_compress_vs_dense_coeffs"] = round(coeffs[args.precision]["ms_per_call"] / factor["compress_ms"], 1)
 
