@@ -724,6 +724,12 @@ def main():
         ppl = pairs / kernels[name]["launches_per_step"] if not name.startswith("corr") else pairs
         kb = kernel_bytes(name, N, b, info["L"], info["r"], ppl)
         kernels[name]["alg_GBs"] = kb / (kernels[name]["avg_us"] * 1e-6) / 1e9
+        # measured HBM bytes per launch (rocprofv3 counters, when the committed
+        # summary was taken with the current sources) over this run's duration
+        t = read_traffic(name, args.workload)
+        if t is not None:
+            kernels[name]["hbm_bytes"] = t
+            kernels[name]["hbm_GBs"] = t / (kernels[name]["avg_us"] * 1e-6) / 1e9
     traffic = read_traffic(dom, args.workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
