@@ -43,7 +43,19 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(name: str, N: int, b: int, L: int, r: int, pairs_per_launch: int) -> float:
+def _finite(v):
+    """The JSON line with NaN and infinities replaced by null (strict JSON)."""
+    import math
+    if isinstance(v, float):
+        return v if math.isfinite(v) else None
+    if isinstance(v, dict):
+        return {k: _finite(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [_finite(x) for x in v]
+    return v
+
+
+def kernel_bytes(name: str, N: int, b: int, L: int, r: int, pairs_per_launch: int):
     """Algorithmic HBM bytes of one launch of each kernel of the path: what the
     method must move (FP32 signal in/out 4 B/sample, complex64 intermediates
     8 B/point, spectrum 4 B/point once, U 4 B/entry once)."""
@@ -63,7 +75,10 @@ def kernel_bytes(name: str, N: int, b: int, L: int, r: int, pairs_per_launch: in
         return 8.0 * N * b + 4.0 * N * r
     if name in ("conv_single", "conv_single_corr"):
         return P * 8.0 * N + 4.0 * L + 4.0 * N * r
-    return float("nan")
+    if name == "corr_reduce":
+        # chunk partials (one per 256 samples) read once, d (.) C written once
+        return 4.0 * b * r * ((N + 255) // 256 + 1)
+    return None
 
 
 def read_traffic(kernel: str, workload: str):
@@ -723,7 +738,7 @@ def main():
     for name in kernels:
         ppl = pairs / kernels[name]["launches_per_step"] if not name.startswith("corr") else pairs
         kb = kernel_bytes(name, N, b, info["L"], info["r"], ppl)
-        kernels[name]["alg_GBs"] = kb / (kernels[name]["avg_us"] * 1e-6) / 1e9
+        kernels[name]["alg_GBs"] = None if kb is None else kb / (kernels[name]["avg_us"] * 1e-6) / 1e9
         # measured HBM bytes per launch (rocprofv3 counters, when the committed
         # summary was taken with the current sources) over this run's duration
         t = read_traffic(name, args.workload)
@@ -799,7 +814,7 @@ def main():
         "coefficients_workload": coeffs,
         "factorization_workload": factor,
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(_finite(out)), flush=True)
 
 
 if __name__ == "__main__":
