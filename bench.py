@@ -151,12 +151,12 @@ def cpu_baseline(N, W, eps, x_sample, min_seconds):
     # 1e-13 ||x||); outside the timed loop
     with threadpool_limits(limits=1):
         exact = o.project_fast(N, W, 1e-13, xs)
-    # the oracle's fast factorization (Section 2.3): compression T2^T x and
+    # the oracle's fast factorization (Section 1.3): compression T2^T x and
     # recovery T1 c of the same sample, timed the same way after its setup
     from oracle import factorization as fz
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        fac = fz.fast_factorization(N, W, eps)
+        fac = fz.fast_factorization(N, W, eps, method="eig")
         fsetup = time.perf_counter() - t0
         freps = 0
         t0 = time.perf_counter()
@@ -289,7 +289,7 @@ def bench_precision(args, dev):
 
 
 def bench_fourier_extension(args, dev):
-    """The Fourier-extension experiment at its largest size (Section 4.3):
+    """The Fourier-extension experiment at its largest size (Section 4.2):
     M = 2560 (N = 5121, W = 1/3, T = 1.5), the right-hand side by a
     2^24-point quadrature, solved with the fast pseudoinverse (eps = 1e-5,
     rank K = #{lambda >= 1e-4}) and the fast Tikhonov operator (alpha =
@@ -342,7 +342,7 @@ def bench_eigen_gap(args, dev):
     """Figure 1's study from the GPU plans: #{eps < lambda < 1 - eps} for
     W = 1/4, N = 2^4 .. 2^16, and for N = 2^16, W = 2^-14 .. 2^-2, with eps
     in {1e-3, 1e-6, 1e-9, 1e-12}, beside the asymptotic count
-    (2/pi^2) log N log(1/eps - 1) (Section 2.2) and Corollary 1's bound."""
+    (2/pi^2) log N log(1/eps - 1) (Section 1.2) and Corollary 1's bound."""
     import torch
 
     from paper_1611_04950_amd import slepian as S
@@ -370,7 +370,7 @@ def bench_eigen_gap(args, dev):
 
 
 def bench_multiband(args, dev):
-    """Multiband (modulated Slepian) dictionary projection (Section 2.3,
+    """Multiband (modulated Slepian) dictionary projection (Section 1.4,
     application i): N = 2^20, W = 1/256, eps = 1e-6, eight bands centred at
     (2k + 1)/32, k = 0..7, 16 real signals, in the bench's correction
     precision.  The prepared band set (one FFT product with the band-sum
@@ -419,7 +419,7 @@ def bench_multiband(args, dev):
 
 
 def bench_factorization(args, dev, check=None):
-    """Fast factorization S_K S_K^T ~= T1 T2^T (Section 2.3, Theorem 1) at the
+    """Fast factorization S_K S_K^T ~= T1 T2^T (Section 1.3, Theorem 1) at the
     paper-scale size N = 65536, W = 1/8, eps = 1e-6, 256 signals: compression
     T2^T x (length-N DFT bins through the FFT passes plus [V U]^T x on the
     matrix cores) and recovery T1 c, in the bench's correction precision.
@@ -513,7 +513,7 @@ def bench_factorization(args, dev, check=None):
 
 
 def bench_coeffs(args, dev):
-    """Slepian coefficients c = S_K^T x (Section 2.3, the compression to K
+    """Slepian coefficients c = S_K^T x (Section 1.3, the compression to K
     numbers) at the paper-scale size N = 65536, W = 1/8 (K = 16384), 256
     signals: a plain GEMM on the matrix cores (hipBLASLt), FP32 for an FP32
     plan and three BF16 products of hi/lo halves for a mixed plan.  The first

@@ -3,7 +3,7 @@
  * fast Slepian transform of Karnik, Zhu, Wakin, Romberg and Davenport
  * ("The Fast Slepian Transform", arXiv:1611.04950).
  *
- * Notation (Section 2.1-2.2 of the paper): N signal length, W in (0, 1/2)
+ * Notation (Sections 1.1-1.2 of the paper): N signal length, W in (0, 1/2)
  * half bandwidth, B the N x N prolate matrix B[m,n] = sin(2 pi W (m-n)) /
  * (pi (m-n)) (diagonal 2W), lambda_0 > ... > lambda_{N-1} its eigenvalues,
  * S = [s_0 ... s_{N-1}] its orthonormal eigenvectors (the Slepian basis),
@@ -78,7 +78,7 @@ enum slepian_op {
 };
 
 typedef struct {
-  double alpha;     /* > 0: also prepare the Tikhonov set for this alpha (Lemma 7); 0: none */
+  double alpha;     /* > 0: also prepare the Tikhonov set for this alpha (Lemma 6); 0: none */
   int64_t K;        /* 0: K = round(2NW); else 1 <= K <= N-1 */
   int precision;    /* enum slepian_precision used by slepian_project */
   int device;       /* HIP device ordinal, -1: the current device */
@@ -89,14 +89,14 @@ typedef struct {
   double W, eps, alpha;
   int64_t K;
   int64_t L;            /* FFT length used for B x: smallest power of two >= 2N */
-  int64_t r;            /* |I2 u I3| = #{eps < lambda < 1-eps} (Lemma 5) */
+  int64_t r;            /* |I2 u I3| = #{eps < lambda < 1-eps} (Lemma 4) */
   int64_t l_first;      /* index l of the first transition vector */
-  int64_t r_tik;        /* #{alpha(1+alpha)eps < lambda < 1-eps/3} (Lemma 7), 0 if alpha == 0 */
+  int64_t r_tik;        /* #{alpha(1+alpha)eps < lambda < 1-eps/3} (Lemma 6), 0 if alpha == 0 */
   int64_t l_first_tik;
   int64_t window_lo, window_hi;  /* eigen-indices solved at setup (inclusive) */
   double lam_Km1, lam_K;         /* lambda_{K-1}, lambda_K */
   double eps_achieved;  /* max(1 - lambda over I1, lambda over I4) seen at the window edges,
-                           an upper bound on ||S_K S_K^T - (B + U diag(d) U^T)|| (Lemma 5) */
+                           an upper bound on ||S_K S_K^T - (B + U diag(d) U^T)|| (Lemma 4) */
   int precision;
   int device;
 } slepian_plan_info;
@@ -109,7 +109,7 @@ typedef struct {
 } slepian_lsq_report;
 
 /* Plan for length-N signals, half bandwidth W, tolerance eps, default options.
- * Setup (Section 2.3 "fast precomputation", Section 4.1): the spectrum of the
+ * Setup (Section 1.3 "fast precomputation", Section 4.1): the spectrum of the
  * circulant embedding of B's first column, and the Slepian vectors with
  * eps < lambda < 1-eps, from bisection and inverse iteration on the
  * tridiagonal matrix that commutes with B (Slepian 1978) in FP64 on the GPU,
@@ -159,7 +159,7 @@ int slepian_plan_destroy(slepian_plan_t plan);
 /* Workspace bytes needed by `op` on `batch` signals. */
 int slepian_workspace_size(slepian_plan_t plan, int op, int64_t batch, size_t *bytes);
 
-/* Fast projection onto span(S_K) (Corollary 2, Lemma 5; Section 2.3 "Fast
+/* Fast projection onto span(S_K) (Corollary 2, Lemma 4; Section 1.3 "Fast
  * projections onto the range of S_K"):
  *     y = B x + U diag(d) U^T x,
  * U = the transition vectors (eps < lambda < 1-eps), d = 1 - lambda for
@@ -176,7 +176,7 @@ int slepian_project_ex(slepian_plan_t plan, int precision, const float *x, int64
                        float *y, int64_t ldy, int64_t batch, void *work, size_t work_bytes,
                        void *stream);
 
-/* Projection onto a multiband (modulated Slepian) dictionary (Section 2.3:
+/* Projection onto a multiband (modulated Slepian) dictionary (Section 1.4:
  * the Slepian basis modulated to several frequency bands and merged): for
  * band centres freqs[i] (cycles/sample; 0 for the baseband band, otherwise
  * W <= f <= 1/2 - W; centres at least 2W apart, so the bands [f - W, f + W]
@@ -191,7 +191,7 @@ int slepian_project_ex(slepian_plan_t plan, int precision, const float *x, int64
 int slepian_project_multiband(slepian_plan_t plan, int nbands, const double *freqs, const float *x, int64_t ldx,
                               float *y, int64_t ldy, int64_t batch, void *work, size_t work_bytes, void *stream);
 
-/* Prepared band set for the same multiband projection (Section 2.3), computed
+/* Prepared band set for the same multiband projection (Section 1.4), computed
  * with one FFT product instead of one per band.  For real x,
  * Re(E_f B E_f^* x) is the Toeplitz product with the kernel
  * cos(2 pi f m) sin(2 pi W m)/(pi m), so the bands' B parts add up to one real
@@ -213,7 +213,7 @@ int slepian_bands_workspace_size(slepian_bands_t bands, int64_t batch, size_t *b
 int slepian_project_bands(slepian_bands_t bands, const float *x, int64_t ldx, float *y, int64_t ldy,
                           int64_t batch, void *work, size_t work_bytes, void *stream);
 
-/* Fast factorization S_K S_K^T ~= T1 T2^T (Section 2.3, "A fast
+/* Fast factorization S_K S_K^T ~= T1 T2^T (Section 1.3, "A fast
  * factorization", with Theorem 1):
  *     T1 = [F, V diag(mu), U diag(d)],   T2 = [F, V, U],
  * F the partial DFT matrix of the 2NW' lowest length-N frequencies (2NW' =
@@ -263,7 +263,7 @@ int slepian_factor_compress(slepian_factor_t f, const float *x, int64_t ldx, flo
 int slepian_factor_recover(slepian_factor_t f, const float *c, int64_t ldc, float *y, int64_t ldy, int64_t batch,
                            void *work, size_t work_bytes, void *stream);
 
-/* Slepian coefficients c = S_K^T x (Section 2.3, "A fast factorization":
+/* Slepian coefficients c = S_K^T x (Section 1.3, "A fast factorization":
  * the K numbers that represent x), exact (dense) semantics.  The first call
  * computes all K Slepian vectors on the GPU and keeps them in the plan
  * (N*K*4 bytes, plus as many again for their BF16 hi/lo halves in plans of
@@ -276,7 +276,7 @@ int slepian_factor_recover(slepian_factor_t f, const float *c, int64_t ldc, floa
 int slepian_coeffs(slepian_plan_t plan, const float *x, int64_t ldx, float *c, int64_t ldc,
                    int64_t batch, void *work, size_t work_bytes, void *stream);
 
-/* Least squares with the prolate matrix (Section 2.3):
+/* Least squares with the prolate matrix (Section 1.3):
  *   SLEPIAN_PINV:      x = B_K^+ y ~= B y + U diag(1/lambda - lambda | -lambda) U^T y
  *                      (Corollary 3, error <= 3 eps ||y||); single pass, tol and
  *                      max_iter ignored.  B y is the FP32 product; the

@@ -20,11 +20,19 @@ Readings of points the paper leaves open:
   * Individual Slepian vectors are signed so that the first entry whose
     magnitude is >= 1e-3 of the vector's largest magnitude is positive.
   * The fast Tikhonov operator is (1/(1+alpha)) B + U5 U5^T (Corollary 4 and
-    Lemma 7); the short restatement in Section 2.3 drops the 1/(1+alpha).
+    Lemma 6); the short restatement in Section 1.3 drops the 1/(1+alpha).
   * The Slepian vectors of large N are computed from the symmetric
     tridiagonal matrix that commutes with B (Slepian 1978, cited by the paper
     as its source for the DPSS); the paper does not print that matrix.  At
     small N the tests pin it against the dense eigendecomposition of B.
+  * The projection onto a multiband (modulated Slepian) dictionary, which
+    Section 1.4 names without an algorithm, is the orthogonal projection
+    onto the span of the modulated bases E_f S_K over the bands' centres
+    +-f_i.  It is computed by conjugate gradients on the sum of the bands'
+    fast projections (multiband_projection), stopped per signal once the
+    residual falls to eps; the plain sum of the bands' projections
+    (multiband_fast) is a separate operator, which differs from the
+    projection by the subspaces' overlap.
 
 Parity status: every public function below is pinned by tests in
 tests/test_oracle_pins.py against closed forms, brute force, invariants the
@@ -46,8 +54,8 @@ __all__ = [
     "transition_plan", "partition", "projection_d", "pinv_d", "tikhonov_g",
     "project_exact", "project_fast", "pinv_exact", "pinv_threshold", "pinv_fast",
     "tikhonov_exact", "tikhonov_fast", "tikhonov_cg", "coeffs_exact", "multiband_fast", "multiband_exact",
-    "multiband_sum_exact",
-    "cor1_bound", "zhu_wakin_bound", "asymptotic_count", "sign_fix",
+    "multiband_sum_exact", "multiband_projection",
+    "cor1_bound", "asymptotic_count", "sign_fix",
 ]
 
 
@@ -70,8 +78,8 @@ def choose_K(N: int, W: float) -> int:
 
 
 # ---------------------------------------------------------------------------
-# The prolate matrix and its product with a vector (Section 2.2, eq. Prolate
-# matrix; Section 2.3 and Section 4.1 for the FFT product)
+# The prolate matrix and its product with a vector (Section 1.2, eq. Prolate
+# matrix; Section 1.3 and Section 4.1 for the FFT product)
 # ---------------------------------------------------------------------------
 
 def _sinc_values(k: np.ndarray, W: float) -> np.ndarray:
@@ -87,7 +95,7 @@ def _sinc_values(k: np.ndarray, W: float) -> np.ndarray:
 
 def prolate_matrix(N: int, W: float) -> np.ndarray:
     """Dense B[m, n] = sin(2 pi W (m - n)) / (pi (m - n)), diagonal 2W
-    (Section 2.2, eq. Prolate matrix)."""
+    (Section 1.2, eq. Prolate matrix)."""
     idx = np.arange(N)
     return _sinc_values(idx[:, None] - idx[None, :], W)
 
@@ -119,7 +127,7 @@ def kernel_spectrum(N: int, W: float, L: int | None = None) -> np.ndarray:
 
 def apply_prolate(N: int, W: float, x: np.ndarray, L: int | None = None) -> np.ndarray:
     """B x by zero padding to length L, FFT, multiply, inverse FFT, keep the
-    first N outputs (Section 2.3 "Fast projections", Section 4.1)."""
+    first N outputs (Section 1.3 "Fast projections", Section 4.1)."""
     x = np.asarray(x, dtype=np.float64)
     if L is None:
         L = fft_length(N)
@@ -138,7 +146,7 @@ def apply_prolate_dense(N: int, W: float, x: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Slepian basis (Definitions 1 and 2; Section 2.2: B = S Lambda S^*)
+# Slepian basis (Definitions 1 and 2; Section 1.2: B = S Lambda S^*)
 # ---------------------------------------------------------------------------
 
 def sign_fix(S: np.ndarray) -> np.ndarray:
@@ -163,7 +171,7 @@ def sign_fix(S: np.ndarray) -> np.ndarray:
 
 def dense_eig(N: int, W: float):
     """Eigen-decomposition of dense B with eigenvalues sorted descending
-    (Section 2.2).  Returns (lam, S) with S[:, l] the l-th Slepian vector."""
+    (Section 1.2).  Returns (lam, S) with S[:, l] the l-th Slepian vector."""
     lam, V = np.linalg.eigh(prolate_matrix(N, W))
     order = np.argsort(lam)[::-1]
     return lam[order], sign_fix(V[:, order])
@@ -208,18 +216,13 @@ def slepian_vectors(N: int, W: float, lo: int, hi: int, L: int | None = None):
 
 def asymptotic_count(N: int, eps: float) -> float:
     """(2/pi^2) log N log(1/eps - 1), the asymptotic number of eigenvalues in
-    [eps, 1-eps] (Section 2.2, eq. asymptotic)."""
+    [eps, 1-eps] (Section 1.2, eq. asymptotic)."""
     return 2.0 / np.pi ** 2 * math.log(N) * math.log(1.0 / eps - 1.0)
 
 
 def cor1_bound(N: int, eps: float) -> float:
     """Corollary 1: #{eps < lambda < 1-eps} <= (8/pi^2 log 8N + 12) log(15/eps)."""
     return (8.0 / np.pi ** 2 * math.log(8 * N) + 12.0) * math.log(15.0 / eps)
-
-
-def zhu_wakin_bound(N: int, eps: float) -> float:
-    """The earlier nonasymptotic bound quoted in Section 2.2."""
-    return (2.0 / np.pi ** 2 * math.log(N - 1) + 2.0 / np.pi ** 2 * (2 * N - 1) / (N - 1)) / (eps * (1 - eps))
 
 
 def transition_plan(N: int, W: float, thr_lo: float, thr_hi: float,
@@ -257,11 +260,11 @@ def transition_plan(N: int, W: float, thr_lo: float, thr_hi: float,
 
 # ---------------------------------------------------------------------------
 # Eigenvalue partition and the diagonal weights of the low-rank corrections
-# (Lemma 5, Lemma 6, Lemma 7 in the appendix proofs of Corollaries 2-4)
+# (Lemma 4, Lemma 5, Lemma 6 in Section 3, the proofs of Corollaries 2-4)
 # ---------------------------------------------------------------------------
 
 def partition(lam: np.ndarray, ells: np.ndarray, K: int, eps: float):
-    """The sets I1..I4 of Lemma 5: I1 = {lambda >= 1-eps},
+    """The sets I1..I4 of Lemma 4: I1 = {lambda >= 1-eps},
     I2 = {l < K, eps < lambda < 1-eps}, I3 = {l >= K, eps < lambda < 1-eps},
     I4 = {lambda <= eps}.  Returns four boolean masks over `ells`."""
     lam = np.asarray(lam)
@@ -271,7 +274,7 @@ def partition(lam: np.ndarray, ells: np.ndarray, K: int, eps: float):
 
 
 def projection_d(lam, ells, K, eps):
-    """d for S_K S_K^T ~= B + U diag(d) U^T over I2 u I3 (Lemma 5):
+    """d for S_K S_K^T ~= B + U diag(d) U^T over I2 u I3 (Lemma 4):
     d = 1 - lambda on I2, d = -lambda on I3 (U1 U2^* written as U diag(d) U^T)."""
     _, i2, i3, _ = partition(lam, ells, K, eps)
     d = np.zeros_like(np.asarray(lam, dtype=np.float64))
@@ -281,7 +284,7 @@ def projection_d(lam, ells, K, eps):
 
 
 def pinv_d(lam, ells, K, eps):
-    """d for B_K^+ ~= B + U diag(d) U^T over I2 u I3 (Lemma 6):
+    """d for B_K^+ ~= B + U diag(d) U^T over I2 u I3 (Lemma 5):
     d = 1/lambda - lambda on I2, d = -lambda on I3."""
     _, i2, i3, _ = partition(lam, ells, K, eps)
     d = np.zeros_like(np.asarray(lam, dtype=np.float64))
@@ -291,7 +294,7 @@ def pinv_d(lam, ells, K, eps):
 
 
 def tikhonov_g(lam, alpha, eps):
-    """g for (B^2 + alpha I)^-1 B ~= B/(1+alpha) + U diag(g) U^T (Lemma 7):
+    """g for (B^2 + alpha I)^-1 B ~= B/(1+alpha) + U diag(g) U^T (Lemma 6):
     g = lambda/(lambda^2 + alpha) - lambda/(1+alpha) on the set
     {alpha(1+alpha) eps < lambda < 1 - eps/3}."""
     lam = np.asarray(lam, dtype=np.float64)
@@ -302,11 +305,11 @@ def tikhonov_g(lam, alpha, eps):
 
 
 # ---------------------------------------------------------------------------
-# Exact operators (dense; Section 2.3 problem statements)
+# Exact operators (dense; Section 1.3 problem statements)
 # ---------------------------------------------------------------------------
 
 def project_exact(N: int, W: float, x: np.ndarray, K: int | None = None) -> np.ndarray:
-    """S_K S_K^T x from the dense eigendecomposition (Section 2.3)."""
+    """S_K S_K^T x from the dense eigendecomposition (Section 1.3)."""
     if K is None:
         K = choose_K(N, W)
     _, S = dense_eig(N, W)
@@ -315,7 +318,7 @@ def project_exact(N: int, W: float, x: np.ndarray, K: int | None = None) -> np.n
 
 
 def coeffs_exact(N: int, W: float, x: np.ndarray, K: int | None = None) -> np.ndarray:
-    """S_K^T x, the K Slepian coefficients (Section 2.3, "A fast factorization"),
+    """S_K^T x, the K Slepian coefficients (Section 1.3, "A fast factorization"),
     with the oracle's sign convention on each Slepian vector.
 
     The vectors come from the tridiagonal route: inside the clusters of
@@ -330,7 +333,7 @@ def coeffs_exact(N: int, W: float, x: np.ndarray, K: int | None = None) -> np.nd
 
 
 def pinv_exact(N: int, W: float, y: np.ndarray, K: int | None = None) -> np.ndarray:
-    """Rank-K truncated pseudoinverse B_K^+ y = S_K Lambda_K^-1 S_K^T y (Lemma 6)."""
+    """Rank-K truncated pseudoinverse B_K^+ y = S_K Lambda_K^-1 S_K^T y (Lemma 5)."""
     if K is None:
         K = choose_K(N, W)
     lam, S = dense_eig(N, W)
@@ -342,7 +345,7 @@ def pinv_exact(N: int, W: float, y: np.ndarray, K: int | None = None) -> np.ndar
 
 def pinv_threshold(N: int, W: float, y: np.ndarray, thr: float) -> tuple[np.ndarray, int]:
     """The truncated pseudoinverse that drops the eigenvalues below thr (the
-    Fourier-extension experiment of Section 4.3): rank K = #{lambda >= thr},
+    Fourier-extension experiment of Section 4.2): rank K = #{lambda >= thr},
     B_K^+ y = S_K Lambda_K^-1 S_K^T y.  Returns (B_K^+ y, K)."""
     lam, _ = dense_eig(N, W)
     K = int((lam >= thr).sum())
@@ -350,7 +353,7 @@ def pinv_threshold(N: int, W: float, y: np.ndarray, thr: float) -> tuple[np.ndar
 
 
 def tikhonov_exact(N: int, W: float, alpha: float, y: np.ndarray) -> np.ndarray:
-    """(B^2 + alpha I)^-1 B y by a dense solve (Section 2.3, Tikhonov)."""
+    """(B^2 + alpha I)^-1 B y by a dense solve (Section 1.3, Tikhonov)."""
     B = prolate_matrix(N, W)
     G = B @ B + alpha * np.eye(N)
     return np.linalg.solve(G, B @ np.asarray(y, dtype=np.float64))
@@ -385,7 +388,7 @@ def tikhonov_cg(N: int, W: float, alpha: float, y: np.ndarray, tol: float = 1e-1
 
 
 # ---------------------------------------------------------------------------
-# Fast operators (Corollaries 2, 3, 4; Section 2.3)
+# Fast operators (Corollaries 2, 3, 4; Section 1.3)
 # ---------------------------------------------------------------------------
 
 def _lowrank(S, d, x):
@@ -397,7 +400,7 @@ def _lowrank(S, d, x):
 def project_fast(N: int, W: float, eps: float, x: np.ndarray, K: int | None = None,
                  tp: dict | None = None) -> np.ndarray:
     """B x + U1 U2^T x, the fast projection onto the span of S_K (Corollary 2,
-    Lemma 5): U1 U2^T = U_T diag(d) U_T^T over the eigenvalues in (eps, 1-eps)."""
+    Lemma 4): U1 U2^T = U_T diag(d) U_T^T over the eigenvalues in (eps, 1-eps)."""
     if tp is None:
         tp = transition_plan(N, W, eps, 1 - eps, K)
     K = tp["K"]
@@ -408,7 +411,7 @@ def project_fast(N: int, W: float, eps: float, x: np.ndarray, K: int | None = No
 
 def pinv_fast(N: int, W: float, eps: float, y: np.ndarray, K: int | None = None,
               tp: dict | None = None) -> np.ndarray:
-    """B y + U3 U4^T y, the fast truncated pseudoinverse (Corollary 3, Lemma 6)."""
+    """B y + U3 U4^T y, the fast truncated pseudoinverse (Corollary 3, Lemma 5)."""
     if tp is None:
         tp = transition_plan(N, W, eps, 1 - eps, K)
     K = tp["K"]
@@ -420,7 +423,7 @@ def pinv_fast(N: int, W: float, eps: float, y: np.ndarray, K: int | None = None,
 def tikhonov_fast(N: int, W: float, eps: float, alpha: float, y: np.ndarray,
                   tp: dict | None = None) -> np.ndarray:
     """B y / (1+alpha) + U5 U5^T y, the fast Tikhonov operator (Corollary 4,
-    Lemma 7), with U5 = V diag(sqrt(g))."""
+    Lemma 6), with U5 = V diag(sqrt(g))."""
     if tp is None:
         tp = transition_plan(N, W, alpha * (1 + alpha) * eps, 1 - eps / 3.0)
     g, sel = tikhonov_g(tp["lam"], alpha, eps)
@@ -428,7 +431,7 @@ def tikhonov_fast(N: int, W: float, eps: float, alpha: float, y: np.ndarray,
 
 
 # ---------------------------------------------------------------------------
-# Multiband (modulated Slepian) dictionaries (Section 2.3)
+# Multiband (modulated Slepian) dictionaries (Section 1.4)
 # ---------------------------------------------------------------------------
 
 def _band_weight(f: float) -> float:
@@ -455,7 +458,7 @@ def multiband_fast(N: int, W: float, eps: float, freqs, x: np.ndarray, tp: dict 
 
 def multiband_exact(N: int, W: float, freqs, x: np.ndarray, K: int | None = None) -> np.ndarray:
     """Orthogonal projection of a real x onto the span of the modulated
-    Slepian bases E_f S_K, f in {+-f_i} (dense; Section 2.3's merged
+    Slepian bases E_f S_K, f in {+-f_i} (dense; Section 1.4's merged
     dictionary)."""
     if K is None:
         K = choose_K(N, W)
@@ -487,3 +490,57 @@ def multiband_sum_exact(N: int, W: float, freqs, x: np.ndarray, K: int | None = 
         e = np.exp(2j * np.pi * f * n)[:, None]
         y += _band_weight(f) * (e * (SK @ (SK.T @ (np.conj(e) * x)))).real
     return y
+
+
+def multiband_projection(N: int, W: float, eps: float, freqs, x: np.ndarray, tol: float | None = None,
+                         max_iter: int = 50, tp: dict | None = None, operator=None):
+    """Orthogonal projection of a real x onto the span of the modulated
+    Slepian dictionary {E_f S_K : f in +-f_i} (Section 1.4, application i),
+    by conjugate gradients on the band-sum operator
+    A = sum_i w_i Re(E_i P~ E_i^* .) (multiband_fast; P~ the fast projection
+    of Corollary 2).
+
+    With exact projections P_f, A is the sum of the orthogonal projections
+    onto the dictionary's subspaces: symmetric, positive semidefinite, with
+    range equal to their span.  CG on A z = A x from z = 0 keeps its iterates
+    in the Krylov space of A x, inside that range, and its solution there is
+    the orthogonal projection of x onto the span.  With the fast P~ the
+    complement of the span carries eigenvalues of A of size at most about
+    eps rather than 0, so the iteration stops per signal at the first step
+    whose residual ||A x - A z|| is at most tol ||A x|| (default tol = eps),
+    before it starts to resolve them.  `operator` replaces A (for tests).
+    Returns (z, iterations per signal)."""
+    if tol is None:
+        tol = eps
+    x = np.asarray(x, dtype=np.float64)
+    X = x if x.ndim == 2 else x[:, None]
+    if operator is None:
+        if tp is None:
+            tp = transition_plan(N, W, eps, 1 - eps)
+
+        def operator(v):
+            return multiband_fast(N, W, eps, freqs, v, tp=tp)
+    b = operator(X)
+    z = np.zeros_like(X)
+    r = b.copy()
+    p = r.copy()
+    rr = np.einsum("ns,ns->s", r, r)
+    nb = np.sqrt(rr)
+    active = np.sqrt(rr) > tol * nb
+    iters = np.zeros(X.shape[1], dtype=np.int64)
+    for _ in range(max_iter):
+        if not active.any():
+            break
+        Ap = operator(p)
+        pAp = np.einsum("ns,ns->s", p, Ap)
+        a = np.where(active, rr / np.where(active, pAp, 1.0), 0.0)
+        z += a * p
+        r -= a * Ap
+        rr_new = np.einsum("ns,ns->s", r, r)
+        beta = np.where(active, rr_new / np.where(active, rr, 1.0), 0.0)
+        p = np.where(active, r + beta * p, p)
+        rr = np.where(active, rr_new, rr)
+        iters += active
+        active = active & (np.sqrt(rr) > tol * nb)
+    return (z if x.ndim == 2 else z[:, 0]), iters
+

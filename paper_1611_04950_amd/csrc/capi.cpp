@@ -725,7 +725,7 @@ void eig_finalize(Plan *P, EigState &E, hipStream_t st) {
       u1 = t1;
     }
   }
-  // Lemma 5's error: max(1 - lambda over I1, lambda over I4), seen at the set edges
+  // Lemma 4's error: max(1 - lambda over I1, lambda over I4), seen at the set edges
   double ea = 0.0;
   if (p0 > 0) ea = std::max(ea, 1.0 - lam[p0 - 1]);
   if (p1 < nv) ea = std::max(ea, lam[p1]);
@@ -742,7 +742,7 @@ void eig_finalize(Plan *P, EigState &E, hipStream_t st) {
   HIPCHK(hipStreamSynchronize(st));
   dfree(E.V);
   E.V = nullptr;
-  // weights of the low-rank corrections (Lemmas 5, 6, 7)
+  // weights of the low-rank corrections (Lemmas 4, 5, 6)
   const double al = P->alpha;
   P->proj.off = P->pinv.off = p0 - u0;
   P->proj.r = P->pinv.r = p1 - p0;
@@ -1271,7 +1271,7 @@ int slepian_project_bands(slepian_bands_t B, const float *x, int64_t ldx, float 
 }
 
 // ---------------------------------------------------------------------------
-// Fast factorization S_K S_K^T ~= T1 T2^T (Section 2.3, Theorem 1)
+// Fast factorization S_K S_K^T ~= T1 T2^T (Section 1.3, Theorem 1)
 // ---------------------------------------------------------------------------
 
 struct slepian_factor_s {

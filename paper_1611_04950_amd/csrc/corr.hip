@@ -1,4 +1,4 @@
-// The pseudoinverse's low-rank correction in FP64 (Corollary 3, Lemma 6):
+// The pseudoinverse's low-rank correction in FP64 (Corollary 3, Lemma 5):
 //     x += U diag(d) U^T y,  d = 1/lambda - lambda on I2, -lambda on I3.
 // The weights 1/lambda reach 1/eps at the edge of the transition set, so
 // rounding in U^T y is amplified by up to that factor; the product runs in

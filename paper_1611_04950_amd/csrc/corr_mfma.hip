@@ -1,4 +1,4 @@
-// Low-rank correction on the matrix cores (Corollaries 2-4, Lemmas 5-7):
+// Low-rank correction on the matrix cores (Corollaries 2-4, Lemmas 4-6):
 //     C = U^T X  (r x N by N x b),   dC = d (.) C,   Y += U dC.
 //
 // The product C = U^T X is split over chunks of samples; each wavefront owns

@@ -1,7 +1,7 @@
 // FP64 setup kernels: the Slepian vectors of the transition region.
 //
 // The paper precomputes the Slepian vectors whose eigenvalues lie in
-// (eps, 1 - eps) (Section 2.3, "fast precomputation"; Section 4.1) and cites
+// (eps, 1 - eps) (Section 1.3, "fast precomputation"; Section 4.1) and cites
 // Slepian 1978 for the DPSS.  There, the DPSS are also the eigenvectors of a
 // symmetric tridiagonal matrix T that commutes with B:
 //     T[n,n]   = ((N-1)/2 - n)^2 cos(2 pi W),   n = 0..N-1

@@ -1,4 +1,4 @@
-// Pieces of the fast factorization S_K S_K^T ~= T1 T2^T (Section 2.3, built
+// Pieces of the fast factorization S_K S_K^T ~= T1 T2^T (Section 1.3, built
 // on Theorem 1) that are not FFT passes: the Toeplitz kernel of B - F F^*
 // for the setup, the random start block of its subspace iteration, a column
 // sign convention, and the conversion between the FFT's packed pair bins and

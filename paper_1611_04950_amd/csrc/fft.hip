@@ -1,11 +1,11 @@
 // FFT-based product y = beta * B x + gamma * x (+ optional low-rank correction)
 // for gfx950.
 //
-// B is the N x N prolate (sinc) Toeplitz matrix (Section 2.2, eq. Prolate
+// B is the N x N prolate (sinc) Toeplitz matrix (Section 1.2, eq. Prolate
 // matrix).  Its product with a vector is a linear convolution with the sinc
 // sequence, computed as a length-L circular convolution of the zero-padded
 // signal with the circulant embedding of B's first column, L the smallest
-// power of two >= 2N (Section 2.3 "Fast projections", Section 4.1).  Two real
+// power of two >= 2N (Section 1.3 "Fast projections", Section 4.1).  Two real
 // signals share one complex transform (x1 + i x2): the embedded kernel is real
 // and even, so its spectrum is real and the real and imaginary parts of the
 // result are B x1 and B x2 exactly.

@@ -1090,7 +1090,7 @@ hipError_t conv_apply_v2(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, 
   return hipGetLastError();
 }
 
-// ---- length-N DFT bins for the fast factorization (Section 2.3) ----
+// ---- length-N DFT bins for the fast factorization (Section 1.3) ----
 //
 // With L = 2N, bin K = 2k of the length-L transform of the zero-padded pair
 // z = x1 + i x2 is bin k of its length-N transform.  The bins kept are

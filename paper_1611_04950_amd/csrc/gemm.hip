@@ -1,4 +1,4 @@
-// Slepian coefficients c = S_K^T x (Section 2.3, the compression S_K^* x) as a
+// Slepian coefficients c = S_K^T x (Section 1.3, the compression S_K^* x) as a
 // plain library GEMM on the matrix cores.  S_K is N x K column-major (every
 // Slepian vector contiguous) and x is N x b column-major, so both operands
 // run along the reduction index n:

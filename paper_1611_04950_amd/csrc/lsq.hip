@@ -1,5 +1,5 @@
 // Elementwise and reduction helpers of the least-squares refinement
-// (Section 2.3 "Fast Tikhonov regularization"): the FP64 residual of the
+// (Section 1.3 "Fast Tikhonov regularization"): the FP64 residual of the
 // regularised normal equations (B^2 + alpha I) x = B y and its norms.
 #include "common.h"
 #include "kernels.h"

@@ -1,4 +1,4 @@
-// Multiband (modulated) Slepian dictionaries (Section 2.3): the projection of
+// Multiband (modulated) Slepian dictionaries (Section 1.4): the projection of
 // a real signal onto the union of the Slepian subspaces modulated to band
 // centres f_i, each band [f_i - W, f_i + W], approximated by the sum of the
 // per-band fast projections

@@ -2,8 +2,8 @@
 
 The Fourier extension of a function y on [-1, 1] to a 2T-periodic function
 with 2M + 1 terms solves the normal equations F F^* g = F y, and F F^* is
-the prolate matrix B with N = 2M + 1 and W = 1/(2T) (Section 2.3, the
-least-squares applications).  Its experiment (Section 4.3) solves them with
+the prolate matrix B with N = 2M + 1 and W = 1/(2T) (Section 1.4, the
+least-squares applications).  Its experiment (Section 4.2) solves them with
 the truncated pseudoinverse that drops eigenvalues below 1e-4, or with
 Tikhonov regularisation, and with the fast operators of Corollaries 3 and 4
 (tolerance eps) in their place.

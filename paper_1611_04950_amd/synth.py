@@ -90,8 +90,8 @@ def batching_plans(n_plans: int = 512, seed: int = 4000):
 
 
 # ---------------------------------------------------------------------------
-# Fourier extension (the least-squares application of Section 2.3 and its
-# experiment in Section 4.3): a function on [-1, 1], the right-hand side
+# Fourier extension (the least-squares application of Section 1.4 and its
+# experiment in Section 4.2): a function on [-1, 1], the right-hand side
 # F y of the normal equations F F^* g = F y (F F^* = B with N = 2M + 1 and
 # W = 1/(2T)), and the evaluation of a coefficient vector as a 2T-periodic
 # series.  Input preparation and error measurement on the host in FP64; the

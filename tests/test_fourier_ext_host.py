@@ -1,5 +1,5 @@
-"""Host checks of the Fourier-extension workload (Section 2.3 applications,
-Section 4.3 experiment): the oracle's threshold pseudoinverse against an
+"""Host checks of the Fourier-extension workload (Section 1.4 applications,
+Section 4.2 experiment): the oracle's threshold pseudoinverse against an
 independent library routine, and the input preparation (quadrature of the
 right-hand side, evaluation of a series) against closed forms and direct
 sums, with the convention F F^* = B pinned by recovering a function of the

@@ -1,4 +1,4 @@
-"""The eigenvalue-gap study (Section 2.2, Figure 1) on the GPU plans: the
+"""The eigenvalue-gap study (Section 1.2, Figure 1) on the GPU plans: the
 number of eigenvalues of B in (eps, 1-eps) that a plan selects equals the
 oracle's count (integer, exact), stays under Corollary 1's bound, and grows
 with log N and log(1/eps - 1) like the asymptotic count.  Both sides decide

@@ -1,4 +1,4 @@
-"""Fast factorization S_K S_K^T ~= T1 T2^T on the GPU (Section 2.3 "A fast
+"""Fast factorization S_K S_K^T ~= T1 T2^T on the GPU (Section 1.3 "A fast
 factorization", Theorem 1) against the FP64 oracle in oracle/factorization.py.
 
 Compared element by element on the same seeded FP32 inputs:
@@ -51,7 +51,7 @@ def _prec(name):
 def _oracle(N, W, eps):
     key = (N, W, eps)
     if key not in _FAC:
-        _FAC[key] = fz.fast_factorization(N, W, eps)
+        _FAC[key] = fz.fast_factorization(N, W, eps, method="eig")
     return _FAC[key]
 
 
@@ -194,7 +194,7 @@ def test_factorization_random_configs():
         prec = str(rng.choice(["fp32", "mixed"]))
         print(f"random factorization case {i}: N={N} W={W:.4f} eps={eps:g} b={b} {prec}", flush=True)
         P, F = _setup(N, W, eps, prec)
-        fac = fz.fast_factorization(N, W, eps)
+        fac = fz.fast_factorization(N, W, eps, method="eig")
         assert F.info["kf"] == fac["kf"]
         _check_r1(F, fac, eps)
         x = _x(N, b, 500 + i)

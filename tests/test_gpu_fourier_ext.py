@@ -1,5 +1,5 @@
-"""The Fourier-extension workload on the GPU (Section 2.3 applications,
-Section 4.3 experiment): 2M + 1 coefficients of a 2T-periodic extension
+"""The Fourier-extension workload on the GPU (Section 1.4 applications,
+Section 4.2 experiment): 2M + 1 coefficients of a 2T-periodic extension
 (T = 1.5, N = 2M + 1, W = 1/3) of a continuous, non-smooth, non-periodic
 function, solved with the library's fast pseudoinverse (Corollary 3, eps =
 1e-5, rank K = #{lambda >= 1e-4}) and fast Tikhonov operator (Corollary 4,

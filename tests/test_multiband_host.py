@@ -1,5 +1,7 @@
 """Oracle pins for the multiband (modulated Slepian) dictionaries (Section
-2.3): the band-by-band fast sum reduces to the fast projection for the
+1.4, application i): the orthogonal projection onto the dictionary's span by
+conjugate gradients on the band-sum operator (against the dense union
+projection, with exact and with fast per-band projections); the band-by-band fast sum reduces to the fast projection for the
 baseband band alone and matches the dense per-band sum within the bands'
 eps; the dense union projection is an orthogonal projector that keeps the
 dictionary's span; the sum differs from the union projection by the
@@ -60,6 +62,89 @@ def test_sum_versus_union_projection_coherence():
     ye = o.multiband_exact(N, W, BANDS, x)
     dev = np.linalg.norm(yf - ye) / np.linalg.norm(ye)
     assert 1e-4 < dev < 3e-2
+
+
+# ---------------------------------------------------------------------------
+# The projection onto the span by conjugate gradients on the band-sum operator
+# ---------------------------------------------------------------------------
+
+SPAN_CASES = [
+    (512, 1 / 32, [0.0, 0.125, 0.25, 0.375], 1e-6),
+    (512, 1 / 32, [0.0, 1 / 16, 2 / 16, 3 / 16], 1e-6),      # adjacent bands
+    (1024, 1 / 64, [1 / 64, 3 / 64, 5 / 64, 7 / 64, 9 / 64], 1e-3),
+    (1000, 1 / 40, [0.1, 0.2, 0.3, 0.4, 0.475], 1e-9),
+    (768, 1 / 16, [1 / 16, 3 / 16], 1e-6),
+]
+
+
+@pytest.mark.parametrize("n,w,freqs", [(c[0], c[1], c[2]) for c in SPAN_CASES[:4]])
+def test_span_cg_with_exact_projections_reaches_the_union_projection(n, w, freqs):
+    """With the band sum of the dense projections S_K S_K^T as the operator,
+    CG from z = 0 converges to the orthogonal projection onto the span (the
+    QR route of multiband_exact), to rounding."""
+    x = np.random.default_rng(11).standard_normal((n, 3))
+    z, it = o.multiband_projection(n, w, 1e-6, freqs, x, tol=1e-12, max_iter=80,
+                                   operator=lambda v: o.multiband_sum_exact(n, w, freqs, v))
+    ref = o.multiband_exact(n, w, freqs, x)
+    assert np.linalg.norm(z - ref, axis=0).max() <= 1e-9 * np.linalg.norm(x, axis=0).max()
+    assert it.max() < 80
+
+
+@pytest.mark.parametrize("n,w,freqs,eps", SPAN_CASES)
+def test_span_cg_with_fast_projections_within_eps(n, w, freqs, eps):
+    """With the fast operator and tol = eps the result lies within a few eps
+    (relative to ||x||) of the orthogonal projection onto the span, its
+    residual x - z is orthogonal to every modulated Slepian vector to the
+    same level, and it stops within 25 steps."""
+    x = np.random.default_rng(12).standard_normal((n, 3))
+    z, it = o.multiband_projection(n, w, eps, freqs, x)
+    ref = o.multiband_exact(n, w, freqs, x)
+    xn = np.linalg.norm(x, axis=0)
+    J = sum(2 if f > 0 else 1 for f in freqs)
+    assert (np.linalg.norm(z - ref, axis=0) / xn).max() <= 2 * J * eps
+    assert it.max() <= 25 and it.min() >= 1
+    _, S = o.dense_eig(n, w)
+    SK = S[:, :o.choose_K(n, w)]
+    t = np.arange(n)
+    for f in freqs:
+        e = np.exp(2j * np.pi * f * t)[:, None]
+        g = SK.T @ (np.conj(e) * (x - z))
+        assert (np.linalg.norm(g, axis=0) / xn).max() <= 2 * J * eps
+    # the band sum alone is much farther from the projection
+    yb = o.multiband_fast(n, w, eps, freqs, x)
+    assert (np.linalg.norm(yb - ref, axis=0) / xn).max() > 10 * (np.linalg.norm(z - ref, axis=0) / xn).max()
+
+
+def test_span_cg_of_a_dictionary_vector_is_itself():
+    n, w, freqs = 512, 1 / 32, [0.0, 0.25]
+    _, S = o.dense_eig(n, w)
+    SK = S[:, :o.choose_K(n, w)]
+    t = np.arange(n)
+    c = np.random.default_rng(5).standard_normal(SK.shape[1])
+    v = SK @ c + 2 * (np.exp(2j * np.pi * 0.25 * t) * (SK @ c)).real
+    z, _ = o.multiband_projection(n, w, 1e-6, freqs, v)
+    assert np.linalg.norm(z - v) <= 1e-5 * np.linalg.norm(v)
+
+
+def test_planted_cg_mistakes_are_caught(monkeypatch):
+    """A wrong sign in the direction update, or a start at z = x, fails the
+    exact-projection pin above."""
+    n, w, freqs = 512, 1 / 32, [0.0, 1 / 16, 2 / 16]
+    x = np.random.default_rng(11).standard_normal((n, 2))
+    ref = o.multiband_exact(n, w, freqs, x)
+    opx = lambda v: o.multiband_sum_exact(n, w, freqs, v)  # noqa: E731
+    src = o.multiband_projection.__code__
+    import types
+    for old, new in (("p = np.where(active, r + beta * p, p)", "p = np.where(active, r - beta * p, p)"),
+                     ("z = np.zeros_like(X)", "z = X.copy()")):
+        import inspect
+        code = inspect.getsource(o.multiband_projection)
+        assert old in code
+        ns = {}
+        exec(compile(code.replace(old, new), "<planted>", "exec"), o.__dict__.copy(), ns)
+        z, _ = ns["multiband_projection"](n, w, 1e-6, freqs, x, tol=1e-12, max_iter=80, operator=opx)
+        assert np.linalg.norm(z - ref, axis=0).max() > 1e-6 * np.linalg.norm(x, axis=0).max()
+    assert src is o.multiband_projection.__code__
 
 
 def test_bad_bands_rejected_before_device_work():

@@ -1,4 +1,4 @@
-"""Pins of the fast-factorization oracle (Section 2.3 "A fast factorization",
+"""Pins of the fast-factorization oracle (Section 1.3 "A fast factorization",
 Theorem 1): each function is checked against something other than itself,
 namely closed forms, numpy's FFT, dense eigendecomposition, and the error
 and rank bounds the paper proves."""
@@ -27,7 +27,7 @@ def test_kf_is_nearest_odd_integer():
 @pytest.mark.parametrize("N,W", [(64, 0.1), (256, 1 / 8), (300, 0.21)])
 def test_fr_is_orthonormal_and_spans_the_dirichlet_projection(N, W):
     """F_r^T F_r = I and F_r F_r^T equals F F^*, whose entries are the
-    Dirichlet kernel sin(pi kf (m-n)/N) / (N sin(pi (m-n)/N)) (Section 2.2)."""
+    Dirichlet kernel sin(pi kf (m-n)/N) / (N sin(pi (m-n)/N)) (Section 1.2)."""
     kf = fz.kf_count(N, W)
     F = fz.fr_matrix(N, kf)
     np.testing.assert_allclose(F.T @ F, np.eye(kf), atol=1e-12)
@@ -82,20 +82,20 @@ def test_theorem1_factor_error_and_rank(N, W, eps):
 
 @pytest.mark.parametrize("N,W,eps", [(256, 1 / 8, 1e-6), (1024, 1 / 16, 1e-6), (1024, 0.2, 1e-3)])
 def test_t1t2_is_within_two_eps_of_the_projection(N, W, eps):
-    """||S_K S_K^T - T1 T2^T|| <= 2 eps (Section 2.3), with T1 T2^T formed by
+    """||S_K S_K^T - T1 T2^T|| <= 2 eps (Section 1.3), with T1 T2^T formed by
     recovering the compression of every unit vector; the compressed length
-    K' meets Section 2.3's bound."""
+    K' meets Section 1.3's bound."""
     fac = fz.fast_factorization(N, W, eps)
     T = fz.recover(fac, fz.compress(fac, np.eye(N)))
     lam, S = np.linalg.eigh(so.prolate_matrix(N, W))
     K = so.choose_K(N, W)
     P = S[:, -K:] @ S[:, -K:].T
     assert np.linalg.norm(P - T, 2) <= 2 * eps
-    kp = fac["kf"] + len(fac["mu"]) + fac["U"].shape[1]
+    kp = fac["kf"] + fac["r1"] + fac["U"].shape[1]
     assert kp <= fz.kprime_bound(N, W, eps)
     # the factor is not the projection itself: without L1 L2^T the error is O(1)
     c = fz.compress(fac, np.eye(N))
-    c[fac["kf"]:fac["kf"] + len(fac["mu"])] = 0
+    c[fac["kf"]:fac["kf"] + fac["r1"]] = 0
     assert np.linalg.norm(P - fz.recover(fac, c), 2) > 0.1
 
 

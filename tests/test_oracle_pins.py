@@ -3,7 +3,7 @@
 Each test fixes part of the oracle against something other than the oracle
 itself: the operator definition evaluated by quadrature, closed forms at tiny
 N, brute force, invariants the paper states (trace, eigenvalue range,
-orthonormality, the W <-> 1/2 - W symmetry, the error structure of Lemmas 5-7,
+orthonormality, the W <-> 1/2 - W symmetry, the error structure of Lemmas 4-6,
 the bounds of Corollaries 1-4), and scipy's independent DPSS routine.  The
 "planted mistake" tests at the end show that a plausible slip in the oracle
 (a dropped term, a wrong sign, an off-by-one index) fails at least one pin.
@@ -26,7 +26,7 @@ from oracle import slepian_oracle as o
 
 @pytest.mark.parametrize("N,W", [(7, 0.1), (16, 0.25), (33, 0.03)])
 def test_prolate_matrix_is_bandlimit_of_timelimit(N, W):
-    """B is the N x N section of B_W T_N (Definition 1 / Section 2.2):
+    """B is the N x N section of B_W T_N (Definition 1 / Section 1.2):
     B[m, n] = integral over |f| <= W of exp(j 2 pi f (m - n)) df, evaluated
     here by Gauss-Legendre quadrature, independent of the sinc formula."""
     t, w = leggauss(200)
@@ -146,7 +146,7 @@ def test_transition_vectors_match_dense(N, W, eps):
 
 @pytest.mark.parametrize("N,W", [(64, 0.1), (128, 0.2), (100, 0.23)])
 def test_half_band_symmetry(N, W):
-    """lambda_{N,1/2-W}^(l) = 1 - lambda_{N,W}^(N-1-l) (Section 2.2, quoting
+    """lambda_{N,1/2-W}^(l) = 1 - lambda_{N,W}^(N-1-l) (Section 1.2, quoting
     Slepian 1978 eq. 13)."""
     a, _ = o.dense_eig(N, W)
     b, _ = o.dense_eig(N, 0.5 - W)
@@ -207,7 +207,7 @@ def test_exact_projection_invariants(N, W):
 
 @pytest.mark.parametrize("N,W,eps", [(256, 1 / 8, 1e-6), (200, 0.05, 1e-3), (300, 0.3, 1e-9)])
 def test_fast_projection_error_closed_form(N, W, eps):
-    """Lemma 5: S_K S_K^T - (B + U1 U2^T) = V1 (I - Lambda1) V1^T - V4 Lambda4 V4^T,
+    """Lemma 4: S_K S_K^T - (B + U1 U2^T) = V1 (I - Lambda1) V1^T - V4 Lambda4 V4^T,
     whose 2-norm is max(max over I1 of 1 - lambda, max over I4 of lambda) <= eps."""
     K = o.choose_K(N, W)
     lam, _ = o.dense_eig(N, W)
@@ -225,7 +225,7 @@ def test_fast_projection_error_closed_form(N, W, eps):
 
 @pytest.mark.parametrize("N,W,eps", [(256, 1 / 8, 1e-6), (200, 0.1, 1e-4)])
 def test_fast_pinv_error(N, W, eps):
-    """Lemma 6: the error is V1 (Lambda1^-1 - Lambda1) V1^T - V4 Lambda4 V4^T,
+    """Lemma 5: the error is V1 (Lambda1^-1 - Lambda1) V1^T - V4 Lambda4 V4^T,
     of norm <= 3 eps."""
     lam, _ = o.dense_eig(N, W)
     tp = o.transition_plan(N, W, eps, 1 - eps)
@@ -245,7 +245,7 @@ def test_fast_pinv_error(N, W, eps):
 
 @pytest.mark.parametrize("N,W,eps,alpha", [(256, 1 / 8, 1e-6, 1e-3), (200, 0.1, 1e-4, 0.05)])
 def test_fast_tikhonov_error(N, W, eps, alpha):
-    """Lemma 7: (B^2 + alpha I)^-1 B - (B/(1+alpha) + U5 U5^T) has norm <= eps,
+    """Lemma 6: (B^2 + alpha I)^-1 B - (B/(1+alpha) + U5 U5^T) has norm <= eps,
     and the exact operator solves min ||y - B x||^2 + alpha ||x||^2 (checked by
     least squares on the stacked system [B; sqrt(alpha) I] x = [y; 0])."""
     B = o.prolate_matrix(N, W)
@@ -262,7 +262,7 @@ def test_fast_tikhonov_error(N, W, eps, alpha):
 
 
 def test_tikhonov_g_outside_set_bounded():
-    """Lemma 7's bound: outside the selected set, 0 <= lambda(1-lambda^2) /
+    """Lemma 6's bound: outside the selected set, 0 <= lambda(1-lambda^2) /
     ((1+alpha)(lambda^2+alpha)) <= eps."""
     alpha, eps = 1e-3, 1e-6
     lam = np.concatenate([np.linspace(0, alpha * (1 + alpha) * eps, 50),
@@ -304,7 +304,6 @@ def test_transition_count_bounds(N, W, eps):
     tp = o.transition_plan(N, W, eps, 1 - eps)
     r = tp["j1"] - tp["j0"]
     assert r <= o.cor1_bound(N, eps)
-    assert r <= o.zhu_wakin_bound(N, eps)
     a = o.asymptotic_count(N, eps)
     assert 0.5 * a <= r <= 1.5 * a + 2
     # the set is exactly {eps < lambda < 1-eps} over the whole spectrum
