@@ -55,7 +55,8 @@ enum slepian_status {
   SLEPIAN_ENOCONV = -5,    /* eigensolver check or iterative refinement did not converge */
   SLEPIAN_ENOTSUP = -6,    /* size or mode the library does not support  */
   SLEPIAN_ENONFINITE = -7, /* NaN or Inf found where finite values are required */
-  SLEPIAN_EIO = -8         /* plan file could not be read or written, or is malformed */
+  SLEPIAN_EIO = -8,        /* plan file could not be read or written, or is malformed */
+  SLEPIAN_ESCRATCH = -9    /* slepian_project_noalloc: two signals need more than its fixed scratch */
 };
 
 /* Arithmetic of the low-rank correction (the B x product is always FP32). */
@@ -169,6 +170,22 @@ int slepian_workspace_size(slepian_plan_t plan, int op, int64_t batch, size_t *b
  * (in place) but must not otherwise overlap it.  batch == 0 is a no-op. */
 int slepian_project(slepian_plan_t plan, const float *x, int64_t ldx, float *y, int64_t ldy,
                     int64_t batch, void *work, size_t work_bytes, void *stream);
+
+/* slepian_project without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, result and precision as
+ * slepian_project with work = NULL; its workspace is instead a fixed 160 MiB
+ * device array inside the library (one per device, held until the process
+ * ends).  A batch whose workspace exceeds it runs as consecutive sub-batches
+ * of an even number of signals, the largest that fits, with the same
+ * results.  The array is shared by every call on a device and keeps the last
+ * call's contents: calls that overlap in time on one device (different
+ * streams, different threads) race; serialise them.  Returns
+ * SLEPIAN_ESCRATCH if even two signals do not fit (not reachable for
+ * N <= 2^21), else as slepian_project.  No hipMalloc, hipFree or allocating
+ * library call is made. */
+int slepian_project_noalloc(slepian_plan_t plan, const float *x, int64_t ldx, float *y, int64_t ldy,
+                            int64_t batch, void *stream);
 
 /* As slepian_project with an explicit correction precision (enum
  * slepian_precision) instead of the plan's default. */

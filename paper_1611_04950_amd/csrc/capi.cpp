@@ -979,6 +979,7 @@ const char *slepian_status_string(int s) {
     case SLEPIAN_ENOTSUP: return "not supported";
     case SLEPIAN_ENONFINITE: return "non-finite value";
     case SLEPIAN_EIO: return "plan file error";
+    case SLEPIAN_ESCRATCH: return "needs more scratch than the allocation-free entry point holds";
     default: return "unknown status";
   }
 }
@@ -1633,6 +1634,74 @@ int slepian_project(slepian_plan_t P, const float *x, int64_t ldx, float *y, int
                     size_t work_bytes, void *stream) {
   if (!P) return SLEPIAN_EINVAL;
   return slepian_project_ex(P, P->precision, x, ldx, y, ldy, batch, work, work_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// The allocation-free projection: its workspace is a file-scope device array
+// ---------------------------------------------------------------------------
+
+namespace {
+constexpr size_t kNoAllocScratchBytes = (size_t)160 << 20;  // the paper-scale batch in one pass
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+// Each device that runs the library holds its own copy of this array for the
+// life of the process.  In host code `scratch` only names the array: kernels
+// get the device address that hipGetSymbolAddress returns for the device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current.
+void *noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) throw Fail{SLEPIAN_ENOTSUP};
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    DeviceGuard dg(device);
+    void *ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
+}  // namespace
+
+int slepian_project_noalloc(slepian_plan_t P, const float *x, int64_t ldx, float *y, int64_t ldy, int64_t batch,
+                            void *stream) {
+  if (bad_signal_args(P, x, ldx, y, ldy, batch)) return SLEPIAN_EINVAL;
+  if (batch == 0) return SLEPIAN_OK;
+  if (overlapping(x, ldx, y, ldy, P->N, batch)) return SLEPIAN_EINVAL;
+  if (x == y && ldx != ldy) return SLEPIAN_EINVAL;
+  // the largest even sub-batch (or the whole batch) whose workspace fits
+  auto need = [&](int64_t b) { return op_workspace(P, SLEPIAN_OP_PROJECT, b); };
+  int64_t bc = batch;
+  if (need(bc) > kNoAllocScratchBytes) {
+    int64_t lo = 0, hi = batch / 2;  // in pairs: lo fits (or is 0), hi does not
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) / 2;
+      if (need(2 * mid) <= kNoAllocScratchBytes) lo = mid;
+      else hi = mid;
+    }
+    if (lo == 0) return SLEPIAN_ESCRATCH;
+    bc = 2 * lo;
+  }
+  return guarded([&]() -> int {
+    DeviceGuard dg(P->device);
+    void *ws = noalloc_scratch(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    for (int64_t s = 0; s < batch; s += bc) {
+      const int64_t n = std::min(bc, batch - s);
+      Carver cv(ws);
+      ProjWs w = carve_project(P, P->proj, n, cv, P->precision);
+      run_fast_op(P, P->proj, 1.0f, 0.0f, x + s * ldx, ldx, y + s * ldy, ldy, n, w, st, P->precision);
+    }
+    return SLEPIAN_OK;
+  });
 }
 
 int slepian_apply_b64(slepian_plan_t P, const double *x, int64_t ldx, double *y, int64_t ldy, int64_t batch,

@@ -29,6 +29,7 @@ SLEPIAN_ENOCONV = -5
 SLEPIAN_ENOTSUP = -6
 SLEPIAN_ENONFINITE = -7
 SLEPIAN_EIO = -8
+SLEPIAN_ESCRATCH = -9
 
 SLEPIAN_FP32, SLEPIAN_MIXED, SLEPIAN_BF16_RAW = 0, 1, 2
 SLEPIAN_PINV, SLEPIAN_TIKHONOV = 0, 1
@@ -37,7 +38,7 @@ SLEPIAN_OP_PROJECT, SLEPIAN_OP_COEFFS, SLEPIAN_OP_LSQ, SLEPIAN_OP_MULTIBAND = 0,
 EXPORTED = [
     "slepian_plan", "slepian_plan_ex", "slepian_plan_batch", "slepian_plan_info_get", "slepian_plan_eigenpairs",
     "slepian_plan_save", "slepian_plan_load", "slepian_plan_destroy", "slepian_workspace_size",
-    "slepian_project", "slepian_project_ex", "slepian_project_multiband", "slepian_bands_create",
+    "slepian_project", "slepian_project_ex", "slepian_project_noalloc", "slepian_project_multiband", "slepian_bands_create",
     "slepian_bands_destroy", "slepian_bands_workspace_size", "slepian_project_bands", "slepian_coeffs", "slepian_lsq",
     "slepian_factor_create", "slepian_factor_destroy", "slepian_factor_info", "slepian_factor_mu",
     "slepian_factor_workspace_size", "slepian_factor_compress", "slepian_factor_recover",
@@ -94,6 +95,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "slepian_workspace_size": [vp, i32, i64, C.POINTER(sz)],
         "slepian_project": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_project_ex": [vp, i32, vp, i64, vp, i64, i64, vp, sz, vp],
+        "slepian_project_noalloc": [vp, vp, i64, vp, i64, i64, vp],
         "slepian_project_multiband": [vp, i32, C.POINTER(dbl), vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_bands_create": [vp, i32, C.POINTER(dbl), C.POINTER(vp)],
         "slepian_bands_destroy": [vp],
@@ -252,6 +254,16 @@ def slepian_project(plan: Plan, x: torch.Tensor, y: torch.Tensor | None = None,
     prec = plan.info["precision"] if precision is None else precision
     _check(_lib.slepian_project_ex(plan.handle, prec, _ptr(x), ldx, _ptr(y), ldy, x.shape[0], _ptr(work), wb,
                                    _stream(x)), "slepian_project")
+    return y
+
+
+def slepian_project_noalloc(plan: Plan, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    """slepian_project through the entry point that allocates nothing (its
+    workspace is the library's fixed device array); y must be given."""
+    x, ldx = _signals(x, plan.N, torch.float32, "x")
+    y, ldy = _signals(y, plan.N, torch.float32, "y")
+    _check(_lib.slepian_project_noalloc(plan.handle, _ptr(x), ldx, _ptr(y), ldy, x.shape[0], _stream(x)),
+           "slepian_project_noalloc")
     return y
 
 
