@@ -156,7 +156,7 @@ def cpu_baseline(N, W, eps, x_sample, min_seconds):
     from oracle import factorization as fz
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        fac = fz.fast_factorization(N, W, eps, method="eig")
+        fac = fz.fast_factorization(N, W, eps)
         fsetup = time.perf_counter() - t0
         freps = 0
         t0 = time.perf_counter()
@@ -421,22 +421,32 @@ def bench_multiband(args, dev):
 def bench_factorization(args, dev, check=None):
     """Fast factorization S_K S_K^T ~= T1 T2^T (Section 1.3, Theorem 1) at the
     paper-scale size N = 65536, W = 1/8, eps = 1e-6, 256 signals: compression
-    T2^T x (length-N DFT bins through the FFT passes plus [V U]^T x on the
-    matrix cores) and recovery T1 c, in the bench's correction precision.
+    T2^T x (length-N DFT bins through the FFT passes plus [L2 U]^T x on the
+    matrix cores) and recovery T1 c, in the bench's correction precision,
+    with L1, L2 from Theorem 1's construction (the reported figures) and,
+    beside it, from the eigenpairs of B - F F^* (key "eig_factor").
     Also reports the distance of the round trip from the plan's fast
     projection (both within eps of S_K S_K^T, so at most 3 eps apart) and,
     given the CPU leg's `check`, the round trip of its signal sample against
     the oracle's (per-signal relative error, gated at 1e-5) with the oracle's
     timing beside it."""
+    from paper_1611_04950_amd import slepian as S
+    out = _bench_factorization(args, dev, S.SLEPIAN_FACTOR_THEOREM1, check)
+    out["eig_factor"] = _bench_factorization(args, dev, S.SLEPIAN_FACTOR_EIG, None)
+    return out
+
+
+def _bench_factorization(args, dev, method, check):
     import torch
 
     from paper_1611_04950_amd import slepian as S
     from paper_1611_04950_amd import synth
     N, W, eps, b = 65536, 1.0 / 8, 1e-6, 256
-    log("bench: factorization workload")
+    name = "theorem1" if method == S.SLEPIAN_FACTOR_THEOREM1 else "eig"
+    log(f"bench: factorization workload ({name} factor)")
     plan = S.slepian_plan(N, W, eps, precision=S.SLEPIAN_MIXED if args.precision == "mixed" else S.SLEPIAN_FP32)
     t0 = time.perf_counter()
-    F = S.slepian_factor_create(plan)
+    F = S.slepian_factor_create(plan, method)
     setup = time.perf_counter() - t0
     x = synth.gaussian(N, b, 6200, device=dev)
     kp = F.info["kprime"]
@@ -498,9 +508,11 @@ def bench_factorization(args, dev, check=None):
         if not vs_oracle <= 1e-5:
             log(f"bench: factorization parity gate failed ({vs_oracle:.2e})")
             sys.exit(1)
-    log(f"bench: factorization N={N}, K'={kp} (kf {F.info['kf']}, r1 {F.info['r1']}, r {F.info['r']}): "
+    log(f"bench: factorization ({name}) N={N}, K'={kp} (kf {F.info['kf']}, r1 {F.info['r1']}, r {F.info['r']}): "
         f"compress {ms_c:.3f} ms, recover {ms_r:.3f} ms, setup {setup:.2f} s, |T1T2^T x - P~x|/|x| <= {dist:.1e}")
-    return {"workload": f"fast factorization N={N}, W=1/8, eps=1e-6, {b} signals",
+    return {"workload": f"fast factorization N={N}, W=1/8, eps=1e-6, {b} signals", "factor": name,
+            "theorem1_pieces": {"r_h": F.info["r_h"], "r_a": F.info["r_a"], "r_b": F.info["r_b"]}
+            if name == "theorem1" else None,
             "precision": args.precision, "K": plan.info["K"], "kf": F.info["kf"], "r1": F.info["r1"],
             "r": F.info["r"], "kprime": kp, "setup_subspace": F.info["subspace"], "setup_s": round(setup, 3),
             "compress_ms": round(ms_c, 4), "recover_ms": round(ms_r, 4),

@@ -232,51 +232,77 @@ int slepian_project_bands(slepian_bands_t bands, const float *x, int64_t ldx, fl
 
 /* Fast factorization S_K S_K^T ~= T1 T2^T (Section 1.3, "A fast
  * factorization", with Theorem 1):
- *     T1 = [F, V diag(mu), U diag(d)],   T2 = [F, V, U],
+ *     T1 = [F, L1, U diag(d)],   T2 = [F, L2, U],
  * F the partial DFT matrix of the 2NW' lowest length-N frequencies (2NW' =
- * kf, the odd integer nearest to 2NW; ties upward), V diag(mu) V^T the
- * eigenpairs of the symmetric Toeplitz matrix B - F F^* with |mu| > eps (the
- * least-rank factor within eps, so r1 is at most Theorem 1's rank), and
- * U diag(d) U^T the plan's transition correction of Corollary 2.
- * ||S_K S_K^T - T1 T2^T|| <= 2 eps.  For real signals F is used in its real
- * form F_r (same F F^*): columns 1/sqrt(N), sqrt(2/N) cos(2 pi k n / N),
- * -sqrt(2/N) sin(2 pi k n / N) for k = 1 .. (kf - 1)/2, in that interleaved
- * order.  A compressed signal holds kprime = kf + r1 + r FP32 numbers:
- * [F_r^T x; V^T x; U^T x].
+ * kf, the odd integer nearest to 2NW; ties upward), L1 L2^* an approximation
+ * of B - F F^* within eps of rank r1 (Theorem 1), and U diag(d) U^T the
+ * plan's transition correction of Corollary 2.  ||S_K S_K^T - T1 T2^T|| <=
+ * 2 eps.  For real signals F is used in its real form F_r (same F F^*):
+ * columns 1/sqrt(N), sqrt(2/N) cos(2 pi k n / N), -sqrt(2/N) sin(2 pi k n / N)
+ * for k = 1 .. (kf - 1)/2, in that interleaved order.  A compressed signal
+ * holds kprime = kf + r1 + r FP32 numbers: [F_r^T x; L2^T x; U^T x].
+ *
+ * The two ways to get L1, L2 (enum slepian_factor_method):
+ *  - SLEPIAN_FACTOR_THEOREM1 (default): the construction in the proof of
+ *    Theorem 1 (Section 2).  B - F F^* splits into modulated copies of the
+ *    Hilbert matrix, a remainder A1 and a matrix B0 (eq. (BA0), eq. (A0A1));
+ *    the Hilbert matrix gets a CF-ADI factor with rH = ceil(log(8N-4)
+ *    log(4 pi / delta_H) / pi^2) columns and elliptic-function shifts (Lemma 2
+ *    and its proof in the appendix), A1 and B0 truncated power series of 2 rA
+ *    and 2 rB - 1 terms, with delta_H = 4 pi eps / 15 and delta_A = delta_B =
+ *    7 eps / 30.  r1 = 4 rH + 4 rA + 2 (2 rB - 1).  For real signals the
+ *    complex L1, L2 (columns in conjugate pairs) are used in a real form with
+ *    the same product.  The modulation D_B is diag(e^{j pi (W + W') n}).
+ *    Setup (synchronous): the shifts and the series coefficients on the host,
+ *    the N x r1 factors by one FP64 kernel (FP32 results).
+ *  - SLEPIAN_FACTOR_EIG: L1 = V diag(mu), L2 = V, the eigenpairs of the
+ *    symmetric Toeplitz matrix B - F F^* with |mu| > eps (the least rank for
+ *    that error).  Setup (synchronous, FP64): subspace iteration on a random
+ *    +-1 block with the FFT-applied B - F F^*, Householder QR and a
+ *    Rayleigh-Ritz step (rocSOLVER), widening the block until it resolves
+ *    every |mu| > eps with a residual of at most eps / 4 (checked with one
+ *    more product); ENOCONV if it cannot.
+ *
  * Requires N a power of two (the plan's FFT length is then exactly 2N) with
- * 256 <= N <= 2^20, else ENOTSUP.  Setup (synchronous, FP64 on the GPU):
- * subspace iteration on a random +-1 block with the FFT-applied B - F F^*,
- * Householder QR and a Rayleigh-Ritz step (rocSOLVER), widening the block
- * until it resolves every |mu| > eps with a residual of at most eps / 4
- * (checked with one more product); ENOCONV if it cannot.  The plan must
- * outlive the factorization. */
+ * 256 <= N <= 2^20, else ENOTSUP.  The plan must outlive the factorization. */
 typedef struct slepian_factor_s *slepian_factor_t;
+enum slepian_factor_method {
+  SLEPIAN_FACTOR_THEOREM1 = 0,
+  SLEPIAN_FACTOR_EIG = 1
+};
 typedef struct {
   int64_t kf;         /* 2NW': rows of the F part of a compressed signal */
-  int64_t r1;         /* columns of V */
+  int64_t r1;         /* columns of L1 and L2 */
   int64_t r;          /* columns of U (the plan's projection transition set) */
   int64_t kprime;     /* kf + r1 + r */
-  int64_t subspace;   /* block size the setup converged with */
-  double mu_dropped;  /* largest |Ritz value| of B - F F^* left out (<= eps) */
-  double ritz_residual; /* largest ||(B - F F^*) v - mu v|| of the kept pairs (<= eps / 4) */
+  int64_t subspace;   /* EIG: block size the setup converged with; THEOREM1: 0 */
+  double mu_dropped;  /* EIG: largest |Ritz value| of B - F F^* left out (<= eps); THEOREM1: 0 */
+  double ritz_residual; /* EIG: largest ||(B - F F^*) v - mu v|| of the kept pairs (<= eps / 4) */
+  int32_t method;     /* enum slepian_factor_method */
+  int32_t r_h, r_a, r_b; /* THEOREM1: rH, rA, rB of the construction; EIG: 0 */
 } slepian_factor_info_t;
+/* slepian_factor_create_ex with SLEPIAN_FACTOR_THEOREM1. */
 int slepian_factor_create(slepian_plan_t plan, slepian_factor_t *out);
+int slepian_factor_create_ex(slepian_plan_t plan, int method, slepian_factor_t *out);
 int slepian_factor_destroy(slepian_factor_t f);
 int slepian_factor_info(slepian_factor_t f, slepian_factor_info_t *info);
-/* mu (r1 values, decreasing |mu|) to host memory of n >= r1 doubles. */
+/* EIG: mu (r1 values, decreasing |mu|) to host memory of n >= r1 doubles;
+ * THEOREM1: ENOTSUP (the construction has no eigenvalues). */
 int slepian_factor_mu(slepian_factor_t f, double *mu, int64_t n);
 /* Workspace bytes of compress or recover on `batch` signals. */
 int slepian_factor_workspace_size(slepian_factor_t f, int64_t batch, size_t *bytes);
 /* c = T2^T x.  x: N x batch FP32 (device, ldx >= N); c: kprime x batch FP32
  * (device, ldc >= kprime), no overlap with x.  F_r^T x runs through the
- * plan's FP32 FFT passes; V^T x and U^T x as one product on the matrix cores
- * in the plan's precision (FP32, or BF16 hi/lo operands).  batch == 0 is a
- * no-op; batch <= 32 * 65535. */
+ * plan's FP32 FFT passes; L2^T x and U^T x as one product on the matrix cores
+ * in the plan's precision (FP32, or BF16 hi/lo operands with FP32
+ * accumulation).  batch == 0 is a no-op; batch <= 32 * 65535. */
 int slepian_factor_compress(slepian_factor_t f, const float *x, int64_t ldx, float *c, int64_t ldc, int64_t batch,
                             void *work, size_t work_bytes, void *stream);
 /* y = T1 c.  c: kprime x batch FP32 (ldc >= kprime); y: N x batch FP32
  * (ldy >= N), no overlap with c.  F_r c_F through the plan's FP32 inverse FFT
- * passes, then y += [V U] ([mu d] . c_rest) on the matrix cores (FP32). */
+ * passes, then y += [L1 U] ([1 d] . c_rest) on the matrix cores in the
+ * plan's precision (FP32, or BF16 hi/lo operands with FP32 accumulation),
+ * fused into the inverse column pass where that pass takes the update. */
 int slepian_factor_recover(slepian_factor_t f, const float *c, int64_t ldc, float *y, int64_t ldy, int64_t batch,
                            void *work, size_t work_bytes, void *stream);
 

@@ -1283,14 +1283,19 @@ struct slepian_factor_s {
   int64_t p = 0;              // subspace size the setup converged with
   double mu_drop = 0;         // largest |Ritz value| left out (<= eps)
   double ritz_res = 0;        // largest ||T v_j - mu_j v_j|| of the kept pairs
-  float *U = nullptr;         // N x (r1 + r), leading dimension ldu: [V | U_T]
+  int method = SLEPIAN_FACTOR_THEOREM1;
+  int rH = 0, rA = 0, rB = 0; // Theorem 1's construction: Hilbert-factor columns, series terms
+  float *U = nullptr;         // N x (r1 + r), leading dimension ldu: compression [L2 | U_T]
+  float *Urec = nullptr;      // recovery [L1 | U_T] when it differs from U (THEOREM1), else null
   int64_t ldu = 0;
-  float *w = nullptr;         // r1 + r weights [mu | d]
+  float *w = nullptr;         // r1 + r weights: [mu | d] (EIG) or [1 | d] (THEOREM1)
   int mode = 0;               // matrix mode of the coefficient products
-  void *ctile = nullptr;      // [V | U] laid out for the fused inverse column pass (or null)
+  void *ctile = nullptr;      // the recovery matrix laid out for the fused inverse column pass (or null)
   std::vector<double> mu;
+  const float *rec() const { return Urec ? Urec : U; }
   ~slepian_factor_s() {
     dfree(U);
+    dfree(Urec);
     dfree(w);
     dfree(ctile);
   }
@@ -1486,6 +1491,142 @@ void factor_setup(slepian_factor_s *F, hipStream_t st) {
   }
 }
 
+// ---- Theorem 1's construction (Section 2): host-side constants ----
+
+// Arithmetic-geometric mean of 1 and kc with the half-differences c_n
+// (c_0 = sqrt(1 - kc^2)), at most 64 halvings.
+void agm_steps(double kc, std::vector<double> &a, std::vector<double> &c) {
+  a.assign(1, 1.0);
+  c.assign(1, std::sqrt((1.0 - kc) * (1.0 + kc)));
+  double b = kc;
+  for (int i = 0; i < 64 && c.back() > 4e-16 * a.back(); ++i) {
+    const double an = a.back();
+    a.push_back(0.5 * (an + b));
+    c.push_back(0.5 * (an - b));
+    b = std::sqrt(an * b);
+  }
+}
+
+// Jacobi dn(u, tau), tau = sqrt(1 - kc^2), by the descending Landen scheme.
+double jacobi_dn(double u, const std::vector<double> &a, const std::vector<double> &c) {
+  const int n = (int)a.size() - 1;
+  if (n == 0) return 1.0;
+  double phi = std::ldexp(a[n] * u, n), prev = phi;
+  for (int k = n; k >= 1; --k) {
+    prev = phi;
+    phi = 0.5 * (phi + std::asin(c[k] * std::sin(phi) / a[k]));
+  }
+  return std::cos(phi) / std::cos(prev - phi);
+}
+
+// zeta(s) for s >= 2 by Euler-Maclaurin summation with 16 leading terms and
+// five Bernoulli corrections.
+double zeta_em(double s) {
+  constexpr int M = 16;
+  double z = 0.0;
+  for (int n = 1; n < M; ++n) z += std::pow((double)n, -s);
+  const double m = (double)M;
+  z += std::pow(m, 1.0 - s) / (s - 1.0) + 0.5 * std::pow(m, -s);
+  static const double b2j[5] = {1.0 / 6, -1.0 / 30, 1.0 / 42, -1.0 / 30, 5.0 / 66};
+  double rising = s, fact = 2.0;  // s (s+1) ... (s+2j-2) and (2j)!
+  for (int j = 1; j <= 5; ++j) {
+    z += b2j[j - 1] / fact * rising * std::pow(m, -s - 2.0 * j + 1.0);
+    rising *= (s + 2.0 * j - 1.0) * (s + 2.0 * j);
+    fact *= (2.0 * j + 1.0) * (2.0 * j + 2.0);
+  }
+  return z;
+}
+
+double binom(int n, int k) {
+  double v = 1.0;
+  for (int i = 1; i <= k; ++i) v = v * (double)(n - k + i) / (double)i;
+  return std::round(v);
+}
+
+struct Thm1Consts {
+  int rH = 0, rA = 0, rB = 0;
+  std::vector<double> prm;  // [shifts | C_A | C_B]
+};
+
+// delta_H = 4 pi eps / 15, delta_A = delta_B = 7 eps / 30 ("Putting it all
+// together"); rH from Lemma 2 with kappa = 2N - 1, delta = delta_H / pi;
+// shifts p_j = b dn((2j - 1)/(2 rH) I(tau), tau) on [a, b] = [1/2, N - 1/2]
+// (the appendix's remark on the optimal parameters); C_A from the zeta
+// coefficients 1 - (1 - 2^{-(2k-1)}) zeta(2k) of A1's odd series, C_B from the
+// sine series of B0 with theta = pi (W - W') N, both expanded binomially in
+// the centred index u = (n - (N-1)/2) / N.
+Thm1Consts theorem1_consts(int64_t N, double W, double eps, int kf) {
+  Thm1Consts t;
+  const double dH = 4.0 * M_PI * eps / 15.0, dA = 7.0 * eps / 30.0, dB = dA;
+  t.rH = (int)std::ceil(std::log(8.0 * (double)N - 4.0) * std::log(4.0 * M_PI / dH) / (M_PI * M_PI));
+  t.rA = (int)std::ceil(std::log(2.0 / (3.0 * M_PI * dA)) / (2.0 * std::log(2.0)));
+  t.rB = (int)std::ceil(std::log(3.0 / (2.0 * dB)) / (2.0 * std::log(6.0 / M_PI)));
+  const double a = 0.5, b = (double)N - 0.5;
+  std::vector<double> ag, cg;
+  agm_steps(a / b, ag, cg);
+  const double K = M_PI / (2.0 * ag.back());
+  for (int j = 1; j <= t.rH; ++j) t.prm.push_back(b * jacobi_dn((2.0 * j - 1.0) / (2.0 * t.rH) * K, ag, cg));
+  const int na = 2 * t.rA, nb = 2 * t.rB - 1;
+  const size_t oa = t.prm.size();
+  t.prm.resize(oa + (size_t)na * na + (size_t)nb * nb, 0.0);
+  const double scale = 2.0 / ((double)N * M_PI);
+  for (int k = 1; k <= t.rA; ++k) {
+    const double ck = 1.0 - (1.0 - std::ldexp(1.0, -(2 * k - 1))) * zeta_em(2.0 * k);
+    const int pdeg = 2 * k - 1;
+    for (int i = 0; i <= pdeg; ++i)
+      t.prm[oa + (size_t)i * na + (pdeg - i)] = scale * ck * binom(pdeg, i) * (((pdeg - i) & 1) ? -1.0 : 1.0);
+  }
+  const size_t ob = oa + (size_t)na * na;
+  const double Wp = (double)kf / (2.0 * (double)N);
+  const double theta = M_PI * (W - Wp) * (double)N;
+  double pw = theta, fact = 1.0;  // theta^{2k+1} and (2k+1)!
+  for (int k = 0; k < t.rB; ++k) {
+    const double coef = scale * ((k & 1) ? -1.0 : 1.0) * pw / fact;
+    const int pdeg = 2 * k;
+    for (int i = 0; i <= pdeg; ++i)
+      t.prm[ob + (size_t)i * nb + (pdeg - i)] = coef * binom(pdeg, i) * (((pdeg - i) & 1) ? -1.0 : 1.0);
+    pw *= theta * theta;
+    fact *= (2.0 * k + 2.0) * (2.0 * k + 3.0);
+  }
+  return t;
+}
+
+// L1, L2 by the construction; weights [1 | d]; the recovery matrix's tile.
+void factor_setup_theorem1(slepian_factor_s *F, hipStream_t st) {
+  Plan *P = F->P;
+  const int64_t N = P->N;
+  const Thm1Consts t = theorem1_consts(N, P->W, P->eps, F->kf);
+  F->rH = t.rH;
+  F->rA = t.rA;
+  F->rB = t.rB;
+  const int64_t r1 = 2 * (2 * (int64_t)t.rH + 2 * t.rA + 2 * t.rB - 1);
+  F->r1 = r1;
+  const int64_t rt = r1 + F->r;
+  F->ldu = (N + 3) / 4 * 4;
+  F->U = dalloc<float>((size_t)F->ldu * rt);
+  F->Urec = dalloc<float>((size_t)F->ldu * rt);
+  {
+    DBuf<double> prm(t.prm.size());
+    HIPCHK(hipMemcpyAsync(prm.p, t.prm.data(), t.prm.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(theorem1_rows(N, F->kf, P->W, t.rH, t.rA, t.rB, prm.p, F->U, F->Urec, F->ldu, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  if (F->r > 0) {
+    HIPCHK(copy_f32(P->U32 + P->proj.off * P->ldu, P->ldu, F->U + r1 * F->ldu, F->ldu, N, F->r, st));
+    HIPCHK(copy_f32(P->U32 + P->proj.off * P->ldu, P->ldu, F->Urec + r1 * F->ldu, F->ldu, N, F->r, st));
+  }
+  std::vector<float> w32(std::max<int64_t>(rt, 1), 1.0f);
+  for (int64_t j = 0; j < F->r; ++j) w32[r1 + j] = (float)P->proj.d[j];
+  F->w = dalloc<float>(w32.size());
+  HIPCHK(hipMemcpyAsync(F->w, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  const FftGeom &g = P->g32;
+  if (rt > 0 && !g.single() && colinv_corr_tiled(g.log1)) {
+    F->ctile = dalloc<char>(corr_tile_bytes(g.log1, g.log2, (int)rt, F->mode));
+    HIPCHK(build_corr_tile(F->Urec, F->ldu, (int)N, (int)rt, g.log1, g.log2, F->mode, F->ctile, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+}
+
 bool bad_factor_args(const slepian_factor_s *F, const void *in, int64_t ldin, int64_t rows_in, const void *out,
                      int64_t ldout, int64_t rows_out, int64_t batch) {
   if (!F || batch < 0 || batch > 32 * (int64_t)65535) return true;
@@ -1504,9 +1645,14 @@ bool factor_overlap(const void *a, int64_t lda, int64_t rows_a, const void *b, i
 }  // namespace
 
 int slepian_factor_create(slepian_plan_t P, slepian_factor_t *out) {
+  return slepian_factor_create_ex(P, SLEPIAN_FACTOR_THEOREM1, out);
+}
+
+int slepian_factor_create_ex(slepian_plan_t P, int method, slepian_factor_t *out) {
   if (!out) return SLEPIAN_EINVAL;
   *out = nullptr;
   if (!P) return SLEPIAN_EINVAL;
+  if (method != SLEPIAN_FACTOR_THEOREM1 && method != SLEPIAN_FACTOR_EIG) return SLEPIAN_EINVAL;
   if (!dft_bins_ok(P->g32, P->N) || P->N > ((int64_t)1 << 20)) return SLEPIAN_ENOTSUP;
   return guarded([&]() -> int {
     DeviceGuard dg(P->device);
@@ -1516,10 +1662,12 @@ int slepian_factor_create(slepian_plan_t P, slepian_factor_t *out) {
     F->kf = factor_kf(P->N, P->W);
     F->r = P->proj.r;
     F->mode = P->precision == SLEPIAN_FP32 ? 0 : 1;
+    F->method = method;
     hipStream_t st = nullptr;
     try {
       HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-      factor_setup(F, st);
+      if (method == SLEPIAN_FACTOR_THEOREM1) factor_setup_theorem1(F, st);
+      else factor_setup(F, st);
       (void)hipStreamDestroy(st);
     } catch (...) {
       if (st) {
@@ -1553,11 +1701,17 @@ int slepian_factor_info(slepian_factor_t F, slepian_factor_info_t *info) {
   info->subspace = F->p;
   info->mu_dropped = F->mu_drop;
   info->ritz_residual = F->ritz_res;
+  info->method = F->method;
+  info->r_h = F->rH;
+  info->r_a = F->rA;
+  info->r_b = F->rB;
   return SLEPIAN_OK;
 }
 
 int slepian_factor_mu(slepian_factor_t F, double *mu, int64_t n) {
-  if (!F || (n > 0 && !mu) || n < F->r1) return SLEPIAN_EINVAL;
+  if (!F) return SLEPIAN_EINVAL;
+  if (F->method != SLEPIAN_FACTOR_EIG) return SLEPIAN_ENOTSUP;
+  if ((n > 0 && !mu) || n < F->r1) return SLEPIAN_EINVAL;
   std::copy(F->mu.begin(), F->mu.end(), mu);
   return SLEPIAN_OK;
 }
@@ -1617,7 +1771,7 @@ int slepian_factor_recover(slepian_factor_t F, const float *c, int64_t ldc, floa
     Corr<float> corr;
     const bool fused = rt > 0 && F->ctile && colinv_corr_ok(P->g32.log1, ldy, batch, rt);
     if (fused) {
-      corr.U = F->U;
+      corr.U = F->rec();
       corr.ldu = F->ldu;
       corr.r = rt;
       corr.dC = w.dC;
@@ -1625,7 +1779,7 @@ int slepian_factor_recover(slepian_factor_t F, const float *c, int64_t ldc, floa
       corr.ut = F->ctile;
     }
     HIPCHK(dft_bins_inv(w.Zb, F->kf, y, ldy, N, batch, P->g32, P->tb32, w.Z, w.slice, corr, st));
-    if (rt > 0 && !fused) HIPCHK(corr_apply_mfma(y, ldy, N, batch, F->U, F->ldu, rt, w.dC, st));
+    if (rt > 0 && !fused) HIPCHK(corr_apply_mfma(y, ldy, N, batch, F->rec(), F->ldu, rt, w.dC, st));
     return SLEPIAN_OK;
   });
 }

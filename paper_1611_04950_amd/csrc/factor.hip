@@ -207,3 +207,98 @@ hipError_t pack_scale(const float *c, int64_t ldc, int kf, int64_t N, int64_t b,
 }
 
 }  // namespace slp
+
+namespace slp {
+
+// Theorem 1's factor of B - F F^* (Section 2, "Putting it all together"),
+// in the real form used for real signals.  The construction's complex
+// columns come in conjugate pairs, so row n of the real factors holds, for
+// the first member of each pair, Re and Im of the compression column (L2)
+// and twice Re and Im of the recovery column (L1):
+//   group 1: L2 = D_A J Z,         L1 = D_A Z / (2 pi j)      (rH columns)
+//   group 2: L2 = D_A Z,           L1 = -D_A J Z / (2 pi j)   (rH columns)
+//   group 5: L2 = D_A V_A C_A^T,   L1 = D_A V_A / (2 j)       (2 rA columns)
+//   group 7: L2 = D_B V_B C_B^T,   L1 = D_B V_B / 2           (2 rB - 1 columns)
+// with D_A = e^{j pi kf n / N} (2 pi W' n, 2NW' = kf), D_B = e^{j pi (W + W') n},
+// Z the CF-ADI factor of the Hilbert matrix (A = diag(n + 1/2), shifts p_k):
+//   Z_1 = sqrt(2 p_1) / (n + 1/2 + p_1),
+//   Z_k = sqrt(p_k / p_{k-1}) (n + 1/2 - p_{k-1}) / (n + 1/2 + p_k) Z_{k-1},
+// (J Z)[n] = Z[N - 1 - n], and V_A, V_B the monomials u^i of the centred index
+// u = (n - (N-1)/2) / N.  Columns: [Re of groups 1, 2, 5, 7 | Im of the same].
+// FP64 arithmetic, FP32 results; one thread per n.
+__global__ void k_theorem1_rows(int64_t N, int kf, double W, int rH, int rA, int rB,
+                                const double *__restrict__ prm, float *__restrict__ L2, float *__restrict__ L1,
+                                int64_t ld) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const double *p = prm;
+  const double *CA = prm + rH;
+  const int na = 2 * rA, nb = 2 * rB - 1;
+  const double *CB = CA + (int64_t)na * na;
+  const int half = 2 * rH + na + nb;
+  // D_A: angle pi (kf n mod 2N) / N;  D_B: angle pi ((W n mod 2) + (kf n mod 4N) / (2N))
+  const int64_t kn = (int64_t)kf * n;
+  double sa, ca, sb, cb;
+  sincospi((double)(kn % (2 * N)) / (double)N, &sa, &ca);
+  double tb = fmod(W * (double)n, 2.0) + (double)(kn % (4 * N)) / (double)(2 * N);
+  sincospi(fmod(tb, 2.0), &sb, &cb);
+  float *l2r = L2 + n, *l2i = L2 + n + (int64_t)half * ld;
+  float *l1r = L1 + n, *l1i = L1 + n + (int64_t)half * ld;
+  // Hilbert factor at n and at N - 1 - n
+  const double al = (double)n + 0.5, alj = (double)(N - 1 - n) + 0.5;
+  double z = 0.0, zj = 0.0;
+  for (int k = 0; k < rH; ++k) {
+    if (k == 0) {
+      const double s0 = sqrt(2.0 * p[0]);
+      z = s0 / (al + p[0]);
+      zj = s0 / (alj + p[0]);
+    } else {
+      const double f = sqrt(p[k] / p[k - 1]);
+      z *= f * (al - p[k - 1]) / (al + p[k]);
+      zj *= f * (alj - p[k - 1]) / (alj + p[k]);
+    }
+    const int64_t c1 = (int64_t)k * ld, c2 = (int64_t)(rH + k) * ld;
+    l2r[c1] = (float)(zj * ca);
+    l2i[c1] = (float)(zj * sa);
+    l1r[c1] = (float)(z * sa * M_1_PI);
+    l1i[c1] = (float)(-z * ca * M_1_PI);
+    l2r[c2] = (float)(z * ca);
+    l2i[c2] = (float)(z * sa);
+    l1r[c2] = (float)(-zj * sa * M_1_PI);
+    l1i[c2] = (float)(zj * ca * M_1_PI);
+  }
+  // polynomial factors of A1 and B0
+  const double u = ((double)n - 0.5 * (double)(N - 1)) / (double)N;
+  double ui = 1.0;
+  for (int i = 0; i < na; ++i) {
+    double w = 0.0;  // (V_A C_A^T)[n, i] = sum_l C_A[i, l] u^l (Horner)
+    for (int l = na - 1; l >= 0; --l) w = w * u + CA[(int64_t)i * na + l];
+    const int64_t c = (int64_t)(2 * rH + i) * ld;
+    l2r[c] = (float)(w * ca);
+    l2i[c] = (float)(w * sa);
+    l1r[c] = (float)(ui * sa);
+    l1i[c] = (float)(-ui * ca);
+    ui *= u;
+  }
+  ui = 1.0;
+  for (int i = 0; i < nb; ++i) {
+    double w = 0.0;
+    for (int l = nb - 1; l >= 0; --l) w = w * u + CB[(int64_t)i * nb + l];
+    const int64_t c = (int64_t)(2 * rH + na + i) * ld;
+    l2r[c] = (float)(w * cb);
+    l2i[c] = (float)(w * sb);
+    l1r[c] = (float)(ui * cb);
+    l1i[c] = (float)(ui * sb);
+    ui *= u;
+  }
+}
+
+hipError_t theorem1_rows(int64_t N, int kf, double W, int rH, int rA, int rB, const double *prm, float *L2,
+                         float *L1, int64_t ld, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_theorem1_rows, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, kf, W, rH, rA, rB, prm,
+                     L2, L1, ld);
+  return hipGetLastError();
+}
+
+}  // namespace slp

@@ -231,6 +231,11 @@ hipError_t dft_bins_inv(const cpx<float> *Zb, int kf, float *y, int64_t ldy, int
                         const Corr<float> &corr, hipStream_t st);
 // first column of B - F F^* embedded in a length-L circulant (FP64)
 hipError_t diff_embed(double *c, int64_t L, int64_t N, double W, int kf, hipStream_t st);
+// Rows of Theorem 1's real factor: prm = [shifts (rH) | C_A (2rA x 2rA) | C_B
+// ((2rB-1) x (2rB-1))], row-major; L2 (compression) and L1 (recovery) get
+// 2 (2 rH + 2 rA + 2 rB - 1) columns each, leading dimension ld.
+hipError_t theorem1_rows(int64_t N, int kf, double W, int rH, int rA, int rB, const double *prm, float *L2,
+                         float *L1, int64_t ld, hipStream_t st);
 // N x p block of +-1 (FP64, leading dimension ld) from a counter-based generator
 hipError_t rademacher(double *O, int64_t ld, int64_t N, int64_t p, uint64_t seed, hipStream_t st);
 // sign convention of each column: first entry of magnitude >= 1e-3 max positive

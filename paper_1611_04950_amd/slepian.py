@@ -34,13 +34,14 @@ SLEPIAN_ESCRATCH = -9
 SLEPIAN_FP32, SLEPIAN_MIXED, SLEPIAN_BF16_RAW = 0, 1, 2
 SLEPIAN_PINV, SLEPIAN_TIKHONOV = 0, 1
 SLEPIAN_OP_PROJECT, SLEPIAN_OP_COEFFS, SLEPIAN_OP_LSQ, SLEPIAN_OP_MULTIBAND = 0, 1, 2, 3
+SLEPIAN_FACTOR_THEOREM1, SLEPIAN_FACTOR_EIG = 0, 1
 
 EXPORTED = [
     "slepian_plan", "slepian_plan_ex", "slepian_plan_batch", "slepian_plan_info_get", "slepian_plan_eigenpairs",
     "slepian_plan_save", "slepian_plan_load", "slepian_plan_destroy", "slepian_workspace_size",
     "slepian_project", "slepian_project_ex", "slepian_project_noalloc", "slepian_project_multiband", "slepian_bands_create",
     "slepian_bands_destroy", "slepian_bands_workspace_size", "slepian_project_bands", "slepian_coeffs", "slepian_lsq",
-    "slepian_factor_create", "slepian_factor_destroy", "slepian_factor_info", "slepian_factor_mu",
+    "slepian_factor_create", "slepian_factor_create_ex", "slepian_factor_destroy", "slepian_factor_info", "slepian_factor_mu",
     "slepian_factor_workspace_size", "slepian_factor_compress", "slepian_factor_recover",
     "slepian_apply_b64",
     "slepian_group_create", "slepian_group_project", "slepian_group_destroy", "slepian_status_string",
@@ -54,7 +55,8 @@ class PlanOpts(C.Structure):
 
 class FactorInfo(C.Structure):
     _fields_ = [("kf", C.c_int64), ("r1", C.c_int64), ("r", C.c_int64), ("kprime", C.c_int64),
-                ("subspace", C.c_int64), ("mu_dropped", C.c_double), ("ritz_residual", C.c_double)]
+                ("subspace", C.c_int64), ("mu_dropped", C.c_double), ("ritz_residual", C.c_double),
+                ("method", C.c_int32), ("r_h", C.c_int32), ("r_a", C.c_int32), ("r_b", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -103,6 +105,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "slepian_project_bands": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_coeffs": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_factor_create": [vp, C.POINTER(vp)],
+        "slepian_factor_create_ex": [vp, i32, C.POINTER(vp)],
         "slepian_factor_destroy": [vp],
         "slepian_factor_info": [vp, C.POINTER(FactorInfo)],
         "slepian_factor_mu": [vp, C.POINTER(dbl), i64],
@@ -320,10 +323,12 @@ class Factor:
         inf = FactorInfo()
         _check(_lib.slepian_factor_info(self.handle, C.byref(inf)), "slepian_factor_info")
         self.info = {f: getattr(inf, f) for f, _ in FactorInfo._fields_}
-        n = max(self.info["r1"], 1)
-        mu = (C.c_double * n)()
-        _check(_lib.slepian_factor_mu(self.handle, mu, n), "slepian_factor_mu")
-        self.mu = [mu[i] for i in range(self.info["r1"])]
+        self.mu = None
+        if self.info["method"] == SLEPIAN_FACTOR_EIG:
+            n = max(self.info["r1"], 1)
+            mu = (C.c_double * n)()
+            _check(_lib.slepian_factor_mu(self.handle, mu, n), "slepian_factor_mu")
+            self.mu = [mu[i] for i in range(self.info["r1"])]
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -332,10 +337,12 @@ class Factor:
             self.handle = C.c_void_p(0)
 
 
-def slepian_factor_create(plan: Plan) -> Factor:
-    """Fast factorization S_K S_K^T ~= T1 T2^T of the plan (see include/slepian.h)."""
+def slepian_factor_create(plan: Plan, method: int = SLEPIAN_FACTOR_THEOREM1) -> Factor:
+    """Fast factorization S_K S_K^T ~= T1 T2^T of the plan, with L1, L2 from
+    Theorem 1's construction (default) or from the eigenpairs of B - F F^*
+    (SLEPIAN_FACTOR_EIG); see include/slepian.h."""
     h = C.c_void_p()
-    _check(_lib.slepian_factor_create(plan.handle, C.byref(h)), "slepian_factor_create")
+    _check(_lib.slepian_factor_create_ex(plan.handle, method, C.byref(h)), "slepian_factor_create_ex")
     return Factor(h.value, plan)
 
 

@@ -1,7 +1,17 @@
 """Fast factorization S_K S_K^T ~= T1 T2^T on the GPU (Section 1.3 "A fast
-factorization", Theorem 1) against the FP64 oracle in oracle/factorization.py.
+factorization", Theorem 1) against the FP64 oracle in oracle/factorization.py,
+for both ways of getting the factor L1 L2^* of B - F F^*.
 
-Compared element by element on the same seeded FP32 inputs:
+Theorem 1's construction (Section 2, the library's default): r1 and the
+construction's rH, rA, rB equal the oracle's; the rows of T2 and the columns
+of T1 (compression of unit vectors, recovery of unit coefficients) equal the
+oracle's L2 and L1 entry by entry (1e-5 of each column's norm); the
+compressed L2^T x and the round trip match the oracle's (1e-5), and, where
+the dense projection is affordable, the round trip lies within
+(2 eps + 1e-6) ||x|| of S_K S_K^T x.
+
+The eigenpair factor (SLEPIAN_FACTOR_EIG), compared element by element on
+the same seeded FP32 inputs:
   * kf, r and the factor's eigenvalues mu (the setup's subspace iteration
     against dense eigh / Lanczos on the same Toeplitz matrix, 1e-9 absolute);
   * the compressed F_r^T x (unique; 1e-5 of the signal's coefficient norm);
@@ -48,10 +58,12 @@ def _prec(name):
     return {"fp32": S.SLEPIAN_FP32, "mixed": S.SLEPIAN_MIXED}[name]
 
 
-def _oracle(N, W, eps):
-    key = (N, W, eps)
+def _oracle(N, W, eps, method="eig"):
+    key = (N, W, eps, method)
     if key not in _FAC:
-        _FAC[key] = fz.fast_factorization(N, W, eps, method="eig")
+        if len(_FAC) > 4:
+            _FAC.clear()
+        _FAC[key] = fz.fast_factorization(N, W, eps, method=method)
     return _FAC[key]
 
 
@@ -59,9 +71,9 @@ def _x(N, b, seed):
     return synth.gaussian(N, b, seed).numpy().T  # N x b FP32
 
 
-def _setup(N, W, eps, prec):
+def _setup(N, W, eps, prec, method=None):
     P = S.slepian_plan(N, W, eps, precision=_prec(prec))
-    F = S.slepian_factor_create(P)
+    F = S.slepian_factor_create(P, S.SLEPIAN_FACTOR_EIG if method == "eig" else S.SLEPIAN_FACTOR_THEOREM1)
     return P, F
 
 
@@ -75,9 +87,75 @@ def _check_r1(F, fac, eps):
 
 
 @pytest.mark.parametrize("N,W,eps,b,prec", CASES)
-def test_factorization_matches_oracle(N, W, eps, b, prec):
-    print(f"factorization N={N} W={W} eps={eps} b={b} {prec}", flush=True)
+def test_theorem1_factorization_matches_oracle(N, W, eps, b, prec):
+    print(f"theorem1 factorization N={N} W={W} eps={eps} b={b} {prec}", flush=True)
     P, F = _setup(N, W, eps, prec)
+    fac = _oracle(N, W, eps, "theorem1")
+    kf, r, r1 = fac["kf"], fac["U"].shape[1], fac["r1"]
+    dH, dA, dB = fz.theorem1_tolerances(eps)
+    assert F.info["method"] == S.SLEPIAN_FACTOR_THEOREM1 and F.mu is None
+    assert (F.info["r_h"], F.info["r_a"], F.info["r_b"]) == (fz.hilbert_rank(N, dH), fz.a1_terms(dA), fz.b0_terms(dB))
+    assert F.info["kf"] == kf and F.info["r"] == r and F.info["r1"] == r1 == fz.theorem1_rank(N, eps)
+    assert F.info["kprime"] == kf + r1 + r
+    x = _x(N, b, 11)
+    xd = torch.from_numpy(x.T.copy()).cuda()
+    c = S.slepian_factor_compress(F, xd)
+    y = S.slepian_factor_recover(F, c)
+    torch.cuda.synchronize()
+    c = c.cpu().numpy().astype(np.float64).T
+    y = y.cpu().numpy().astype(np.float64).T
+    x64 = x.astype(np.float64)
+    cf = fz.fr_adjoint(x64, kf)
+    for s in range(b):
+        assert np.abs(c[:kf, s] - cf[:, s]).max() <= 1e-5 * np.linalg.norm(cf[:, s])
+    cl = fac["L2"].T @ x64
+    tol = (1e-5 * np.linalg.norm(fac["L2"], axis=0)[:, None] + 1e-30) * np.linalg.norm(x64, axis=0)[None, :]
+    assert np.all(np.abs(c[kf:kf + r1] - cl) <= tol)
+    cu = fac["U"].T @ x64
+    assert np.abs(c[kf + r1:, :] - cu).max() <= 1e-5 * np.linalg.norm(x64, axis=0).max()
+    ref = fz.recover(fac, fz.compress(fac, x64))
+    err = max(np.linalg.norm(y[:, s] - ref[:, s]) / np.linalg.norm(ref[:, s]) for s in range(b))
+    print(f"  r1={r1} (rH {F.info['r_h']}, rA {F.info['r_a']}, rB {F.info['r_b']}) round trip vs oracle {err:.2e}",
+          flush=True)
+    assert err <= 1e-5
+    if N <= 4096:
+        Pk = so.project_exact(N, W, x64)
+        for s in range(b):
+            assert np.linalg.norm(y[:, s] - Pk[:, s]) <= (2 * eps + 1e-6) * np.linalg.norm(x64[:, s])
+
+
+@pytest.mark.parametrize("N,W,eps,prec", [(256, 1 / 8, 1e-6, "fp32"), (1024, 0.2, 1e-9, "fp32"),
+                                          (1024, 1 / 16, 1e-6, "mixed"), (4096, 0.05, 1e-3, "fp32")])
+def test_theorem1_factor_columns_match_oracle(N, W, eps, prec):
+    """The setup's L2 (rows of T2 from compressing unit vectors) and L1
+    (columns of T1 from recovering unit coefficients of the L part) equal
+    the oracle's construction column by column."""
+    P, F = _setup(N, W, eps, prec)
+    L1, L2 = fz.theorem1_factor(N, W, eps)
+    kf, r1, kp = F.info["kf"], F.info["r1"], F.info["kprime"]
+    eye = torch.eye(N, device="cuda")
+    T2 = S.slepian_factor_compress(F, eye).double().cpu().numpy()  # row n = T2^T e_n, i.e. row n of T2
+    g2 = T2[:, kf:kf + r1]
+    cu = torch.zeros((r1, kp), device="cuda")
+    cu[:, kf:kf + r1] = torch.eye(r1, device="cuda")
+    T1 = S.slepian_factor_recover(F, cu).double().cpu().numpy().T  # column j = L1[:, j]
+    # column j enters T1 T2^T as L1[:, j] L2[:, j]^T, so each column is held to
+    # 1e-5 of that term's norm; the highest sine-series columns of L2 fall
+    # below the FP32 range (norms down to 1e-43 at eps = 1e-9) while their
+    # terms are below 1e-40, hence the absolute floor
+    cn1, cn2 = np.linalg.norm(L1, axis=0), np.linalg.norm(L2, axis=0)
+    assert np.all(np.linalg.norm(g2 - L2, axis=0) * cn1 <= 1e-5 * cn1 * cn2 + 1e-20)
+    assert np.all(np.linalg.norm(T1 - L1, axis=0) * cn2 <= 1e-5 * cn1 * cn2 + 1e-20)
+    # the terms that matter are resolved to 1e-5 of their own size
+    big = cn1 * cn2 > 1e-12
+    assert np.all(np.linalg.norm(g2 - L2, axis=0)[big] <= 1e-5 * cn2[big])
+    assert np.all(np.linalg.norm(T1 - L1, axis=0)[big] <= 1e-5 * cn1[big])
+
+
+@pytest.mark.parametrize("N,W,eps,b,prec", CASES)
+def test_eig_factorization_matches_oracle(N, W, eps, b, prec):
+    print(f"eig factorization N={N} W={W} eps={eps} b={b} {prec}", flush=True)
+    P, F = _setup(N, W, eps, prec, "eig")
     fac = _oracle(N, W, eps)
     kf, r = fac["kf"], fac["U"].shape[1]
     assert F.info["kf"] == kf and F.info["r"] == r
@@ -168,6 +246,11 @@ def test_factorization_errors():
         S.slepian_factor_create(P2)
     assert ei.value.status == S.SLEPIAN_ENOTSUP
     P3, F = _setup(1024, 1 / 16, 1e-6, "fp32")
+    import ctypes as C
+    h = C.c_void_p()
+    assert S._lib.slepian_factor_create_ex(P3.handle, 7, C.byref(h)) == S.SLEPIAN_EINVAL
+    mu = (C.c_double * 4)()
+    assert S._lib.slepian_factor_mu(F.handle, mu, 4) == S.SLEPIAN_ENOTSUP
     x = torch.zeros((2, 1024), device="cuda")
     c = torch.zeros((2, F.info["kprime"]), device="cuda")
     lib = S._lib
@@ -181,7 +264,8 @@ def test_factorization_errors():
     assert lib.slepian_factor_workspace_size(F.handle, 4, C.byref(ws)) == S.SLEPIAN_OK and ws.value > 0
 
 
-def test_factorization_random_configs():
+@pytest.mark.parametrize("method", ["theorem1", "eig"])
+def test_factorization_random_configs(method):
     """Seeded random plans (N = 2^8 .. 2^14, W in [0.01, 0.45], eps in {1e-3,
     1e-6, 1e-9}, 1..9 signals, FP32 or mixed): kf and r1 equal the oracle's
     and the round trip matches the oracle's within 1e-5 per signal."""
@@ -192,11 +276,14 @@ def test_factorization_random_configs():
         eps = float(rng.choice([1e-3, 1e-6, 1e-9]))
         b = int(rng.integers(1, 10))
         prec = str(rng.choice(["fp32", "mixed"]))
-        print(f"random factorization case {i}: N={N} W={W:.4f} eps={eps:g} b={b} {prec}", flush=True)
-        P, F = _setup(N, W, eps, prec)
-        fac = fz.fast_factorization(N, W, eps, method="eig")
+        print(f"random factorization case {i} ({method}): N={N} W={W:.4f} eps={eps:g} b={b} {prec}", flush=True)
+        P, F = _setup(N, W, eps, prec, method)
+        fac = fz.fast_factorization(N, W, eps, method=method)
         assert F.info["kf"] == fac["kf"]
-        _check_r1(F, fac, eps)
+        if method == "eig":
+            _check_r1(F, fac, eps)
+        else:
+            assert F.info["r1"] == fac["r1"]
         x = _x(N, b, 500 + i)
         y = S.slepian_factor_recover(F, S.slepian_factor_compress(F, torch.from_numpy(x.T.copy()).cuda()))
         y = y.cpu().numpy().astype(np.float64).T
@@ -212,7 +299,7 @@ def test_factorization_batch_slices():
     oracle's round trip, and the F part of the compression matches F_r^T x."""
     N, W, eps, b = 262144, 0.05, 1e-4, 130
     P, F = _setup(N, W, eps, "mixed")
-    fac = _oracle(N, W, eps)
+    fac = _oracle(N, W, eps, "theorem1")
     x = synth.gaussian(N, b, 77)
     xd = x.cuda()
     c = S.slepian_factor_compress(F, xd)
