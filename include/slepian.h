@@ -193,42 +193,71 @@ int slepian_project_ex(slepian_plan_t plan, int precision, const float *x, int64
                        float *y, int64_t ldy, int64_t batch, void *work, size_t work_bytes,
                        void *stream);
 
-/* Projection onto a multiband (modulated Slepian) dictionary (Section 1.4:
- * the Slepian basis modulated to several frequency bands and merged): for
- * band centres freqs[i] (cycles/sample; 0 for the baseband band, otherwise
+/* Multiband (modulated Slepian) dictionaries (Section 1.4, application i:
+ * the Slepian basis modulated to several frequency bands and merged).  Band
+ * centres freqs[i] (cycles/sample; 0 for the baseband band, otherwise
  * W <= f <= 1/2 - W; centres at least 2W apart, so the bands [f - W, f + W]
- * do not overlap)
- *     y = sum_i w_i Re(E_i P~ E_i^* x),  E_i = diag(exp(2 pi i f_i n)),
- * w_i = 2 for f_i > 0 (the band pair +-f_i of a real signal), 1 for f_i = 0,
- * P~ the plan's fast projection (Corollary 2) in the plan's precision.  The
- * sum is the projection onto the union of the modulated subspaces up to the
- * bands' mutual leakage.  x, y: N x batch FP32 real (y may equal x, no other
- * overlap); 1 <= nbands <= 64; EINVAL on bad bands.  Workspace:
- * slepian_workspace_size(plan, SLEPIAN_OP_MULTIBAND, nbands * batch). */
+ * do not overlap); the dictionary of a real signal is {E_f S_K} over
+ * f in {+-f_i}, E_f = diag(exp(2 pi i f n)).  Three calls:
+ *   - slepian_project_bands_span (prepared band set): the orthogonal
+ *     projection onto the dictionary's span;
+ *   - slepian_project_bands (prepared band set) and slepian_project_multiband
+ *     (no setup): the BAND SUM
+ *         y = sum_i w_i Re(E_i P~ E_i^* x),
+ *     w_i = 2 for f_i > 0 (the band pair +-f_i of a real signal), 1 for
+ *     f_i = 0, P~ the plan's fast projection (Corollary 2).  The band sum is
+ *     not a projection: the modulated subspaces are not orthogonal, and it
+ *     differs from the projection onto their span by their overlap (0.3% to
+ *     1.2% relative for white noise at N = 512..1024, W = 1/32, four bands).
+ *     It is the operator the span projection iterates on.
+ * slepian_project_multiband: band by band, in the plan's precision.  x, y:
+ * N x batch FP32 real (y may equal x, no other overlap); 1 <= nbands <= 64;
+ * EINVAL on bad bands.  Workspace: slepian_workspace_size(plan,
+ * SLEPIAN_OP_MULTIBAND, nbands * batch). */
 int slepian_project_multiband(slepian_plan_t plan, int nbands, const double *freqs, const float *x, int64_t ldx,
                               float *y, int64_t ldy, int64_t batch, void *work, size_t work_bytes, void *stream);
 
-/* Prepared band set for the same multiband projection (Section 1.4), computed
- * with one FFT product instead of one per band.  For real x,
- * Re(E_f B E_f^* x) is the Toeplitz product with the kernel
+/* Prepared band set, computed with one FFT product instead of one per band.
+ * For real x, Re(E_f B E_f^* x) is the Toeplitz product with the kernel
  * cos(2 pi f m) sin(2 pi W m)/(pi m), so the bands' B parts add up to one real
  * symmetric Toeplitz product, whose circulant spectrum (FP64 transform, stored
  * FP32) and a table of cos(2 pi f_i n), -sin(2 pi f_i n) (2 nbands x N FP32)
  * are built here; the correction parts form one correction of rank
  * 2 nbands r (r = the plan's transition count, at most 128, else ENOTSUP),
  * in the plan's precision (FP32, or BF16 hi/lo operands for MIXED and
- * BF16_RAW).  The result equals slepian_project_multiband's up to FP32
+ * BF16_RAW).  The band sum equals slepian_project_multiband's up to FP32
  * rounding.  The band rules and errors are slepian_project_multiband's; the
  * plan must outlive the band set.  Setup is synchronous. */
 int slepian_bands_create(slepian_plan_t plan, int nbands, const double *freqs, slepian_bands_t *out);
 int slepian_bands_destroy(slepian_bands_t bands);
 /* Workspace bytes of slepian_project_bands on `batch` signals. */
 int slepian_bands_workspace_size(slepian_bands_t bands, int64_t batch, size_t *bytes);
-/* y = sum_i w_i Re(E_i P~ E_i^* x) for the prepared bands; x, y: N x batch
- * FP32 real (y may equal x, no other overlap); batch == 0 is a no-op;
- * ENOTSUP when the batch exceeds the launch limits of the correction. */
+/* The band sum y = sum_i w_i Re(E_i P~ E_i^* x) for the prepared bands; x, y:
+ * N x batch FP32 real (y may equal x, no other overlap); batch == 0 is a
+ * no-op; ENOTSUP when the batch exceeds the launch limits of the correction. */
 int slepian_project_bands(slepian_bands_t bands, const float *x, int64_t ldx, float *y, int64_t ldy,
                           int64_t batch, void *work, size_t work_bytes, void *stream);
+/* Workspace bytes of slepian_project_bands_span on `batch` signals. */
+int slepian_bands_span_workspace_size(slepian_bands_t bands, int64_t batch, size_t *bytes);
+/* The orthogonal projection of each real signal onto the span of the band
+ * set's modulated Slepian dictionary, by conjugate gradients on the band sum
+ * A (above): A z = A x from z = 0, so the iterates stay in A's range, whose
+ * solution is that projection when the bands' projections are exact.  Per
+ * signal: a = rr / (p . Ap), z += a p, r -= a Ap, beta = rr_new / rr,
+ * p = r + beta p, stopping once ||r|| <= tol ||A x|| (before the iteration
+ * starts to resolve the eigenvalues of at most about eps that the fast
+ * projections leave outside the span).  Vectors FP32, dot products and
+ * scalars FP64 in a fixed order, A in the plan's precision.  Result within a
+ * few eps ||x|| of the exact projection onto the span (the bound the tests
+ * hold: 2 J eps, J the number of modulated bases).  tol = 0 selects
+ * max(eps, 1e-6); else 1e-6 <= tol < 1/2.  1 <= max_iter <= 1000.  x, y:
+ * N x batch FP32 (y may equal x, no other overlap).  iters (host, nullable,
+ * batch entries) receives each signal's steps.  Synchronous (one small
+ * device-to-host copy per step).  Returns SLEPIAN_ENOCONV, with y holding
+ * the last iterate, if some signal has not met tol after max_iter steps. */
+int slepian_project_bands_span(slepian_bands_t bands, const float *x, int64_t ldx, float *y, int64_t ldy,
+                               int64_t batch, double tol, int max_iter, void *work, size_t work_bytes,
+                               void *stream, int *iters);
 
 /* Fast factorization S_K S_K^T ~= T1 T2^T (Section 1.3, "A fast
  * factorization", with Theorem 1):

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libslepian.so")
 
-SOURCES = ["fft.hip", "fft2.hip", "eig.hip", "corr.hip", "corr_mfma.hip", "lsq.hip", "multiband.hip", "gemm.hip", "factor.hip",
+SOURCES = ["fft.hip", "fft2.hip", "eig.hip", "corr.hip", "corr_mfma.hip", "lsq.hip", "multiband.hip", "gemm.hip", "factor.hip", "mbcg.hip",
            "capi.cpp",
            "trace.cpp"]
 ARCH = os.environ.get("SLEPIAN_ARCH", "gfx950")

@@ -104,6 +104,7 @@ size_t slice_budget() {
   return v;
 }
 constexpr int kMaxLogL = 22;                          // N <= 2^21
+constexpr double kSpanMinTol = 1e-6;                  // FP32 vectors: the span projection's smallest tolerance
 constexpr size_t kCoeffsCap = (size_t)16 << 30;       // bytes of S_K kept for slepian_coeffs
 
 int ilog2_ceil(int64_t v) {
@@ -1240,6 +1241,47 @@ int slepian_bands_workspace_size(slepian_bands_t B, int64_t batch, size_t *bytes
   return SLEPIAN_OK;
 }
 
+namespace {
+
+// y = sum_i w_i Re(E_i P~ E_i^* x) for the prepared bands, with the band
+// sum's workspace at ws (bands_workspace bytes); y may equal x.
+void bands_apply(slepian_bands_s *B, const float *x, int64_t ldx, float *y, int64_t ldy, int64_t batch, void *ws,
+                 hipStream_t st) {
+  Plan *P = B->P;
+  const int64_t N = P->N;
+  const int r = (int)P->proj.r;
+  const MbShape sh = mb_shape(N, batch, r, B->bs.J);
+  Carver cv(ws);
+  const int64_t pairs = (batch + 1) / 2;
+  const int64_t slice = (int64_t)conv_workspace_pairs(P->g32, pairs, sizeof(cpx<float>), slice_budget());
+  cpx<float> *Z = P->g32.single() ? nullptr : cv.take<cpx<float>>((size_t)slice * (size_t)P->L);
+  MbWs mw;
+  if (r > 0) mw = mb_carve(sh, batch, cv.take<char>(mb_workspace_bytes(sh, batch)));
+  // the coefficients read x before the product writes y (which may be x)
+  HIPCHK(mb_coeffs(B->mode, x, ldx, N, batch, B->u, r, P->proj.d32, B->M, B->ldm, B->bs, sh, mw, st));
+  FftTables<float> tb = P->tb32;
+  tb.chat = B->chat32;
+  HIPCHK(conv_apply<float>(x, ldx, y, ldy, N, batch, P->g32, tb, 1.0f, 0.0f, Corr<float>(), Z, slice, st));
+  HIPCHK(mb_apply(B->mode, y, ldy, N, batch, B->u, r, B->M, B->ldm, sh, mw, st));
+}
+
+int64_t span_ld(int64_t N) { return (N + 63) / 64 * 64; }
+
+// The span projection's workspace: the band sum's, then r, p and A p
+// (leading dimension span_ld(N)), the dot products' chunk partials and one
+// iteration record per signal.
+size_t bands_span_workspace(const slepian_bands_s *B, int64_t b) {
+  const int64_t N = B->P->N;
+  Carver cv(nullptr);
+  cv.take<char>(bands_workspace(B, b));
+  cv.take<float>((size_t)span_ld(N) * b * 3);
+  cv.take<double>((size_t)cg_nchunks(N) * b);
+  cv.take<CgState>((size_t)b);
+  return cv.off + 256;
+}
+
+}  // namespace
+
 int slepian_project_bands(slepian_bands_t B, const float *x, int64_t ldx, float *y, int64_t ldy, int64_t batch,
                           void *work, size_t work_bytes, void *stream) {
   if (!B) return SLEPIAN_EINVAL;
@@ -1252,22 +1294,67 @@ int slepian_project_bands(slepian_bands_t B, const float *x, int64_t ldx, float 
   if (r > 0 && !mb_ok(sh, P->N, batch, r)) return SLEPIAN_ENOTSUP;
   return guarded([&]() -> int {
     DeviceGuard dg(P->device);
-    hipStream_t st = (hipStream_t)stream;
-    const int64_t N = P->N;
     void *ws = get_ws(P, work, work_bytes, bands_workspace(B, batch));
-    Carver cv(ws);
-    const int64_t pairs = (batch + 1) / 2;
-    const int64_t slice = (int64_t)conv_workspace_pairs(P->g32, pairs, sizeof(cpx<float>), slice_budget());
-    cpx<float> *Z = P->g32.single() ? nullptr : cv.take<cpx<float>>((size_t)slice * (size_t)P->L);
-    MbWs mw;
-    if (r > 0) mw = mb_carve(sh, batch, cv.take<char>(mb_workspace_bytes(sh, batch)));
-    // the coefficients read x before the product writes y (which may be x)
-    HIPCHK(mb_coeffs(B->mode, x, ldx, N, batch, B->u, r, P->proj.d32, B->M, B->ldm, B->bs, sh, mw, st));
-    FftTables<float> tb = P->tb32;
-    tb.chat = B->chat32;
-    HIPCHK(conv_apply<float>(x, ldx, y, ldy, N, batch, P->g32, tb, 1.0f, 0.0f, Corr<float>(), Z, slice, st));
-    HIPCHK(mb_apply(B->mode, y, ldy, N, batch, B->u, r, B->M, B->ldm, sh, mw, st));
+    bands_apply(B, x, ldx, y, ldy, batch, ws, (hipStream_t)stream);
     return SLEPIAN_OK;
+  });
+}
+
+int slepian_bands_span_workspace_size(slepian_bands_t B, int64_t batch, size_t *bytes) {
+  if (!B || !bytes || batch < 0) return SLEPIAN_EINVAL;
+  *bytes = bands_span_workspace(B, batch);
+  return SLEPIAN_OK;
+}
+
+int slepian_project_bands_span(slepian_bands_t B, const float *x, int64_t ldx, float *y, int64_t ldy,
+                               int64_t batch, double tol, int max_iter, void *work, size_t work_bytes, void *stream,
+                               int *iters) {
+  if (!B) return SLEPIAN_EINVAL;
+  Plan *P = B->P;
+  if (bad_signal_args(P, x, ldx, y, ldy, batch)) return SLEPIAN_EINVAL;
+  if (tol == 0.0) tol = std::max(P->eps, kSpanMinTol);
+  if (!(tol >= kSpanMinTol && tol < 0.5) || max_iter < 1 || max_iter > 1000) return SLEPIAN_EINVAL;
+  if (batch == 0) return SLEPIAN_OK;
+  if (overlapping(x, ldx, y, ldy, P->N, batch)) return SLEPIAN_EINVAL;
+  const int r = (int)P->proj.r;
+  const MbShape sh = mb_shape(P->N, batch, r, B->bs.J);
+  if (r > 0 && !mb_ok(sh, P->N, batch, r)) return SLEPIAN_ENOTSUP;
+  return guarded([&]() -> int {
+    DeviceGuard dg(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = P->N, ldw = span_ld(N);
+    void *ws = get_ws(P, work, work_bytes, bands_span_workspace(B, batch));
+    Carver cv(ws);
+    void *wa = cv.take<char>(bands_workspace(B, batch));
+    float *rv = cv.take<float>((size_t)ldw * batch);
+    float *pv = cv.take<float>((size_t)ldw * batch);
+    float *ap = cv.take<float>((size_t)ldw * batch);
+    double *part = cv.take<double>((size_t)cg_nchunks(N) * batch);
+    CgState *state = cv.take<CgState>((size_t)batch);
+    // r = A x (x is not read again, so y may be x), z = 0, p = r
+    bands_apply(B, x, ldx, rv, ldw, batch, wa, st);
+    HIPCHK(cg_dot(rv, ldw, rv, ldw, N, batch, part, st));
+    HIPCHK(cg_init(part, N, batch, tol, state, st));
+    HIPCHK(fill_zero_rows(y, ldy, N, batch, st));
+    HIPCHK(copy_rows(rv, ldw, pv, ldw, N, batch, st));
+    std::vector<CgState> hs((size_t)batch);
+    bool any = true;
+    for (int k = 0; k <= max_iter; ++k) {
+      HIPCHK(hipMemcpyAsync(hs.data(), state, (size_t)batch * sizeof(CgState), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      any = false;
+      for (const CgState &q : hs) any = any || q.active;
+      if (!any || k == max_iter) break;
+      bands_apply(B, pv, ldw, ap, ldw, batch, wa, st);
+      HIPCHK(cg_dot(pv, ldw, ap, ldw, N, batch, part, st));
+      HIPCHK(cg_alpha(part, N, batch, state, st));
+      HIPCHK(cg_update(y, ldy, rv, pv, ap, ldw, N, batch, state, part, st));
+      HIPCHK(cg_beta(part, N, batch, tol, state, st));
+      HIPCHK(cg_direction(pv, rv, ldw, N, batch, state, st));
+    }
+    if (iters)
+      for (int64_t s = 0; s < batch; ++s) iters[s] = hs[(size_t)s].iters;
+    return any ? SLEPIAN_ENOCONV : SLEPIAN_OK;
   });
 }
 

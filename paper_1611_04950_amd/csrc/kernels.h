@@ -215,6 +215,26 @@ int coeffs_gemm(int device, int mode, const void *S, const void *Slo, int64_t ld
                 int64_t ldx, float *c, int64_t ldc, int64_t N, int64_t K, int64_t b, void *ws, size_t ws_bytes,
                 GemmCache &cache, hipStream_t st);
 
+// ---- Conjugate gradients on a multiband band-sum operator (mbcg.hip) ----
+constexpr int kCgChunk = 8192;  // samples per chunk of the fixed-order FP64 dot products
+struct CgState {
+  double rr, nb2, a, beta;  // ||r||^2, ||A x||^2, step, direction weight
+  int iters, active, upd;   // steps taken; still iterating; direction updated in the last step
+  int pad;
+};
+int cg_nchunks(int64_t N);
+hipError_t cg_dot(const float *u, int64_t ldu, const float *v, int64_t ldv, int64_t N, int64_t b, double *part,
+                  hipStream_t st);
+hipError_t cg_init(const double *part, int64_t N, int64_t b, double tol, CgState *state, hipStream_t st);
+hipError_t cg_alpha(const double *part, int64_t N, int64_t b, CgState *state, hipStream_t st);
+hipError_t cg_update(float *z, int64_t ldz, float *r, const float *p, const float *ap, int64_t ldw, int64_t N,
+                     int64_t b, const CgState *state, double *part, hipStream_t st);
+hipError_t cg_beta(const double *part, int64_t N, int64_t b, double tol, CgState *state, hipStream_t st);
+hipError_t cg_direction(float *p, const float *r, int64_t ldw, int64_t N, int64_t b, const CgState *state,
+                        hipStream_t st);
+hipError_t fill_zero_rows(float *y, int64_t ldy, int64_t N, int64_t b, hipStream_t st);
+hipError_t copy_rows(const float *src, int64_t lds, float *dst, int64_t ldd, int64_t N, int64_t b, hipStream_t st);
+
 // ---- Fast factorization T1 T2^T (fft2.hip, factor.hip) ----
 // Length-N DFT bins |k| <= M = (kf - 1)/2 of signal pairs through the FP32
 // product's geometry g (L = 2N): forward from x into Zb (kf bins per pair,

@@ -40,7 +40,8 @@ EXPORTED = [
     "slepian_plan", "slepian_plan_ex", "slepian_plan_batch", "slepian_plan_info_get", "slepian_plan_eigenpairs",
     "slepian_plan_save", "slepian_plan_load", "slepian_plan_destroy", "slepian_workspace_size",
     "slepian_project", "slepian_project_ex", "slepian_project_noalloc", "slepian_project_multiband", "slepian_bands_create",
-    "slepian_bands_destroy", "slepian_bands_workspace_size", "slepian_project_bands", "slepian_coeffs", "slepian_lsq",
+    "slepian_bands_destroy", "slepian_bands_workspace_size", "slepian_project_bands",
+    "slepian_bands_span_workspace_size", "slepian_project_bands_span", "slepian_coeffs", "slepian_lsq",
     "slepian_factor_create", "slepian_factor_create_ex", "slepian_factor_destroy", "slepian_factor_info", "slepian_factor_mu",
     "slepian_factor_workspace_size", "slepian_factor_compress", "slepian_factor_recover",
     "slepian_apply_b64",
@@ -103,6 +104,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "slepian_bands_destroy": [vp],
         "slepian_bands_workspace_size": [vp, i64, C.POINTER(sz)],
         "slepian_project_bands": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
+        "slepian_bands_span_workspace_size": [vp, i64, C.POINTER(sz)],
+        "slepian_project_bands_span": [vp, vp, i64, vp, i64, i64, dbl, i32, vp, sz, vp, C.POINTER(i32)],
         "slepian_coeffs": [vp, vp, i64, vp, i64, i64, vp, sz, vp],
         "slepian_factor_create": [vp, C.POINTER(vp)],
         "slepian_factor_create_ex": [vp, i32, C.POINTER(vp)],
@@ -272,8 +275,9 @@ def slepian_project_noalloc(plan: Plan, x: torch.Tensor, y: torch.Tensor) -> tor
 
 def slepian_project_multiband(plan: Plan, freqs, x: torch.Tensor, y: torch.Tensor | None = None,
                               work: torch.Tensor | None = None) -> torch.Tensor:
-    """Projection onto the union of the Slepian subspaces modulated to the
-    band centres `freqs` (see include/slepian.h)."""
+    """Band sum of the Slepian projections modulated to the band centres
+    `freqs`, band by band (see include/slepian.h; the projection onto the
+    dictionary's span is slepian_project_bands_span)."""
     x, ldx = _signals(x, plan.N, torch.float32, "x")
     if y is None:
         y = torch.empty_like(x)
@@ -391,6 +395,35 @@ def slepian_project_bands(bands: Bands, x: torch.Tensor, y: torch.Tensor | None 
     _check(_lib.slepian_project_bands(bands.handle, _ptr(x), ldx, _ptr(y), ldy, x.shape[0], _ptr(work), wb,
                                       _stream(x)), "slepian_project_bands")
     return y
+
+
+def slepian_bands_span_workspace_size(bands: Bands, batch: int) -> int:
+    n = C.c_size_t()
+    _check(_lib.slepian_bands_span_workspace_size(bands.handle, batch, C.byref(n)),
+           "slepian_bands_span_workspace_size")
+    return n.value
+
+
+def slepian_project_bands_span(bands: Bands, x: torch.Tensor, y: torch.Tensor | None = None, tol: float = 0.0,
+                               max_iter: int = 100, work: torch.Tensor | None = None, check: bool = True):
+    """Orthogonal projection onto the span of the band set's modulated
+    Slepian dictionary (conjugate gradients on the band sum); returns
+    (y, iterations per signal).  With check=False a non-convergence
+    (SLEPIAN_ENOCONV) is returned in place of raising."""
+    N = bands.plan.N
+    x, ldx = _signals(x, N, torch.float32, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    y, ldy = _signals(y, N, torch.float32, "y")
+    wb = 0 if work is None else work.numel() * work.element_size()
+    b = x.shape[0]
+    it = (C.c_int32 * max(b, 1))()
+    st = _lib.slepian_project_bands_span(bands.handle, _ptr(x), ldx, _ptr(y), ldy, b, float(tol), int(max_iter),
+                                         _ptr(work), wb, _stream(x), it)
+    if check:
+        _check(st, "slepian_project_bands_span")
+    iters = [it[i] for i in range(b)]
+    return (y, iters) if check else (y, iters, st)
 
 
 def slepian_coeffs(plan: Plan, x: torch.Tensor, c: torch.Tensor | None = None,

@@ -1,7 +1,12 @@
-"""Multiband (modulated Slepian) dictionary projection on the GPU (Section
-2.3): the library's band-by-band sum y = sum_i w_i Re(E_i P~ E_i^* x)
-against the FP64 oracle's (1e-5 relative per signal, FP32 and mixed
-plans), in place, and the band validation of the C entry point."""
+"""Multiband (modulated Slepian) dictionaries on the GPU (Section 1.4,
+application i): the projection onto the span of the modulated dictionary
+(conjugate gradients on the band sum, slepian_project_bands_span) against
+the FP64 oracle's same iteration (1e-5 relative per signal, FP32 and mixed
+plans, N = 512..4096 with 2 to 8 bands, and sampled signals at N = 2^16) and
+against the dense projection onto the span; the band sum
+y = sum_i w_i Re(E_i P~ E_i^* x) band by band against the oracle's; in
+place, the iteration's failure return, and the band validation of the C
+entry point."""
 
 import numpy as np
 import pytest
@@ -38,6 +43,81 @@ def test_multiband_matches_oracle(N, W, eps, bands, prec):
     S.slepian_project_multiband(P, bands, z, z)
     torch.cuda.synchronize()
     assert torch.equal(z, y)
+
+
+SPAN_CASES = [(512, 1 / 32, 1e-6, [0.0, 0.125, 0.25, 0.375]),
+              (1024, 1 / 64, 1e-6, [1 / 64, 3 / 64, 5 / 64, 7 / 64, 9 / 64]),
+              (2048, 1 / 128, 1e-6, [1 / 32 + k / 16 for k in range(8)]),
+              (4096, 1 / 64, 1e-3, [0.05, 0.2, 0.41]),
+              (3001, 0.02, 1e-6, [0.0, 0.3])]
+
+
+@pytest.mark.parametrize("N,W,eps,bands", SPAN_CASES)
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_span_projection_matches_oracle(N, W, eps, bands, prec):
+    print(f"span projection N={N} W={W} eps={eps} bands={len(bands)} {prec}", flush=True)
+    P = S.slepian_plan(N, W, eps, precision=S.SLEPIAN_MIXED if prec == "mixed" else S.SLEPIAN_FP32)
+    B = S.slepian_bands_create(P, bands)
+    x = synth.gaussian(N, 4, 93, device="cuda")
+    y, it = S.slepian_project_bands_span(B, x)
+    torch.cuda.synchronize()
+    xh = x.double().cpu().numpy().T
+    tol = max(eps, 1e-6)
+    ref, it_o = o.multiband_projection(N, W, eps, bands, xh, tol=tol)
+    e = _rel(y.double().cpu().numpy(), ref.T)
+    print(f"  steps GPU {it}, oracle {list(it_o)}; max rel diff {e.max():.2e}", flush=True)
+    assert e.max() <= 1e-5, e
+    assert all(abs(a - b) <= 1 for a, b in zip(it, it_o))
+    if N <= 2048:
+        ex = o.multiband_exact(N, W, bands, xh).T
+        J = sum(2 if f > 0 else 1 for f in bands)
+        d = np.linalg.norm(y.double().cpu().numpy() - ex, axis=1) / np.linalg.norm(xh.T, axis=1)
+        assert d.max() <= 2 * J * eps + 1e-5
+
+
+def test_span_projection_sampled_at_2p16():
+    """N = 2^16, W = 1/64, four bands, 6 signals on the GPU; signals 0 and 5
+    against the oracle's iteration."""
+    N, W, eps = 1 << 16, 1 / 64, 1e-6
+    bands = [0.0, 0.1, 0.25, 0.4]
+    P = S.slepian_plan(N, W, eps, precision=S.SLEPIAN_MIXED)
+    B = S.slepian_bands_create(P, bands)
+    x = synth.gaussian(N, 6, 95, device="cuda")
+    y, it = S.slepian_project_bands_span(B, x)
+    torch.cuda.synchronize()
+    pick = [0, 5]
+    xh = x[pick].double().cpu().numpy().T
+    ref, it_o = o.multiband_projection(N, W, eps, bands, xh, tol=eps)
+    e = _rel(y[pick].double().cpu().numpy(), ref.T)
+    print(f"  N=2^16 steps GPU {it}, oracle {list(it_o)}; max rel diff {e.max():.2e}", flush=True)
+    assert e.max() <= 1e-5, e
+
+
+def test_span_projection_in_place_workspace_and_failure():
+    N, W, eps = 2048, 1 / 64, 1e-6
+    P = S.slepian_plan(N, W, eps)
+    B = S.slepian_bands_create(P, [0.0, 0.25])
+    x = synth.gaussian(N, 3, 7, device="cuda")
+    y, it = S.slepian_project_bands_span(B, x)
+    z = x.clone()
+    nbytes = S.slepian_bands_span_workspace_size(B, 3)
+    assert nbytes >= 3 * 3 * N * 4
+    work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    z2, it2 = S.slepian_project_bands_span(B, z, z, work=work)
+    torch.cuda.synchronize()
+    assert torch.equal(z, y) and it2 == it
+    # one step cannot meet the tolerance: ENOCONV, the first iterate kept
+    y1, it1, st = S.slepian_project_bands_span(B, x, max_iter=1, check=False)
+    assert st == S.SLEPIAN_ENOCONV and it1 == [1, 1, 1]
+    # bad tolerances and step counts
+    for tol, mi in ((1e-8, 10), (0.5, 10), (1e-3, 0), (1e-3, 1001)):
+        with pytest.raises(S.SlepianError) as ei:
+            S.slepian_project_bands_span(B, x, tol=tol, max_iter=mi)
+        assert ei.value.status == S.SLEPIAN_EINVAL
+    # a zero signal stops at once with a zero projection
+    y0, it0 = S.slepian_project_bands_span(B, torch.zeros((2, N), device="cuda"))
+    torch.cuda.synchronize()
+    assert it0 == [0, 0] and bool((y0 == 0).all())
 
 
 def test_bad_bands_rejected():
