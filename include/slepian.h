@@ -54,9 +54,12 @@ enum slepian_status {
   SLEPIAN_EHIP = -4,       /* a HIP runtime call failed */
   SLEPIAN_ENOCONV = -5,    /* eigensolver check or iterative refinement did not converge */
   SLEPIAN_ENOTSUP = -6,    /* size or mode the library does not support  */
-  SLEPIAN_ENONFINITE = -7, /* NaN or Inf found where finite values are required */
+  SLEPIAN_ENONFINITE = -7, /* NaN or Inf in the input, seen by the synchronous iterative calls
+                              (slepian_lsq when it computes residuals, slepian_project_bands_span)
+                              as a non-finite norm; the asynchronous calls do not check */
   SLEPIAN_EIO = -8,        /* plan file could not be read or written, or is malformed */
-  SLEPIAN_ESCRATCH = -9    /* slepian_project_noalloc: two signals need more than its fixed scratch */
+  SLEPIAN_ESCRATCH = -9,   /* slepian_project_noalloc: two signals need more than its fixed scratch */
+  SLEPIAN_EINTERNAL = -10  /* unexpected internal failure (a bug; please report) */
 };
 
 /* Arithmetic of the low-rank correction (the B x product is always FP32). */

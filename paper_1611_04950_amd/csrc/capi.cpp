@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <new>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -866,8 +867,10 @@ int guarded(F &&f) {
     return f();
   } catch (const Fail &e) {
     return e.status;
-  } catch (...) {
+  } catch (const std::bad_alloc &) {
     return SLEPIAN_ENOMEM;
+  } catch (...) {
+    return SLEPIAN_EINTERNAL;
   }
 }
 
@@ -981,6 +984,7 @@ const char *slepian_status_string(int s) {
     case SLEPIAN_ENONFINITE: return "non-finite value";
     case SLEPIAN_EIO: return "plan file error";
     case SLEPIAN_ESCRATCH: return "needs more scratch than the allocation-free entry point holds";
+    case SLEPIAN_EINTERNAL: return "internal error";
     default: return "unknown status";
   }
 }
@@ -1343,7 +1347,11 @@ int slepian_project_bands_span(slepian_bands_t B, const float *x, int64_t ldx, f
       HIPCHK(hipMemcpyAsync(hs.data(), state, (size_t)batch * sizeof(CgState), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       any = false;
-      for (const CgState &q : hs) any = any || q.active;
+      for (const CgState &q : hs) {
+        // a NaN or Inf in x shows up in ||A x||^2 and the residual norms
+        if (!std::isfinite(q.nb2) || !std::isfinite(q.rr)) return SLEPIAN_ENONFINITE;
+        any = any || q.active;
+      }
       if (!any || k == max_iter) break;
       bands_apply(B, pv, ldw, ap, ldw, batch, wa, st);
       HIPCHK(cg_dot(pv, ldw, ap, ldw, N, batch, part, st));
@@ -2028,6 +2036,8 @@ int slepian_lsq(slepian_plan_t P, int mode, double alpha, const float *y, int64_
       HIPCHK(hipStreamSynchronize(st));
       rel = 0.0;
       for (int64_t s = 0; s < b; ++s) {
+        // a NaN or Inf in y (or produced from it) shows up in these norms
+        if (!std::isfinite(nBy[s]) || !std::isfinite(nr[s])) return SLEPIAN_ENONFINITE;
         const double v = nBy[s] > 0 ? nr[s] / nBy[s] : (nr[s] > 0 ? INFINITY : 0.0);
         rel = std::max(rel, v);
       }
@@ -2209,21 +2219,41 @@ int slepian_plan_save(slepian_plan_t P, const char *path) {
 
 int slepian_plan_load(const char *path, int device, slepian_plan_t *out) {
   if (!path || !out) return SLEPIAN_EINVAL;
+  *out = nullptr;
   return guarded([&]() -> int {
+    // the whole file is read and checked on the host before any device work
     FILE *f = std::fopen(path, "rb");
     if (!f) return SLEPIAN_EIO;
-    FileHeader h;
-    auto bad = [&]() {
+    std::vector<char> buf;
+    {
+      char chunk[1 << 16];
+      size_t got;
+      while ((got = std::fread(chunk, 1, sizeof(chunk), f)) > 0) {
+        buf.insert(buf.end(), chunk, chunk + got);
+        if (buf.size() > ((size_t)1 << 36)) break;  // larger than any valid plan
+      }
       std::fclose(f);
-      return SLEPIAN_EIO;
-    };
-    if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, kMagic, 8) != 0) return bad();
+    }
+    FileHeader h;
+    if (buf.size() < sizeof(h)) return SLEPIAN_EIO;
+    std::memcpy(&h, buf.data(), sizeof(h));
+    if (std::memcmp(h.magic, kMagic, 8) != 0) return SLEPIAN_EIO;
     slepian_plan_opts o{h.alpha, h.K, h.precision, device};
-    if (validate_domain(h.N, h.W, h.eps, &o) != SLEPIAN_OK) return bad();
+    if (validate_domain(h.N, h.W, h.eps, &o) != SLEPIAN_OK) return SLEPIAN_EIO;
+    if (h.win_lo < 0 || h.win_hi < h.win_lo || h.win_hi >= h.N) return SLEPIAN_EIO;
     const int64_t nw = h.win_hi - h.win_lo + 1;
-    if (nw < 1 || nw > h.N || h.u_r < 0 || h.u_r > nw || h.proj_r < 0 || h.tik_r < 0 ||
-        h.proj_off < 0 || h.tik_off < 0 || h.proj_off + h.proj_r > h.u_r || h.tik_off + h.tik_r > h.u_r)
-      return bad();
+    if (h.u_r < 0 || h.u_r > nw || h.proj_r < 0 || h.tik_r < 0 || h.proj_off < 0 || h.tik_off < 0 ||
+        h.proj_off + h.proj_r > h.u_r || h.tik_off + h.tik_r > h.u_r || h.u_l0 < h.win_lo ||
+        h.u_l0 + h.u_r > h.win_hi + 1)
+      return SLEPIAN_EIO;
+    // sizes are bounded by the checks above (N <= 2^21, u_r <= nw <= N), so
+    // the expected length is computed without overflow and compared exactly
+    const size_t want = sizeof(h) + sizeof(double) * ((size_t)nw + 2 * (size_t)h.proj_r + 2 * (size_t)h.tik_r +
+                                                      (size_t)h.N * (size_t)h.u_r);
+    if (buf.size() != want) return SLEPIAN_EIO;
+    const double *body = reinterpret_cast<const double *>(buf.data() + sizeof(h));
+    for (size_t k = 0; k < (want - sizeof(h)) / sizeof(double); ++k)
+      if (!std::isfinite(body[k])) return SLEPIAN_EIO;
     int dev = device;
     if (dev < 0) HIPCHK(hipGetDevice(&dev));
     DeviceGuard dg(dev);
@@ -2243,21 +2273,18 @@ int slepian_plan_load(const char *path, int device, slepian_plan_t *out) {
       P->lam_Km1 = h.lam_Km1;
       P->lam_K = h.lam_K;
       P->eps_ach = h.eps_ach;
-      P->lam.resize(nw);
-      bool ok = std::fread(P->lam.data(), sizeof(double), nw, f) == (size_t)nw;
+      const double *q = body;
+      P->lam.assign(q, q + nw);
+      q += nw;
       P->proj.off = P->pinv.off = h.proj_off;
       P->proj.r = P->pinv.r = h.proj_r;
       P->tik.off = P->tikm.off = h.tik_off;
       P->tik.r = P->tikm.r = h.tik_r;
       for (OpSet *op : {&P->proj, &P->pinv, &P->tik, &P->tikm}) {
-        op->d.resize(op->r);
-        ok = ok && std::fread(op->d.data(), sizeof(double), op->r, f) == (size_t)op->r;
+        op->d.assign(q, q + op->r);
+        q += op->r;
       }
-      std::vector<double> U((size_t)P->N * P->u_r);
-      ok = ok && std::fread(U.data(), sizeof(double), U.size(), f) == U.size();
-      std::fclose(f);
-      f = nullptr;
-      if (!ok) throw Fail{SLEPIAN_EIO};
+      std::vector<double> U(q, q + (size_t)P->N * P->u_r);
       hipStream_t st = nullptr;
       HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
       try {
@@ -2279,7 +2306,6 @@ int slepian_plan_load(const char *path, int device, slepian_plan_t *out) {
       for (OpSet *op : {&P->proj, &P->pinv, &P->tik, &P->tikm}) upload_d(*op);
       build_corr_tiles(P, nullptr);
     } catch (...) {
-      if (f) std::fclose(f);
       delete P;
       throw;
     }

@@ -30,6 +30,7 @@ SLEPIAN_ENOTSUP = -6
 SLEPIAN_ENONFINITE = -7
 SLEPIAN_EIO = -8
 SLEPIAN_ESCRATCH = -9
+SLEPIAN_EINTERNAL = -10
 
 SLEPIAN_FP32, SLEPIAN_MIXED, SLEPIAN_BF16_RAW = 0, 1, 2
 SLEPIAN_PINV, SLEPIAN_TIKHONOV = 0, 1

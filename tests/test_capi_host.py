@@ -136,3 +136,51 @@ def test_header_is_plain_c():
         r = subprocess.run([cc, "-fsyntax-only", "-Wall", "-Wextra", "-Werror", *args, hdr], capture_output=True,
                            text=True)
         assert r.returncode == 0, r.stderr
+
+
+def test_host_code_under_address_and_ub_sanitizers(tmp_path):
+    """The library's host code (argument checks, plan-file parser) built with
+    AddressSanitizer and UndefinedBehaviorSanitizer (host pass only) and
+    driven by tests/host_sanitize_main.c: null and out-of-domain arguments on
+    every entry point, and malformed plan files.  No GPU is needed: the
+    checks run before any device work."""
+    import shutil
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    hipcc = "/opt/rocm/bin/hipcc"
+    clang = "/opt/rocm/llvm/bin/clang++"
+    if not (os.path.exists(hipcc) and os.path.exists(clang) and shutil.which("gcc")):
+        pytest.skip("ROCm compilers not available")
+    from paper_1611_04950_amd import build as B
+    objdir = os.path.join(root, "_build")
+    plain = [os.path.join(objdir, os.path.splitext(f)[0] + ".o") for f in B.SOURCES
+             if f not in ("capi.cpp", "trace.cpp")]
+    if not all(os.path.exists(o) for o in plain):
+        B.build()
+    out = tmp_path
+    flags = ["--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang",
+             "-packed-fp32-ops", f"-I{os.path.join(root, 'include')}", f"-I{B.CSRC}", "-Wno-unused-result",
+             "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+    objs = []
+    for src in ("capi.cpp", "trace.cpp"):
+        o = str(out / (src + ".o"))
+        r = subprocess.run([hipcc, *flags, "-x", "hip", "-c", os.path.join(B.CSRC, src), "-o", o],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr[-3000:]
+        objs.append(o)
+    main_o = str(out / "main.o")
+    r = subprocess.run(["gcc", "-std=c99", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                        f"-I{os.path.join(root, 'include')}", "-c", os.path.join(root, "tests", "host_sanitize_main.c"),
+                        "-o", main_o], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    exe = str(out / "host_check")
+    r = subprocess.run([clang, "-fsanitize=address,undefined", main_o, *objs, *plain, "-L/opt/rocm/lib",
+                        "-lamdhip64", "-lhipblaslt", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib", "-o", exe],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([exe, str(out)], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, (r.stdout + r.stderr)[-4000:]
+    assert "host checks passed" in r.stdout
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr
