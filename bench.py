@@ -82,23 +82,31 @@ def kernel_bytes(name: str, N: int, b: int, L: int, r: int, pairs_per_launch: in
 
 
 def read_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken with the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.md")
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    for line in open(path):
-        if ":" in line and line.startswith("- "):
-            k, v = line[2:].split(":", 1)
-            vals[k.strip()] = v.strip()
+    """HBM bytes per launch from a committed rocprofv3 counter summary
+    (profiles/traffic_<kernel>.md or traffic_<kernel>_<tag>.md) taken on this
+    workload with the current kernel sources; else None."""
+    import glob
     try:
         from paper_1611_04950_amd.build import source_digest
-        if vals.get("source_digest") != source_digest() or vals.get("workload") != workload:
-            return None
-        return float(vals["hbm_bytes_per_launch"])
+        digest = source_digest()
     except Exception:
         return None
+    paths = [os.path.join(ROOT, "profiles", f"traffic_{kernel}.md")] + \
+        sorted(glob.glob(os.path.join(ROOT, "profiles", f"traffic_{kernel}_*.md")))
+    for path in paths:
+        if not os.path.exists(path):
+            continue
+        vals = {}
+        for line in open(path):
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip()
+        if vals.get("source_digest") == digest and vals.get("workload") == workload:
+            try:
+                return float(vals["hbm_bytes_per_launch"])
+            except (KeyError, ValueError):
+                return None
+    return None
 
 
 def copy_bandwidth(dev, mib=256, reps=10):
@@ -170,10 +178,197 @@ def cpu_baseline(N, W, eps, x_sample, min_seconds):
             "cores": 1, "kind": "oracle",
             "sample": f"{xs.shape[1]} signals of the workload, compressed and recovered {freps} times ({fel:.1f} s); "
                       f"oracle setup {fsetup:.1f} s not included", "setup_s": fsetup}
+    # the same fast projection with every host core (FFT workers and BLAS threads)
+    import scipy.fft as sfft
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    with threadpool_limits(limits=ncores), sfft.set_workers(ncores):
+        mreps = 0
+        t0 = time.perf_counter()
+        while True:
+            o.project_fast(N, W, eps, xs, tp=tp)
+            mreps += 1
+            mel = time.perf_counter() - t0
+            if mel >= min_seconds / 2:
+                break
+    multi = {"value": mreps * xs.shape[0] * xs.shape[1] / mel / 1e6, "unit": "MSamples/s", "cores": ncores,
+             "kind": "oracle", "sample": f"{xs.shape[1]} signals of the workload, projected {mreps} times ({mel:.1f} s) "
+                                         f"with {ncores} FFT workers and BLAS threads"}
     return {"value": samples / el / 1e6, "unit": "MSamples/s", "cores": 1, "kind": "oracle",
             "sample": f"{xs.shape[1]} signals of the workload, projected {reps} times ({el:.1f} s); "
                       f"oracle setup (transition vectors) {setup:.1f} s not included",
-            "setup_s": setup}, ref.T, exact.T, fcpu, fref.T
+            "setup_s": setup, "all_cores": multi, "host": host_info()}, ref.T, exact.T, fcpu, fref.T
+
+
+def host_info():
+    """nproc and the CPU model of the host the oracle ran on."""
+    import platform
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count(),
+            "cpu_model": model or platform.processor(), "machine": platform.machine()}
+
+
+def exact_vs_fast(sizes=(1024, 2048, 4096), W=1.0 / 16, eps=1e-6, b=8):
+    """Section 4.1's comparison on the CPU oracle (all host cores): the exact
+    projection S_K S_K^T x (precompute: dense eigendecomposition of B; apply:
+    two products with the N x K basis) against the fast projection B x +
+    U diag(d) U^T x (precompute: transition vectors; apply: FFT product plus
+    the rank-r correction), per signal, at W = 1/16, eps = 1e-6."""
+    import numpy as np
+    import scipy.fft as sfft
+    from threadpoolctl import threadpool_limits
+
+    from oracle import slepian_oracle as o
+    out = []
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    rng = np.random.default_rng(4100)
+    with threadpool_limits(limits=ncores), sfft.set_workers(ncores):
+        for N in sizes:
+            x = rng.standard_normal((N, b))
+            K = o.choose_K(N, W)
+            t0 = time.perf_counter()
+            _, S = o.dense_eig(N, W)
+            SK = np.ascontiguousarray(S[:, :K])
+            t_pre_exact = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            reps = 0
+            while reps < 3 or time.perf_counter() - t0 < 0.2:
+                ye = SK @ (SK.T @ x)
+                reps += 1
+            t_exact = (time.perf_counter() - t0) / reps / b
+            t0 = time.perf_counter()
+            tp = o.transition_plan(N, W, eps, 1 - eps)
+            t_pre_fast = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            reps = 0
+            while reps < 3 or time.perf_counter() - t0 < 0.2:
+                yf = o.project_fast(N, W, eps, x, tp=tp)
+                reps += 1
+            t_fast = (time.perf_counter() - t0) / reps / b
+            dist = float((np.linalg.norm(yf - ye, axis=0) / np.linalg.norm(x, axis=0)).max())
+            out.append({"N": N, "K": K, "exact_apply_us_per_signal": round(t_exact * 1e6, 2),
+                        "fast_apply_us_per_signal": round(t_fast * 1e6, 2),
+                        "exact_precompute_s": round(t_pre_exact, 3), "fast_precompute_s": round(t_pre_fast, 3),
+                        "fast_vs_exact_rel_to_x": dist})
+    return {"W": W, "eps": eps, "signals": b, "cores": ncores, "sizes": out}
+
+
+def traced_roofline(call, steps, N, b, info, workload):
+    """Per-kernel average launch durations over `steps` traced calls (HIP
+    events around each launch, on the launch's stream), each kernel's
+    algorithmic and (when the committed counter summary matches the current
+    sources) measured HBM GB/s, and the roofline record of the kernel with
+    the largest share of the step."""
+    from paper_1611_04950_amd import slepian as S
+    import torch
+    S.slepian_trace_enable(True)
+    S.slepian_trace_read(reset=True)
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    stats = S.slepian_trace_read(reset=True)
+    S.slepian_trace_enable(False)
+    kernels = {}
+    total = sum(v["total_ms"] for v in stats.values())
+    for name, st in stats.items():
+        kernels[name] = {"avg_us": st["total_ms"] / st["launches"] * 1e3, "launches_per_step": st["launches"] / steps,
+                         "share": st["total_ms"] / total}
+    pairs = (b + 1) // 2
+    dom = max(stats, key=lambda k: stats[k]["total_ms"])
+    for name in kernels:
+        ppl = pairs / kernels[name]["launches_per_step"] if not name.startswith("corr") else pairs
+        kb = kernel_bytes(name, N, b, info["L"], info["r"], ppl)
+        kernels[name]["alg_bytes"] = kb
+        kernels[name]["alg_GBs"] = None if kb is None else kb / (kernels[name]["avg_us"] * 1e-6) / 1e9
+        t = read_traffic(name, workload)
+        if t is not None:
+            kernels[name]["hbm_bytes"] = t
+            kernels[name]["hbm_GBs"] = t / (kernels[name]["avg_us"] * 1e-6) / 1e9
+    nbytes = kernels[dom]["alg_bytes"]
+    achieved = nbytes / (kernels[dom]["avg_us"] * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(dom, workload), "kernel": dom,
+                "alg_bytes_per_launch": nbytes, "avg_launch_us": round(kernels[dom]["avg_us"], 3)}
+    return kernels, roofline
+
+
+def plain_fp32_per_signal(plan, x, N, W, eps, info, dev, ms_batched, work):
+    """The plain FP32 per-signal path the batched path is compared with: one
+    signal at a time, no pair packing, no fusion, no graph: a complex FP32
+    FFT of the zero-padded signal (torch.fft, i.e. the ROCm FFT library), the
+    spectrum multiply, the inverse FFT and truncation, then the correction as
+    two FP32 matrix-vector products (torch.mv) with the plan's transition
+    vectors.  Its output is checked against the library's.  Also the
+    library's own path called with one signal per call."""
+    import math
+
+    import torch
+
+    from paper_1611_04950_amd import slepian as S
+    L, K = info["L"], info["K"]
+    # kernel spectrum: DFT of the circulant embedding of B's first column (FP64, kept FP32)
+    k = torch.arange(1, N, dtype=torch.float64, device=dev)
+    col = torch.zeros(L, dtype=torch.float64, device=dev)
+    col[0] = 2 * W
+    col[1:N] = torch.sin(2 * math.pi * W * k) / (math.pi * k)
+    col[L - N + 1:] = torch.flip(col[1:N], dims=[0])
+    chat = torch.fft.fft(col).real.to(torch.float32)
+    # transition vectors and projection weights (Lemma 4)
+    l0, lam, V = S.slepian_plan_eigenpairs(plan)
+    ells = torch.arange(l0, l0 + lam.numel())
+    sel = (lam > eps) & (lam < 1 - eps)
+    d = torch.where(ells < K, 1 - lam, -lam)[sel]
+    U = V[sel.to(V.device)].T.contiguous().to(torch.float32)          # N x r
+    d32 = d.to(torch.float32).to(dev)
+
+    def one(xs):
+        z = torch.zeros(L, dtype=torch.complex64, device=dev)
+        z[:N] = xs
+        yv = torch.fft.ifft(torch.fft.fft(z) * chat)[:N].real
+        return yv + torch.mv(U, d32 * torch.mv(U.T, xs))
+
+    b = x.shape[0]
+    yp = torch.empty_like(x)
+    for s in range(min(b, 4)):
+        yp[s] = one(x[s])
+    torch.cuda.synchronize()
+    yl = S.slepian_project(plan, x[:4], precision=S.SLEPIAN_FP32)
+    torch.cuda.synchronize()
+    agree = float((torch.linalg.vector_norm((yp[:4] - yl).double(), dim=1) /
+                   torch.linalg.vector_norm(yl.double(), dim=1)).max())
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for s in range(b):
+        yp[s] = one(x[s])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    pms = e0.elapsed_time(e1)
+    # the library's own batched path, called with one signal per call
+    ys = torch.empty_like(x)
+    for s in range(min(b, 8)):
+        S.slepian_project(plan, x[s:s + 1], ys[s:s + 1], work=work)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for s in range(b):
+        S.slepian_project(plan, x[s:s + 1], ys[s:s + 1], work=work)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    lms = e0.elapsed_time(e1)
+    return {"value": round(N * b / (pms * 1e-3) / 1e9, 3), "unit": "GSamples/s", "ms_per_step": round(pms, 4),
+            "speedup_batched": round(pms / ms_batched, 2),
+            "impl": "per signal: complex FP32 FFT (torch.fft) of the zero-padded signal, spectrum multiply, inverse "
+                    "FFT, FP32 U^T x and U (d C) by torch.mv; no pair packing, fusion or graph",
+            "max_rel_diff_vs_library": agree,
+            "library_one_signal_per_call": {"value": round(N * b / (lms * 1e-3) / 1e9, 3), "ms_per_step": round(lms, 4),
+                                            "speedup_batched": round(lms / ms_batched, 2)}}
 
 
 def bench_batching(args, dev):
@@ -280,11 +475,22 @@ def bench_precision(args, dev):
     y = torch.empty_like(x)
     out = {"workload": "precision N=262144 W=0.05 eps=1e-4 b=1024", "plan_setup_s": round(setup, 3),
            "r": plan.info["r"], "L": plan.info["L"]}
+    wsz = S.slepian_workspace_size(plan, S.SLEPIAN_OP_PROJECT, b)
+    work = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
     for name, p in (("mixed", S.SLEPIAN_MIXED), ("fp32", S.SLEPIAN_FP32), ("bf16_raw", S.SLEPIAN_BF16_RAW)):
-        ms = _time_calls(lambda: S.slepian_project(plan, x, y, precision=p), max(3, args.steps // 4), 2, dev)
+        ms = _time_calls(lambda: S.slepian_project(plan, x, y, work=work, precision=p), max(3, args.steps // 4), 2,
+                         dev)
         out[name] = {"ms_per_call": round(ms, 4), "value": round(N * b / (ms * 1e-3) / 1e9, 3), "unit": "GSamples/s"}
-    log(f"bench: precision workload mixed {out['mixed']['value']} GSamples/s, fp32 {out['fp32']['value']}")
-    del x, y
+    prec = S.SLEPIAN_MIXED if args.precision == "mixed" else S.SLEPIAN_FP32
+    kernels, roof = traced_roofline(lambda: S.slepian_project(plan, x, y, work=work, precision=prec),
+                                    max(3, args.steps // 4), N, b, plan.info, out["workload"])
+    out["roofline"] = roof
+    out["kernels"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                      for k, v in kernels.items()}
+    out["compulsory_byte_efficiency"] = round(out[args.precision]["value"] * 1e9 * 8 / (HBM_PEAK_GBS * 1e9), 4)
+    log(f"bench: precision workload mixed {out['mixed']['value']} GSamples/s, fp32 {out['fp32']['value']}; "
+        f"dominant kernel {roof['kernel']} at {roof['frac']:.3f} of 8 TB/s")
+    del x, y, work
     return out
 
 
@@ -639,6 +845,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-signal FP32 comparison")
+    ap.add_argument("--exact-vs-fast", type=int, default=1,
+                    help="1: time the oracle's exact and fast projections at N = 1024..4096 (CPU)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a plain 256 MiB device-to-device copy (HBM calibration)")
     ap.add_argument("--precision", choices=["mixed", "fp32"], default="mixed",
@@ -750,56 +958,11 @@ def main():
         f"other precision {ms_other:.4f} ms/step")
 
     # per-kernel durations with HIP events around each launch (traced pass)
-    S.slepian_trace_enable(True)
-    for _ in range(args.steps):
-        S.slepian_project(plan, x, y, work=work, precision=prec)
-    torch.cuda.synchronize()
-    stats = S.slepian_trace_read(reset=True)
-    S.slepian_trace_enable(False)
-    kernels = {}
-    slice_pairs = None
-    for name, s in stats.items():
-        launches_per_step = s["launches"] / args.steps
-        kernels[name] = {"avg_us": s["total_ms"] / s["launches"] * 1e3, "launches_per_step": launches_per_step,
-                         "share": s["total_ms"] / sum(v["total_ms"] for v in stats.values())}
-    pairs = (b + 1) // 2
-    dom = max(stats, key=lambda k: stats[k]["total_ms"])
-    per_step = kernels[dom]["launches_per_step"]
-    pairs_per_launch = pairs / per_step if not dom.startswith("corr") else pairs
-    nbytes = kernel_bytes(dom, N, b, info["L"], info["r"], pairs_per_launch)
-    avg_s = kernels[dom]["avg_us"] * 1e-6
-    achieved = nbytes / avg_s / 1e9
-    for name in kernels:
-        ppl = pairs / kernels[name]["launches_per_step"] if not name.startswith("corr") else pairs
-        kb = kernel_bytes(name, N, b, info["L"], info["r"], ppl)
-        kernels[name]["alg_GBs"] = None if kb is None else kb / (kernels[name]["avg_us"] * 1e-6) / 1e9
-        # measured HBM bytes per launch (rocprofv3 counters, when the committed
-        # summary was taken with the current sources) over this run's duration
-        t = read_traffic(name, args.workload)
-        if t is not None:
-            kernels[name]["hbm_bytes"] = t
-            kernels[name]["hbm_GBs"] = t / (kernels[name]["avg_us"] * 1e-6) / 1e9
-    traffic = read_traffic(dom, args.workload)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "alg_bytes_per_launch": nbytes, "avg_launch_us": round(kernels[dom]["avg_us"], 3)}
-
+    kernels, roofline = traced_roofline(lambda: S.slepian_project(plan, x, y, work=work, precision=prec),
+                                        args.steps, N, b, info, args.workload)
     plain = None
     if not args.no_plain:
-        # the plain per-signal FP32 path: one signal per call
-        nrep = 2
-        for s in range(min(b, 8)):
-            S.slepian_project(plan, x[s:s + 1], y[s:s + 1], work=work)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(nrep):
-            for s in range(b):
-                S.slepian_project(plan, x[s:s + 1], y[s:s + 1], work=work)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        pms = ev0.elapsed_time(ev1) / nrep
-        plain = {"value": N * b / (pms * 1e-3) / 1e9, "unit": "GSamples/s", "ms_per_step": pms,
-                 "speedup_batched": round(pms / ms_per_step, 2)}
+        plain = plain_fp32_per_signal(plan, x, N, W, eps, info, dev, ms_per_step, work)
 
     batching = None if args.no_batching else bench_batching(args, dev)
     extras = set() if args.no_extra else (
@@ -818,7 +981,8 @@ def main():
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GSamples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32+bf16x3" if args.precision == "mixed" else "fp32",
         "precision": ("FP32 FFT product; correction on matrix cores, BF16 hi/lo operands, FP32 accumulation"
                       if args.precision == "mixed" else "FP32 FFT product; FP32 matrix-core correction"),
         "fp32_batched": {"value": round(N * b / (ms_other * 1e-3) / 1e9, 3) if prec == S.SLEPIAN_MIXED else None,
@@ -848,6 +1012,9 @@ def main():
         "coefficients_workload": coeffs,
         "factorization_workload": factor,
     }
+    if not args.no_cpu and args.exact_vs_fast:
+        log("bench: exact vs fast projection on the CPU oracle")
+        out["cpu_exact_vs_fast"] = exact_vs_fast()
     print(json.dumps(_finite(out)), flush=True)
 
 
