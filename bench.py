@@ -468,13 +468,15 @@ def bench_precision(args, dev):
     N, W, eps, b, cfg = WORKLOADS["precision N=262144 W=0.05 eps=1e-4 b=1024"]
     log("bench: precision workload")
     t0 = time.perf_counter()
-    plan = S.slepian_plan(N, W, eps)
+    plan = S.slepian_plan(N, W, eps, precision=S.SLEPIAN_MIXED if args.precision == "mixed" else S.SLEPIAN_FP32,
+                          tune=args.tune, tune_batch=b)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     x = synth.config_signals(cfg, N, b, W, device=dev)
     y = torch.empty_like(x)
     out = {"workload": "precision N=262144 W=0.05 eps=1e-4 b=1024", "plan_setup_s": round(setup, 3),
-           "r": plan.info["r"], "L": plan.info["L"]}
+           "r": plan.info["r"], "L": plan.info["L"],
+           "launch": {k: plan.info[k] for k in ("row_log2", "col_log2", "cic_shape", "cic_maxlog1", "tuned")}}
     wsz = S.slepian_workspace_size(plan, S.SLEPIAN_OP_PROJECT, b)
     work = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
     for name, p in (("mixed", S.SLEPIAN_MIXED), ("fp32", S.SLEPIAN_FP32), ("bf16_raw", S.SLEPIAN_BF16_RAW)):
@@ -845,6 +847,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-signal FP32 comparison")
+    ap.add_argument("--tune", type=int, default=1, help="1: tune the plans' launch variants at creation")
     ap.add_argument("--exact-vs-fast", type=int, default=1,
                     help="1: time the oracle's exact and fast projections at N = 1024..4096 (CPU)")
     ap.add_argument("--copy-only", action="store_true",
@@ -883,11 +886,14 @@ def main():
 
     log(f"bench: plan N={N} W={W} eps={eps}")
     t0 = time.perf_counter()
-    plan = S.slepian_plan(N, W, eps)
+    # launch variants tuned at creation for this batch size, in the timed precision
+    prec0 = S.SLEPIAN_MIXED if args.precision == "mixed" else S.SLEPIAN_FP32
+    plan = S.slepian_plan(N, W, eps, precision=prec0, tune=args.tune, tune_batch=b)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = plan.info
-    log(f"bench: plan ready in {setup_s:.2f} s: K={info['K']} L={info['L']} r={info['r']}")
+    log(f"bench: plan ready in {setup_s:.2f} s: K={info['K']} L={info['L']} r={info['r']}; rows 2^{info['row_log2']}, "
+        f"L1 2^{info['col_log2']}, pass C shape {info['cic_shape']}, fused up to 2^{info['cic_maxlog1']}")
 
     x = synth.config_signals(cfg, N, b, W, device=dev)
     y = torch.empty_like(x)
@@ -989,7 +995,9 @@ def main():
                          "ms_per_step": round(ms_other, 5) if prec == S.SLEPIAN_MIXED else None},
         "data": "synthetic",
         "config": {"workload": args.workload, "N": N, "W": W, "eps": eps, "batch": b, "K": info["K"],
-                   "L": info["L"], "r": info["r"]},
+                   "L": info["L"], "r": info["r"],
+                   "launch": {k: info[k] for k in ("row_log2", "col_log2", "cic_shape", "cic_maxlog1", "tuned",
+                                                   "tune_us")}},
         "parity_max_rel_err": err_sel,
         "parity_max_rel_err_fp32": err,
         "errors": extra_err,

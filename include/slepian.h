@@ -86,6 +86,13 @@ typedef struct {
   int64_t K;        /* 0: K = round(2NW); else 1 <= K <= N-1 */
   int precision;    /* enum slepian_precision used by slepian_project */
   int device;       /* HIP device ordinal, -1: the current device */
+  int tune;         /* 1: choose the product's launch variants by timing at creation (three-pass
+                       plans: rows of 2^13 or 2^12 points, the update fused into the inverse
+                       column pass up to L1 = 16 or 32, that pass's workgroup shape); 0: defaults */
+  int64_t tune_batch;     /* signals to time with (0: 64); the choice is for batches of this size */
+  const char *tune_cache; /* host path of a text tuning cache, or NULL: a choice recorded there for
+                             the same (N, W, eps, precision, tune_batch) is reused without timing,
+                             and a new one is appended.  Unreadable or malformed lines are skipped. */
 } slepian_plan_opts;
 
 typedef struct {
@@ -103,6 +110,14 @@ typedef struct {
                            an upper bound on ||S_K S_K^T - (B + U diag(d) U^T)|| (Lemma 4) */
   int precision;
   int device;
+  int32_t row_log2;     /* FP32 product: log2 of its row transform length (L for a single pass) */
+  int32_t col_log2;     /* FP32 product: log2 L1 of its column transforms (0: single pass) */
+  int32_t cic_shape;    /* tuned inverse-column-pass shape (0: default; 1: 1 pair x 4 wavefronts,
+                           2: 1 x 8, 3: 2 x 4) */
+  int32_t cic_maxlog1;  /* tuned largest log2 L1 with the update fused (0: default) */
+  int32_t tuned;        /* 0: not tuned, 1: timed at creation, 2: from the tuning cache */
+  int64_t tune_batch;   /* batch size the choice was made for */
+  double tune_us;       /* time of the chosen variant on tune_batch signals (microseconds) */
 } slepian_plan_info;
 
 typedef struct {
@@ -385,9 +400,24 @@ int slepian_apply_b64(slepian_plan_t plan, const double *x, int64_t ldx, double 
  * plans (host array of n plan handles) must outlive the group; batch (host)
  * gives each plan's signal count.  The group owns its workspace and a HIP
  * graph of the whole batch, built on the first slepian_group_project call and
- * re-launched as one graph while the pointer arrays stay the same. */
+ * re-launched as one graph while the pointer arrays stay the same.  Plans
+ * are sorted into kernel classes (single-pass rows of 2^9..2^13 points with
+ * or without the correction inside; three-pass rows of 2^13 points by L1),
+ * one grouped launch per class and pass.  The first call tunes the launch
+ * variants that have alternatives (signals per workgroup of the correction
+ * partials; wavefronts per workgroup of each fused inverse column pass) by
+ * timing them on the group's own data, or takes them from the tuning cache
+ * of the first plan created with opts.tune_cache (an entry keyed by a hash of
+ * every plan's N, W, eps, precision and batch), appending new choices. */
 int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batch,
                          slepian_group_t *out);
+typedef struct {
+  int32_t plans, grouped, other;  /* plans; in the graph's grouped launches; run plan by plan */
+  int32_t tuned;                  /* 0: not yet, 1: timed, 2: from the tuning cache */
+  int32_t partial_variant;        /* correction partials: 0 64, 1 32 signals per workgroup */
+  int32_t cic_variant[5];         /* fused inverse column pass at L1 = 2..32: 0 8, 1 4 wavefronts */
+} slepian_group_info_t;
+int slepian_group_info(slepian_group_t group, slepian_group_info_t *info);
 
 /* x, y: host arrays of n device pointers; plan i reads x[i] (N_i x batch_i,
  * ld N_i) and writes y[i] (same shape).  Asynchronous on `stream`. */

@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <string>
 #include <mutex>
 #include <vector>
 
@@ -106,6 +107,7 @@ size_t slice_budget() {
 }
 constexpr int kMaxLogL = 22;                          // N <= 2^21
 constexpr double kSpanMinTol = 1e-6;                  // FP32 vectors: the span projection's smallest tolerance
+constexpr int64_t kTuneBatch = 64;                    // signals the plan tuner times with by default
 constexpr size_t kCoeffsCap = (size_t)16 << 30;       // bytes of S_K kept for slepian_coeffs
 
 int ilog2_ceil(int64_t v) {
@@ -161,6 +163,12 @@ struct slepian_plan_s {
   // matrix mode (0: FP32 U^T; 1: BF16 hi/lo planes of U and U^T)
   void *mbu[2] = {nullptr, nullptr};
   std::mutex mbu_mu;
+  // launch tuning (slepian_plan_opts.tune): 0 none, 1 timed at creation,
+  // 2 taken from the tuning cache; the time of the chosen variant
+  int tuned = 0;
+  double tune_us = 0;
+  int64_t tune_batch = 0;
+  std::string tune_cache;  // the tuning cache named at creation (groups of this plan use it too)
 
   ~slepian_plan_s() {
     for (auto *p : tw32) dfree(p);
@@ -224,7 +232,7 @@ struct slepian_group_s {
   // wavefronts per workgroup.
   Span single_corr[14], single[14], partial[2], reduce, colfwd[6], row, colinv_corr[6][2], colinv[6], apply;
   int partial_var = 0, colinv_var[6] = {0, 0, 0, 0, 0, 0};
-  bool tuned = false;
+  bool tuned = false, tuned_from_cache = false;
   std::vector<int> grouped, other;  // plan indices
   void *ws = nullptr;               // grouped workspace (Z, partials, dC per plan)
   void *ws_other = nullptr;         // for the plans run one by one
@@ -436,7 +444,7 @@ void run_fast_op(const Plan *P, const OpSet &op, float beta, float gamma, const 
   const int umode = mode == 0 ? 0 : 1;
   const void *tile = P->ctile[op.set][umode];
   const bool fused =
-      op.r > 0 && P->g32.v2 && !P->g32.single() && colinv_corr_ok(P->g32.log1, ldy, b, (int)op.r) && tile;
+      op.r > 0 && P->g32.v2 && !P->g32.single() && colinv_corr_ok(P->g32, ldy, b, (int)op.r) && tile;
   Corr<float> c;
   if (fused) {
     c.U = U;
@@ -473,7 +481,7 @@ void upload_d(OpSet &o) {
 // column sets), for three-pass plans whose L1 it handles.
 void build_corr_tiles(Plan *P, hipStream_t st) {
   const FftGeom &g = P->g32;
-  if (!g.v2 || g.single() || !colinv_corr_tiled(g.log1)) return;
+  if (!g.v2 || g.single() || !colinv_corr_tiled(g)) return;
   for (const OpSet *o : {&P->proj, &P->tik}) {
     if (o->r <= 0) continue;
     for (int mode = 0; mode < 2; ++mode) {
@@ -485,32 +493,25 @@ void build_corr_tiles(Plan *P, hipStream_t st) {
   HIPCHK(hipStreamSynchronize(st));
 }
 
-void build_fft_state(Plan *P, hipStream_t st) {
+// FP32 tables and kernel spectrum for rows of 2^row32 points (three-pass
+// plans; a single-pass plan keeps its one geometry), keeping the plan's tuned
+// launch choices.  spec: the kernel spectrum in the generic FP64 layout (the
+// plan's FP64 tables must exist), or null to compute it here.
+void build_fp32_state(Plan *P, int row32, const cpx<double> *spec, hipStream_t st) {
   const int logL = ilog2_ceil(2 * P->N);
-  P->L = (int64_t)1 << logL;
-  int row32 = Lds<float>::logE;
-  if (const char *e = std::getenv("SLEPIAN_ROW_LOG2")) {
-    // tuning override of the FP32 row length of the three-pass product
-    const int v = std::atoi(e);
-    if (v >= 9 && v <= Lds<float>::logE) row32 = v;
-  }
-  P->g32 = make_geom(logL, logL <= Lds<float>::logE ? Lds<float>::logE : row32, true);
-  P->g64 = make_geom(logL, Lds<double>::logE, true);
   const int64_t L = P->L;
+  const int cic = P->g32.cic, cicmax = P->g32.cicmax;
+  P->g32 = make_geom(logL, logL <= Lds<float>::logE ? Lds<float>::logE : row32, true);
+  P->g32.cic = cic;
+  P->g32.cicmax = cicmax;
   P->tw32[0] = dalloc<cpx<float>>((size_t)1 << P->g32.logT);
   P->tw32[1] = dalloc<cpx<float>>((size_t)1 << P->g32.s);
   P->tw32[2] = dalloc<cpx<float>>((size_t)1 << (logL - P->g32.s));
-  P->tw64[0] = dalloc<cpx<double>>((size_t)1 << P->g64.logT);
-  P->tw64[1] = dalloc<cpx<double>>((size_t)1 << P->g64.s);
-  P->tw64[2] = dalloc<cpx<double>>((size_t)1 << (logL - P->g64.s));
   HIPCHK(build_tables<float>(P->g32, P->tw32[0], P->tw32[1], P->tw32[2], st));
-  HIPCHK(build_tables<double>(P->g64, P->tw64[0], P->tw64[1], P->tw64[2], st));
+  P->tb32 = FftTables<float>();
   P->tb32.tw_sub = P->tw32[0];
   P->tb32.tw_lo = P->tw32[1];
   P->tb32.tw_hi = P->tw32[2];
-  P->tb64.tw_sub = P->tw64[0];
-  P->tb64.tw_lo = P->tw64[1];
-  P->tb64.tw_hi = P->tw64[2];
   if (P->g32.v2) {
     P->tw32[3] = dalloc<cpx<float>>((size_t)P->g32.R1 * P->g32.R2 * P->g32.R3);
     P->tw32[4] = dalloc<cpx<float>>((size_t)P->g32.R2 * P->g32.R3);
@@ -523,6 +524,55 @@ void build_fft_state(Plan *P, hipStream_t st) {
       P->tb32.col = P->tw32[5];
     }
   }
+  const FftGeom gen64 = generic_twin(P->g64);
+  std::unique_ptr<DBuf<cpx<double>>> own;
+  if (!spec) {
+    DBuf<double> c(L);
+    own.reset(new DBuf<cpx<double>>(L));
+    HIPCHK(sinc_embed(c.p, L, P->N, P->W, st));
+    HIPCHK(fft_forward_real64(c.p, gen64, P->tb64, own->p, st));
+    spec = own->p;
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  P->chat32 = dalloc<float>(L);
+  HIPCHK(spectrum_relayout<float>(spec, gen64, P->chat32, P->g32, st));
+  P->tb32.chat = P->chat32;
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// Frees the FP32 tables, spectrum and fused-pass U tiles (before a rebuild).
+void free_fp32_state(Plan *P) {
+  for (auto *&p : P->tw32) {
+    dfree(p);
+    p = nullptr;
+  }
+  dfree(P->chat32);
+  P->chat32 = nullptr;
+  for (auto &t : P->ctile)
+    for (void *&p : t) {
+      dfree(p);
+      p = nullptr;
+    }
+}
+
+void build_fft_state(Plan *P, hipStream_t st) {
+  const int logL = ilog2_ceil(2 * P->N);
+  P->L = (int64_t)1 << logL;
+  int row32 = Lds<float>::logE;
+  if (const char *e = std::getenv("SLEPIAN_ROW_LOG2")) {
+    // tuning override of the FP32 row length of the three-pass product
+    const int v = std::atoi(e);
+    if (v >= 9 && v <= Lds<float>::logE) row32 = v;
+  }
+  P->g64 = make_geom(logL, Lds<double>::logE, true);
+  const int64_t L = P->L;
+  P->tw64[0] = dalloc<cpx<double>>((size_t)1 << P->g64.logT);
+  P->tw64[1] = dalloc<cpx<double>>((size_t)1 << P->g64.s);
+  P->tw64[2] = dalloc<cpx<double>>((size_t)1 << (logL - P->g64.s));
+  HIPCHK(build_tables<double>(P->g64, P->tw64[0], P->tw64[1], P->tw64[2], st));
+  P->tb64.tw_sub = P->tw64[0];
+  P->tb64.tw_lo = P->tw64[1];
+  P->tb64.tw_hi = P->tw64[2];
   if (P->g64.v2) {
     P->tw64[3] = dalloc<cpx<double>>((size_t)P->g64.R1 * P->g64.R2 * P->g64.R3);
     P->tw64[4] = dalloc<cpx<double>>((size_t)P->g64.R2 * P->g64.R3);
@@ -542,11 +592,9 @@ void build_fft_state(Plan *P, hipStream_t st) {
   DBuf<cpx<double>> spec(L);
   HIPCHK(sinc_embed(c.p, L, P->N, P->W, st));
   HIPCHK(fft_forward_real64(c.p, gen64, P->tb64, spec.p, st));
-  P->chat32 = dalloc<float>(L);
+  build_fp32_state(P, row32, spec.p, st);
   P->chat64 = dalloc<double>(L);
-  HIPCHK(spectrum_relayout<float>(spec.p, gen64, P->chat32, P->g32, st));
   HIPCHK(spectrum_relayout<double>(spec.p, gen64, P->chat64, P->g64, st));
-  P->tb32.chat = P->chat32;
   P->tb64.chat = P->chat64;
   HIPCHK(hipStreamSynchronize(st));
 }
@@ -857,6 +905,7 @@ int validate_domain(int64_t N, double W, double eps, const slepian_plan_opts *o)
     if (!(o->alpha >= 0.0) || !std::isfinite(o->alpha)) return SLEPIAN_EINVAL;
     if (o->K < 0 || o->K > N - 1) return SLEPIAN_EINVAL;
     if (o->precision < SLEPIAN_FP32 || o->precision > SLEPIAN_BF16_RAW) return SLEPIAN_EINVAL;
+    if (o->tune < 0 || o->tune > 1 || o->tune_batch < 0 || o->tune_batch > 32 * (int64_t)65535) return SLEPIAN_EINVAL;
   }
   return SLEPIAN_OK;
 }
@@ -989,6 +1038,176 @@ const char *slepian_status_string(int s) {
   }
 }
 
+}  // extern "C"
+
+namespace {
+
+// ---- launch tuning of a plan (slepian_plan_opts.tune) ----
+
+__global__ void k_fill_signs(float *__restrict__ x, int64_t n, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = seed + (uint64_t)i * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  x[i] = (z >> 63) ? 1.0f : -1.0f;
+}
+
+struct TuneChoice {
+  int row = 0, cicmax = 0, cic = 0;
+  double us = 0;
+};
+
+// One cache line: "slepian-tune-v1 N W eps precision batch row cicmax cic us",
+// W and eps with 17 significant digits (they read back exactly).
+bool tune_cache_lookup(const char *path, const Plan *P, int64_t batch, TuneChoice &c) {
+  if (!path) return false;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    long long n = 0, b = 0;
+    double w = 0, e = 0, us = 0;
+    int prec = 0, row = 0, cmx = 0, cic = 0;
+    if (std::sscanf(line, "slepian-tune-v1 %lld %lf %lf %d %lld %d %d %d %lf", &n, &w, &e, &prec, &b, &row, &cmx, &cic,
+                    &us) != 9)
+      continue;
+    if (n != P->N || w != P->W || e != P->eps || prec != P->precision || b != batch) continue;
+    if (row < 9 || row > Lds<float>::logE || (cmx != 0 && cmx != 4 && cmx != 5) || cic < 0 || cic > 3) continue;
+    c.row = row;
+    c.cicmax = cmx;
+    c.cic = cic;
+    c.us = us;
+    found = true;  // the last matching line wins
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_store(const char *path, const Plan *P, int64_t batch, const TuneChoice &c) {
+  if (!path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "slepian-tune-v1 %lld %.17g %.17g %d %lld %d %d %d %.3f\n", (long long)P->N, P->W, P->eps,
+               P->precision, (long long)batch, c.row, c.cicmax, c.cic, c.us);
+  std::fclose(f);
+}
+
+void set_fp32_geometry(Plan *P, int row, int cicmax, int cic, hipStream_t st) {
+  if (P->g32.log2 != row) {
+    free_fp32_state(P);
+    P->g32.cicmax = cicmax;
+    P->g32.cic = cic;
+    build_fp32_state(P, row, nullptr, st);
+    build_corr_tiles(P, st);
+    return;
+  }
+  const bool retile = colinv_corr_tiled(P->g32) != [&] {
+    FftGeom g = P->g32;
+    g.cicmax = cicmax;
+    return colinv_corr_tiled(g);
+  }();
+  P->g32.cicmax = cicmax;
+  P->g32.cic = cic;
+  if (retile) {
+    for (auto &t : P->ctile)
+      for (void *&q : t) {
+        dfree(q);
+        q = nullptr;
+      }
+    build_corr_tiles(P, st);
+  }
+}
+
+// Times the plan's projection (its precision, `batch` signals of +-1) for
+// each launch variant: rows of 2^13 or 2^12 points (three-pass plans), the
+// update fused into the inverse column pass up to L1 = 16 or 32, and that
+// pass's three workgroup shapes; keeps the fastest.  The variants change how
+// the work is split, not what is computed.  A cache file (path may be null)
+// holds earlier choices per (N, W, eps, precision, batch).
+void tune_plan(Plan *P, int64_t batch, const char *cache, hipStream_t st) {
+  const int logL = ilog2_ceil(2 * P->N);
+  if (logL <= Lds<float>::logE) return;  // single pass: one launch shape
+  TuneChoice best;
+  if (tune_cache_lookup(cache, P, batch, best)) {
+    set_fp32_geometry(P, best.row, best.cicmax, best.cic, st);
+    P->tuned = 2;
+    P->tune_us = best.us;
+    P->tune_batch = batch;
+    return;
+  }
+  const int64_t N = P->N;
+  DBuf<float> x((size_t)N * batch), y((size_t)N * batch);
+  hipLaunchKernelGGL(k_fill_signs, dim3((unsigned)(((int64_t)N * batch + 255) / 256)), dim3(256), 0, st, x.p,
+                     (int64_t)N * batch, 0x7e57ull);
+  HIPCHK(hipGetLastError());
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    throw Fail{SLEPIAN_EHIP};
+  }
+  best.us = 1e30;
+  try {
+    std::vector<int> rows = {Lds<float>::logE};
+    if (logL - (Lds<float>::logE - 1) <= 9) rows.push_back(Lds<float>::logE - 1);
+    for (int row : rows) {
+      set_fp32_geometry(P, row, 0, 0, st);
+      const int log1 = P->g32.log1;
+      std::vector<int> maxes = {4};
+      if (log1 == 5) maxes.push_back(5);
+      for (int cmx : maxes) {
+        FftGeom g = P->g32;
+        g.cicmax = cmx;
+        const bool fused = P->proj.r > 0 && colinv_corr_ok(g, N, batch, (int)P->proj.r);
+        const std::vector<int> shapes = fused ? std::vector<int>{1, 2, 3} : std::vector<int>{0};
+        for (int cic : shapes) {
+          set_fp32_geometry(P, row, cmx, cic, st);
+          Carver c0(nullptr);
+          carve_project(P, P->proj, batch, c0, P->precision);
+          DBuf<char> ws(c0.off + 256);
+          Carver cv(ws.p);
+          const ProjWs w = carve_project(P, P->proj, batch, cv, P->precision);
+          run_fast_op(P, P->proj, 1.0f, 0.0f, x.p, N, y.p, N, batch, w, st, P->precision);
+          float t = 1e30f;
+          for (int rep = 0; rep < 3; ++rep) {
+            HIPCHK(hipEventRecord(e0, st));
+            run_fast_op(P, P->proj, 1.0f, 0.0f, x.p, N, y.p, N, batch, w, st, P->precision);
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            t = std::min(t, ms);
+          }
+          if (1e3 * t < best.us) {
+            best.row = row;
+            best.cicmax = cmx;
+            best.cic = cic;
+            best.us = 1e3 * t;
+          }
+        }
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  set_fp32_geometry(P, best.row, best.cicmax, best.cic, st);
+  P->tuned = 1;
+  P->tune_us = best.us;
+  P->tune_batch = batch;
+  tune_cache_store(cache, P, batch, best);
+}
+
+}  // namespace
+
+extern "C" {
+
 int slepian_plan_ex(int64_t N, double W, double eps, const slepian_plan_opts *opts, slepian_plan_t *out) {
   if (!out) return SLEPIAN_EINVAL;
   int v = validate_domain(N, W, eps, opts);
@@ -1014,6 +1233,9 @@ int slepian_plan_ex(int64_t N, double W, double eps, const slepian_plan_opts *op
       HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
       build_fft_state(P, st);
       build_eigen_state(P, st);
+      if (opts && opts->tune_cache) P->tune_cache = opts->tune_cache;
+      if (opts && opts->tune)
+        tune_plan(P, opts->tune_batch > 0 ? opts->tune_batch : kTuneBatch, opts->tune_cache, st);
       HIPCHK(hipStreamSynchronize(st));
       (void)hipStreamDestroy(st);
     } catch (...) {
@@ -1062,6 +1284,11 @@ int slepian_plan_batch(int n, const int64_t *N, const double *W, const double *e
       HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
       for (Plan *P : Ps) build_fft_state(P, st);
       build_eigen_states(Ps, st);
+      for (int i = 0; i < n; ++i)
+        if (opts && opts[i].tune_cache) Ps[i]->tune_cache = opts[i].tune_cache;
+      for (int i = 0; i < n; ++i)
+        if (opts && opts[i].tune)
+          tune_plan(Ps[i], opts[i].tune_batch > 0 ? opts[i].tune_batch : kTuneBatch, opts[i].tune_cache, st);
       HIPCHK(hipStreamSynchronize(st));
       (void)hipStreamDestroy(st);
     } catch (...) {
@@ -1111,6 +1338,13 @@ int slepian_plan_info_get(slepian_plan_t P, slepian_plan_info *info) {
   info->eps_achieved = P->eps_ach;
   info->precision = P->precision;
   info->device = P->device;
+  info->row_log2 = P->g32.log2;
+  info->col_log2 = P->g32.log1;
+  info->cic_shape = P->g32.cic;
+  info->cic_maxlog1 = P->g32.cicmax;
+  info->tuned = P->tuned;
+  info->tune_batch = P->tune_batch;
+  info->tune_us = P->tune_us;
   return SLEPIAN_OK;
 }
 
@@ -1577,7 +1811,7 @@ void factor_setup(slepian_factor_s *F, hipStream_t st) {
     F->w = dalloc<float>(w32.size());
     HIPCHK(hipMemcpyAsync(F->w, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice, st));
     const FftGeom &g = P->g32;
-    if (rt > 0 && !g.single() && colinv_corr_tiled(g.log1)) {
+    if (rt > 0 && !g.single() && colinv_corr_tiled(g)) {
       F->ctile = dalloc<char>(corr_tile_bytes(g.log1, g.log2, (int)rt, F->mode));
       HIPCHK(build_corr_tile(F->U, F->ldu, (int)N, (int)rt, g.log1, g.log2, F->mode, F->ctile, st));
     }
@@ -1715,7 +1949,7 @@ void factor_setup_theorem1(slepian_factor_s *F, hipStream_t st) {
   F->w = dalloc<float>(w32.size());
   HIPCHK(hipMemcpyAsync(F->w, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice, st));
   const FftGeom &g = P->g32;
-  if (rt > 0 && !g.single() && colinv_corr_tiled(g.log1)) {
+  if (rt > 0 && !g.single() && colinv_corr_tiled(g)) {
     F->ctile = dalloc<char>(corr_tile_bytes(g.log1, g.log2, (int)rt, F->mode));
     HIPCHK(build_corr_tile(F->Urec, F->ldu, (int)N, (int)rt, g.log1, g.log2, F->mode, F->ctile, st));
   }
@@ -1864,7 +2098,7 @@ int slepian_factor_recover(slepian_factor_t F, const float *c, int64_t ldc, floa
     const int rt = (int)(F->r1 + F->r);
     HIPCHK(pack_scale(c, ldc, F->kf, N, batch, w.Zb, rt, F->w, w.dC, st));
     Corr<float> corr;
-    const bool fused = rt > 0 && F->ctile && colinv_corr_ok(P->g32.log1, ldy, batch, rt);
+    const bool fused = rt > 0 && F->ctile && colinv_corr_ok(P->g32, ldy, batch, rt);
     if (fused) {
       corr.U = F->rec();
       corr.ldu = F->ldu;
@@ -2371,7 +2605,76 @@ void launch_grouped(const slepian_group_s *G, hipStream_t s1, hipStream_t s2, in
 // data), then time each launch that has alternatives, best of two runs per
 // alternative, and keep the faster.  The alternatives differ only in how the
 // work is cut into workgroups, so every run writes the same results.
+// The group's entry in the tuning cache of its first plan that names one:
+// "slepian-group-v1 <hash> <plans> <partial> <pass C per L1 = 2..32>", the
+// hash (FNV-1a, 64 bits) over each plan's N, W, eps, precision and batch.
+uint64_t group_key(const slepian_group_s *G) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void *p, size_t n) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  };
+  for (size_t i = 0; i < G->plans.size(); ++i) {
+    const Plan *P = G->plans[i];
+    mix(&P->N, sizeof(P->N));
+    mix(&P->W, sizeof(P->W));
+    mix(&P->eps, sizeof(P->eps));
+    mix(&P->precision, sizeof(P->precision));
+    mix(&G->batch[i], sizeof(G->batch[i]));
+  }
+  return h;
+}
+
+const char *group_cache_path(const slepian_group_s *G) {
+  for (const Plan *P : G->plans)
+    if (!P->tune_cache.empty()) return P->tune_cache.c_str();
+  return nullptr;
+}
+
+bool group_cache_lookup(slepian_group_s *G) {
+  const char *path = group_cache_path(G);
+  if (!path) return false;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  const uint64_t key = group_key(G);
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    unsigned long long k = 0;
+    long long n = 0;
+    int pv = 0, cv[5] = {0, 0, 0, 0, 0};
+    if (std::sscanf(line, "slepian-group-v1 %llx %lld %d %d %d %d %d %d", &k, &n, &pv, &cv[0], &cv[1], &cv[2], &cv[3],
+                    &cv[4]) != 8)
+      continue;
+    if (k != key || n != (long long)G->plans.size() || (pv & ~1) != 0) continue;
+    bool ok = true;
+    for (int v : cv) ok = ok && (v & ~1) == 0;
+    if (!ok) continue;
+    G->partial_var = pv;
+    for (int l1 = 1; l1 <= 5; ++l1) G->colinv_var[l1] = cv[l1 - 1];
+    found = true;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void group_cache_store(const slepian_group_s *G) {
+  const char *path = group_cache_path(G);
+  if (!path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "slepian-group-v1 %016llx %lld %d %d %d %d %d %d\n", (unsigned long long)group_key(G),
+               (long long)G->plans.size(), G->partial_var, G->colinv_var[1], G->colinv_var[2], G->colinv_var[3],
+               G->colinv_var[4], G->colinv_var[5]);
+  std::fclose(f);
+}
+
 void tune_group(slepian_group_s *G, hipStream_t st, int vec) {
+  if (group_cache_lookup(G)) {
+    G->tuned = true;
+    G->tuned_from_cache = true;
+    return;
+  }
   launch_grouped(G, st, st, vec);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
@@ -2412,6 +2715,7 @@ void tune_group(slepian_group_s *G, hipStream_t st, int vec) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   G->tuned = true;
+  group_cache_store(G);
 }
 
 }  // namespace
@@ -2540,7 +2844,7 @@ int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batc
         by_l1[P->g32.log1].push_back(i);
         // the update rides on the inverse column pass exactly when the
         // single-plan path fuses it there
-        if (r > 0 && colinv_corr_ok(P->g32.log1, P->N, batch[i], r) && P->ctile[0][umode]) {
+        if (r > 0 && colinv_corr_ok(P->g32, P->N, batch[i], r) && P->ctile[0][umode]) {
           by_l1_fused[P->g32.log1].push_back(i);
         } else {
           by_l1_plain[P->g32.log1].push_back(i);
@@ -2646,6 +2950,17 @@ int slepian_group_project(slepian_group_t G, const float *const *x, float *const
     }
     return SLEPIAN_OK;
   });
+}
+
+int slepian_group_info(slepian_group_t G, slepian_group_info_t *info) {
+  if (!G || !info) return SLEPIAN_EINVAL;
+  info->plans = (int32_t)G->plans.size();
+  info->grouped = (int32_t)G->grouped.size();
+  info->other = (int32_t)G->other.size();
+  info->tuned = G->tuned ? (G->tuned_from_cache ? 2 : 1) : 0;
+  info->partial_variant = G->partial_var;
+  for (int l1 = 1; l1 <= 5; ++l1) info->cic_variant[l1 - 1] = G->colinv_var[l1];
+  return SLEPIAN_OK;
 }
 
 int slepian_group_destroy(slepian_group_t G) {

@@ -48,6 +48,11 @@ struct FftGeom {
   int s = 0;      // split of the two-level table for W_L^m: m = (hi << s) | lo
   int v2 = 0;     // 1: register-stage kernels; rows of length R1 R2 R3
   int R1 = 0, R2 = 0, R3 = 0;
+  // launch choices of a tuned plan (host side; 0: the process default):
+  // cic, the fused inverse column pass's shape (1: one pair per lane and 4
+  // wavefronts per workgroup, 2: one pair and 8, 3: two pairs and 4);
+  // cicmax, the largest log2 L1 whose inverse column pass takes the update
+  int cic = 0, cicmax = 0;
   __host__ __device__ bool single() const { return log1 == 0; }
 };
 

@@ -309,16 +309,18 @@ __global__ __launch_bounds__(256) void k_corr_partial_tiles(const float *__restr
   }
 }
 
-// out[j * ldo_j + s * ldo_s] = d[j] * sum over chunks of part[chunk][j][s]
-// (d == nullptr: no weights).  16 outputs per workgroup (consecutive s),
-// 16 lanes per output each summing every 16th chunk with two accumulators,
-// then a fixed-order sum of the 16 through LDS.
+// Fixed-order sum of the chunk partials: a workgroup of 512 lanes owns the
+// 32 outputs o = 32 bx + og (o = j b + s, one whole 128-byte line of every
+// chunk's partials); lane group cg (16 groups of 32 lanes) sums chunks cg,
+// cg + 16, ..., then a fixed-order sum of the 16 through LDS.
+constexpr int kReduceOuts = 32;
+constexpr int kReduceThreads = 512;
 __device__ __forceinline__ void corr_reduce_body(const float *__restrict__ part, int chunks, int rpad, int b, int r,
                                                  const float *__restrict__ d, float *__restrict__ out, int64_t ldo_j,
                                                  int64_t ldo_s, int bx) {
-  __shared__ float red[16][17];
-  const int og = threadIdx.x & 15, cg = threadIdx.x >> 4;
-  const int64_t o = (int64_t)bx * 16 + og;  // o = j * b + s
+  __shared__ float red[16][kReduceOuts + 1];
+  const int og = threadIdx.x & 31, cg = threadIdx.x >> 5;
+  const int64_t o = (int64_t)bx * kReduceOuts + og;  // o = j * b + s
   const bool valid = o < (int64_t)r * b;
   const int j = valid ? (int)(o / b) : 0, s = valid ? (int)(o % b) : 0;
   // chunks cg, cg + 16, ...: eight independent loads in flight per round,
@@ -345,7 +347,7 @@ __device__ __forceinline__ void corr_reduce_body(const float *__restrict__ part,
   }
 }
 
-__global__ __launch_bounds__(256) void k_corr_reduce2(const float *__restrict__ part, int chunks, int rpad, int b,
+__global__ __launch_bounds__(kReduceThreads) void k_corr_reduce2(const float *__restrict__ part, int chunks, int rpad, int b,
                                                       int r, const float *__restrict__ d, float *__restrict__ out,
                                                       int64_t ldo_j, int64_t ldo_s) {
   corr_reduce_body(part, chunks, rpad, b, r, d, out, ldo_j, ldo_s, blockIdx.x);
@@ -526,7 +528,9 @@ hipError_t corr_reduce_mfma(const float *part, int64_t N, int64_t b, int r, cons
                             hipStream_t st) {
   if (r == 0 || b == 0) return hipSuccess;
   const int64_t outs = (int64_t)r * b;
-  SLP_LAUNCH("corr_reduce", k_corr_reduce2, dim3((unsigned)((outs + 15) / 16)), dim3(256), 0, st, part,
+  SLP_LAUNCH("corr_reduce", k_corr_reduce2, dim3((unsigned)((outs + kReduceOuts - 1) / kReduceOuts)),
+             dim3(kReduceThreads), 0,
+             st, part,
              corr_nchunks(N, b, r), corr_rpad(r), (int)b, r, d, dC, (int64_t)b, (int64_t)1);
   return hipGetLastError();
 }
@@ -534,7 +538,9 @@ hipError_t corr_reduce_mfma(const float *part, int64_t N, int64_t b, int r, cons
 hipError_t corr_sum_mfma(const float *part, int64_t N, int64_t b, int r, float *c, int64_t ldc, hipStream_t st) {
   if (r == 0 || b == 0) return hipSuccess;
   const int64_t outs = (int64_t)r * b;
-  SLP_LAUNCH("coeffs_sum", k_corr_reduce2, dim3((unsigned)((outs + 15) / 16)), dim3(256), 0, st, part,
+  SLP_LAUNCH("coeffs_sum", k_corr_reduce2, dim3((unsigned)((outs + kReduceOuts - 1) / kReduceOuts)),
+             dim3(kReduceThreads), 0,
+             st, part,
              corr_nchunks(N, b, r), corr_rpad(r), (int)b, r, nullptr, c, (int64_t)1, ldc);
   return hipGetLastError();
 }
@@ -563,7 +569,7 @@ __global__ __launch_bounds__(256) void k_corr_partial_group(const GroupPlan *__r
                                             w % gx, (w / gx) % gy, w / (gx * gy));
 }
 
-__global__ __launch_bounds__(256) void k_corr_reduce_group(const GroupPlan *__restrict__ gp,
+__global__ __launch_bounds__(kReduceThreads) void k_corr_reduce_group(const GroupPlan *__restrict__ gp,
                                                            const int *__restrict__ idx,
                                                            const int *__restrict__ start, int m) {
   const int q = group_slot_c(start, m, blockIdx.x);
@@ -577,7 +583,7 @@ int64_t group_blocks_partial(const GroupPlan &P, int nb) {
   return (int64_t)P.chunks * ((P.b + 32 * nb - 1) / (32 * nb)) * ((P.corr.r + 31) / 32);
 }
 
-int64_t group_blocks_reduce(const GroupPlan &P) { return ((int64_t)P.corr.r * P.b + 15) / 16; }
+int64_t group_blocks_reduce(const GroupPlan &P) { return ((int64_t)P.corr.r * P.b + kReduceOuts - 1) / kReduceOuts; }
 
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_corr_apply_group(const GroupPlan *__restrict__ gp,
@@ -630,7 +636,8 @@ hipError_t group_corr_partial(int mode, int nb, bool vec, const GroupPlan *gp, c
 
 hipError_t group_corr_reduce(const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
   if (sp.m == 0 || sp.blocks == 0) return hipSuccess;
-  SLP_LAUNCH("corr_reduce_group", k_corr_reduce_group, dim3((unsigned)sp.blocks), dim3(256), 0, st, gp, sp.idx,
+  SLP_LAUNCH("corr_reduce_group", k_corr_reduce_group, dim3((unsigned)sp.blocks), dim3(kReduceThreads), 0, st, gp,
+             sp.idx,
              sp.start, sp.m);
   return hipGetLastError();
 }

@@ -965,18 +965,20 @@ int colinv_corr_rp(int r, int mode) { return mode == 0 ? (r + 15) / 16 * 16 : (r
 
 // L1 = 32 keeps 64 complex inputs per lane on top of the accumulators; there
 // the plain pass plus the separate matrix-core update is faster.
-bool colinv_corr_ok(int log1, int64_t ldy, int64_t b, int r) {
-  // tuning override: SLEPIAN_CIC_MAXLOG1 (4 or 5), the largest L1 = 2^log1 fused
+bool colinv_corr_ok(const FftGeom &g, int64_t ldy, int64_t b, int r) {
+  // tuning override: SLEPIAN_CIC_MAXLOG1 (4 or 5), the largest L1 = 2^log1
+  // fused, unless the plan was tuned (g.cicmax)
   static const int maxlog1 = [] {
     const char *e = std::getenv("SLEPIAN_CIC_MAXLOG1");
     return e && std::atoi(e) == 5 ? 5 : 4;
   }();
+  const int mx = g.cicmax ? g.cicmax : maxlog1;
   // the pass addresses y and dC by 32-bit byte offsets from a wavefront's base
   const bool fits = ldy < ((int64_t)1 << 25) && (int64_t)colinv_corr_rp(r, 1) * b < ((int64_t)1 << 29);
-  return log1 >= 1 && log1 <= maxlog1 && fits;
+  return g.log1 >= 1 && g.log1 <= mx && fits;
 }
 
-bool colinv_corr_tiled(int log1) { return colinv_corr_ok(log1, 1, 1, 1); }
+bool colinv_corr_tiled(const FftGeom &g) { return colinv_corr_ok(g, 1, 1, 1); }
 
 template <int L1, int MODE, int CW, int PPL, bool EVEN = false>
 static void launch_cic(hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np, const FftGeom &g,
@@ -995,6 +997,11 @@ static void launch_cic_shape(hipStream_t st, const cpx<float> *Z, int N, int b, 
   // times the projection's) re-reads a larger U tile per pair group; two pairs
   // per lane halve the groups (measured 77 -> 53 us at rank 91)
   CicShape sh = cic_shape();
+  if (g.cic >= 1 && g.cic <= 3) {
+    sh.ppl = g.cic == 3 ? 2 : 1;
+    sh.cw = g.cic == 2 ? 8 : 4;
+    sh.set = true;
+  }
   if (EVEN && !sh.set) {
     sh.ppl = 2;
     sh.cw = 4;

@@ -22,8 +22,8 @@ int colinv_corr_rp(int r, int mode);
 // whether the inverse column pass carries the correction update (L1 = 2^log1 <= 16,
 // or <= 32 with the tuning override; output leading dimension ldy, b signals, rank r
 // within its 32-bit offsets), and whether a plan of that L1 keeps the tiles it reads
-bool colinv_corr_ok(int log1, int64_t ldy, int64_t b, int r);
-bool colinv_corr_tiled(int log1);
+bool colinv_corr_ok(const FftGeom &g, int64_t ldy, int64_t b, int r);
+bool colinv_corr_tiled(const FftGeom &g);
 // U's rows laid out for the fused inverse column pass (mode 0: FP32; mode 1: BF16 hi
 // and lo planes); bytes, and the layout kernel (U: N x r, leading dimension ldu)
 size_t corr_tile_bytes(int log1, int log2, int r, int mode);

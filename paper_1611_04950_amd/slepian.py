@@ -46,13 +46,15 @@ EXPORTED = [
     "slepian_factor_create", "slepian_factor_create_ex", "slepian_factor_destroy", "slepian_factor_info", "slepian_factor_mu",
     "slepian_factor_workspace_size", "slepian_factor_compress", "slepian_factor_recover",
     "slepian_apply_b64",
-    "slepian_group_create", "slepian_group_project", "slepian_group_destroy", "slepian_status_string",
+    "slepian_group_create", "slepian_group_project", "slepian_group_destroy", "slepian_group_info",
+    "slepian_status_string",
     "slepian_trace_enable", "slepian_trace_read",
 ]
 
 
 class PlanOpts(C.Structure):
-    _fields_ = [("alpha", C.c_double), ("K", C.c_int64), ("precision", C.c_int), ("device", C.c_int)]
+    _fields_ = [("alpha", C.c_double), ("K", C.c_int64), ("precision", C.c_int), ("device", C.c_int),
+                ("tune", C.c_int), ("tune_batch", C.c_int64), ("tune_cache", C.c_char_p)]
 
 
 class FactorInfo(C.Structure):
@@ -68,12 +70,19 @@ class PlanInfo(C.Structure):
         ("r_tik", C.c_int64), ("l_first_tik", C.c_int64), ("window_lo", C.c_int64),
         ("window_hi", C.c_int64), ("lam_Km1", C.c_double), ("lam_K", C.c_double),
         ("eps_achieved", C.c_double), ("precision", C.c_int), ("device", C.c_int),
+        ("row_log2", C.c_int32), ("col_log2", C.c_int32), ("cic_shape", C.c_int32), ("cic_maxlog1", C.c_int32),
+        ("tuned", C.c_int32), ("tune_batch", C.c_int64), ("tune_us", C.c_double),
     ]
 
 
 class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double),
                 ("min_ms", C.c_double), ("max_ms", C.c_double)]
+
+
+class GroupInfo(C.Structure):
+    _fields_ = [("plans", C.c_int32), ("grouped", C.c_int32), ("other", C.c_int32), ("tuned", C.c_int32),
+                ("partial_variant", C.c_int32), ("cic_variant", C.c_int32 * 5)]
 
 
 class LsqReport(C.Structure):
@@ -121,6 +130,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "slepian_group_create": [C.POINTER(vp), i32, C.POINTER(i64), C.POINTER(vp)],
         "slepian_group_project": [vp, C.POINTER(vp), C.POINTER(vp), vp],
         "slepian_group_destroy": [vp],
+        "slepian_group_info": [vp, C.POINTER(GroupInfo)],
         "slepian_status_string": [i32],
         "slepian_trace_enable": [i32],
         "slepian_trace_read": [C.POINTER(KernelStat), i32, C.POINTER(i32), i32],
@@ -191,15 +201,18 @@ class Plan:
 
 
 def slepian_plan(N: int, W: float, eps: float, alpha: float = 0.0, K: int = 0,
-                 precision: int = SLEPIAN_FP32, device: int = -1) -> Plan:
+                 precision: int = SLEPIAN_FP32, device: int = -1, tune: bool = False, tune_batch: int = 0,
+                 tune_cache: str | None = None) -> Plan:
     h = C.c_void_p()
-    opts = PlanOpts(alpha, K, precision, device)
+    opts = PlanOpts(alpha, K, precision, device, int(tune), tune_batch,
+                    None if tune_cache is None else tune_cache.encode())
     _check(_lib.slepian_plan_ex(N, W, eps, C.byref(opts), C.byref(h)), "slepian_plan")
     return Plan(h.value)
 
 
 def slepian_plan_batch(specs, alpha: float = 0.0, K: int = 0, precision: int = SLEPIAN_FP32,
-                       device: int = -1) -> list:
+                       device: int = -1, tune: bool = False, tune_batch: int = 0,
+                       tune_cache: str | None = None) -> list:
     """Plans for (N, W, eps) triples in one call (the eigensolves run
     together); the options apply to every plan."""
     n = len(specs)
@@ -208,7 +221,8 @@ def slepian_plan_batch(specs, alpha: float = 0.0, K: int = 0, precision: int = S
     Ns = (C.c_int64 * n)(*[int(sp[0]) for sp in specs])
     Ws = (C.c_double * n)(*[float(sp[1]) for sp in specs])
     Es = (C.c_double * n)(*[float(sp[2]) for sp in specs])
-    opts = (PlanOpts * n)(*[PlanOpts(alpha, K, precision, device) for _ in range(n)])
+    cache = None if tune_cache is None else tune_cache.encode()
+    opts = (PlanOpts * n)(*[PlanOpts(alpha, K, precision, device, int(tune), tune_batch, cache) for _ in range(n)])
     hs = (C.c_void_p * n)()
     _check(_lib.slepian_plan_batch(n, Ns, Ws, Es, opts, hs), "slepian_plan_batch")
     return [Plan(h) for h in hs]
@@ -473,6 +487,13 @@ class Group:
     def __init__(self, handle: int, plans):
         self.handle = C.c_void_p(handle)
         self.plans = list(plans)   # the plans must outlive the group
+
+    @property
+    def info(self) -> dict:
+        gi = GroupInfo()
+        _check(_lib.slepian_group_info(self.handle, C.byref(gi)), "slepian_group_info")
+        return {"plans": gi.plans, "grouped": gi.grouped, "other": gi.other, "tuned": gi.tuned,
+                "partial_variant": gi.partial_variant, "cic_variant": list(gi.cic_variant)}
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -84,6 +84,13 @@ int main(int argc, char **argv) {
   o.precision = 7;
   EXPECT(slepian_plan_ex(64, 0.1, 1e-6, &o, &plan), SLEPIAN_EINVAL);
   o.precision = 0;
+  o.tune = 2;
+  EXPECT(slepian_plan_ex(64, 0.1, 1e-6, &o, &plan), SLEPIAN_EINVAL);
+  o.tune = 1;
+  o.tune_batch = -5;
+  EXPECT(slepian_plan_ex(64, 0.1, 1e-6, &o, &plan), SLEPIAN_EINVAL);
+  o.tune = 0;
+  o.tune_batch = 0;
   {
     int64_t Ns[3] = {100, 200, 1};
     double Ws[3] = {0.1, 0.1, 0.1}, Es[3] = {1e-6, 1e-6, 1e-6};
@@ -134,6 +141,8 @@ int main(int argc, char **argv) {
     EXPECT(slepian_group_create(NULL, 0, NULL, &gh), SLEPIAN_EINVAL);
     EXPECT(slepian_group_destroy(NULL), SLEPIAN_OK);
     EXPECT(slepian_group_project(NULL, NULL, NULL, NULL), SLEPIAN_EINVAL);
+    slepian_group_info_t gi;
+    EXPECT(slepian_group_info(NULL, &gi), SLEPIAN_EINVAL);
   }
   for (int s = -12; s <= 0; ++s)
     if (slepian_status_string(s) == NULL || strlen(slepian_status_string(s)) == 0) {

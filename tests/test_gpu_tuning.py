@@ -1,0 +1,99 @@
+"""Launch tuning (slepian_plan_opts.tune) and its cache file on the GPU.
+
+A tuned three-pass plan reports its chosen variant (row length, fused-pass
+shape), computes the fast projection of Corollary 2 to the oracle's 1e-5 in
+every variant it may choose, and a second plan with the same cache takes the
+choice from the file without timing; malformed cache lines are skipped.  A
+group of tuned plans records its own choices in the first plan's cache and
+a second group reads them back, with bitwise-equal results."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import slepian_oracle as o
+from paper_1611_04950_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1611_04950_amd import slepian as S
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+@pytest.mark.parametrize("N,W,eps,prec", [(65536, 1 / 8, 1e-6, "mixed"), (131072, 1 / 16, 1e-6, "fp32")])
+def test_tuned_plan_and_cache(tmp_path, N, W, eps, prec):
+    cache = str(tmp_path / "tune.txt")
+    with open(cache, "w") as f:
+        f.write("garbage line\nslepian-tune-v1 1 2 3\nslepian-tune-v1 5 0.1 1e-6 0 8 99 0 0 1.0\n")
+    p = S.SLEPIAN_MIXED if prec == "mixed" else S.SLEPIAN_FP32
+    P = S.slepian_plan(N, W, eps, precision=p, tune=True, tune_batch=64, tune_cache=cache)
+    info = P.info
+    print(f"tuned N={N}: rows 2^{info['row_log2']}, L1 2^{info['col_log2']}, pass C shape {info['cic_shape']}, "
+          f"fused up to 2^{info['cic_maxlog1']}, {info['tune_us']:.1f} us", flush=True)
+    assert info["tuned"] == 1 and info["tune_batch"] == 64 and info["row_log2"] in (12, 13)
+    assert info["tune_us"] > 0
+    x = synth.gaussian(N, 6, 81, device="cuda")
+    y = S.slepian_project(P, x)
+    torch.cuda.synchronize()
+    ref = o.project_fast(N, W, eps, x.double().cpu().numpy().T).T
+    assert _rel(y.double().cpu().numpy(), ref).max() <= 1e-5
+    # the same key again: from the cache, the same choice, the same result
+    Q = S.slepian_plan(N, W, eps, precision=p, tune=True, tune_batch=64, tune_cache=cache)
+    qi = Q.info
+    assert qi["tuned"] == 2
+    for k in ("row_log2", "col_log2", "cic_shape", "cic_maxlog1"):
+        assert qi[k] == info[k]
+    assert torch.equal(S.slepian_project(Q, x), y)
+    lines = [ln for ln in open(cache) if ln.startswith("slepian-tune-v1")]
+    assert len(lines) == 3  # two malformed ones kept, one new entry
+
+
+def test_every_variant_matches_oracle(tmp_path):
+    """Each variant the tuner can choose computes the same projection to the
+    oracle's 1e-5: at N = 2^17 (L = 2^18) rows of 2^13 points (L1 = 32, the
+    update fused into the inverse column pass or not, all three shapes of
+    that pass) and rows of 2^12 (L1 = 64), each forced through a cache entry."""
+    N, W, eps = 131072, 1 / 16, 1e-6
+    x = synth.gaussian(N, 4, 82, device="cuda")
+    ref = o.project_fast(N, W, eps, x.double().cpu().numpy().T).T
+    cache = str(tmp_path / "c.txt")
+    for row, cmx, cic in ((13, 4, 0), (13, 5, 1), (13, 5, 2), (13, 5, 3), (12, 4, 0)):
+        with open(cache, "w") as f:
+            f.write(f"slepian-tune-v1 {N} {W!r} {eps!r} 1 16 {row} {cmx} {cic} 1.0\n")
+        P = S.slepian_plan(N, W, eps, precision=S.SLEPIAN_MIXED, tune=True, tune_batch=16, tune_cache=cache)
+        info = P.info
+        assert info["tuned"] == 2 and info["row_log2"] == row and info["cic_maxlog1"] == cmx
+        assert info["cic_shape"] == cic
+        y = S.slepian_project(P, x)
+        torch.cuda.synchronize()
+        e = _rel(y.double().cpu().numpy(), ref).max()
+        print(f"variant rows 2^{row} fused up to 2^{cmx} shape {cic}: {e:.2e}", flush=True)
+        assert e <= 1e-5
+
+
+def test_group_tuning_cache(tmp_path):
+    cache = str(tmp_path / "g.txt")
+    specs = [(3000, 0.1, 1e-6, 5), (65536, 1 / 8, 1e-6, 12), (131072, 0.05, 1e-3, 7), (20000, 0.2, 1e-6, 9)]
+    plans = [S.slepian_plan(n, w, e, precision=S.SLEPIAN_MIXED, tune_cache=cache) for n, w, e, _ in specs]
+    xs = [synth.gaussian(n, b, 90 + i, device="cuda") for i, (n, _, _, b) in enumerate(specs)]
+    ys = [torch.empty_like(x) for x in xs]
+    G = S.slepian_group_create(plans, [b for *_, b in specs])
+    assert G.info["tuned"] == 0
+    S.slepian_group_project(G, xs, ys)
+    torch.cuda.synchronize()
+    gi = G.info
+    assert gi["tuned"] == 1 and gi["plans"] == 4
+    assert any(ln.startswith("slepian-group-v1") for ln in open(cache))
+    G2 = S.slepian_group_create(plans, [b for *_, b in specs])
+    ys2 = [torch.empty_like(x) for x in xs]
+    S.slepian_group_project(G2, xs, ys2)
+    torch.cuda.synchronize()
+    g2 = G2.info
+    assert g2["tuned"] == 2
+    assert g2["partial_variant"] == gi["partial_variant"] and g2["cic_variant"] == gi["cic_variant"]
+    for a, b in zip(ys, ys2):
+        assert torch.equal(a, b)
