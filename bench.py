@@ -387,7 +387,9 @@ def bench_batching(args, dev):
     log("bench: batching workload, creating 512 plans")
     t0 = time.perf_counter()
     prec = S.SLEPIAN_MIXED if args.precision == "mixed" else S.SLEPIAN_FP32
-    plans = S.slepian_plan_batch([(n, w, e) for n, w, e, _ in specs], precision=prec)
+    # tuned among the variants the grouped launches take, for each plan's batch
+    plans = S.slepian_plan_batch([(n, w, e) for n, w, e, _ in specs], precision=prec, tune=2 * args.tune,
+                                 tune_batch=[bb for *_, bb in specs])
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     xs = [synth.gaussian(n, bb, 4000 * 1000 + 100 * i, device=dev) for i, (n, _, _, bb) in enumerate(specs)]
@@ -431,13 +433,19 @@ def bench_batching(args, dev):
     st = S.slepian_trace_read(reset=True)
     S.slepian_trace_enable(False)
     value = total / (ms * 1e-3) / 1e9
-    log(f"bench: batching {ms:.3f} ms per grouped call, {value:.2f} GSamples/s; plan by plan {ms_each:.3f} ms")
+    gi = G.info
+    rows = {}
+    for p in plans:
+        k = f"rows_2^{p.info['row_log2']}"
+        rows[k] = rows.get(k, 0) + 1
+    log(f"bench: batching {ms:.3f} ms per grouped call, {value:.2f} GSamples/s; plan by plan {ms_each:.3f} ms; "
+        f"{gi['grouped']} plans grouped, {gi['other']} one by one; {rows}")
     return {"workload": "512 plans, N log-uniform 2^10..2^17, W U[0.01,0.25], eps {1e-3,1e-6}, 4-64 signals",
             "precision": args.precision,
             "value": round(value, 3), "unit": "GSamples/s", "ms_per_call": round(ms, 4), "steps": steps,
             "samples": total, "plan_by_plan_ms": round(ms_each, 4),
             "speedup_vs_plan_by_plan": round(ms_each / ms, 2), "plans_setup_s": round(setup, 2),
-            "matches_single_plan_calls": same,
+            "matches_single_plan_calls": same, "group_info": gi, "plan_rows": rows,
             "kernels_traced_ms": {k: round(v["total_ms"], 4) for k, v in st.items()}}
 
 

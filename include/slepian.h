@@ -88,7 +88,11 @@ typedef struct {
   int device;       /* HIP device ordinal, -1: the current device */
   int tune;         /* 1: choose the product's launch variants by timing at creation (three-pass
                        plans: rows of 2^13 or 2^12 points, the update fused into the inverse
-                       column pass up to L1 = 16 or 32, that pass's workgroup shape); 0: defaults */
+                       column pass up to L1 = 16 or 32, that pass's workgroup shape); 2: the
+                       same among the variants groups launch together (L1 <= 32); 0: defaults.
+                       The variants split the work differently, not the arithmetic: results stay
+                       within FP32 rounding of the untuned plan's, and a group reproduces a tuned
+                       plan's own calls bit for bit. */
   int64_t tune_batch;     /* signals to time with (0: 64); the choice is for batches of this size */
   const char *tune_cache; /* host path of a text tuning cache, or NULL: a choice recorded there for
                              the same (N, W, eps, precision, tune_batch) is reused without timing,
@@ -112,8 +116,8 @@ typedef struct {
   int device;
   int32_t row_log2;     /* FP32 product: log2 of its row transform length (L for a single pass) */
   int32_t col_log2;     /* FP32 product: log2 L1 of its column transforms (0: single pass) */
-  int32_t cic_shape;    /* tuned inverse-column-pass shape (0: default; 1: 1 pair x 4 wavefronts,
-                           2: 1 x 8, 3: 2 x 4) */
+  int32_t cic_shape;    /* tuned inverse-column-pass shape (0: default; 1: 1 pair per lane x 4
+                           wavefronts, 2: 1 x 8) */
   int32_t cic_maxlog1;  /* tuned largest log2 L1 with the update fused (0: default) */
   int32_t tuned;        /* 0: not tuned, 1: timed at creation, 2: from the tuning cache */
   int64_t tune_batch;   /* batch size the choice was made for */

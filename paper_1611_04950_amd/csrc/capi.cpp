@@ -230,7 +230,7 @@ struct slepian_group_s {
   // Alternatives chosen by timing at the first call (autotuning):
   // partial[v]: 32 (2 - v) signals per wavefront; colinv_corr[l1][v]: 8 >> v
   // wavefronts per workgroup.
-  Span single_corr[14], single[14], partial[2], reduce, colfwd[6], row, colinv_corr[6][2], colinv[6], apply;
+  Span single_corr[14], single[14], partial[2], reduce, colfwd[6], row[2], colinv_corr[6][2], colinv[6], apply;
   int partial_var = 0, colinv_var[6] = {0, 0, 0, 0, 0, 0};
   bool tuned = false, tuned_from_cache = false;
   std::vector<int> grouped, other;  // plan indices
@@ -905,7 +905,7 @@ int validate_domain(int64_t N, double W, double eps, const slepian_plan_opts *o)
     if (!(o->alpha >= 0.0) || !std::isfinite(o->alpha)) return SLEPIAN_EINVAL;
     if (o->K < 0 || o->K > N - 1) return SLEPIAN_EINVAL;
     if (o->precision < SLEPIAN_FP32 || o->precision > SLEPIAN_BF16_RAW) return SLEPIAN_EINVAL;
-    if (o->tune < 0 || o->tune > 1 || o->tune_batch < 0 || o->tune_batch > 32 * (int64_t)65535) return SLEPIAN_EINVAL;
+    if (o->tune < 0 || o->tune > 2 || o->tune_batch < 0 || o->tune_batch > 32 * (int64_t)65535) return SLEPIAN_EINVAL;
   }
   return SLEPIAN_OK;
 }
@@ -1075,7 +1075,7 @@ bool tune_cache_lookup(const char *path, const Plan *P, int64_t batch, TuneChoic
                     &us) != 9)
       continue;
     if (n != P->N || w != P->W || e != P->eps || prec != P->precision || b != batch) continue;
-    if (row < 9 || row > Lds<float>::logE || (cmx != 0 && cmx != 4 && cmx != 5) || cic < 0 || cic > 3) continue;
+    if (row < 9 || row > Lds<float>::logE || (cmx != 0 && cmx != 4 && cmx != 5) || cic < 0 || cic > 2) continue;
     c.row = row;
     c.cicmax = cmx;
     c.cic = cic;
@@ -1124,10 +1124,10 @@ void set_fp32_geometry(Plan *P, int row, int cicmax, int cic, hipStream_t st) {
 // Times the plan's projection (its precision, `batch` signals of +-1) for
 // each launch variant: rows of 2^13 or 2^12 points (three-pass plans), the
 // update fused into the inverse column pass up to L1 = 16 or 32, and that
-// pass's three workgroup shapes; keeps the fastest.  The variants change how
+// pass's workgroup shapes with one pair per lane; keeps the fastest.  The variants change how
 // the work is split, not what is computed.  A cache file (path may be null)
 // holds earlier choices per (N, W, eps, precision, batch).
-void tune_plan(Plan *P, int64_t batch, const char *cache, hipStream_t st) {
+void tune_plan(Plan *P, int64_t batch, const char *cache, bool groupable, hipStream_t st) {
   const int logL = ilog2_ceil(2 * P->N);
   if (logL <= Lds<float>::logE) return;  // single pass: one launch shape
   TuneChoice best;
@@ -1152,7 +1152,8 @@ void tune_plan(Plan *P, int64_t batch, const char *cache, hipStream_t st) {
   best.us = 1e30;
   try {
     std::vector<int> rows = {Lds<float>::logE};
-    if (logL - (Lds<float>::logE - 1) <= 9) rows.push_back(Lds<float>::logE - 1);
+    // groupable: only geometries the grouped launches take (L1 <= 32)
+    if (logL - (Lds<float>::logE - 1) <= (groupable ? 5 : 9)) rows.push_back(Lds<float>::logE - 1);
     for (int row : rows) {
       set_fp32_geometry(P, row, 0, 0, st);
       const int log1 = P->g32.log1;
@@ -1162,7 +1163,10 @@ void tune_plan(Plan *P, int64_t batch, const char *cache, hipStream_t st) {
         FftGeom g = P->g32;
         g.cicmax = cmx;
         const bool fused = P->proj.r > 0 && colinv_corr_ok(g, N, batch, (int)P->proj.r);
-        const std::vector<int> shapes = fused ? std::vector<int>{1, 2, 3} : std::vector<int>{0};
+        // one pair per lane only: groups run the fused pass that way, and with
+        // the same lanes per pair a grouped call reproduces this plan's own
+        // calls bit for bit (the wavefront count does not change the arithmetic)
+        const std::vector<int> shapes = fused ? std::vector<int>{1, 2} : std::vector<int>{0};
         for (int cic : shapes) {
           set_fp32_geometry(P, row, cmx, cic, st);
           Carver c0(nullptr);
@@ -1235,7 +1239,7 @@ int slepian_plan_ex(int64_t N, double W, double eps, const slepian_plan_opts *op
       build_eigen_state(P, st);
       if (opts && opts->tune_cache) P->tune_cache = opts->tune_cache;
       if (opts && opts->tune)
-        tune_plan(P, opts->tune_batch > 0 ? opts->tune_batch : kTuneBatch, opts->tune_cache, st);
+        tune_plan(P, opts->tune_batch > 0 ? opts->tune_batch : kTuneBatch, opts->tune_cache, opts->tune == 2, st);
       HIPCHK(hipStreamSynchronize(st));
       (void)hipStreamDestroy(st);
     } catch (...) {
@@ -1288,7 +1292,8 @@ int slepian_plan_batch(int n, const int64_t *N, const double *W, const double *e
         if (opts && opts[i].tune_cache) Ps[i]->tune_cache = opts[i].tune_cache;
       for (int i = 0; i < n; ++i)
         if (opts && opts[i].tune)
-          tune_plan(Ps[i], opts[i].tune_batch > 0 ? opts[i].tune_batch : kTuneBatch, opts[i].tune_cache, st);
+          tune_plan(Ps[i], opts[i].tune_batch > 0 ? opts[i].tune_batch : kTuneBatch, opts[i].tune_cache,
+                    opts[i].tune == 2, st);
       HIPCHK(hipStreamSynchronize(st));
       (void)hipStreamDestroy(st);
     } catch (...) {
@@ -2560,7 +2565,7 @@ namespace {
 // 8192 points and at most 32 columns.
 bool group_three_pass(const Plan *P) {
   const FftGeom &g = P->g32;
-  return g.v2 && !g.single() && g.log2 == 13 && g.log1 >= 1 && g.log1 <= 5;
+  return g.v2 && !g.single() && (g.log2 == 13 || g.log2 == 12) && g.log1 >= 1 && g.log1 <= 5;
 }
 
 GroupSpan span_of(const slepian_group_s *G, const slepian_group_s::Span &sp) {
@@ -2593,7 +2598,8 @@ void launch_grouped(const slepian_group_s *G, hipStream_t s1, hipStream_t s2, in
   HIPCHK(group_corr_reduce(G->gp_dev, span_of(G, G->reduce), s1));
   for (int l2 = 9; l2 <= 13; ++l2) HIPCHK(group_single(l2, false, G->gp_dev, span_of(G, G->single[l2]), s1));
   for (int l1 = 1; l1 <= 5; ++l1) HIPCHK(group_colfwd(l1, G->gp_dev, span_of(G, G->colfwd[l1]), s1));
-  HIPCHK(group_row(13, G->gp_dev, span_of(G, G->row), s1));
+  HIPCHK(group_row(13, G->gp_dev, span_of(G, G->row[1]), s1));
+  HIPCHK(group_row(12, G->gp_dev, span_of(G, G->row[0]), s1));
   for (int l1 = 1; l1 <= 5; ++l1) {
     group_colinv_fused(G, l1, G->colinv_var[l1], s1);
     HIPCHK(group_colinv(l1, G->gp_dev, span_of(G, G->colinv[l1]), s1));
@@ -2851,8 +2857,9 @@ int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batc
           if (r > 0) apply.push_back(i);
         }
       }
-      std::vector<int> three;
-      for (int l1 = 1; l1 <= 5; ++l1) three.insert(three.end(), by_l1[l1].begin(), by_l1[l1].end());
+      std::vector<int> three[2];  // rows of 2^12, 2^13 points
+      for (int l1 = 1; l1 <= 5; ++l1)
+        for (int i : by_l1[l1]) three[plans[i]->g32.log2 - 12].push_back(i);
       for (int l2 = 9; l2 <= 13; ++l2) {
         add_span(G->single_corr[l2], by_single_corr[l2], group_blocks_single);
         add_span(G->single[l2], by_single[l2], group_blocks_single);
@@ -2861,7 +2868,7 @@ int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batc
         add_span(G->partial[v], mfma, [v](const GroupPlan &g) { return group_blocks_partial(g, 2 - v); });
       add_span(G->reduce, mfma, group_blocks_reduce);
       for (int l1 = 1; l1 <= 5; ++l1) add_span(G->colfwd[l1], by_l1[l1], group_blocks_colfwd);
-      add_span(G->row, three, group_blocks_row);
+      for (int k = 0; k < 2; ++k) add_span(G->row[k], three[k], group_blocks_row);
       for (int l1 = 1; l1 <= 5; ++l1) {
         for (int v = 0; v < 2; ++v)
           add_span(G->colinv_corr[l1][v], by_l1_fused[l1],

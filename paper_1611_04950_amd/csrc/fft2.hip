@@ -1430,9 +1430,15 @@ hipError_t group_colinv(int log1, const GroupPlan *gp, const GroupSpan &sp, hipS
 
 hipError_t group_row(int log2, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
   if (sp.m == 0) return hipSuccess;
-  if (log2 != 13) return hipErrorInvalidValue;
-  SLP_LAUNCH("row_conv_group", (k_row2_group<32, 16, 16>), dim3((unsigned)sp.blocks), dim3(256), 0, st, gp, sp.idx,
-             sp.start, sp.m);
+  if (log2 == 13) {
+    SLP_LAUNCH("row_conv_group", (k_row2_group<32, 16, 16>), dim3((unsigned)sp.blocks), dim3(256), 0, st, gp,
+               sp.idx, sp.start, sp.m);
+  } else if (log2 == 12) {
+    SLP_LAUNCH("row_conv_group_4096", (k_row2_group<16, 16, 16>), dim3((unsigned)sp.blocks), dim3(256), 0, st, gp,
+               sp.idx, sp.start, sp.m);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

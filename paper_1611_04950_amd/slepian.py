@@ -214,7 +214,8 @@ def slepian_plan_batch(specs, alpha: float = 0.0, K: int = 0, precision: int = S
                        device: int = -1, tune: bool = False, tune_batch: int = 0,
                        tune_cache: str | None = None) -> list:
     """Plans for (N, W, eps) triples in one call (the eigensolves run
-    together); the options apply to every plan."""
+    together); the options apply to every plan (tune_batch may also be a
+    list, one batch size per plan)."""
     n = len(specs)
     if n == 0:
         return []
@@ -222,7 +223,8 @@ def slepian_plan_batch(specs, alpha: float = 0.0, K: int = 0, precision: int = S
     Ws = (C.c_double * n)(*[float(sp[1]) for sp in specs])
     Es = (C.c_double * n)(*[float(sp[2]) for sp in specs])
     cache = None if tune_cache is None else tune_cache.encode()
-    opts = (PlanOpts * n)(*[PlanOpts(alpha, K, precision, device, int(tune), tune_batch, cache) for _ in range(n)])
+    tb = list(tune_batch) if isinstance(tune_batch, (list, tuple)) else [tune_batch] * n
+    opts = (PlanOpts * n)(*[PlanOpts(alpha, K, precision, device, int(tune), int(tb[i]), cache) for i in range(n)])
     hs = (C.c_void_p * n)()
     _check(_lib.slepian_plan_batch(n, Ns, Ws, Es, opts, hs), "slepian_plan_batch")
     return [Plan(h) for h in hs]

@@ -255,17 +255,28 @@ def test_group_matches_single_plans(plans):
             assert torch.equal(y, ref), rep
 
 
-@pytest.mark.parametrize("prec", ["fp32", "mixed"])
-def test_group_paths_match_single_plans(prec):
+@pytest.mark.parametrize("prec,rows", [("fp32", 13), ("mixed", 13), ("mixed", 12)])
+def test_group_paths_match_single_plans(prec, rows, tmp_path):
     """Every grouped path: single pass with and without the in-kernel
     correction, three passes with the update fused into the inverse column
     pass (L1 <= 16) or applied separately (L1 = 32), odd and unaligned
-    lengths; the grouped call reproduces the single-plan calls bit for bit,
-    on two calls in a row with different buffers."""
+    lengths, and (rows = 12) three-pass plans tuned to rows of 4096 points
+    through a tuning-cache entry (L1 = 64 runs plan by plan); the grouped call
+    reproduces the single-plan calls bit for bit, on two calls in a row with
+    different buffers."""
     pr = S.SLEPIAN_FP32 if prec == "fp32" else S.SLEPIAN_MIXED
     specs = [(1024, 0.05, 1e-3, 20), (3001, 0.2, 1e-6, 33), (700, 0.3, 1e-6, 3), (20000, 0.11, 1e-6, 9),
              (70001, 0.05, 1e-6, 5), (5000, 0.03, 1e-6, 64), (100, 0.1, 1e-3, 6)]
-    ps = [S.slepian_plan(N, W, e, precision=pr) for N, W, e, _ in specs]
+    if rows == 12:
+        cache = str(tmp_path / "rows.txt")
+        with open(cache, "w") as f:
+            for N, W, e, b in specs:
+                f.write(f"slepian-tune-v1 {N} {W!r} {e!r} {pr} {b} 12 4 0 1.0\n")
+        ps = [S.slepian_plan(N, W, e, precision=pr, tune=True, tune_batch=b, tune_cache=cache)
+              for N, W, e, b in specs]
+        assert sum(p.info["row_log2"] == 12 and p.info["col_log2"] > 0 for p in ps) >= 3
+    else:
+        ps = [S.slepian_plan(N, W, e, precision=pr) for N, W, e, _ in specs]
     G = S.slepian_group_create(ps, [b for *_, b in specs])
     for rep in range(2):
         xs = [synth.gaussian(N, b, 700 + 10 * rep + i, device="cuda") for i, (N, _, _, b) in enumerate(specs)]

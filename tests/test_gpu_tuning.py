@@ -61,7 +61,7 @@ def test_every_variant_matches_oracle(tmp_path):
     x = synth.gaussian(N, 4, 82, device="cuda")
     ref = o.project_fast(N, W, eps, x.double().cpu().numpy().T).T
     cache = str(tmp_path / "c.txt")
-    for row, cmx, cic in ((13, 4, 0), (13, 5, 1), (13, 5, 2), (13, 5, 3), (12, 4, 0)):
+    for row, cmx, cic in ((13, 4, 0), (13, 5, 1), (13, 5, 2), (12, 4, 0), (12, 5, 1)):
         with open(cache, "w") as f:
             f.write(f"slepian-tune-v1 {N} {W!r} {eps!r} 1 16 {row} {cmx} {cic} 1.0\n")
         P = S.slepian_plan(N, W, eps, precision=S.SLEPIAN_MIXED, tune=True, tune_batch=16, tune_cache=cache)
