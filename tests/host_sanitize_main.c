@@ -84,7 +84,7 @@ int main(int argc, char **argv) {
   o.precision = 7;
   EXPECT(slepian_plan_ex(64, 0.1, 1e-6, &o, &plan), SLEPIAN_EINVAL);
   o.precision = 0;
-  o.tune = 2;
+  o.tune = 3;
   EXPECT(slepian_plan_ex(64, 0.1, 1e-6, &o, &plan), SLEPIAN_EINVAL);
   o.tune = 1;
   o.tune_batch = -5;
