@@ -548,7 +548,7 @@ __device__ __forceinline__ void st_at(T *base, uint32_t byte_off, T v) {
 // keeps 64 complex inputs per lane and is compiled for 3).
 constexpr int kCicWaves = 6;
 
-template <int L1, int MODE, int CW, int PPL, bool EVEN = false>
+template <int L1, int MODE, int CW, int PPL, bool EVEN = false, bool ONE = false>
 __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ Z, int N, int b, int pair0, int np,
                                                  int logL, int log2, const cpx<float> *__restrict__ tcol,
                                                  float *__restrict__ y, int64_t ldy, const void *__restrict__ ut,
@@ -602,6 +602,31 @@ __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ 
   const uint32_t sac = sav ? (uint32_t)sa : 0u;
   const uint32_t tile_row = 16u * (uint32_t)rp;  // elements per row n1 of one column block
   float *yw = y + (int64_t)2 * (pair0 + pw) * ldy;
+  // ONE (the host launches it for rp = 32, rank <= 32): the contraction over
+  // j is one step per row, the A operand is the same for every row and is
+  // formed once, and a chunk's tile loads are all in flight together.  Lane
+  // (col, blk) holds dC^T[col][j] for j = 8 blk + e (MODE 1) or
+  // j = 16 g + 4 blk + m (MODE 0, g = e / 4, m = e % 4).  The sums run in the
+  // same order as the general loop's, so both give the same bits.
+  constexpr bool one = ONE;
+  float dcv[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int j = MODE ? 8 * blk + e : 16 * (e >> 2) + 4 * blk + (e & 3);
+    dcv[e] = (one && sav && j < r) ? ld_at(dC, ((uint32_t)j * (uint32_t)b + sac) * 4u) : 0.f;
+  }
+  bf16x8 ahi1, alo1;
+  if constexpr (MODE == 1 && one) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const __bf16 hh = (__bf16)dcv[e];
+      ahi1[e] = hh;
+      alo1[e] = (__bf16)(dcv[e] - (float)hh);
+    }
+  }
+  // every row of this column block lies below N: stores need only the
+  // signal check (uniform per wavefront)
+  const bool full = c0 + 15 + ((ROWS - 1) << log2) < N;
   // Rows go through the matrix cores in chunks of at most eight, so only one
   // chunk's accumulators are live next to the DFT outputs.
   constexpr int RC = ROWS < 8 ? ROWS : 8;
@@ -622,20 +647,40 @@ __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ 
     if constexpr (MODE == 0) {
       const float *T = static_cast<const float *>(ut) + base;
       const uint32_t lo = (uint32_t)col * rp + 4u * blk;
-      for (int g = 0; g < rp; g += 16) {
-        float av[4];
+      if constexpr (one) {
+        float4 u0[RC], u1[RC];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int j = g + 4 * blk + m;
-          av[m] = (sav && j < r) ? ld_at(dC, ((uint32_t)j * (uint32_t)b + sac) * 4u) : 0.f;
+        for (int i = 0; i < RC; ++i) {
+          u0[i] = ld_at(reinterpret_cast<const float4 *>(T), (lo + i * tile_row) * 4u);
+          u1[i] = ld_at(reinterpret_cast<const float4 *>(T), (lo + i * tile_row + 16u) * 4u);
         }
 #pragma unroll
         for (int i = 0; i < RC; ++i) {
-          const float4 u = ld_at(reinterpret_cast<const float4 *>(T), (lo + i * tile_row + g) * 4u);
-          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], u.x, acc[i], 0, 0, 0);
-          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1], u.y, acc[i], 0, 0, 0);
-          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2], u.z, acc[i], 0, 0, 0);
-          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[3], u.w, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(dcv[0], u0[i].x, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(dcv[1], u0[i].y, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(dcv[2], u0[i].z, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(dcv[3], u0[i].w, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(dcv[4], u1[i].x, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(dcv[5], u1[i].y, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(dcv[6], u1[i].z, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(dcv[7], u1[i].w, acc[i], 0, 0, 0);
+        }
+      } else {
+        for (int g = 0; g < rp; g += 16) {
+          float av[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int j = g + 4 * blk + m;
+            av[m] = (sav && j < r) ? ld_at(dC, ((uint32_t)j * (uint32_t)b + sac) * 4u) : 0.f;
+          }
+#pragma unroll
+          for (int i = 0; i < RC; ++i) {
+            const float4 u = ld_at(reinterpret_cast<const float4 *>(T), (lo + i * tile_row + g) * 4u);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], u.x, acc[i], 0, 0, 0);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1], u.y, acc[i], 0, 0, 0);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2], u.z, acc[i], 0, 0, 0);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[3], u.w, acc[i], 0, 0, 0);
+          }
         }
       }
     } else {
@@ -643,24 +688,40 @@ __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ 
       const __bf16 *Th = static_cast<const __bf16 *>(ut) + base;
       const __bf16 *Tl = Th + plane;
       const uint32_t lo = (uint32_t)col * rp + 8u * blk;
-      for (int g = 0; g < rp; g += 32) {
-        bf16x8 ahi, alo;
+      if constexpr (one) {
+        bf16x8 bhi[RC], blo[RC];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int j = g + 8 * blk + e;
-          const float av = (sav && j < r) ? ld_at(dC, ((uint32_t)j * (uint32_t)b + sac) * 4u) : 0.f;
-          const __bf16 hh = (__bf16)av;
-          ahi[e] = hh;
-          alo[e] = (__bf16)(av - (float)hh);
+        for (int i = 0; i < RC; ++i) {
+          const uint32_t o = (lo + i * tile_row) * 2u;
+          bhi[i] = ld_at(reinterpret_cast<const bf16x8 *>(Th), o);
+          blo[i] = ld_at(reinterpret_cast<const bf16x8 *>(Tl), o);
         }
 #pragma unroll
         for (int i = 0; i < RC; ++i) {
-          const uint32_t o = (lo + i * tile_row + g) * 2u;
-          const bf16x8 bhi = ld_at(reinterpret_cast<const bf16x8 *>(Th), o);
-          const bf16x8 blo = ld_at(reinterpret_cast<const bf16x8 *>(Tl), o);
-          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[i], 0, 0, 0);
-          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[i], 0, 0, 0);
-          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi1, bhi[i], acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi1, blo[i], acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo1, bhi[i], acc[i], 0, 0, 0);
+        }
+      } else {
+        for (int g = 0; g < rp; g += 32) {
+          bf16x8 ahi, alo;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int j = g + 8 * blk + e;
+            const float av = (sav && j < r) ? ld_at(dC, ((uint32_t)j * (uint32_t)b + sac) * 4u) : 0.f;
+            const __bf16 hh = (__bf16)av;
+            ahi[e] = hh;
+            alo[e] = (__bf16)(av - (float)hh);
+          }
+#pragma unroll
+          for (int i = 0; i < RC; ++i) {
+            const uint32_t o = (lo + i * tile_row + g) * 2u;
+            const bf16x8 bhi = ld_at(reinterpret_cast<const bf16x8 *>(Th), o);
+            const bf16x8 blo = ld_at(reinterpret_cast<const bf16x8 *>(Tl), o);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[i], 0, 0, 0);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[i], 0, 0, 0);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[i], 0, 0, 0);
+          }
         }
       }
     }
@@ -671,16 +732,21 @@ __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ 
       const int sg = 2 * (pair0 + pl) + (v & 1);
       if (pl >= np || sg >= b) continue;
       const uint32_t so = (uint32_t)(2 * PPL * blk + v) * (uint32_t)ldy + (uint32_t)n2;
+      if (full) {
 #pragma unroll
-      for (int i = 0; i < RC; ++i) {
-        const int n = n2 + ((rc + i) << log2);
-        if (n < N) st_at(yw, (so + ((uint32_t)(rc + i) << log2)) * 4u, acc[i][v]);
+        for (int i = 0; i < RC; ++i) st_at(yw, (so + ((uint32_t)(rc + i) << log2)) * 4u, acc[i][v]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+          const int n = n2 + ((rc + i) << log2);
+          if (n < N) st_at(yw, (so + ((uint32_t)(rc + i) << log2)) * 4u, acc[i][v]);
+        }
       }
     }
   }
 }
 
-template <int L1, int MODE, int CW, int PPL, bool EVEN = false>
+template <int L1, int MODE, int CW, int PPL, bool EVEN = false, bool ONE = false>
 __global__ __launch_bounds__(64 * CW, L1 >= 32 ? 3 : kCicWaves) void k_colinv_corr(const cpx<float> *__restrict__ Z, int N, int b, int pair0,
                                                          int np, int logL, int log2,
                                                          const cpx<float> *__restrict__ tcol, float *__restrict__ y,
@@ -691,8 +757,8 @@ __global__ __launch_bounds__(64 * CW, L1 >= 32 ? 3 : kCicWaves) void k_colinv_co
   // a 128-byte line of y are handled within one L2.
   const int gx = gridDim.x;
   const int cb = (gx & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (gx >> 3) + (int)(blockIdx.x >> 3);
-  colinv_corr_body<L1, MODE, CW, PPL, EVEN>(Z, N, b, pair0, np, logL, log2, tcol, y, ldy, ut, r, rp, dC, cb,
-                                            blockIdx.y);
+  colinv_corr_body<L1, MODE, CW, PPL, EVEN, ONE>(Z, N, b, pair0, np, logL, log2, tcol, y, ldy, ut, r, rp, dC, cb,
+                                                 blockIdx.y);
 }
 
 // U's rows in the order the fused inverse column pass reads them (see
@@ -985,6 +1051,15 @@ static void launch_cic(hipStream_t st, const cpx<float> *Z, int N, int b, int p0
                        const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c, int rp) {
   constexpr int PW = 4 * PPL * CW;  // pairs per workgroup
   const dim3 grid((1u << g.log2) / 16, (unsigned)((np + PW - 1) / PW));
+  // L1 = 32, one pair per lane, rank <= 32: the single-step contraction
+  // (same bits; with two pairs per lane its registers would spill)
+  if constexpr (L1 >= 32 && !EVEN && PPL == 1) {
+    if (rp == 32) {
+      SLP_LAUNCH(MODE ? "col_inv_corr_bf16x3" : "col_inv_corr", (k_colinv_corr<L1, MODE, CW, PPL, false, true>), grid,
+                 dim3(64 * CW), 0, st, Z, N, b, p0, np, g.logL, g.log2, tb.col, y, ldy, c.ut, c.r, rp, c.dC);
+      return;
+    }
+  }
   SLP_LAUNCH(MODE ? (EVEN ? "col_inv_even_corr_bf16x3" : "col_inv_corr_bf16x3") : (EVEN ? "col_inv_even_corr" : "col_inv_corr"),
              (k_colinv_corr<L1, MODE, CW, PPL, EVEN>), grid, dim3(64 * CW),
              0, st, Z, N, b, p0, np, g.logL, g.log2, tb.col, y, ldy, c.ut, c.r, rp, c.dC);

@@ -52,26 +52,33 @@ def test_tuned_plan_and_cache(tmp_path, N, W, eps, prec):
     assert len(lines) == 3  # two malformed ones kept, one new entry
 
 
-def test_every_variant_matches_oracle(tmp_path):
+@pytest.mark.parametrize("N,b,prec", [(131072, 4, "mixed"), (131072, 4, "fp32"), (100003, 5, "mixed"),
+                                      (100003, 5, "fp32")])
+def test_every_variant_matches_oracle(tmp_path, N, b, prec):
     """Each variant the tuner can choose computes the same projection to the
-    oracle's 1e-5: at N = 2^17 (L = 2^18) rows of 2^13 points (L1 = 32, the
-    update fused into the inverse column pass or not, all three shapes of
-    that pass) and rows of 2^12 (L1 = 64), each forced through a cache entry."""
-    N, W, eps = 131072, 1 / 16, 1e-6
-    x = synth.gaussian(N, 4, 82, device="cuda")
+    oracle's 1e-5: at L = 2^18 rows of 2^13 points (L1 = 32, the update fused
+    into the inverse column pass or not, both one-pair shapes of that pass)
+    and rows of 2^12 (L1 = 64), each forced through a cache entry; both
+    matrix modes of the fused update (rank <= 32 takes its single-step
+    contraction), a length whose last rows fall partly beyond N, and an odd
+    batch whose last pair holds one signal."""
+    W, eps = 1 / 16, 1e-6
+    code = S.SLEPIAN_MIXED if prec == "mixed" else S.SLEPIAN_FP32
+    x = synth.gaussian(N, b, 82, device="cuda")
     ref = o.project_fast(N, W, eps, x.double().cpu().numpy().T).T
     cache = str(tmp_path / "c.txt")
     for row, cmx, cic in ((13, 4, 0), (13, 5, 1), (13, 5, 2), (12, 4, 0), (12, 5, 1)):
         with open(cache, "w") as f:
-            f.write(f"slepian-tune-v1 {N} {W!r} {eps!r} 1 16 {row} {cmx} {cic} 1.0\n")
-        P = S.slepian_plan(N, W, eps, precision=S.SLEPIAN_MIXED, tune=True, tune_batch=16, tune_cache=cache)
+            f.write(f"slepian-tune-v1 {N} {W!r} {eps!r} {code} 16 {row} {cmx} {cic} 1.0\n")
+        P = S.slepian_plan(N, W, eps, precision=code, tune=True, tune_batch=16, tune_cache=cache)
         info = P.info
         assert info["tuned"] == 2 and info["row_log2"] == row and info["cic_maxlog1"] == cmx
         assert info["cic_shape"] == cic
         y = S.slepian_project(P, x)
         torch.cuda.synchronize()
         e = _rel(y.double().cpu().numpy(), ref).max()
-        print(f"variant rows 2^{row} fused up to 2^{cmx} shape {cic}: {e:.2e}", flush=True)
+        print(f"N={N} b={b} {prec} r={info['r']}: rows 2^{row} fused up to 2^{cmx} shape {cic}: {e:.2e}",
+              flush=True)
         assert e <= 1e-5
 
 
