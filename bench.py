@@ -55,7 +55,8 @@ def _finite(v):
     return v
 
 
-def kernel_bytes(name: str, N: int, b: int, L: int, r: int, pairs_per_launch: int):
+def kernel_bytes(name: str, N: int, b: int, L: int, r: int, pairs_per_launch: int, col_log2: int = 0,
+                 fwd_chunks: bool = False):
     """Algorithmic HBM bytes of one launch of each kernel of the path: what the
     method must move (FP32 signal in/out 4 B/sample, complex64 intermediates
     8 B/point, spectrum 4 B/point once, U 4 B/entry once)."""
@@ -64,6 +65,10 @@ def kernel_bytes(name: str, N: int, b: int, L: int, r: int, pairs_per_launch: in
         return P * 16.0 * L + 4.0 * L
     if name == "col_fwd":
         return P * (8.0 * N + 8.0 * L)
+    if name.startswith("col_fwd_corr"):
+        # x in, Z out, U read once, one partial of C per 16 columns written
+        chunks = L // (2 ** col_log2) // 16 if col_log2 else 0
+        return P * (8.0 * N + 8.0 * L) + 4.0 * N * r + 4.0 * r * b * chunks
     if name == "col_inv":
         return P * (8.0 * L + 8.0 * N)
     if name.startswith("col_inv_corr"):
@@ -76,8 +81,10 @@ def kernel_bytes(name: str, N: int, b: int, L: int, r: int, pairs_per_launch: in
     if name in ("conv_single", "conv_single_corr"):
         return P * 8.0 * N + 4.0 * L + 4.0 * N * r
     if name == "corr_reduce":
-        # chunk partials (one per 256 samples) read once, d (.) C written once
-        return 4.0 * b * r * ((N + 255) // 256 + 1)
+        # chunk partials read once (one per 256 samples, or one per 16
+        # columns when pass A forms them), d (.) C written once
+        chunks = L // (2 ** col_log2) // 16 if fwd_chunks else (N + 255) // 256
+        return 4.0 * b * r * (chunks + 1)
     return None
 
 
@@ -283,7 +290,8 @@ def traced_roofline(call, steps, N, b, info, workload):
     dom = max(stats, key=lambda k: stats[k]["total_ms"])
     for name in kernels:
         ppl = pairs / kernels[name]["launches_per_step"] if not name.startswith("corr") else pairs
-        kb = kernel_bytes(name, N, b, info["L"], info["r"], ppl)
+        kb = kernel_bytes(name, N, b, info["L"], info["r"], ppl, info["col_log2"],
+                          any(k.startswith("col_fwd_corr") for k in stats))
         kernels[name]["alg_bytes"] = kb
         kernels[name]["alg_GBs"] = None if kb is None else kb / (kernels[name]["avg_us"] * 1e-6) / 1e9
         t = read_traffic(name, workload)

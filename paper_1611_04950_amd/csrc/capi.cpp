@@ -19,6 +19,7 @@
 
 #include "slepian.h"
 #include "common.h"
+#include "corr_sum.h"
 #include "kernels.h"
 #include "trace.h"
 
@@ -159,6 +160,9 @@ struct slepian_plan_s {
   // U's rows laid out for the fused inverse column pass, per column set and
   // matrix mode (FP32, BF16 hi/lo); null where that pass does not apply
   void *ctile[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  // U's rows laid out for pass A with the correction's coefficients, per
+  // column set and matrix mode; null where that pass does not apply
+  void *ftile[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   // U's layouts for prepared band sets, built by the first band set of each
   // matrix mode (0: FP32 U^T; 1: BF16 hi/lo planes of U and U^T)
   void *mbu[2] = {nullptr, nullptr};
@@ -186,6 +190,8 @@ struct slepian_plan_s {
     dfree(SKh);
     dfree(SKl);
     for (auto &t : ctile)
+      for (void *p : t) dfree(p);
+    for (auto &t : ftile)
       for (void *p : t) dfree(p);
     for (void *p : mbu) dfree(p);
   }
@@ -230,7 +236,10 @@ struct slepian_group_s {
   // Alternatives chosen by timing at the first call (autotuning):
   // partial[v]: 32 (2 - v) signals per wavefront; colinv_corr[l1][v]: 8 >> v
   // wavefronts per workgroup.
-  Span single_corr[14], single[14], partial[2], reduce, colfwd[6], row[2], colinv_corr[6][2], colinv[6], apply;
+  // colfwd_corr: pass A with the coefficients' partials (L1 = 16, 32).
+  // colinv_corr1: L1 = 32 plans of rank <= 32 (the single-step contraction).
+  Span single_corr[14], single[14], partial[2], reduce, colfwd[6], colfwd_corr[6], row[2], colinv_corr[6][2],
+      colinv_corr1[2], colinv[6], apply;
   int partial_var = 0, colinv_var[6] = {0, 0, 0, 0, 0, 0};
   bool tuned = false, tuned_from_cache = false;
   std::vector<int> grouped, other;  // plan indices
@@ -281,6 +290,35 @@ struct ProjWs {
   float *part = nullptr, *dC = nullptr;
 };
 
+// Pass A forms the chunk partials of U^T x itself when the plan holds its
+// tile for this column set and matrix mode (FP32 or BF16 hi/lo) and one
+// slice of the three-pass intermediate holds every pair of the batch
+// (tuning override: SLEPIAN_FWD_CORR=0 keeps the separate partial kernel).
+bool fwd_corr_enabled() {
+  static const bool on = [] {
+    const char *e = std::getenv("SLEPIAN_FWD_CORR");
+    return !(e && std::atoi(e) == 0);
+  }();
+  return on;
+}
+
+bool fwd_corr_applies(const Plan *P, const OpSet &op, int mode, int64_t b) {
+  if (!fwd_corr_enabled()) return false;
+  if (op.r <= 0 || mode < 0 || mode > 1 || !P->ftile[op.set][mode]) return false;
+  if (!colfwd_corr_ok(P->g32, (int)op.r)) return false;
+  const int64_t pairs = (b + 1) / 2;
+  if (pairs == 0 || (pairs + 15) / 16 > 65535) return false;
+  return (int64_t)conv_workspace_pairs(P->g32, pairs, sizeof(cpx<float>), slice_budget()) >= pairs;
+}
+
+// Chunk partials of U^T x: the matrix-core partial kernel's chunks or pass
+// A's column blocks, whichever path the call takes (the larger of the two).
+int64_t corr_part_chunks(const Plan *P, const OpSet &op, int64_t b) {
+  int64_t c = corr_nchunks(P->N, b, (int)op.r);
+  if (colfwd_corr_ok(P->g32, (int)op.r)) c = std::max<int64_t>(c, colfwd_corr_chunks(P->g32));
+  return c;
+}
+
 ProjWs carve_project(const Plan *P, const OpSet &op, int64_t b, Carver &cv, int prec = SLEPIAN_FP32) {
   ProjWs w;
   if (fused_single(P, op, prec, b)) return w;
@@ -289,7 +327,7 @@ ProjWs carve_project(const Plan *P, const OpSet &op, int64_t b, Carver &cv, int 
   if (!P->g32.single()) w.Z = cv.take<cpx<float>>((size_t)w.slice * (size_t)P->L);
   if (op.r > 0) {
     const int rpad = corr_rpad((int)op.r);
-    w.part = cv.take<float>((size_t)corr_nchunks(P->N, b, (int)op.r) * rpad * b);
+    w.part = cv.take<float>((size_t)corr_part_chunks(P, op, b) * rpad * b);
     w.dC = cv.take<float>((size_t)b * rpad);
   }
   return w;
@@ -436,7 +474,9 @@ void run_fast_op(const Plan *P, const OpSet &op, float beta, float gamma, const 
     return;
   }
   const int mode = prec == SLEPIAN_MIXED ? 1 : (prec == SLEPIAN_BF16_RAW ? 2 : 0);
-  if (op.r > 0) {
+  // the coefficients U^T x ride on pass A where its tile exists
+  const bool fwd = fwd_corr_applies(P, op, mode, b);
+  if (op.r > 0 && !fwd) {
     HIPCHK(corr_partial_mfma(mode, x, ldx, N, b, U, P->ldu, (int)op.r, w.part, st));
     HIPCHK(corr_reduce_mfma(w.part, N, b, (int)op.r, op.d32, w.dC, st));
   }
@@ -455,7 +495,22 @@ void run_fast_op(const Plan *P, const OpSet &op, float beta, float gamma, const 
     c.mode = umode;
     c.ut = tile;
   }
-  HIPCHK(conv_apply<float>(x, ldx, y, ldy, N, b, P->g32, P->tb32, beta, gamma, c, w.Z, w.slice, st));
+  if (fwd) {
+    HIPCHK(colfwd_corr(x, ldx, N, b, P->g32, P->tb32, w.Z, P->ftile[op.set][mode], (int)op.r, mode, w.part, st));
+    // the row pass sums the partials into dC on the side
+    RowSum rs;
+    rs.part = w.part;
+    rs.d = op.d32;
+    rs.dC = w.dC;
+    rs.chunks = colfwd_corr_chunks(P->g32);
+    rs.rpad = corr_rpad((int)op.r);
+    rs.b = (int)b;
+    rs.r = (int)op.r;
+    rs.blocks = (int)corr_reduce_blocks((int)op.r, b);
+    HIPCHK(conv_rows_inv(y, ldy, N, b, P->g32, P->tb32, beta, gamma, c, w.Z, &rs, st));
+  } else {
+    HIPCHK(conv_apply<float>(x, ldx, y, ldy, N, b, P->g32, P->tb32, beta, gamma, c, w.Z, w.slice, st));
+  }
   if (op.r > 0 && !fused) HIPCHK(corr_apply_mfma(y, ldy, N, b, U, P->ldu, (int)op.r, w.dC, st));
 }
 
@@ -481,7 +536,19 @@ void upload_d(OpSet &o) {
 // column sets), for three-pass plans whose L1 it handles.
 void build_corr_tiles(Plan *P, hipStream_t st) {
   const FftGeom &g = P->g32;
-  if (!g.v2 || g.single() || !colinv_corr_tiled(g)) return;
+  for (const OpSet *o : {&P->proj, &P->tik}) {
+    if (o->r <= 0 || !colfwd_corr_ok(g, (int)o->r)) continue;
+    for (int mode = 0; mode < 2; ++mode) {
+      if (P->ftile[o->set][mode]) continue;  // depends on the geometry only
+      void *t = dalloc<char>(fwd_tile_bytes(g, (int)o->r));
+      P->ftile[o->set][mode] = t;
+      HIPCHK(build_fwd_tile(P->U32 + o->off * P->ldu, P->ldu, (int)P->N, (int)o->r, g, mode, t, st));
+    }
+  }
+  if (!g.v2 || g.single() || !colinv_corr_tiled(g)) {
+    HIPCHK(hipStreamSynchronize(st));
+    return;
+  }
   for (const OpSet *o : {&P->proj, &P->tik}) {
     if (o->r <= 0) continue;
     for (int mode = 0; mode < 2; ++mode) {
@@ -549,6 +616,11 @@ void free_fp32_state(Plan *P) {
   dfree(P->chat32);
   P->chat32 = nullptr;
   for (auto &t : P->ctile)
+    for (void *&p : t) {
+      dfree(p);
+      p = nullptr;
+    }
+  for (auto &t : P->ftile)
     for (void *&p : t) {
       dfree(p);
       p = nullptr;
@@ -2586,7 +2658,9 @@ void group_partial(const slepian_group_s *G, int var, bool vec, hipStream_t st) 
 
 void group_colinv_fused(const slepian_group_s *G, int l1, int var, hipStream_t st) {
   const int umode = G->prec == SLEPIAN_MIXED ? 1 : 0;
-  HIPCHK(group_colinv_corr(l1, umode, 8 >> var, G->gp_dev, span_of(G, G->colinv_corr[l1][var]), st));
+  HIPCHK(group_colinv_corr(l1, umode, 8 >> var, false, G->gp_dev, span_of(G, G->colinv_corr[l1][var]), st));
+  if (l1 == 5)
+    HIPCHK(group_colinv_corr(l1, umode, 8 >> var, true, G->gp_dev, span_of(G, G->colinv_corr1[var]), st));
 }
 
 // The grouped launches, in the order of the single-plan path: plans whose
@@ -2595,6 +2669,8 @@ void group_colinv_fused(const slepian_group_s *G, int l1, int var, hipStream_t s
 void launch_grouped(const slepian_group_s *G, hipStream_t s1, hipStream_t s2, int vec) {
   for (int l2 = 9; l2 <= 13; ++l2) HIPCHK(group_single(l2, true, G->gp_dev, span_of(G, G->single_corr[l2]), s2));
   group_partial(G, G->partial_var, vec & 1, s1);
+  const int umode = G->prec == SLEPIAN_MIXED ? 1 : 0;
+  for (int l1 = 4; l1 <= 5; ++l1) HIPCHK(group_colfwd_corr(l1, umode, G->gp_dev, span_of(G, G->colfwd_corr[l1]), s1));
   HIPCHK(group_corr_reduce(G->gp_dev, span_of(G, G->reduce), s1));
   for (int l2 = 9; l2 <= 13; ++l2) HIPCHK(group_single(l2, false, G->gp_dev, span_of(G, G->single[l2]), s1));
   for (int l1 = 1; l1 <= 5; ++l1) HIPCHK(group_colfwd(l1, G->gp_dev, span_of(G, G->colfwd[l1]), s1));
@@ -2708,7 +2784,7 @@ void tune_group(slepian_group_s *G, hipStream_t st, int vec) {
       G->partial_var = t1 < t0 ? 1 : 0;
     }
     for (int l1 = 1; l1 <= 5; ++l1) {
-      if (!G->colinv_corr[l1][0].m) continue;
+      if (!G->colinv_corr[l1][0].m && !(l1 == 5 && G->colinv_corr1[0].m)) continue;
       const float t0 = timed([&] { group_colinv_fused(G, l1, 0, st); });
       const float t1 = timed([&] { group_colinv_fused(G, l1, 1, st); });
       G->colinv_var[l1] = t1 < t0 ? 1 : 0;
@@ -2756,6 +2832,7 @@ int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batc
       };
       std::vector<size_t> zoff(n, 0), poff(n, 0), doff(n, 0);
       std::vector<char> fused(n, 0);  // single pass with the correction inside
+      std::vector<char> fwdc(n, 0);   // pass A forms the coefficients' partials (as a single-plan call does)
       for (int i = 0; i < n; ++i) {
         const Plan *P = plans[i];
         const int64_t b = batch[i];
@@ -2774,8 +2851,10 @@ int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batc
         }
         G->grouped.push_back(i);
         if (!single) zoff[i] = reserve((size_t)((b + 1) / 2) * (size_t)P->L * sizeof(cpx<float>));
+        fwdc[i] = !single && fwd_corr_applies(P, P->proj, umode, b);
         if (r > 0) {
-          poff[i] = reserve((size_t)corr_nchunks(P->N, b, r) * corr_rpad(r) * b * sizeof(float));
+          const int64_t chunks = fwdc[i] ? colfwd_corr_chunks(P->g32) : corr_nchunks(P->N, b, r);
+          poff[i] = reserve((size_t)chunks * corr_rpad(r) * b * sizeof(float));
           doff[i] = reserve((size_t)corr_rpad(r) * b * sizeof(float));
         }
       }
@@ -2806,7 +2885,8 @@ int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batc
           g.corr.ut = P->ctile[0][umode];
           g.rp = colinv_corr_rp(r, umode);
           g.rpad = corr_rpad(r);
-          g.chunks = corr_nchunks(P->N, batch[i], r);
+          g.chunks = fwdc[i] ? colfwd_corr_chunks(P->g32) : corr_nchunks(P->N, batch[i], r);
+          if (fwdc[i]) g.ftile = P->ftile[0][umode];
           if (!P->g32.single()) g.Z = reinterpret_cast<cpx<float> *>(ws + zoff[i]);
           if (r > 0) {
             g.part = reinterpret_cast<float *>(ws + poff[i]);
@@ -2833,7 +2913,8 @@ int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batc
         G->span_host.insert(G->span_host.end(), idx.begin(), idx.end());
         G->span_host.insert(G->span_host.end(), start.begin(), start.end());
       };
-      std::vector<int> by_single_corr[14], by_single[14], mfma, by_l1[6], by_l1_fused[6], by_l1_plain[6], apply;
+      std::vector<int> by_single_corr[14], by_single[14], mfma, red, by_l1[6], by_l1_fc[6], by_l1_fused[6],
+          fused_one, by_l1_plain[6], apply;
       for (int i : G->grouped) {
         const Plan *P = plans[i];
         const int r = (int)P->proj.r;
@@ -2841,38 +2922,47 @@ int slepian_group_create(const slepian_plan_t *plans, int n, const int64_t *batc
           by_single_corr[P->g32.log2].push_back(i);
           continue;
         }
-        if (r > 0) mfma.push_back(i);
+        if (r > 0 && !fwdc[i]) mfma.push_back(i);
+        if (r > 0) red.push_back(i);
         if (P->g32.single()) {
           by_single[P->g32.log2].push_back(i);
           if (r > 0) apply.push_back(i);
           continue;
         }
-        by_l1[P->g32.log1].push_back(i);
+        (fwdc[i] ? by_l1_fc : by_l1)[P->g32.log1].push_back(i);
         // the update rides on the inverse column pass exactly when the
         // single-plan path fuses it there
         if (r > 0 && colinv_corr_ok(P->g32, P->N, batch[i], r) && P->ctile[0][umode]) {
-          by_l1_fused[P->g32.log1].push_back(i);
+          (colinv_corr_one(P->g32.log1, G->gp[i].rp) ? fused_one : by_l1_fused[P->g32.log1]).push_back(i);
         } else {
           by_l1_plain[P->g32.log1].push_back(i);
           if (r > 0) apply.push_back(i);
         }
       }
       std::vector<int> three[2];  // rows of 2^12, 2^13 points
-      for (int l1 = 1; l1 <= 5; ++l1)
+      for (int l1 = 1; l1 <= 5; ++l1) {
         for (int i : by_l1[l1]) three[plans[i]->g32.log2 - 12].push_back(i);
+        for (int i : by_l1_fc[l1]) three[plans[i]->g32.log2 - 12].push_back(i);
+      }
       for (int l2 = 9; l2 <= 13; ++l2) {
         add_span(G->single_corr[l2], by_single_corr[l2], group_blocks_single);
         add_span(G->single[l2], by_single[l2], group_blocks_single);
       }
       for (int v = 0; v < 2; ++v)
         add_span(G->partial[v], mfma, [v](const GroupPlan &g) { return group_blocks_partial(g, 2 - v); });
-      add_span(G->reduce, mfma, group_blocks_reduce);
-      for (int l1 = 1; l1 <= 5; ++l1) add_span(G->colfwd[l1], by_l1[l1], group_blocks_colfwd);
+      add_span(G->reduce, red, group_blocks_reduce);
+      for (int l1 = 1; l1 <= 5; ++l1) {
+        add_span(G->colfwd[l1], by_l1[l1], group_blocks_colfwd);
+        add_span(G->colfwd_corr[l1], by_l1_fc[l1], group_blocks_colfwd_corr);
+      }
       for (int k = 0; k < 2; ++k) add_span(G->row[k], three[k], group_blocks_row);
       for (int l1 = 1; l1 <= 5; ++l1) {
         for (int v = 0; v < 2; ++v)
           add_span(G->colinv_corr[l1][v], by_l1_fused[l1],
                    [v](const GroupPlan &g) { return group_blocks_colinv(g, 8 >> v); });
+        if (l1 == 5)
+          for (int v = 0; v < 2; ++v)
+            add_span(G->colinv_corr1[v], fused_one, [v](const GroupPlan &g) { return group_blocks_colinv(g, 8 >> v); });
         add_span(G->colinv[l1], by_l1_plain[l1], group_blocks_colfwd);
       }
       add_span(G->apply, apply, group_blocks_apply);

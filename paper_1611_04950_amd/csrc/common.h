@@ -94,6 +94,16 @@ struct Corr {
 // One plan's operands for the grouped launches, held in a device table that
 // every grouped kernel indexes: signals, FFT tables, correction operands and
 // the plan's share of the group workspace (FP32 path).
+// The fixed-order chunk sum dC[j b + s] = d[j] sum_c part[(c rpad + j) b + s]
+// (blocks workgroups of 32 outputs) as the row pass carries it; ey is set by
+// the launch.
+struct RowSum {
+  const float *part = nullptr;
+  const float *d = nullptr;
+  float *dC = nullptr;
+  int chunks = 0, rpad = 0, b = 0, r = 0, blocks = 0, ey = 0;
+};
+
 struct GroupPlan {
   const float *x = nullptr;
   float *y = nullptr;
@@ -104,6 +114,7 @@ struct GroupPlan {
   const cpx<float> *rt1 = nullptr, *rt2 = nullptr, *tcol = nullptr;
   float beta = 1.f, gl = 0.f;
   Corr<float> corr;          // U, ldu, r, d (and dC on the three-pass path)
+  const void *ftile = nullptr;  // U laid out for pass A with the coefficients (or null)
   int rp = 0, rpad = 0, chunks = 0;
   cpx<float> *Z = nullptr;   // three-pass intermediate, np * L
   float *part = nullptr;     // correction partials, chunks * rpad * b

@@ -17,6 +17,7 @@
 // accumulators (output layout: row 8 (v/4) + 4 (lane/32) + v % 4, column
 // lane % 32), adds U dC with FP32 matrix instructions over j, and stores it.
 #include "common.h"
+#include "corr_sum.h"
 #include "kernels.h"
 #include "trace.h"
 
@@ -309,42 +310,12 @@ __global__ __launch_bounds__(256) void k_corr_partial_tiles(const float *__restr
   }
 }
 
-// Fixed-order sum of the chunk partials: a workgroup of 512 lanes owns the
-// 32 outputs o = 32 bx + og (o = j b + s, one whole 128-byte line of every
-// chunk's partials); lane group cg (16 groups of 32 lanes) sums chunks cg,
-// cg + 16, ..., then a fixed-order sum of the 16 through LDS.
-constexpr int kReduceOuts = 32;
 constexpr int kReduceThreads = 512;
 __device__ __forceinline__ void corr_reduce_body(const float *__restrict__ part, int chunks, int rpad, int b, int r,
                                                  const float *__restrict__ d, float *__restrict__ out, int64_t ldo_j,
                                                  int64_t ldo_s, int bx) {
   __shared__ float red[16][kReduceOuts + 1];
-  const int og = threadIdx.x & 31, cg = threadIdx.x >> 5;
-  const int64_t o = (int64_t)bx * kReduceOuts + og;  // o = j * b + s
-  const bool valid = o < (int64_t)r * b;
-  const int j = valid ? (int)(o / b) : 0, s = valid ? (int)(o % b) : 0;
-  // chunks cg, cg + 16, ...: eight independent loads in flight per round,
-  // summed in a fixed order
-  const int64_t stride = (int64_t)rpad * b;
-  const float *pp = part + (int64_t)j * b + s;
-  float acc = 0.f;
-  for (int c0 = cg; c0 < chunks; c0 += 128) {
-    float v[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int c = c0 + 16 * e;
-      v[e] = c < chunks ? pp[(int64_t)c * stride] : 0.f;
-    }
-    acc += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
-  }
-  red[cg][og] = acc;
-  __syncthreads();
-  if (cg == 0 && valid) {
-    float t = 0.f;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) t += red[q][og];
-    out[(int64_t)j * ldo_j + (int64_t)s * ldo_s] = d ? d[j] * t : t;
-  }
+  corr_reduce_block<kReduceThreads>(part, chunks, rpad, b, r, d, out, ldo_j, ldo_s, bx, red);
 }
 
 __global__ __launch_bounds__(kReduceThreads) void k_corr_reduce2(const float *__restrict__ part, int chunks, int rpad, int b,

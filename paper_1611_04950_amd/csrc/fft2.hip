@@ -24,6 +24,7 @@
 #include <cstdlib>
 
 #include "common.h"
+#include "corr_sum.h"
 #include "fft_reg.h"
 #include "kernels.h"
 #include "trace.h"
@@ -195,6 +196,25 @@ __global__ __launch_bounds__(R2 *R3) void k_row2(cpx<R> *__restrict__ Z, int log
                                                  const cpx<R> *__restrict__ rt1, const cpx<R> *__restrict__ rt2,
                                                  const R *__restrict__ chat, R beta, R gl) {
   row_body<R, R1, R2, R3>(Z, logL, log2, rt1, rt2, chat, beta, gl, blockIdx.x, blockIdx.y);
+}
+
+// The row pass with the fixed-order chunk sum of the correction's
+// coefficients riding on its first ey rows of workgroups (pass A has written
+// the partials; pass C reads dC): the sum takes no launch of its own.
+template <int R1, int R2, int R3>
+__global__ __launch_bounds__(R2 *R3) void k_row2_sum(cpx<float> *__restrict__ Z, int logL, int log2,
+                                                     const cpx<float> *__restrict__ rt1,
+                                                     const cpx<float> *__restrict__ rt2,
+                                                     const float *__restrict__ chat, float beta, float gl,
+                                                     RowSum rs) {
+  if ((int)blockIdx.y < rs.ey) {
+    __shared__ float red[16][kReduceOuts + 1];
+    const int rb = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    if (rb < rs.blocks)  // uniform per workgroup
+      corr_reduce_block<R2 * R3>(rs.part, rs.chunks, rs.rpad, rs.b, rs.r, rs.d, rs.dC, (int64_t)rs.b, 1, rb, red);
+    return;
+  }
+  row_body<float, R1, R2, R3>(Z, logL, log2, rt1, rt2, chat, beta, gl, blockIdx.x, (int)blockIdx.y - rs.ey);
 }
 
 // Single-pass product of one signal pair (L = L2).  With CORR the kernel also
@@ -802,6 +822,276 @@ hipError_t build_corr_tile(const float *U, int64_t ldu, int N, int r, int log1, 
   return hipGetLastError();
 }
 
+// ---- pass A fused with the correction's coefficients ----
+//
+// Pass A also forms the chunk partials of C = U^T X (Corollary 2's U^T x)
+// from the signal values it loads, so x is read from memory once for both.
+// A workgroup owns 16 columns c0..c0+15 and 16 signal pairs (4 per
+// wavefront); lane (col, blk) = (lane % 16, lane / 16) loads rows n1 < R =
+// L1/2 (the rows that can hold n < N, as L >= 2N) of column c0 + col for its
+// wavefront's pair blk, keeps them for its column DFT and stores them in LDS
+// as xs[wave][slot 2 blk + c][q = col R + n1].  After one barrier the column
+// block's partial sum over its 16 R samples runs on the matrix cores for all
+// 32 signals of the workgroup, the T = Q / 32 steps dealt evenly to the four
+// wavefronts: step t takes samples q = 32 t + 8 g + e (e < 8, g = lane / 16);
+// the A operand (U^T, 16 j at a time) comes from the column block's tile
+// (k_fwd_tile, built with the plan), lane (m, g) holding U[n_q][16 jt + m];
+// the B operand (16 signals at a time, sb = 0, 1) comes from LDS, lane (s, g)
+// holding x[n_q] of signal 16 sb + s of the workgroup.
+//   MODE 0: FP32, v_mfma_f32_16x16x4_f32, instruction e takes sample q(e, g)
+//           from lane group g;
+//   MODE 1: BF16 hi and lo planes, three v_mfma_f32_16x16x32_bf16 per step
+//           (hi hi, hi lo, lo hi), FP32 accumulation.
+// The wavefronts' sums meet in LDS (reusing xs), are added in a fixed order,
+// and one partial per (column block, signal) reaches memory, at
+// part[(cb rpad + j) b + s]: the layout the fixed-order chunk sum reads, with
+// the column blocks as its chunks.
+constexpr int kFcWaves = 4;
+
+template <int L1, int MODE>
+__device__ __forceinline__ void colfwd_corr_body(const float *__restrict__ x, int64_t ldx, int N, int b, int np,
+                                                 int logL, int log2, const cpx<float> *__restrict__ tcol,
+                                                 cpx<float> *__restrict__ Z, const void *__restrict__ ft, int r,
+                                                 float *__restrict__ part, int rpad, int cb, int by) {
+  constexpr int R = L1 / 2;  // rows n1 that can hold n < N
+  constexpr int Q = 16 * R;  // samples of one signal in the column block
+  constexpr int T = Q / 32;  // matrix steps
+  constexpr int TW = T / kFcWaves;  // steps per wavefront
+  static_assert(R >= 8 && T % kFcWaves == 0, "column length");
+  // the wavefronts' sums (2 x 2 tiles of 4 x 64 values each) fit in xs
+  static_assert(kFcWaves * 8 * Q >= kFcWaves * 4 * 4 * 64, "reduction space");
+  __shared__ float xs[kFcWaves][8][Q];
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15, blk = lane >> 4;
+  const int pg = by * 4 * kFcWaves;      // first pair of the workgroup
+  const int pw = pg + wave * 4;          // first pair of the wavefront
+  const int n2 = cb * 16 + col;
+  const int p = pw + blk;
+  const bool pv = p < np;
+  const bool has1 = pv && 2 * p + 1 < b;
+  const float *x0 = x + (int64_t)(pv ? 2 * p : 0) * ldx;
+  const float *x1 = x + (int64_t)(has1 ? 2 * p + 1 : 0) * ldx;
+  cpx<float> a[L1];
+#pragma unroll
+  for (int n1 = 0; n1 < R; ++n1) {
+    const int n = n2 + (n1 << log2);
+    a[n1].x = (pv && n < N) ? x0[n] : 0.f;
+    a[n1].y = (has1 && n < N) ? x1[n] : 0.f;
+  }
+#pragma unroll
+  for (int n1 = R; n1 < L1; ++n1) a[n1] = cpx<float>{0.f, 0.f};
+  float *xw0 = &xs[wave][2 * blk][col * R];
+  float *xw1 = &xs[wave][2 * blk + 1][col * R];
+#pragma unroll
+  for (int n1 = 0; n1 < R; n1 += 4) {
+    *reinterpret_cast<float4 *>(xw0 + n1) = float4{a[n1].x, a[n1 + 1].x, a[n1 + 2].x, a[n1 + 3].x};
+    *reinterpret_cast<float4 *>(xw1 + n1) = float4{a[n1].y, a[n1 + 1].y, a[n1 + 2].y, a[n1 + 3].y};
+  }
+  reg::dft<L1, -1>(a);
+  if (pv) {
+    cpx<float> *Zp = Z + ((int64_t)p << logL) + n2;
+    Zp[0] = a[0];
+#pragma unroll
+    for (int k1 = 1; k1 < L1; ++k1) Zp[(int64_t)k1 << log2] = cmul(a[k1], tcol[(k1 << log2) + n2]);
+  }
+  const int s = lane & 15, g = lane >> 4;
+  const int njt = (r + 15) >> 4;  // 16-column tiles of U (1 or 2)
+  // the wavefront's A operands, in flight across the barrier: per step and
+  // U tile, two 16-byte pieces (FP32 samples e < 4 and e >= 4, or the BF16
+  // hi and lo planes)
+  float4 ua[TW][2][2];
+#pragma unroll
+  for (int tt = 0; tt < TW; ++tt)
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) {
+      const int64_t tile = ((int64_t)cb * T + wave * TW + tt) * njt + (jt < njt ? jt : 0);
+      const float4 *Tj = reinterpret_cast<const float4 *>(static_cast<const char *>(ft) + tile * 2048);
+      ua[tt][jt][0] = Tj[lane];
+      ua[tt][jt][1] = Tj[64 + lane];
+    }
+  __syncthreads();
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+    for (int sb = 0; sb < 2; ++sb) acc[jt][sb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int tt = 0; tt < TW; ++tt) {
+    const int t = wave * TW + tt;
+    float bv[2][8];
+#pragma unroll
+    for (int sb = 0; sb < 2; ++sb) {
+      // signal 16 sb + s of the workgroup: wavefront 2 sb + s / 8, slot s % 8
+      const float *xr = &xs[2 * sb + (s >> 3)][s & 7][32 * t + 8 * g];
+      const float4 v0 = *reinterpret_cast<const float4 *>(xr);
+      const float4 v1 = *reinterpret_cast<const float4 *>(xr + 4);
+      bv[sb][0] = v0.x; bv[sb][1] = v0.y; bv[sb][2] = v0.z; bv[sb][3] = v0.w;
+      bv[sb][4] = v1.x; bv[sb][5] = v1.y; bv[sb][6] = v1.z; bv[sb][7] = v1.w;
+    }
+    if constexpr (MODE == 0) {
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt) {
+        if (jt >= njt) break;
+        const float4 u0 = ua[tt][jt][0], u1 = ua[tt][jt][1];
+        const float uv[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+        for (int sb = 0; sb < 2; ++sb)
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            acc[jt][sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(uv[e], bv[sb][e], acc[jt][sb], 0, 0, 0);
+      }
+    } else {
+      bf16x8 bhi[2], blo[2];
+#pragma unroll
+      for (int sb = 0; sb < 2; ++sb)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const __bf16 h = (__bf16)bv[sb][e];
+          bhi[sb][e] = h;
+          blo[sb][e] = (__bf16)(bv[sb][e] - (float)h);
+        }
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt) {
+        if (jt >= njt) break;
+        const bf16x8 ahi = __builtin_bit_cast(bf16x8, ua[tt][jt][0]);
+        const bf16x8 alo = __builtin_bit_cast(bf16x8, ua[tt][jt][1]);
+#pragma unroll
+        for (int sb = 0; sb < 2; ++sb) {
+          acc[jt][sb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi[sb], acc[jt][sb], 0, 0, 0);
+          acc[jt][sb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo[sb], acc[jt][sb], 0, 0, 0);
+          acc[jt][sb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi[sb], acc[jt][sb], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // the four wavefronts' sums, red[wave][jt][sb][lane][v], added in wave order
+  __syncthreads();  // every wavefront is done reading xs
+  float *red = &xs[0][0][0];
+#pragma unroll
+  for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+    for (int sb = 0; sb < 2; ++sb)
+      *reinterpret_cast<f32x4 *>(red + (((wave * 2 + jt) * 2 + sb) * 64 + lane) * 4) = acc[jt][sb];
+  __syncthreads();
+  // thread (jt, sb, l) = (tid / 128, tid / 64 % 2, tid % 64): D[4 g + v][s]
+  // of tile (jt, sb), i.e. U column 16 jt + 4 (l / 16) + v, signal 16 sb + l % 16
+  const int tid = threadIdx.x;
+  const int l = tid & 63, sb = (tid >> 6) & 1, jt = tid >> 7;
+  f32x4 t4 = *reinterpret_cast<const f32x4 *>(red + (((0 * 2 + jt) * 2 + sb) * 64 + l) * 4);
+#pragma unroll
+  for (int w = 1; w < kFcWaves; ++w) t4 += *reinterpret_cast<const f32x4 *>(red + (((w * 2 + jt) * 2 + sb) * 64 + l) * 4);
+  const int sg = 2 * pg + 16 * sb + (l & 15);
+  if (jt < njt && sg < b) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = 16 * jt + 4 * (l >> 4) + v;
+      if (j < r) part[((int64_t)cb * rpad + j) * b + sg] = t4[v];
+    }
+  }
+}
+
+template <int L1, int MODE>
+__global__ __launch_bounds__(64 * kFcWaves, 3) void k_colfwd_corr(const float *__restrict__ x, int64_t ldx, int N, int b,
+                                                               int np, int logL, int log2,
+                                                               const cpx<float> *__restrict__ tcol,
+                                                               cpx<float> *__restrict__ Z,
+                                                               const void *__restrict__ ft, int r,
+                                                               float *__restrict__ part, int rpad) {
+  // each XCD takes a contiguous run of column blocks, so the two 64-byte
+  // halves of a 128-byte line of x are read within one L2
+  const int gx = gridDim.x;
+  const int cb = (gx & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (gx >> 3) + (int)(blockIdx.x >> 3);
+  colfwd_corr_body<L1, MODE>(x, ldx, N, b, np, logL, log2, tcol, Z, ft, r, part, rpad, cb, blockIdx.y);
+}
+
+// U laid out for colfwd_corr_body's A operand: per (column block, step, U
+// tile jt) 512 values, lane (m, g) holding U[n_q][16 jt + m] for
+// q = 32 t + 8 g + e, n_q = 16 cb + q / R + L2 (q % R); zero for n >= N and
+// j >= r.  Mode 0: FP32, e = 4 h + i at [h][lane][i] (one 1 KB block per
+// float4 load); mode 1: BF16 hi plane then lo plane, [lane][e] each.
+__global__ void k_fwd_tile(const float *__restrict__ U, int64_t ldu, int N, int r, int log2, int R, int njt, int mode,
+                           void *__restrict__ out, int64_t steps) {
+  const int64_t total = steps * 512;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t st = i >> 9;  // (cb T + t) njt + jt
+    const int w = (int)(i & 511);
+    int lane, e;
+    if (mode == 0) {
+      lane = (w & 255) >> 2;
+      e = 4 * (w >> 8) + (w & 3);
+    } else {
+      lane = w >> 3;
+      e = w & 7;
+    }
+    const int jt = (int)(st % njt);
+    const int64_t ct = st / njt;
+    const int T = 8 * R / 16;  // Q / 32 with Q = 16 R
+    const int t = (int)(ct % T);
+    const int64_t cb = ct / T;
+    const int m = lane & 15, g = lane >> 4;
+    const int q = 32 * t + 8 * g + e;
+    const int64_t n = cb * 16 + q / R + ((int64_t)(q % R) << log2);
+    const int j = 16 * jt + m;
+    const float u = (j < r && n < N) ? U[(int64_t)j * ldu + n] : 0.f;
+    if (mode == 0) {
+      static_cast<float *>(out)[i] = u;
+    } else {
+      const __bf16 h = (__bf16)u;
+      __bf16 *o = static_cast<__bf16 *>(out) + st * 1024;
+      o[w] = h;
+      o[512 + w] = (__bf16)(u - (float)h);
+    }
+  }
+}
+
+bool colfwd_corr_ok(const FftGeom &g, int r) {
+  return g.v2 && !g.single() && (g.log1 == 4 || g.log1 == 5) && r >= 1 && r <= 32;
+}
+
+int colfwd_corr_chunks(const FftGeom &g) { return 1 << (g.log2 - 4); }
+
+static int64_t fwd_tile_steps(const FftGeom &g, int r) {
+  const int R = (1 << g.log1) / 2;
+  return ((int64_t)1 << (g.log2 - 4)) * (16 * R / 32) * ((r + 15) / 16);
+}
+
+size_t fwd_tile_bytes(const FftGeom &g, int r) { return (size_t)fwd_tile_steps(g, r) * 2048; }
+
+hipError_t build_fwd_tile(const float *U, int64_t ldu, int N, int r, const FftGeom &g, int mode, void *out,
+                          hipStream_t st) {
+  if (!colfwd_corr_ok(g, r)) return hipErrorInvalidValue;
+  const int64_t steps = fwd_tile_steps(g, r);
+  const int64_t blocks = std::min<int64_t>((steps * 512 + 255) / 256, 65536);
+  SLP_LAUNCH("fwd_tile", k_fwd_tile, dim3((unsigned)blocks), dim3(256), 0, st, U, ldu, N, r, g.log2,
+             (1 << g.log1) / 2, (r + 15) / 16, mode, out, steps);
+  return hipGetLastError();
+}
+
+hipError_t colfwd_corr(const float *x, int64_t ldx, int64_t N, int64_t b, const FftGeom &g,
+                       const FftTables<float> &tb, cpx<float> *Z, const void *ft, int r, int mode, float *part,
+                       hipStream_t st) {
+  if (!colfwd_corr_ok(g, r) || (mode != 0 && mode != 1)) return hipErrorInvalidValue;
+  const int64_t np = (b + 1) / 2;
+  const int64_t pwg = 4 * kFcWaves;  // pairs per workgroup
+  if (np == 0) return hipSuccess;
+  if ((np + pwg - 1) / pwg > 65535) return hipErrorInvalidValue;
+  const dim3 grid(1u << (g.log2 - 4), (unsigned)((np + pwg - 1) / pwg));
+  const int rpad = corr_rpad(r);
+#define SLP_CFC(L1, M, NAME)                                                                                        \
+  SLP_LAUNCH(NAME, (k_colfwd_corr<L1, M>), grid, dim3(64 * kFcWaves), 0, st, x, ldx, (int)N, (int)b, (int)np,     \
+             g.logL, g.log2, tb.col, Z, ft, r, part, rpad)
+  if (g.log1 == 5) {
+    if (mode) SLP_CFC(32, 1, "col_fwd_corr_bf16x3");
+    else SLP_CFC(32, 0, "col_fwd_corr");
+  } else {
+    if (mode) SLP_CFC(16, 1, "col_fwd_corr_bf16x3");
+    else SLP_CFC(16, 0, "col_fwd_corr");
+  }
+#undef SLP_CFC
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Grouped launches: workgroup -> (plan, local workgroup) by binary search over
 // the span's start offsets, then the same bodies as the single-plan kernels.
@@ -855,15 +1145,29 @@ __global__ __launch_bounds__(R2 *R3) void k_row2_group(const GroupPlan *__restri
                               w >> P.log1);
 }
 
-template <int L1, int MODE, int CW, int PPL>
+// ONE: the single-step contraction (L1 = 32, one pair per lane, rank <= 32),
+// as the single-plan launch takes it for those plans, so that the grouped
+// call reproduces the plan's own calls bit for bit.
+template <int L1, int MODE, int CW, int PPL, bool ONE = false>
 __global__ __launch_bounds__(64 * CW, L1 >= 32 ? 3 : kCicWaves) void k_colinv_corr_group(const GroupPlan *__restrict__ gp,
                                                                const int *__restrict__ idx,
                                                                const int *__restrict__ start, int m) {
   const int q = group_slot(start, m, blockIdx.x);
   const GroupPlan &P = gp[idx[q]];
   const int w = (int)blockIdx.x - start[q], sh = P.log2 - 4;  // 2^sh column blocks of 16
-  colinv_corr_body<L1, MODE, CW, PPL>(P.Z, P.N, P.b, 0, P.np, P.logL, P.log2, P.tcol, P.y, P.ldy, P.corr.ut,
-                                      P.corr.r, P.rp, P.corr.dC, w & ((1 << sh) - 1), w >> sh);
+  colinv_corr_body<L1, MODE, CW, PPL, false, ONE>(P.Z, P.N, P.b, 0, P.np, P.logL, P.log2, P.tcol, P.y, P.ldy,
+                                                  P.corr.ut, P.corr.r, P.rp, P.corr.dC, w & ((1 << sh) - 1), w >> sh);
+}
+
+template <int L1, int MODE>
+__global__ __launch_bounds__(64 * kFcWaves, 3) void k_colfwd_corr_group(const GroupPlan *__restrict__ gp,
+                                                                     const int *__restrict__ idx,
+                                                                     const int *__restrict__ start, int m) {
+  const int q = group_slot(start, m, blockIdx.x);
+  const GroupPlan &P = gp[idx[q]];
+  const int w = (int)blockIdx.x - start[q], sh = P.log2 - 4;  // 2^sh column blocks of 16
+  colfwd_corr_body<L1, MODE>(P.x, P.ldx, P.N, P.b, P.np, P.logL, P.log2, P.tcol, P.Z, P.ftile, P.corr.r, P.part,
+                             P.rpad, w & ((1 << sh) - 1), w >> sh);
 }
 
 // Row twiddle tables: rt1[k1 T + t] = W_L2^{t k1}, rt2[k2 R3 + m'] = W_T^{m' k2}.
@@ -921,7 +1225,16 @@ hipError_t build_row_tables(const FftGeom &g, cpx<R> *rt1, cpx<R> *rt2, hipStrea
 
 template <typename R, int R1, int R2, int R3>
 static void launch_row(dim3 grid, hipStream_t st, cpx<R> *Z, const FftGeom &g, const FftTables<R> &tb, R beta,
-                       R gl) {
+                       R gl, const RowSum *rs = nullptr) {
+  if constexpr (sizeof(R) == 4) {
+    if (rs && rs->blocks > 0) {
+      RowSum a = *rs;
+      a.ey = (int)((a.blocks + grid.x - 1) / grid.x);
+      SLP_LAUNCH("row_conv", (k_row2_sum<R1, R2, R3>), dim3(grid.x, grid.y + (unsigned)a.ey), dim3(R2 * R3), 0, st,
+                 Z, g.logL, g.log2, tb.row1, tb.row2, tb.chat, beta, gl, a);
+      return;
+    }
+  }
   SLP_LAUNCH(sizeof(R) == 4 ? "row_conv" : "row_conv_f64", (k_row2<R, R1, R2, R3>), grid, dim3(R2 * R3), 0, st, Z,
              g.logL, g.log2, tb.row1, tb.row2, tb.chat, beta, gl);
 }
@@ -1046,6 +1359,8 @@ bool colinv_corr_ok(const FftGeom &g, int64_t ldy, int64_t b, int r) {
 
 bool colinv_corr_tiled(const FftGeom &g) { return colinv_corr_ok(g, 1, 1, 1); }
 
+bool colinv_corr_one(int log1, int rp) { return log1 == 5 && rp == 32; }
+
 template <int L1, int MODE, int CW, int PPL, bool EVEN = false>
 static void launch_cic(hipStream_t st, const cpx<float> *Z, int N, int b, int p0, int np, const FftGeom &g,
                        const FftTables<float> &tb, float *y, int64_t ldy, const Corr<float> &c, int rp) {
@@ -1054,7 +1369,7 @@ static void launch_cic(hipStream_t st, const cpx<float> *Z, int N, int b, int p0
   // L1 = 32, one pair per lane, rank <= 32: the single-step contraction
   // (same bits; with two pairs per lane its registers would spill)
   if constexpr (L1 >= 32 && !EVEN && PPL == 1) {
-    if (rp == 32) {
+    if (colinv_corr_one(g.log1, rp)) {
       SLP_LAUNCH(MODE ? "col_inv_corr_bf16x3" : "col_inv_corr", (k_colinv_corr<L1, MODE, CW, PPL, false, true>), grid,
                  dim3(64 * CW), 0, st, Z, N, b, p0, np, g.logL, g.log2, tb.col, y, ldy, c.ut, c.r, rp, c.dC);
       return;
@@ -1115,10 +1430,13 @@ static bool launch_colinv_corr(hipStream_t st, const cpx<float> *Z, int N, int b
   X(16, 16, 16)           \
   X(32, 16, 16)
 
+// fwd_done: pass A has already written Z (one slice; x is not read).  rs: the
+// chunk sum the row pass carries (or null).
 template <typename R>
-hipError_t conv_apply_v2(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, int64_t b, const FftGeom &g,
-                         const FftTables<R> &tb, R beta, R gamma, const Corr<R> &corr, cpx<R> *Z, int64_t slice_pairs,
-                         hipStream_t st) {
+static hipError_t conv_apply_impl(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, int64_t b,
+                                  const FftGeom &g, const FftTables<R> &tb, R beta, R gamma, const Corr<R> &corr,
+                                  cpx<R> *Z, int64_t slice_pairs, bool fwd_done, hipStream_t st,
+                                  const RowSum *rs = nullptr) {
   const int64_t pairs = (b + 1) / 2;
   if (pairs == 0) return hipSuccess;
   const R gl = gamma / (R)((int64_t)1 << g.logL);
@@ -1146,13 +1464,13 @@ hipError_t conv_apply_v2(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, 
     const int64_t np = pairs - p0 < slice_pairs ? pairs - p0 : slice_pairs;
     const dim3 gcol((1u << g.log2) / 256, (unsigned)np);
     const dim3 grow(1u << g.log1, (unsigned)np);
-    if (!dispatch_cols<R>(true, gcol, st, x, ldx, y, ldy, (int)N, (int)b, (int)p0, g, tb, Z))
+    if (!fwd_done && !dispatch_cols<R>(true, gcol, st, x, ldx, y, ldy, (int)N, (int)b, (int)p0, g, tb, Z))
       return hipErrorInvalidValue;
     bool ok = false;
 #define SLP_ROW(A, B, C)                                                                                     \
   if (!ok && g.R1 == A && g.R2 == B && g.R3 == C) {                                                           \
     if constexpr (sizeof(R) == 4 || A * B * C <= 4096) {                                                      \
-      launch_row<R, A, B, C>(grow, st, Z, g, tb, beta, gl);                                                   \
+      launch_row<R, A, B, C>(grow, st, Z, g, tb, beta, gl, rs);                                               \
       ok = true;                                                                                              \
     }                                                                                                         \
   }
@@ -1170,6 +1488,22 @@ hipError_t conv_apply_v2(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, 
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename R>
+hipError_t conv_apply_v2(const R *x, int64_t ldx, R *y, int64_t ldy, int64_t N, int64_t b, const FftGeom &g,
+                         const FftTables<R> &tb, R beta, R gamma, const Corr<R> &corr, cpx<R> *Z, int64_t slice_pairs,
+                         hipStream_t st) {
+  return conv_apply_impl<R>(x, ldx, y, ldy, N, b, g, tb, beta, gamma, corr, Z, slice_pairs, false, st);
+}
+
+hipError_t conv_rows_inv(float *y, int64_t ldy, int64_t N, int64_t b, const FftGeom &g, const FftTables<float> &tb,
+                         float beta, float gamma, const Corr<float> &corr, cpx<float> *Z, const RowSum *rs,
+                         hipStream_t st) {
+  if (g.single() || !g.v2) return hipErrorInvalidValue;
+  const int64_t pairs = (b + 1) / 2;
+  return conv_apply_impl<float>(nullptr, 0, y, ldy, N, b, g, tb, beta, gamma, corr, Z, pairs > 0 ? pairs : 1, true,
+                                st, rs);
 }
 
 // ---- length-N DFT bins for the fast factorization (Section 1.3) ----
@@ -1517,10 +1851,52 @@ hipError_t group_row(int log2, const GroupPlan *gp, const GroupSpan &sp, hipStre
   return hipGetLastError();
 }
 
+int64_t group_blocks_colfwd_corr(const GroupPlan &P) {
+  constexpr int pwg = 4 * kFcWaves;
+  return ((int64_t)(P.np + pwg - 1) / pwg) << (P.log2 - 4);
+}
+
+hipError_t group_colfwd_corr(int log1, int mode, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
+  if (sp.m == 0) return hipSuccess;
+  const dim3 grid((unsigned)sp.blocks), block(64 * kFcWaves);
+  switch (log1 * 2 + (mode ? 1 : 0)) {
+    case 8:
+      SLP_LAUNCH("col_fwd_corr_group_L1_16", (k_colfwd_corr_group<16, 0>), grid, block, 0, st, gp, sp.idx, sp.start,
+                 sp.m);
+      break;
+    case 9:
+      SLP_LAUNCH("col_fwd_corr_bf16x3_group_L1_16", (k_colfwd_corr_group<16, 1>), grid, block, 0, st, gp, sp.idx,
+                 sp.start, sp.m);
+      break;
+    case 10:
+      SLP_LAUNCH("col_fwd_corr_group_L1_32", (k_colfwd_corr_group<32, 0>), grid, block, 0, st, gp, sp.idx, sp.start,
+                 sp.m);
+      break;
+    case 11:
+      SLP_LAUNCH("col_fwd_corr_bf16x3_group_L1_32", (k_colfwd_corr_group<32, 1>), grid, block, 0, st, gp, sp.idx,
+                 sp.start, sp.m);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int CW>
-static hipError_t group_colinv_cw(int log1, int mode, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
+static hipError_t group_colinv_cw(int log1, int mode, bool one, const GroupPlan *gp, const GroupSpan &sp,
+                                  hipStream_t st) {
   const dim3 grid((unsigned)sp.blocks), block(64 * CW);
   constexpr int PPL = kGroupCicPPL;
+  static_assert(PPL == 1, "the single-step contraction takes one pair per lane");
+  if (one) {
+    if (log1 != 5) return hipErrorInvalidValue;
+    if (mode)
+      SLP_LAUNCH("col_inv_corr_bf16x3_group_L1_32", (k_colinv_corr_group<32, 1, CW, PPL, true>), grid, block, 0, st,
+                 gp, sp.idx, sp.start, sp.m);
+    else
+      SLP_LAUNCH("col_inv_corr_group_L1_32", (k_colinv_corr_group<32, 0, CW, PPL, true>), grid, block, 0, st, gp,
+                 sp.idx, sp.start, sp.m);
+    return hipGetLastError();
+  }
   switch (log1 * 2 + (mode ? 1 : 0)) {
 #define SLP_GCI(LG, L1)                                                                                            \
   case 2 * LG:                                                                                                    \
@@ -1538,10 +1914,11 @@ static hipError_t group_colinv_cw(int log1, int mode, const GroupPlan *gp, const
   return hipGetLastError();
 }
 
-hipError_t group_colinv_corr(int log1, int mode, int cw, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st) {
+hipError_t group_colinv_corr(int log1, int mode, int cw, bool one, const GroupPlan *gp, const GroupSpan &sp,
+                             hipStream_t st) {
   if (sp.m == 0) return hipSuccess;
-  if (cw == 8) return group_colinv_cw<8>(log1, mode, gp, sp, st);
-  if (cw == 4) return group_colinv_cw<4>(log1, mode, gp, sp, st);
+  if (cw == 8) return group_colinv_cw<8>(log1, mode, one, gp, sp, st);
+  if (cw == 4) return group_colinv_cw<4>(log1, mode, one, gp, sp, st);
   return hipErrorInvalidValue;
 }
 

@@ -30,6 +30,26 @@ size_t corr_tile_bytes(int log1, int log2, int r, int mode);
 hipError_t build_corr_tile(const float *U, int64_t ldu, int N, int r, int log1, int log2, int mode, void *out,
                            hipStream_t st);
 
+// Pass A fused with the correction's coefficients C = U^T x (L1 = 16 or 32,
+// rank 1..32): Z as pass A writes it, and one partial of C per column block
+// of 16 columns (colfwd_corr_chunks of them, layout of the chunk sum) into
+// part; ft from build_fwd_tile for the same geometry, rank and mode (0: FP32,
+// 1: BF16 hi/lo).  One slice: all (b + 1) / 2 pairs in Z.
+bool colfwd_corr_ok(const FftGeom &g, int r);
+int colfwd_corr_chunks(const FftGeom &g);
+size_t fwd_tile_bytes(const FftGeom &g, int r);
+hipError_t build_fwd_tile(const float *U, int64_t ldu, int N, int r, const FftGeom &g, int mode, void *out,
+                          hipStream_t st);
+hipError_t colfwd_corr(const float *x, int64_t ldx, int64_t N, int64_t b, const FftGeom &g,
+                       const FftTables<float> &tb, cpx<float> *Z, const void *ft, int r, int mode, float *part,
+                       hipStream_t st);
+// The rest of the product after colfwd_corr: rows (carrying the chunk sum of
+// the coefficients into rs->dC when rs is set), then the inverse column pass
+// (with the update when corr.dC is set).
+hipError_t conv_rows_inv(float *y, int64_t ldy, int64_t N, int64_t b, const FftGeom &g, const FftTables<float> &tb,
+                         float beta, float gamma, const Corr<float> &corr, cpx<float> *Z, const RowSum *rs,
+                         hipStream_t st);
+
 // ---- grouped launches over many plans (fft2.hip, corr_mfma.hip) ----
 // Workgroups each plan contributes to a grouped launch.
 int64_t group_blocks_single(const GroupPlan &P);
@@ -48,7 +68,13 @@ hipError_t group_corr_apply(bool vec, const GroupPlan *gp, const GroupSpan &sp, 
 // three-pass passes; all plans of the span share L1 = 2^log1 (columns) or L2 = 2^log2 (rows)
 hipError_t group_colfwd(int log1, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
 hipError_t group_row(int log2, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
-hipError_t group_colinv_corr(int log1, int mode, int cw, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
+// one: plans whose single-plan pass takes the single-step contraction (L1 =
+// 32, rank <= 32; colinv_corr_one)
+hipError_t group_colinv_corr(int log1, int mode, int cw, bool one, const GroupPlan *gp, const GroupSpan &sp,
+                             hipStream_t st);
+bool colinv_corr_one(int log1, int rp);
+int64_t group_blocks_colfwd_corr(const GroupPlan &P);
+hipError_t group_colfwd_corr(int log1, int mode, const GroupPlan *gp, const GroupSpan &sp, hipStream_t st);
 // C = U^T x partials and dC = d (.) C for every plan of the span
 hipError_t group_corr_partial(int mode, int nb, bool vec, const GroupPlan *gp, const GroupSpan &sp,
                               hipStream_t st);

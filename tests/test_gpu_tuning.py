@@ -53,7 +53,7 @@ def test_tuned_plan_and_cache(tmp_path, N, W, eps, prec):
 
 
 @pytest.mark.parametrize("N,b,prec", [(131072, 4, "mixed"), (131072, 4, "fp32"), (100003, 5, "mixed"),
-                                      (100003, 5, "fp32")])
+                                      (100003, 5, "fp32"), (33000, 7, "mixed"), (33000, 7, "fp32")])
 def test_every_variant_matches_oracle(tmp_path, N, b, prec):
     """Each variant the tuner can choose computes the same projection to the
     oracle's 1e-5: at L = 2^18 rows of 2^13 points (L1 = 32, the update fused
@@ -61,7 +61,9 @@ def test_every_variant_matches_oracle(tmp_path, N, b, prec):
     and rows of 2^12 (L1 = 64), each forced through a cache entry; both
     matrix modes of the fused update (rank <= 32 takes its single-step
     contraction), a length whose last rows fall partly beyond N, and an odd
-    batch whose last pair holds one signal."""
+    batch whose last pair holds one signal.  At N = 33000 (L = 2^17) the rows
+    of 2^13 and 2^12 points give L1 = 16 and 32, where pass A also forms the
+    coefficients U^T x (both matrix modes)."""
     W, eps = 1 / 16, 1e-6
     code = S.SLEPIAN_MIXED if prec == "mixed" else S.SLEPIAN_FP32
     x = synth.gaussian(N, b, 82, device="cuda")
