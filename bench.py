@@ -773,7 +773,7 @@ def _bench_factorization(args, dev, method, check):
 def bench_coeffs(args, dev):
     """Slepian coefficients c = S_K^T x (Section 1.3, the compression to K
     numbers) at the paper-scale size N = 65536, W = 1/8 (K = 16384), 256
-    signals: a plain GEMM on the matrix cores (hipBLASLt), FP32 for an FP32
+    signals: a hand-written matrix-core GEMM (coeffs.hip), FP32 for an FP32
     plan and three BF16 products of hi/lo halves for a mixed plan.  The first
     call computes all K Slepian vectors; the timed calls reuse them."""
     import torch

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libslepian.so")
 
-SOURCES = ["fft.hip", "fft2.hip", "eig.hip", "corr.hip", "corr_mfma.hip", "lsq.hip", "multiband.hip", "gemm.hip", "factor.hip", "mbcg.hip",
+SOURCES = ["fft.hip", "fft2.hip", "eig.hip", "corr.hip", "corr_mfma.hip", "lsq.hip", "multiband.hip", "coeffs.hip", "factor.hip", "mbcg.hip",
            "capi.cpp",
            "trace.cpp"]
 ARCH = os.environ.get("SLEPIAN_ARCH", "gfx950")
@@ -30,6 +30,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # private arrays (register-staged loads) stay in registers rather than
+    # being moved into LDS behind the kernel's back
+    "-mllvm", "-disable-promote-alloca-to-lds",
     f"-I{INCLUDE}", f"-I{CSRC}",
     "-Wno-unused-result",
 ]
@@ -60,7 +63,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-lhipblaslt", "-lrocsolver", "-lrocblas", "-o", tmp]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-lrocsolver", "-lrocblas", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

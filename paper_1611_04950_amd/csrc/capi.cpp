@@ -110,6 +110,7 @@ constexpr int kMaxLogL = 22;                          // N <= 2^21
 constexpr double kSpanMinTol = 1e-6;                  // FP32 vectors: the span projection's smallest tolerance
 constexpr int64_t kTuneBatch = 64;                    // signals the plan tuner times with by default
 constexpr size_t kCoeffsCap = (size_t)16 << 30;       // bytes of S_K kept for slepian_coeffs
+constexpr int64_t kCoeffsChunk = 65535;               // signals per coefficient GEMM launch
 
 int ilog2_ceil(int64_t v) {
   int l = 0;
@@ -128,7 +129,6 @@ struct OpSet {
 
 }  // namespace
 
-constexpr size_t kCoeffsGemmWs = (size_t)64 << 20;  // the library GEMM's workspace
 
 struct slepian_plan_s {
   int device = 0;
@@ -152,10 +152,12 @@ struct slepian_plan_s {
   double lam_Km1 = 0, lam_K = 0, eps_ach = 0;
   void *ws = nullptr;
   size_t ws_bytes = 0;
-  float *SK = nullptr;   // all K Slepian vectors (slepian_coeffs), leading dimension ldsk
+  // all K Slepian vectors for slepian_coeffs, as the coefficient GEMM's
+  // operand image: FP32 columns (leading dimension ldsk, N rounded up to 32,
+  // zero past N) for FP32 plans, the BF16 hi/lo image otherwise
+  float *SK = nullptr;
+  void *SKimg = nullptr;
   int64_t ldsk = 0;
-  __bf16 *SKh = nullptr, *SKl = nullptr;  // their BF16 hi/lo planes (plans of MIXED or BF16_RAW precision)
-  GemmCache coeffs_cache;                 // the library's algorithm for the last coefficient GEMM shape
   std::mutex coeffs_mu;
   // U's rows laid out for the fused inverse column pass, per column set and
   // matrix mode (FP32, BF16 hi/lo); null where that pass does not apply
@@ -187,8 +189,7 @@ struct slepian_plan_s {
     }
     dfree(ws);
     dfree(SK);
-    dfree(SKh);
-    dfree(SKl);
+    dfree(SKimg);
     for (auto &t : ctile)
       for (void *p : t) dfree(p);
     for (auto &t : ftile)
@@ -412,12 +413,11 @@ size_t op_workspace(const Plan *P, int op, int64_t b) {
       return std::max(cv.off, c2.off) + 256;
     }
     case SLEPIAN_OP_COEFFS: {
-      // staged x (FP32, or BF16 hi and lo), the product, the library's workspace
-      const size_t ldxb = (size_t)(P->N + 7) / 8 * 8, ldcb = (size_t)(P->K + 3) / 4 * 4;
-      if (P->precision == SLEPIAN_FP32) cv.take<float>(ldxb * b);
-      else cv.take<__bf16>(2 * ldxb * b);
-      cv.take<float>(ldcb * b);
-      cv.take<char>(kCoeffsGemmWs);
+      // x's operand image and the GEMM's per-split partial tiles, for up to
+      // kCoeffsChunk signals at a time
+      const int64_t bc = std::min<int64_t>(b, kCoeffsChunk);
+      cv.take<char>(coeffs_image_bytes(P->N, bc));
+      cv.take<float>(coeffs_part_floats(P->N, P->K, bc));
       break;
     }
     case SLEPIAN_OP_LSQ: {
@@ -2383,19 +2383,24 @@ int slepian_coeffs(slepian_plan_t P, const float *x, int64_t ldx, float *c, int6
     DeviceGuard dg(P->device);
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = P->N, K = P->K;
-    // the vectors, their BF16 halves and the library's algorithm are built on
-    // first use and kept by the plan; one call at a time builds or reads them
+    // the vectors' operand image is built on first use and kept by the plan;
+    // one call at a time builds or reads it
     std::lock_guard<std::mutex> lock(P->coeffs_mu);
-    if (!P->SK) {
-      // all K Slepian vectors, l = 0..K-1 (column l), FP64 then FP32
+    const int mode = P->precision == SLEPIAN_FP32 ? 0 : 1;
+    const int64_t Tn = coeffs_steps(N);
+    if (mode == 0 ? !P->SK : !P->SKimg) {
+      // all K Slepian vectors, l = 0..K-1 (column l), FP64 then FP32, zero
+      // past N; for the BF16 image the FP32 columns are a temporary
       Tridiag T;
       hipStream_t s2 = nullptr;
       HIPCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
       float *SK = nullptr;
+      void *img = nullptr;
       try {
         build_tridiag(P, T, s2);
-        const int64_t ldsk = (N + 3) / 4 * 4;
+        const int64_t ldsk = Tn * 32;
         SK = dalloc<float>((size_t)ldsk * K);
+        HIPCHK(hipMemsetAsync(SK, 0, (size_t)ldsk * K * sizeof(float), s2));
         DBuf<double> theta(K);
         HIPCHK(tridiag_bisect(T.a, T.e2, N, T.gl, T.gu, T.pivmin, N - K, K, theta.p, s2));
         const size_t per = inviter_scratch_bytes(N, 1) + N * sizeof(double);
@@ -2408,66 +2413,38 @@ int slepian_coeffs(slepian_plan_t P, const float *x, int64_t ldx, float *c, int6
           HIPCHK(tridiag_inviter(T.a, T.off, N, theta.p + j0, cc, V.p, scratch.p, 3, s2));
           HIPCHK(cast_f64_to_f32(V.p, N, SK + (K - j0 - cc) * ldsk, ldsk, N, cc, s2));
         }
+        if (mode == 1) {
+          img = dalloc<char>(coeffs_image_bytes(N, K));
+          HIPCHK(coeffs_image(1, SK, ldsk, N, K, img, s2));
+        }
         HIPCHK(hipStreamSynchronize(s2));
         (void)hipStreamDestroy(s2);
       } catch (...) {
         (void)hipStreamSynchronize(s2);
         (void)hipStreamDestroy(s2);
         dfree(SK);
+        dfree(img);
         throw;
       }
-      P->SK = SK;
-      P->ldsk = (N + 3) / 4 * 4;
-    }
-    const int mode = P->precision == SLEPIAN_FP32 ? 0 : 1;
-    if (mode == 1 && !P->SKh) {
-      // BF16 hi/lo planes of the Slepian vectors, built once
-      __bf16 *h = dalloc<__bf16>((size_t)P->ldsk * K), *l = nullptr;
-      try {
-        l = dalloc<__bf16>((size_t)P->ldsk * K);
-        for (int64_t j0 = 0; j0 < K; j0 += 32768) {
-          const int64_t cc = std::min<int64_t>(32768, K - j0);
-          HIPCHK(split_bf16(P->SK + j0 * P->ldsk, P->ldsk, N, cc, h + j0 * P->ldsk, l + j0 * P->ldsk, P->ldsk, st));
-        }
-        HIPCHK(hipStreamSynchronize(st));
-      } catch (...) {
-        dfree(h);
-        dfree(l);
-        throw;
+      P->ldsk = Tn * 32;
+      if (mode == 1) {
+        dfree(SK);
+        P->SKimg = img;
+      } else {
+        P->SK = SK;
       }
-      P->SKh = h;
-      P->SKl = l;
     }
     const size_t need = op_workspace(P, SLEPIAN_OP_COEFFS, batch);
     void *ws = get_ws(P, work, work_bytes, need);
     Carver cv(ws);
-    const int64_t ldxb = (N + 7) / 8 * 8, ldcb = (K + 3) / 4 * 4;
-    float *x32 = nullptr;
-    __bf16 *xh = nullptr, *xl = nullptr;
-    if (mode == 0) {
-      x32 = cv.take<float>((size_t)ldxb * batch);
-    } else {
-      xh = cv.take<__bf16>((size_t)ldxb * batch);
-      xl = xh + (size_t)ldxb * batch;
-      cv.off += (size_t)ldxb * batch * sizeof(__bf16);
-    }
-    float *cw = cv.take<float>((size_t)ldcb * batch);
-    void *gws = cv.take<char>(kCoeffsGemmWs);
-    // x staged into aligned planes, the product into an aligned buffer, then c
-    for (int64_t s0 = 0; s0 < batch; s0 += 65535) {
-      const int64_t bb = std::min<int64_t>(65535, batch - s0);
-      if (mode == 0) HIPCHK(copy_f32(x + s0 * ldx, ldx, x32 + s0 * ldxb, ldxb, N, bb, st));
-      else HIPCHK(split_bf16(x + s0 * ldx, ldx, N, bb, xh + s0 * ldxb, xl + s0 * ldxb, ldxb, st));
-    }
-    const int g = mode == 0 ? coeffs_gemm(P->device, 0, P->SK, nullptr, P->ldsk, x32, nullptr, ldxb, cw, ldcb, N, K,
-                                          batch, gws, kCoeffsGemmWs, P->coeffs_cache, st)
-                            : coeffs_gemm(P->device, 1, P->SKh, P->SKl, P->ldsk, xh, xl, ldxb, cw, ldcb, N, K, batch,
-                                          gws, kCoeffsGemmWs, P->coeffs_cache, st);
-    if (g == -2) return SLEPIAN_ENOTSUP;
-    if (g != 0) return SLEPIAN_EHIP;
-    for (int64_t s0 = 0; s0 < batch; s0 += 65535) {
-      const int64_t bb = std::min<int64_t>(65535, batch - s0);
-      HIPCHK(copy_f32(cw + s0 * ldcb, ldcb, c + s0 * ldc, ldc, K, bb, st));
+    const int64_t bc = std::min<int64_t>(batch, kCoeffsChunk);
+    void *ximg = cv.take<char>(coeffs_image_bytes(N, bc));
+    float *part = cv.take<float>(coeffs_part_floats(N, K, bc));
+    const void *simg = mode == 0 ? static_cast<const void *>(P->SK) : P->SKimg;
+    for (int64_t s0 = 0; s0 < batch; s0 += kCoeffsChunk) {
+      const int64_t bb = std::min<int64_t>(kCoeffsChunk, batch - s0);
+      HIPCHK(coeffs_image(mode, x + s0 * ldx, ldx, N, bb, ximg, st));
+      HIPCHK(coeffs_gemm(mode, simg, ximg, N, K, bb, part, c + s0 * ldc, ldc, st));
     }
     return SLEPIAN_OK;
   });

@@ -220,26 +220,25 @@ hipError_t corr_apply_mfma(float *y, int64_t ldy, int64_t N, int64_t b, const fl
                            const float *dC, hipStream_t st);
 
 // ---- Slepian coefficients as a library GEMM (gemm.hip) ----
-// hi/lo BF16 halves of an N x b FP32 matrix into planes with leading dimension ld
-hipError_t split_bf16(const float *x, int64_t ldx, int64_t N, int64_t b, __bf16 *hi, __bf16 *lo, int64_t ld,
-                      hipStream_t st);
 // dst (rows x cols, ldd) = src (lds), FP32
 hipError_t copy_f32(const float *src, int64_t lds, float *dst, int64_t ldd, int64_t rows, int64_t cols,
                     hipStream_t st);
-// The algorithm chosen for one GEMM shape (kept per plan and mode).
-struct GemmCache {
-  bool valid = false;
-  int mode = -1;
-  int64_t N = 0, K = 0, b = 0, lds = 0, ldx = 0, ldc = 0;
-  size_t ws_max = 0, ws = 0;
-  alignas(16) unsigned char algo[128];  // hipblasLtMatmulAlgo_t, opaque here
-};
-// c (K x b, ldc) = S^T X with S: N x K (lds) and X: N x b (ldx); mode 0 FP32 operands
-// (S, X), mode 1 BF16 hi (S, X) and lo (Slo, Xlo) planes, three products.  Returns 0,
-// -1 (library error) or -2 (no algorithm for the shape).
-int coeffs_gemm(int device, int mode, const void *S, const void *Slo, int64_t lds, const void *X, const void *Xlo,
-                int64_t ldx, float *c, int64_t ldc, int64_t N, int64_t K, int64_t b, void *ws, size_t ws_bytes,
-                GemmCache &cache, hipStream_t st);
+
+// ---- Slepian coefficients c = S_K^T x on the matrix cores (coeffs.hip) ----
+// Operand images: columns in 32-sample steps of one 128-byte line each (mode
+// 0: FP32 columns with leading dimension 32 coeffs_steps(N); mode 1: BF16
+// hi/lo pieces), zero past N.
+int64_t coeffs_steps(int64_t N);
+size_t coeffs_image_bytes(int64_t N, int64_t ncols);
+hipError_t coeffs_image(int mode, const float *src, int64_t lds, int64_t N, int64_t ncols, void *dst,
+                        hipStream_t st);
+// Reduction splits of one GEMM and the floats of its partial tiles.
+int coeffs_splits(int64_t N, int64_t K, int64_t b);
+size_t coeffs_part_floats(int64_t N, int64_t K, int64_t b);
+// c (K x b, ldc) = S^T X from the images of S (K columns) and X (b <= 65535
+// columns); part holds coeffs_part_floats(N, K, b) floats.
+hipError_t coeffs_gemm(int mode, const void *Simg, const void *Ximg, int64_t N, int64_t K, int64_t b, float *part,
+                       float *c, int64_t ldc, hipStream_t st);
 
 // ---- Conjugate gradients on a multiband band-sum operator (mbcg.hip) ----
 constexpr int kCgChunk = 8192;  // samples per chunk of the fixed-order FP64 dot products

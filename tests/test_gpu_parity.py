@@ -224,6 +224,25 @@ def test_coeffs_match_oracle(plans, N, W, prec):
     assert torch.isnan(cb[:, P.K:]).all()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_coeffs_tiles_and_splits(prec):
+    """The coefficient GEMM across its tiling: K = 820 Slepian indices (seven
+    128-row tiles, the last one partial), 300 signals (a full and a partial
+    256-signal tile), N = 2050 (65 steps of 32 samples, the last one partial)
+    cut into two reduction splits of 33 and 32 steps; against the oracle's
+    S_K^T x, and deterministic."""
+    N, W, b = 2050, 0.2, 300
+    pr = S.SLEPIAN_FP32 if prec == "fp32" else S.SLEPIAN_MIXED
+    P = S.slepian_plan(N, W, 1e-6, precision=pr)
+    x = synth.gaussian(N, b, 13, device="cuda")
+    c = S.slepian_coeffs(P, x)
+    torch.cuda.synchronize()
+    ref = o.coeffs_exact(N, W, x.double().cpu().numpy().T).T
+    e = rel_err(c.cpu().numpy(), ref)
+    assert e.max() <= 1e-5, e.max()
+    assert torch.equal(S.slepian_coeffs(P, x), c)
+
+
 def test_save_load_roundtrip(plans, tmp_path):
     N, W, eps = 3000, 0.15, 1e-6
     P = plans(N, W, eps)
