@@ -47,9 +47,9 @@ constexpr int kBM = 128;      // Slepian indices per workgroup
 constexpr int kBN = 256;      // signals per workgroup
 constexpr int kCfThreads = 256;
 static_assert(kBM * 8 / kCfThreads == 4 && kBN * 8 / kCfThreads == 8, "pieces per lane (Stage)");
-constexpr int kSlabA = kBM * 16;          // bytes of one piece slab of the S tile
-constexpr int kSlabB = kBN * 16;
-constexpr int kStage = 8 * (kSlabA + kSlabB);  // 48 KB per buffer
+constexpr int kLine = 128;                    // bytes per column and step
+constexpr int kStageA = kBM * kLine;          // the S lines of a step (16 KB)
+constexpr int kStage = (kBM + kBN) * kLine;   // one step's lines (48 KB)
 
 struct Img {
   const char *p;     // base of column 0
@@ -94,15 +94,24 @@ __device__ __forceinline__ void issue(const Img &A, const Img &B, int64_t k0, in
   g.b7 = ld_piece(bb, sb, 224 + r, cb, t, p);
 }
 
-__device__ __forceinline__ void put(char *slab, int c, int p, float4 v) {
-  *reinterpret_cast<float4 *>(slab + ((c ^ p) << 4)) = v;
+// Piece p of line `row` of a stage region sits at slot p ^ ((row / 2) % 8):
+// the 16 rows one read of 16 lanes touches cover all 16 bank groups of two
+// 128-byte rows, and the eight pieces of one line still fill the line.
+__device__ __forceinline__ int slot_of(int row, int p) { return p ^ ((row >> 1) & 7); }
+
+__device__ __forceinline__ const char *piece_at(const char *region, int row, int p) {
+  return region + row * kLine + (slot_of(row, p) << 4);
+}
+
+__device__ __forceinline__ void put(char *region, int row, int p, float4 v) {
+  *reinterpret_cast<float4 *>(region + row * kLine + (slot_of(row, p) << 4)) = v;
 }
 
 __device__ __forceinline__ void commit(const Stage &g, char *buf) {
   const int tid = threadIdx.x;
   const int p = tid & 7, r = tid >> 3;
-  char *sa = buf + p * kSlabA;
-  char *sb = buf + 8 * kSlabA + p * kSlabB;
+  char *sa = buf;
+  char *sb = buf + kStageA;
   put(sa, r, p, g.a0);
   put(sa, 32 + r, p, g.a1);
   put(sa, 64 + r, p, g.a2);
@@ -117,12 +126,46 @@ __device__ __forceinline__ void commit(const Stage &g, char *buf) {
   put(sb, 224 + r, p, g.b7);
 }
 
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Direct-to-LDS loads of one step: each instruction moves 8 whole lines (1 KB;
+// lane L writes line c0 + L / 8, slot L % 8, so it fetches the piece that
+// slot holds).  Wavefront w issues line groups w, w + 4, ... of S's 16 and
+// x's 32.
+__device__ __forceinline__ void dma_step(const Img &A, const Img &B, int64_t k0, int64_t s0, int t, char *stage) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int rl = lane >> 3;
+  const char *ba = A.p + k0 * A.stride, *bb = B.p + s0 * B.stride;
+  const uint32_t sa = (uint32_t)A.stride, sb = (uint32_t)B.stride;
+  const int ca = (int)(A.ncols - 1 - k0), cb = (int)(B.ncols - 1 - s0);
+  const uint32_t t128 = (uint32_t)t * 128u;
+#pragma unroll
+  for (int j = 0; j < kBM / 32; ++j) {
+    const int grp = wave + 4 * j;
+    const int c = 8 * grp + rl;
+    const int p = slot_of(c, lane & 7);  // the slot map is its own inverse
+    const uint32_t cc = (uint32_t)(c < ca ? c : ca);
+    __builtin_amdgcn_global_load_lds(ba + (cc * sa + t128 + (uint32_t)p * 16u), (lds_void_t *)(stage + grp * 1024), 16,
+                                     0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < kBN / 32; ++j) {
+    const int grp = wave + 4 * j;
+    const int c = 8 * grp + rl;
+    const int p = slot_of(c, lane & 7);
+    const uint32_t cc = (uint32_t)(c < cb ? c : cb);
+    __builtin_amdgcn_global_load_lds(bb + (cc * sb + t128 + (uint32_t)p * 16u),
+                                     (lds_void_t *)(stage + kStageA + grp * 1024), 16, 0, 0);
+  }
+}
+
 template <int MODE>
 __device__ __forceinline__ void compute(const char *buf, f32x16 (&acc)[2][4], int wk, int ws) {
   const int lane = threadIdx.x & 63;
   const int i = lane & 31, kb = lane >> 5;
   const char *sa = buf;
-  const char *sb = buf + 8 * kSlabA;
+  const char *sb = buf + kStageA;
 #pragma unroll
   for (int sub = 0; sub < 2; ++sub) {
     if constexpr (MODE == 1) {
@@ -131,15 +174,15 @@ __device__ __forceinline__ void compute(const char *buf, f32x16 (&acc)[2][4], in
       for (int mb = 0; mb < 2; ++mb) {
         const int row = 64 * wk + 32 * mb + i;
         const int ph = 4 * sub + kb, pl = 4 * sub + 2 + kb;
-        ah[mb] = *reinterpret_cast<const bf16x8 *>(sa + ph * kSlabA + ((row ^ ph) << 4));
-        al[mb] = *reinterpret_cast<const bf16x8 *>(sa + pl * kSlabA + ((row ^ pl) << 4));
+        ah[mb] = *reinterpret_cast<const bf16x8 *>(piece_at(sa, row, ph));
+        al[mb] = *reinterpret_cast<const bf16x8 *>(piece_at(sa, row, pl));
       }
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
         const int row = 128 * ws + 32 * nb + i;
         const int ph = 4 * sub + kb, pl = 4 * sub + 2 + kb;
-        const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(sb + ph * kSlabB + ((row ^ ph) << 4));
-        const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(sb + pl * kSlabB + ((row ^ pl) << 4));
+        const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(piece_at(sb, row, ph));
+        const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(piece_at(sb, row, pl));
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mb], bh, acc[mb][nb], 0, 0, 0);
@@ -155,7 +198,7 @@ __device__ __forceinline__ void compute(const char *buf, f32x16 (&acc)[2][4], in
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int p = 4 * sub + 2 * kb + h;
-          const float4 v = *reinterpret_cast<const float4 *>(sa + p * kSlabA + ((row ^ p) << 4));
+          const float4 v = *reinterpret_cast<const float4 *>(piece_at(sa, row, p));
           a[mb][4 * h + 0] = v.x;
           a[mb][4 * h + 1] = v.y;
           a[mb][4 * h + 2] = v.z;
@@ -169,7 +212,7 @@ __device__ __forceinline__ void compute(const char *buf, f32x16 (&acc)[2][4], in
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int p = 4 * sub + 2 * kb + h;
-          const float4 v = *reinterpret_cast<const float4 *>(sb + p * kSlabB + ((row ^ p) << 4));
+          const float4 v = *reinterpret_cast<const float4 *>(piece_at(sb, row, p));
           bv[4 * h + 0] = v.x;
           bv[4 * h + 1] = v.y;
           bv[4 * h + 2] = v.z;
@@ -188,11 +231,11 @@ __device__ __forceinline__ void compute(const char *buf, f32x16 (&acc)[2][4], in
 // Grid: one workgroup per (tile of 128 k, tile of 256 s, reduction split),
 // tiles ordered with k fastest and dealt to the eight XCDs in contiguous
 // runs, so that the workgroups sharing x's lines share an L2.
-template <int MODE>
+template <int MODE, bool DMA>
 __global__ __launch_bounds__(kCfThreads, 1) void k_coeffs(Img A, Img B, int tiles_k, int tiles_s, int splits,
                                                          int steps, int steps_per_split, float *__restrict__ out,
                                                          int64_t ldo, int64_t split_stride, int64_t K, int64_t b) {
-  __shared__ __align__(16) char lds[2 * kStage];
+  __shared__ __align__(16) char lds[(DMA ? 3 : 2) * kStage];
   const int G = tiles_k * tiles_s * splits;
   const int L = blockIdx.x;
   const int tile = (G & 7) ? L : (L & 7) * (G >> 3) + (L >> 3);
@@ -212,27 +255,56 @@ __global__ __launch_bounds__(kCfThreads, 1) void k_coeffs(Img A, Img B, int tile
     for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[mb][nb][v] = 0.f;
-  // Step i computes from LDS buffer i % 2 while the loads of step i + 1 are
-  // in flight into registers; they are stored into the other buffer after
-  // the step's matrix work, and one barrier per step orders the two.  Loads
-  // are issued unconditionally (the last step reloads itself, unused): loads
-  // under a branch would be waited for at the branch's end.
-  Stage g;
-  if (nt > 0) {
-    issue(A, B, k0, s0, t0, g);
-    commit(g, lds);
-  }
-  __syncthreads();
-  for (int i = 0; i < nt; ++i) {
-    char *cur = lds + (i & 1) * kStage;
-    char *nxt = lds + ((i + 1) & 1) * kStage;
-    issue(A, B, k0, s0, i + 1 < nt ? t0 + i + 1 : t0 + i, g);
-    // keep the loads ahead of the matrix work (the scheduler would otherwise
-    // sink them below it to share registers, exposing their latency)
-    __builtin_amdgcn_sched_barrier(0);
-    compute<MODE>(cur, acc, wk, ws);
-    if (i + 1 < nt) commit(g, nxt);
+  if constexpr (DMA) {
+    // Three LDS stages, two steps' direct-to-LDS loads in flight: step i + 2
+    // is issued into the stage step i - 1 used, right after the barrier that
+    // ends step i - 1's matrix work, and this wavefront's share is waited
+    // for two steps later; the barrier then makes every share visible.  Past
+    // the range the loads repeat the last step (unused), so every step issues
+    // the same number of loads and the wait count stays fixed.  The barrier
+    // is the bare instruction (a full __syncthreads would also wait for the
+    // loads still in flight).
+    const int tl = t0 + nt - 1;  // last step of the range (no loads when it is empty)
+    static_assert((kBM + kBN) / 32 == 12, "loads per wavefront and step (the wait count)");
+    if (nt > 0) {
+      dma_step(A, B, k0, s0, t0, lds);
+      dma_step(A, B, k0, s0, t0 + 1 <= tl ? t0 + 1 : tl, lds + kStage);
+    }
+    for (int i = 0; i < nt; ++i) {
+      __builtin_amdgcn_s_waitcnt(12 | (7 << 4) | (15 << 8));  // vmcnt(12): step i's share has landed
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+      dma_step(A, B, k0, s0, t0 + i + 2 <= tl ? t0 + i + 2 : tl, lds + ((i + 2) % 3) * kStage);
+      __builtin_amdgcn_sched_barrier(0);
+      compute<MODE>(lds + (i % 3) * kStage, acc, wk, ws);
+    }
+    // no load may still be writing LDS when the workgroup ends
+    __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8));
+  } else {
+    // Step i computes from LDS buffer i % 2 while the loads of step i + 1 are
+    // in flight into registers; they are stored into the other buffer after
+    // the step's matrix work, and one barrier per step orders the two.  Loads
+    // are issued unconditionally (the last step reloads itself, unused): loads
+    // under a branch would be waited for at the branch's end.
+    Stage g;
+    if (nt > 0) {
+      issue(A, B, k0, s0, t0, g);
+      commit(g, lds);
+    }
     __syncthreads();
+    for (int i = 0; i < nt; ++i) {
+      char *cur = lds + (i & 1) * kStage;
+      char *nxt = lds + ((i + 1) & 1) * kStage;
+      issue(A, B, k0, s0, i + 1 < nt ? t0 + i + 1 : t0 + i, g);
+      // keep the loads ahead of the matrix work (the scheduler would otherwise
+      // sink them below it to share registers, exposing their latency)
+      __builtin_amdgcn_sched_barrier(0);
+      compute<MODE>(cur, acc, wk, ws);
+      if (i + 1 < nt) commit(g, nxt);
+      __syncthreads();
+    }
   }
   // D[8 (v / 4) + 4 kb + v % 4][i] of block (mb, nb): k = k0 + 64 wk + 32 mb
   // + 8 (v / 4) + 4 kb + v % 4, s = s0 + 128 ws + 32 nb + i
@@ -350,10 +422,10 @@ hipError_t coeffs_gemm(int mode, const void *Simg, const void *Ximg, int64_t N, 
   Img A{static_cast<const char *>(Simg), steps * 128, K};
   Img B{static_cast<const char *>(Ximg), steps * 128, b};
   if (mode == 1)
-    SLP_LAUNCH("coeffs_gemm_bf16x3", k_coeffs<1>, dim3((unsigned)G), dim3(kCfThreads), 0, st, A, B, tiles_k, tiles_s,
+    SLP_LAUNCH("coeffs_gemm_bf16x3", (k_coeffs<1, true>), dim3((unsigned)G), dim3(kCfThreads), 0, st, A, B, tiles_k, tiles_s,
                splits, (int)steps, per, part, ldp, zstride, K, b);
   else
-    SLP_LAUNCH("coeffs_gemm", k_coeffs<0>, dim3((unsigned)G), dim3(kCfThreads), 0, st, A, B, tiles_k, tiles_s, splits,
+    SLP_LAUNCH("coeffs_gemm", (k_coeffs<0, false>), dim3((unsigned)G), dim3(kCfThreads), 0, st, A, B, tiles_k, tiles_s, splits,
                (int)steps, per, part, ldp, zstride, K, b);
   SLP_LAUNCH("coeffs_sum", k_coeffs_sum, dim3((unsigned)((K + 255) / 256), (unsigned)b), dim3(256), 0, st, part, ldp,
              zstride, splits, c, ldc, K);
