@@ -310,9 +310,11 @@ int slepian_project_bands_span(slepian_bands_t bands, const float *x, int64_t ld
  *    symmetric Toeplitz matrix B - F F^* with |mu| > eps (the least rank for
  *    that error).  Setup (synchronous, FP64): subspace iteration on a random
  *    +-1 block with the FFT-applied B - F F^*, Householder QR and a
- *    Rayleigh-Ritz step (rocSOLVER), widening the block until it resolves
- *    every |mu| > eps with a residual of at most eps / 4 (checked with one
- *    more product); ENOCONV if it cannot.
+ *    Rayleigh-Ritz step (rocSOLVER), widening the block until the kept
+ *    pairs have residuals of at most eps / 4 (checked with one more product)
+ *    and six block power steps on the operator deflated by them (a fresh
+ *    random block of 8 columns) find no eigenvalue above eps outside their
+ *    span; ENOCONV if the block reaches its cap (1024) first.
  *
  * Requires N a power of two (the plan's FFT length is then exactly 2N) with
  * 256 <= N <= 2^20, else ENOTSUP.  The plan must outlive the factorization. */
@@ -331,6 +333,7 @@ typedef struct {
   double ritz_residual; /* EIG: largest ||(B - F F^*) v - mu v|| of the kept pairs (<= eps / 4) */
   int32_t method;     /* enum slepian_factor_method */
   int32_t r_h, r_a, r_b; /* THEOREM1: rH, rA, rB of the construction; EIG: 0 */
+  double deflated_norm; /* EIG: estimated largest |mu| outside the kept pairs' span (<= eps); THEOREM1: 0 */
 } slepian_factor_info_t;
 /* slepian_factor_create_ex with SLEPIAN_FACTOR_THEOREM1. */
 int slepian_factor_create(slepian_plan_t plan, slepian_factor_t *out);

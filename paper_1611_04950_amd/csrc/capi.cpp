@@ -1687,6 +1687,7 @@ struct slepian_factor_s {
   int kf = 0;                 // 2NW', the odd integer nearest to 2NW
   int64_t r1 = 0, r = 0;      // columns of the Theorem 1 factor and of the transition set
   int64_t p = 0;              // subspace size the setup converged with
+  double defl = 0;            // estimated norm of B - F F^* deflated by the kept pairs
   double mu_drop = 0;         // largest |Ritz value| left out (<= eps)
   double ritz_res = 0;        // largest ||T v_j - mu_j v_j|| of the kept pairs
   int method = SLEPIAN_FACTOR_THEOREM1;
@@ -1771,11 +1772,53 @@ FactorWs carve_factor(const slepian_factor_s *F, int64_t b, void *base) {
   return w;
 }
 
+// Estimate of the largest |eigenvalue| of (I - V V^T) T (I - V V^T), T the
+// FP64 product with spectrum tbt and V (N x r1, orthonormal columns) the kept
+// eigenvectors: kDeflSteps block power steps on 8 +-1 columns, the block
+// re-orthonormalised (Householder QR) before each product and V's component
+// removed before and after it; the largest column norm of the last deflated
+// product.
+double deflated_norm(const Plan *P, const FftTables<double> &tbt, const B64Ws &bw, const double *V, int64_t r1,
+                     RocHandle &rh, hipStream_t st) {
+  constexpr int kDeflSteps = 6;
+  constexpr int64_t q = 8;
+  const int64_t N = P->N;
+  DBuf<double> G((size_t)N * q), Y((size_t)N * q), tau(q), Cq((size_t)std::max<int64_t>(r1, 1) * q), nrm(q),
+      part((size_t)q * kNormParts);
+  const double one = 1.0, zero = 0.0, mone = -1.0;
+  auto deflate = [&](double *X) {
+    if (r1 == 0) return;
+    ROCCHK(rocblas_dgemm(rh.h, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)r1, (rocblas_int)q,
+                         (rocblas_int)N, &one, V, (rocblas_int)N, X, (rocblas_int)N, &zero, Cq.p, (rocblas_int)r1));
+    ROCCHK(rocblas_dgemm(rh.h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)N, (rocblas_int)q,
+                         (rocblas_int)r1, &mone, V, (rocblas_int)N, Cq.p, (rocblas_int)r1, &one, X, (rocblas_int)N));
+  };
+  HIPCHK(rademacher(G.p, N, N, q, 0xdef1a7edull, st));
+  for (int it = 0; it < kDeflSteps; ++it) {
+    deflate(G.p);
+    ROCCHK(rocsolver_dgeqrf(rh.h, (rocblas_int)N, (rocblas_int)q, G.p, (rocblas_int)N, tau.p));
+    ROCCHK(rocsolver_dorgqr(rh.h, (rocblas_int)N, (rocblas_int)q, (rocblas_int)q, G.p, (rocblas_int)N, tau.p));
+    deflate(G.p);
+    HIPCHK(conv_apply<double>(G.p, N, Y.p, N, N, q, P->g64, tbt, 1.0, 0.0, Corr<double>(), bw.Z, bw.slice, st));
+    deflate(Y.p);
+    std::swap(G.p, Y.p);
+  }
+  HIPCHK(col_norms(G.p, N, N, q, nrm.p, part.p, st));
+  std::vector<double> h(q);
+  HIPCHK(hipMemcpyAsync(h.data(), nrm.p, (size_t)q * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double m = 0;
+  for (double v : h) m = std::max(m, v);
+  return m;
+}
+
 // V, mu with B - F F^* ~= V diag(mu) V^T over the eigenpairs with |mu| > eps:
 // subspace iteration on a +-1 start block of p columns with the FP64 product
 // (Toeplitz kernel t of B - F F^*), Householder QR after every product, then
 // a Rayleigh-Ritz step.  p doubles until at least 24 Ritz values fall at or
-// below eps and every kept pair's residual ||T v - mu v|| is at most eps / 4.
+// below eps, every kept pair's residual ||T v - mu v|| is at most eps / 4,
+// and the operator deflated by the kept vectors has norm at most eps
+// (deflated_norm).
 void factor_setup(slepian_factor_s *F, hipStream_t st) {
   Plan *P = F->P;
   const int64_t N = P->N, L = P->L;
@@ -1868,10 +1911,22 @@ void factor_setup(slepian_factor_s *F, hipStream_t st) {
         continue;
       }
     }
+    // A posteriori: no eigenvalue with |mu| > eps may lie outside span(V).
+    // Block power steps on the deflated operator (I - V V^T) T (I - V V^T)
+    // from a fresh +-1 block (QR between steps); its largest column norm
+    // after the last product estimates the largest |mu| left out.  Above eps
+    // the block was too narrow: widen it, or ENOCONV at the cap.
+    const double defl = deflated_norm(P, tbt, bw, V ? V->p : nullptr, r1, rh, st);
+    if (!(defl <= P->eps)) {
+      if (p >= std::min<int64_t>(1024, N - 1)) throw Fail{SLEPIAN_ENOCONV};
+      p = std::min<int64_t>(2 * p, std::min<int64_t>(1024, N - 1));
+      continue;
+    }
     F->r1 = r1;
     F->p = p;
     F->mu_drop = drop;
     F->ritz_res = res;
+    F->defl = defl;
     F->mu = mu;
     const int64_t rt = r1 + F->r;
     F->ldu = (N + 3) / 4 * 4;
@@ -2105,6 +2160,7 @@ int slepian_factor_info(slepian_factor_t F, slepian_factor_info_t *info) {
   info->r = F->r;
   info->kprime = F->kf + F->r1 + F->r;
   info->subspace = F->p;
+  info->deflated_norm = F->defl;
   info->mu_dropped = F->mu_drop;
   info->ritz_residual = F->ritz_res;
   info->method = F->method;

@@ -60,7 +60,8 @@ class PlanOpts(C.Structure):
 class FactorInfo(C.Structure):
     _fields_ = [("kf", C.c_int64), ("r1", C.c_int64), ("r", C.c_int64), ("kprime", C.c_int64),
                 ("subspace", C.c_int64), ("mu_dropped", C.c_double), ("ritz_residual", C.c_double),
-                ("method", C.c_int32), ("r_h", C.c_int32), ("r_a", C.c_int32), ("r_b", C.c_int32)]
+                ("method", C.c_int32), ("r_h", C.c_int32), ("r_a", C.c_int32), ("r_b", C.c_int32),
+                ("deflated_norm", C.c_double)]
 
 
 class PlanInfo(C.Structure):

@@ -164,7 +164,10 @@ def test_eig_factorization_matches_oracle(N, W, eps, b, prec):
     assert F.info["kprime"] == kf + r1 + r
     assert F.info["mu_dropped"] <= eps
     assert F.info["ritz_residual"] <= 0.25 * eps
-    print(f"  r1={F.info['r1']} subspace={F.info['subspace']} ritz residual {F.info['ritz_residual']:.2e}", flush=True)
+    # no eigenvalue above eps left outside the kept pairs' span
+    assert 0 < F.info["deflated_norm"] <= eps
+    print(f"  r1={F.info['r1']} subspace={F.info['subspace']} ritz residual {F.info['ritz_residual']:.2e} "
+          f"deflated norm {F.info['deflated_norm']:.2e}", flush=True)
     n = min(r1, len(fac["mu"]))
     np.testing.assert_allclose(np.array(F.mu[:n]), fac["mu"][:n], rtol=0, atol=1e-9)
 
