@@ -830,7 +830,8 @@ hipError_t build_corr_tile(const float *U, int64_t ldu, int N, int r, int log1, 
 // wavefront); lane (col, blk) = (lane % 16, lane / 16) loads rows n1 < R =
 // L1/2 (the rows that can hold n < N, as L >= 2N) of column c0 + col for its
 // wavefront's pair blk, keeps them for its column DFT and stores them in LDS
-// as xs[wave][slot 2 blk + c][q = col R + n1].  After one barrier the column
+// as sample q = col R + n1 of xs[wave][slot 2 blk + c] (at col CS + n1, CS =
+// R + 4: padded against bank conflicts).  After one barrier the column
 // block's partial sum over its 16 R samples runs on the matrix cores for all
 // 32 signals of the workgroup, the T = Q / 32 steps dealt evenly to the four
 // wavefronts: step t takes samples q = 32 t + 8 g + e (e < 8, g = lane / 16);
@@ -857,10 +858,14 @@ __device__ __forceinline__ void colfwd_corr_body(const float *__restrict__ x, in
   constexpr int Q = 16 * R;  // samples of one signal in the column block
   constexpr int T = Q / 32;  // matrix steps
   constexpr int TW = T / kFcWaves;  // steps per wavefront
+  // LDS strides padded by 16 bytes: a column's R samples at stride CS, a
+  // slot (signal) at stride SS, so that the 16 lanes of a store (16 columns)
+  // and of an operand read (16 signals) each hit 16 different bank groups
+  constexpr int CS = R + 4, SS = 16 * CS + 4;
   static_assert(R >= 8 && T % kFcWaves == 0, "column length");
   // the wavefronts' sums (2 x 2 tiles of 4 x 64 values each) fit in xs
-  static_assert(kFcWaves * 8 * Q >= kFcWaves * 4 * 4 * 64, "reduction space");
-  __shared__ float xs[kFcWaves][8][Q];
+  static_assert(kFcWaves * 8 * SS >= kFcWaves * 4 * 4 * 64, "reduction space");
+  __shared__ __align__(16) float xs[kFcWaves][8][SS];
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, blk = lane >> 4;
@@ -881,8 +886,8 @@ __device__ __forceinline__ void colfwd_corr_body(const float *__restrict__ x, in
   }
 #pragma unroll
   for (int n1 = R; n1 < L1; ++n1) a[n1] = cpx<float>{0.f, 0.f};
-  float *xw0 = &xs[wave][2 * blk][col * R];
-  float *xw1 = &xs[wave][2 * blk + 1][col * R];
+  float *xw0 = &xs[wave][2 * blk][col * CS];
+  float *xw1 = &xs[wave][2 * blk + 1][col * CS];
 #pragma unroll
   for (int n1 = 0; n1 < R; n1 += 4) {
     *reinterpret_cast<float4 *>(xw0 + n1) = float4{a[n1].x, a[n1 + 1].x, a[n1 + 2].x, a[n1 + 3].x};
@@ -922,8 +927,10 @@ __device__ __forceinline__ void colfwd_corr_body(const float *__restrict__ x, in
     float bv[2][8];
 #pragma unroll
     for (int sb = 0; sb < 2; ++sb) {
-      // signal 16 sb + s of the workgroup: wavefront 2 sb + s / 8, slot s % 8
-      const float *xr = &xs[2 * sb + (s >> 3)][s & 7][32 * t + 8 * g];
+      // signal 16 sb + s of the workgroup: wavefront 2 sb + s / 8, slot s % 8;
+      // samples q = 32 t + 8 g + e, i.e. column q / R, rows q % R .. + 7
+      const int q0 = 32 * t + 8 * g;
+      const float *xr = &xs[2 * sb + (s >> 3)][s & 7][(q0 / R) * CS + q0 % R];
       const float4 v0 = *reinterpret_cast<const float4 *>(xr);
       const float4 v1 = *reinterpret_cast<const float4 *>(xr + 4);
       bv[sb][0] = v0.x; bv[sb][1] = v0.y; bv[sb][2] = v0.z; bv[sb][3] = v0.w;
@@ -968,6 +975,7 @@ __device__ __forceinline__ void colfwd_corr_body(const float *__restrict__ x, in
   // the four wavefronts' sums, red[wave][jt][sb][lane][v], added in wave order
   __syncthreads();  // every wavefront is done reading xs
   float *red = &xs[0][0][0];
+  static_assert(sizeof(xs) >= 4 * 2 * 2 * 64 * 4 * sizeof(float), "reduction space");
 #pragma unroll
   for (int jt = 0; jt < 2; ++jt)
 #pragma unroll
