@@ -227,13 +227,13 @@ hipError_t copy_f32(const float *src, int64_t lds, float *dst, int64_t ldd, int6
 // ---- Slepian coefficients c = S_K^T x on the matrix cores (coeffs.hip) ----
 // Operand images: columns in 32-sample steps of one 128-byte line each (mode
 // 0: FP32 columns with leading dimension 32 coeffs_steps(N); mode 1: BF16
-// hi/lo pieces), zero past N.
+// hi/lo pieces, step-major), zero past N.
 int64_t coeffs_steps(int64_t N);
 size_t coeffs_image_bytes(int64_t N, int64_t ncols);
 hipError_t coeffs_image(int mode, const float *src, int64_t lds, int64_t N, int64_t ncols, void *dst,
                         hipStream_t st);
 // Reduction splits of one GEMM and the floats of its partial tiles.
-int coeffs_splits(int64_t N, int64_t K, int64_t b);
+int coeffs_splits(int mode, int64_t N, int64_t K, int64_t b);
 size_t coeffs_part_floats(int64_t N, int64_t K, int64_t b);
 // c (K x b, ldc) = S^T X from the images of S (K columns) and X (b <= 65535
 // columns); part holds coeffs_part_floats(N, K, b) floats.

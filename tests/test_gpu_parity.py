@@ -227,10 +227,11 @@ def test_coeffs_match_oracle(plans, N, W, prec):
 @pytest.mark.parametrize("prec", ["fp32", "mixed"])
 def test_coeffs_tiles_and_splits(prec):
     """The coefficient GEMM across its tiling: K = 820 Slepian indices (seven
-    128-row tiles, the last one partial), 300 signals (a full and a partial
-    256-signal tile), N = 2050 (65 steps of 32 samples, the last one partial)
-    cut into two reduction splits of 33 and 32 steps; against the oracle's
-    S_K^T x, and deterministic."""
+    128-row FP32 tiles or four 256-row mixed tiles, the last one partial),
+    300 signals (a full and a partial 256-signal tile), N = 2050 (65 steps
+    of 32 samples, 130 substeps of 16, the last ones partial) cut into two
+    reduction splits of 33 and 32 steps; against the oracle's S_K^T x, and
+    deterministic."""
     N, W, b = 2050, 0.2, 300
     pr = S.SLEPIAN_FP32 if prec == "fp32" else S.SLEPIAN_MIXED
     P = S.slepian_plan(N, W, 1e-6, precision=pr)
