@@ -457,26 +457,47 @@ __global__ __launch_bounds__(256) void k_coeffs_sum(const float *__restrict__ pa
   c[s * ldc + k] = t;
 }
 
-// The BF16 hi/lo image of FP32 columns (mode 1), substep-major: one 16-byte
-// piece per thread, piece q' = (u ncols + col) 4 + q of substep u (samples
-// 16 u ..), q = 2 plane + kb holding samples 16 u + 8 kb + (0..7).
+// The BF16 hi/lo image of FP32 columns (mode 1), substep-major: one thread
+// per (substep u, column), consecutive threads on consecutive columns, so a
+// thread reads the column's 16 samples 16 u .. 16 u + 15 (64 bytes) and the
+// threads' half-lines (u ncols + col) fill consecutive memory; pieces
+// q = 2 plane + kb (hi kb 0, hi kb 1, lo kb 0, lo kb 1).
 __global__ __launch_bounds__(256) void k_coeffs_image_bf16(const float *__restrict__ src, int64_t lds, int64_t N,
                                                             int64_t ncols, int64_t Tu, uint4 *__restrict__ dst) {
-  const int64_t total = ncols * Tu * 4;
+  const int64_t total = ncols * Tu;
   for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total; q += (int64_t)gridDim.x * 256) {
-    const int64_t u = q / (ncols * 4);
-    const int64_t col = (q >> 2) % ncols;
-    const int plane = (int)(q >> 1) & 1, kb = (int)q & 1;
-    const int64_t n0 = 16 * u + 8 * kb;
-    const float *col_src = src + col * lds;
-    bf16x8 v;
+    const int64_t u = q / ncols, col = q % ncols;
+    const int64_t n0 = 16 * u;
+    const float *s = src + col * lds + n0;
+    float v[16];
+    if (n0 + 16 <= N && (reinterpret_cast<uintptr_t>(s) & 15) == 0) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float f = n0 + e < N ? col_src[n0 + e] : 0.f;
-      const __bf16 h = (__bf16)f;
-      v[e] = plane ? (__bf16)(f - (float)h) : h;
+      for (int k = 0; k < 4; ++k) {
+        const float4 f = reinterpret_cast<const float4 *>(s)[k];
+        v[4 * k] = f.x;
+        v[4 * k + 1] = f.y;
+        v[4 * k + 2] = f.z;
+        v[4 * k + 3] = f.w;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = n0 + e < N ? s[e] : 0.f;
     }
-    dst[q] = __builtin_bit_cast(uint4, v);
+    bf16x8 h[2], l[2];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float f = v[8 * kb + e];
+        const __bf16 hi = (__bf16)f;
+        h[kb][e] = hi;
+        l[kb][e] = (__bf16)(f - (float)hi);
+      }
+    uint4 *d = dst + 4 * q;
+    d[0] = __builtin_bit_cast(uint4, h[0]);
+    d[1] = __builtin_bit_cast(uint4, h[1]);
+    d[2] = __builtin_bit_cast(uint4, l[0]);
+    d[3] = __builtin_bit_cast(uint4, l[1]);
   }
 }
 
@@ -514,7 +535,7 @@ hipError_t coeffs_image(int mode, const float *src, int64_t lds, int64_t N, int6
   if (ncols == 0 || N == 0) return hipSuccess;
   const int64_t Tn = coeffs_steps(N);
   if (mode == 1) {
-    SLP_LAUNCH("coeffs_image_bf16x2", k_coeffs_image_bf16, dim3(grid_for(ncols * Tn * 8)), dim3(256), 0, st, src, lds,
+    SLP_LAUNCH("coeffs_image_bf16x2", k_coeffs_image_bf16, dim3(grid_for(ncols * Tn * 2)), dim3(256), 0, st, src, lds,
                N, ncols, 2 * Tn, static_cast<uint4 *>(dst));
   } else {
     SLP_LAUNCH("coeffs_image_f32", k_coeffs_image_f32, dim3(grid_for(ncols * Tn * 32)), dim3(256), 0, st, src, lds,
