@@ -579,11 +579,35 @@ __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ 
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, blk = lane >> 4;
   const int pw = (by * CW + wave) * 4 * PPL;  // first pair of the wavefront, within the slice
-  if (pw >= np) return;                       // uniform per wavefront; the kernel has no barrier
+  // LDSU (BF16 planes, one-step contraction, L1 = 32): the column block's U
+  // tile (hi and lo planes, 16 rows of 1 KB each) is staged once per
+  // workgroup in LDS by direct-to-LDS loads, instead of every wavefront
+  // reading it through the caches.  In LDS the 16-byte piece blk of column
+  // col in a row sits at slot blk ^ ((col / 4) % 4), so that the 16 lanes of
+  // one read (16 columns) hit 16 different bank groups; the lane that fills
+  // a slot fetches the piece that belongs there.  Every wavefront then takes
+  // part in one barrier, so a wavefront past the pairs runs the pass on pair
+  // 0's values and stores nothing.
+  constexpr bool LDSU = MODE == 1 && ONE;
+  static_assert(!LDSU || L1 == 32, "staged tile: 16 rows of 16 columns x 32 j");
+  __shared__ __align__(16) char utl[LDSU ? 2 * 16 * 1024 : 16];
+  if constexpr (LDSU) {
+    if (by * CW * 4 * PPL >= np) return;  // the whole workgroup is past the pairs (uniform)
+    const char *th = static_cast<const char *>(ut) + (int64_t)cb * (16 * 1024);
+    const char *tlo = th + (((int64_t)ROWS << log2) * 32) * 2;
+    const int cq = lane >> 2, sl = lane & 3;
+    const uint32_t src = (uint32_t)cq * 64u + (uint32_t)(sl ^ ((cq >> 2) & 3)) * 16u;
+    for (int k = wave; k < 32; k += CW)
+      __builtin_amdgcn_global_load_lds((k < 16 ? th : tlo) + (k & 15) * 1024 + src,
+                                       (__attribute__((address_space(3))) void *)(utl + k * 1024), 16, 0, 0);
+  } else {
+    if (pw >= np) return;  // uniform per wavefront; the kernel has no barrier
+  }
+  const int pwz = pw < np ? pw : 0;  // LDSU: a wavefront past the pairs reads pair 0
   const int c0 = cb * 16, n2 = c0 + col;
   // lane offsets below stay under 2^32 bytes: pairs pw .. pw + 4 PPL - 1
   // span 4 PPL L complex values; the host bounds ldy, r and b
-  const cpx<float> *Zw = Z + ((int64_t)pw << logL) + c0;
+  const cpx<float> *Zw = Z + ((int64_t)pwz << logL) + c0;
   cpx<float> a[PPL][L1];
 #pragma unroll
   for (int h = 0; h < PPL; ++h) {
@@ -643,6 +667,11 @@ __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ 
       ahi1[e] = hh;
       alo1[e] = (__bf16)(dcv[e] - (float)hh);
     }
+  }
+  if constexpr (LDSU) {
+    // this wavefront's tile loads have landed; the barrier makes all visible
+    __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8));  // vmcnt(0)
+    __syncthreads();
   }
   // every row of this column block lies below N: stores need only the
   // signal check (uniform per wavefront)
@@ -710,11 +739,20 @@ __device__ __forceinline__ void colinv_corr_body(const cpx<float> *__restrict__ 
       const uint32_t lo = (uint32_t)col * rp + 8u * blk;
       if constexpr (one) {
         bf16x8 bhi[RC], blo[RC];
+        if constexpr (LDSU) {
+          const int so = col * 64 + ((blk ^ ((col >> 2) & 3)) << 4);
 #pragma unroll
-        for (int i = 0; i < RC; ++i) {
-          const uint32_t o = (lo + i * tile_row) * 2u;
-          bhi[i] = ld_at(reinterpret_cast<const bf16x8 *>(Th), o);
-          blo[i] = ld_at(reinterpret_cast<const bf16x8 *>(Tl), o);
+          for (int i = 0; i < RC; ++i) {
+            bhi[i] = *reinterpret_cast<const bf16x8 *>(utl + (rc + i) * 1024 + so);
+            blo[i] = *reinterpret_cast<const bf16x8 *>(utl + (16 + rc + i) * 1024 + so);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < RC; ++i) {
+            const uint32_t o = (lo + i * tile_row) * 2u;
+            bhi[i] = ld_at(reinterpret_cast<const bf16x8 *>(Th), o);
+            blo[i] = ld_at(reinterpret_cast<const bf16x8 *>(Tl), o);
+          }
         }
 #pragma unroll
         for (int i = 0; i < RC; ++i) {
