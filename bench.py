@@ -858,8 +858,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    # 200 untimed steps (~30 ms of work): after the CPU leg the GPU has idled
-    # for seconds and needs about that long to bring its clocks back up
+    # 200 untimed steps (~30 ms of work) before the timed ones
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -919,44 +918,19 @@ def main():
     work = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
-    # The CPU leg: the FP64 oracle timed on a sample of the signals; its
-    # outputs also gate the GPU results for those signals (both precisions).
+    # The GPU outputs for a sample of the signals in every precision, kept on
+    # the host: the CPU oracle leg gates them after the timed region, so the
+    # seconds of CPU work do not leave the GPU idle (and its clocks down)
+    # right before the timed steps.
     prec = S.SLEPIAN_MIXED if args.precision == "mixed" else S.SLEPIAN_FP32
-    cpu = None
-    err = err_sel = None
-    extra_err = None
-    fac_check = None
+    ns = min(b, 32)
+    gpu_out = {}
     if not args.no_cpu:
-        ns = min(b, 32)
-        log(f"bench: timing the CPU oracle on {ns} signals")
-        cpu, ref, exact, fcpu, fref = cpu_baseline(N, W, eps, x[:ns].double().cpu().numpy(), args.cpu_seconds)
-        fac_check = {"sample": x[:ns].contiguous(), "ref": fref, "cpu": fcpu}
-        errs = {}
-        for p in (S.SLEPIAN_FP32, prec):
+        for p in (S.SLEPIAN_FP32, S.SLEPIAN_BF16_RAW, prec):
             S.slepian_project(plan, x, y, work=work, precision=p)
             torch.cuda.synchronize()
-            ys = y[:ns].double().cpu().numpy()
-            errs[p] = float((np.linalg.norm(ys - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
-        err, err_sel = errs[S.SLEPIAN_FP32], errs[prec]
-        log(f"bench: max rel err vs oracle on signals 0..{ns - 1}: fp32 {err:.3e}, {args.precision} {err_sel:.3e}")
-        if not (err <= 1e-5 and err_sel <= 1e-5):
-            log("bench: parity gate failed; no throughput reported")
-            sys.exit(1)
-        # the BF16 correction without its lo terms, and the distance of the
-        # selected precision's result from the exact projection
-        S.slepian_project(plan, x, y, work=work, precision=S.SLEPIAN_BF16_RAW)
-        torch.cuda.synchronize()
-        ys = y[:ns].double().cpu().numpy()
-        err_raw = float((np.linalg.norm(ys - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
-        S.slepian_project(plan, x, y, work=work, precision=prec)
-        torch.cuda.synchronize()
-        ys = y[:ns].double().cpu().numpy()
-        xn = np.linalg.norm(x[:ns].double().cpu().numpy(), axis=1)
-        err_exact = float((np.linalg.norm(ys - exact, axis=1) / xn).max())
-        log(f"bench: bf16 without lo terms {err_raw:.3e} vs the oracle; {args.precision} vs the exact projection "
-            f"{err_exact:.3e} of ||x|| (Corollary 2 bound eps = {eps:g})")
-        extra_err = {"bf16_raw_vs_oracle": err_raw, "vs_exact_projection_rel_to_x": err_exact,
-                     "corollary2_bound_rel_to_x": eps}
+            gpu_out[p] = y[:ns].double().cpu().numpy()
+        x_sample = x[:ns].double().cpu().numpy()
 
     stream = torch.cuda.current_stream(dev)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -984,6 +958,35 @@ def main():
     # per-kernel durations with HIP events around each launch (traced pass)
     kernels, roofline = traced_roofline(lambda: S.slepian_project(plan, x, y, work=work, precision=prec),
                                         args.steps, N, b, info, args.workload)
+
+    # The CPU leg: the FP64 oracle timed on the sample; its outputs gate the
+    # GPU results kept above (both precisions) before anything is reported.
+    cpu = None
+    err = err_sel = None
+    extra_err = None
+    fac_check = None
+    if not args.no_cpu:
+        log(f"bench: timing the CPU oracle on {ns} signals")
+        cpu, ref, exact, fcpu, fref = cpu_baseline(N, W, eps, x_sample, args.cpu_seconds)
+        fac_check = {"sample": x[:ns].contiguous(), "ref": fref, "cpu": fcpu}
+
+        def rel(ys, r):
+            return float((np.linalg.norm(ys - r, axis=1) / np.linalg.norm(r, axis=1)).max())
+
+        err, err_sel = rel(gpu_out[S.SLEPIAN_FP32], ref), rel(gpu_out[prec], ref)
+        log(f"bench: max rel err vs oracle on signals 0..{ns - 1}: fp32 {err:.3e}, {args.precision} {err_sel:.3e}")
+        if not (err <= 1e-5 and err_sel <= 1e-5):
+            log("bench: parity gate failed; no throughput reported")
+            sys.exit(1)
+        # the BF16 correction without its lo terms, and the distance of the
+        # selected precision's result from the exact projection
+        err_raw = rel(gpu_out[S.SLEPIAN_BF16_RAW], ref)
+        xn = np.linalg.norm(x_sample, axis=1)
+        err_exact = float((np.linalg.norm(gpu_out[prec] - exact, axis=1) / xn).max())
+        log(f"bench: bf16 without lo terms {err_raw:.3e} vs the oracle; {args.precision} vs the exact projection "
+            f"{err_exact:.3e} of ||x|| (Corollary 2 bound eps = {eps:g})")
+        extra_err = {"bf16_raw_vs_oracle": err_raw, "vs_exact_projection_rel_to_x": err_exact,
+                     "corollary2_bound_rel_to_x": eps}
     plain = None
     if not args.no_plain:
         plain = plain_fp32_per_signal(plan, x, N, W, eps, info, dev, ms_per_step, work)

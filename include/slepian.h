@@ -365,11 +365,13 @@ int slepian_factor_recover(slepian_factor_t f, const float *c, int64_t ldc, floa
  * computes all K Slepian vectors on the GPU and keeps them in the plan
  * (N*K*4 bytes, plus as many again for their BF16 hi/lo halves in plans of
  * MIXED or BF16_RAW precision); ENOTSUP if N*K*4 bytes exceed 16 GiB.  The
- * product is a library GEMM (hipBLASLt) on the matrix cores: FP32 for FP32
- * plans, otherwise three BF16 products of the hi/lo halves (hi*hi + hi*lo +
- * lo*hi) accumulated in FP32.  Vector signs follow the convention of
- * slepian_plan_eigenpairs.  c: K x batch FP32, ldc >= K; EHIP if the library
- * fails, ENOTSUP if it has no algorithm for the shape. */
+ * product runs on the library's own matrix-core GEMM: FP32 matrix
+ * instructions for FP32 plans, otherwise three BF16 products of the hi/lo
+ * halves (hi*hi + hi*lo + lo*hi) accumulated in FP32; partial sums over
+ * the sample dimension are added in a fixed order, so results are
+ * reproducible.  Vector signs follow the convention of
+ * slepian_plan_eigenpairs.  c: K x batch FP32, ldc >= K, no overlap with x;
+ * EHIP if a launch fails. */
 int slepian_coeffs(slepian_plan_t plan, const float *x, int64_t ldx, float *c, int64_t ldc,
                    int64_t batch, void *work, size_t work_bytes, void *stream);
 

@@ -924,25 +924,22 @@ __device__ __forceinline__ void colfwd_corr_body(const float *__restrict__ x, in
   }
 #pragma unroll
   for (int n1 = R; n1 < L1; ++n1) a[n1] = cpx<float>{0.f, 0.f};
-  float *xw0 = &xs[wave][2 * blk][col * CS];
-  float *xw1 = &xs[wave][2 * blk + 1][col * CS];
+  // The column's twiddles, loaded with the samples so that no load sits
+  // between the stores of Z below: W_L^{k1 n2} = W_L^{(k1 mod 8) n2}
+  // W_L^{8 (k1 div 8) n2}, seven plus L1/8 - 1 table entries per lane.
+  constexpr int TH = L1 / 8;
+  const cpx<float> *tc = tcol + n2;
+  cpx<float> tl[8], th[TH];
 #pragma unroll
-  for (int n1 = 0; n1 < R; n1 += 4) {
-    *reinterpret_cast<float4 *>(xw0 + n1) = float4{a[n1].x, a[n1 + 1].x, a[n1 + 2].x, a[n1 + 3].x};
-    *reinterpret_cast<float4 *>(xw1 + n1) = float4{a[n1].y, a[n1 + 1].y, a[n1 + 2].y, a[n1 + 3].y};
-  }
-  reg::dft<L1, -1>(a);
-  if (pv) {
-    cpx<float> *Zp = Z + ((int64_t)p << logL) + n2;
-    Zp[0] = a[0];
+  for (int k = 1; k < 8; ++k) tl[k] = tc[k << log2];
 #pragma unroll
-    for (int k1 = 1; k1 < L1; ++k1) Zp[(int64_t)k1 << log2] = cmul(a[k1], tcol[(k1 << log2) + n2]);
-  }
+  for (int m = 1; m < TH; ++m) th[m] = tc[(8 * m) << log2];
   const int s = lane & 15, g = lane >> 4;
   const int njt = (r + 15) >> 4;  // 16-column tiles of U (1 or 2)
-  // the wavefront's A operands, in flight across the barrier: per step and
-  // U tile, two 16-byte pieces (FP32 samples e < 4 and e >= 4, or the BF16
-  // hi and lo planes)
+  // the wavefront's A operands, loaded with the samples too, so that the
+  // matrix phase waits on no memory operation issued after the stores of Z:
+  // per step and U tile, two 16-byte pieces (FP32 samples e < 4 and e >= 4,
+  // or the BF16 hi and lo planes)
   float4 ua[TW][2][2];
 #pragma unroll
   for (int tt = 0; tt < TW; ++tt)
@@ -953,6 +950,28 @@ __device__ __forceinline__ void colfwd_corr_body(const float *__restrict__ x, in
       ua[tt][jt][0] = Tj[lane];
       ua[tt][jt][1] = Tj[64 + lane];
     }
+  float *xw0 = &xs[wave][2 * blk][col * CS];
+  float *xw1 = &xs[wave][2 * blk + 1][col * CS];
+#pragma unroll
+  for (int n1 = 0; n1 < R; n1 += 4) {
+    *reinterpret_cast<float4 *>(xw0 + n1) = float4{a[n1].x, a[n1 + 1].x, a[n1 + 2].x, a[n1 + 3].x};
+    *reinterpret_cast<float4 *>(xw1 + n1) = float4{a[n1].y, a[n1 + 1].y, a[n1 + 2].y, a[n1 + 3].y};
+  }
+  reg::dft<L1, -1>(a);
+  // every load of the lane (samples, twiddles, A operands) has landed before
+  // the first store of Z, so the matrix phase below waits on none of the
+  // stores (vector memory operations complete in order)
+  __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8));  // vmcnt(0)
+  if (pv) {
+    cpx<float> *Zp = Z + ((int64_t)p << logL) + n2;
+    Zp[0] = a[0];
+#pragma unroll
+    for (int k1 = 1; k1 < L1; ++k1) {
+      const int kl = k1 & 7, kh = k1 >> 3;
+      const cpx<float> w = kh == 0 ? tl[kl] : (kl == 0 ? th[kh] : cmul(tl[kl], th[kh]));
+      Zp[(int64_t)k1 << log2] = cmul(a[k1], w);
+    }
+  }
   __syncthreads();
   f32x4 acc[2][2];
 #pragma unroll
