@@ -181,11 +181,29 @@ __device__ __forceinline__ void corr_partial_body(const float *__restrict__ X, i
   }
 }
 
+// Workgroup (bx, by) of an nx x ny grid, dealt so that the ny workgroups of
+// one bx (which share U's rows for those samples) run on one XCD: the
+// dispatcher hands consecutive workgroups to the eight XCDs in turn, so the
+// k-th workgroup of XCD x takes bx = 8 (k / ny) + x, by = k % ny.  Grids with
+// nx not a multiple of 8 keep the plain order.
+struct Blk2 {
+  int bx, by;
+};
+__device__ __forceinline__ Blk2 xcd_blocks() {
+  const int nx = gridDim.x, ny = gridDim.y;
+  if (nx & 7) return Blk2{(int)blockIdx.x, (int)blockIdx.y};
+  const int64_t l = (int64_t)blockIdx.x + (int64_t)nx * blockIdx.y;
+  const int x = (int)(l & 7);
+  const int64_t k = l >> 3;
+  return Blk2{(int)(8 * (k / ny) + x), (int)(k % ny)};
+}
+
 template <int MODE, int NB, int KS, bool VEC>
 __global__ __launch_bounds__(256) void k_corr_partial_mfma(const float *__restrict__ X, int64_t ldx, int N, int b,
                                                            const float *__restrict__ U, int64_t ldu, int r,
                                                            float *__restrict__ part, int rpad) {
-  corr_partial_body<MODE, NB, KS, VEC>(X, ldx, N, b, U, ldu, r, part, rpad, blockIdx.x, blockIdx.y, blockIdx.z);
+  const Blk2 w = xcd_blocks();
+  corr_partial_body<MODE, NB, KS, VEC>(X, ldx, N, b, U, ldu, r, part, rpad, w.bx, w.by, blockIdx.z);
 }
 
 // The same partials for r > 32 in one pass over x: each workgroup loads its
