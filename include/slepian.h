@@ -391,6 +391,11 @@ int slepian_coeffs(slepian_plan_t plan, const float *x, int64_t ldx, float *c, i
  *                      rho = B y - (B^2 + alpha I) x, x += M rho, where M is an
  *                      FP32 fast approximation of (B^2 + alpha I)^{-1}, until
  *                      max_s ||rho_s|| / ||B y_s|| <= tol or max_iter sweeps.
+ *                      B x and B^2 x of the starting point come from FP64
+ *                      products; each correction e then adds B e and B (B e)
+ *                      from FP32 products (rounding near 1e-7 ||e||, far
+ *                      below the tolerance), so a sweep costs two FP32
+ *                      products and the fast operator M.
  *                      max_iter = 0 returns the fast operator's output.  alpha
  *                      must equal the plan's alpha (opts.alpha).
  * y: N x batch FP32; x: N x batch FP64 (FP64 so that the refined residual can

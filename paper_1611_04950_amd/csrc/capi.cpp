@@ -2394,9 +2394,14 @@ int slepian_lsq(slepian_plan_t P, int mode, double alpha, const float *y, int64_
     int it = 0;
     double rel = INFINITY, first = INFINITY;
     bool conv = false;
+    // t = B x and u = B^2 x of the current iterate, in FP64: FP64 products for
+    // the starting point, then, since B (x + e) = B x + B e, each correction
+    // e (FP32 values) adds B e and B (B e) from FP32 products.  Their
+    // rounding, about 1e-7 of the correction's size (itself about 1e-7 of
+    // x's after the first step), stays far below the residual tolerance.
+    run_b64(P, x, ldx, w.t, N, b, w.bw, st);
+    run_b64(P, w.t, N, w.u, N, b, w.bw, st);
     for (;; ++it) {
-      run_b64(P, x, ldx, w.t, N, b, w.bw, st);
-      run_b64(P, w.t, N, w.u, N, b, w.bw, st);
       HIPCHK(lsq_residual(w.By, w.u, x, ldx, alpha, w.rho, N, b, st));
       HIPCHK(col_norms(w.rho, N, N, b, w.nr, w.npart, st));
       HIPCHK(hipMemcpyAsync(nr.data(), w.nr, b * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -2417,6 +2422,11 @@ int slepian_lsq(slepian_plan_t P, int mode, double alpha, const float *y, int64_
       HIPCHK(cast_f64_to_f32(w.rho, N, w.rho32, N, N, b, st));
       run_fast_op(P, P->tikm, betaM, gammaM, w.rho32, N, w.e32, N, b, w.pw, st);
       HIPCHK(add_f32_to_f64(w.e32, N, x, ldx, N, b, st));
+      static const OpSet none;
+      run_fast_op(P, none, 1.0f, 0.0f, w.e32, N, w.rho32, N, b, w.pw, st);   // B e
+      HIPCHK(add_f32_to_f64(w.rho32, N, w.t, N, N, b, st));
+      run_fast_op(P, none, 1.0f, 0.0f, w.rho32, N, w.x32, N, b, w.pw, st);   // B (B e)
+      HIPCHK(add_f32_to_f64(w.x32, N, w.u, N, N, b, st));
     }
     if (rep) {
       rep->iterations = it;
