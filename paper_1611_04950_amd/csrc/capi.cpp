@@ -342,7 +342,9 @@ struct B64Ws {
 B64Ws carve_b64(const Plan *P, int64_t b, Carver &cv) {
   B64Ws w;
   const int64_t pairs = (b + 1) / 2;
-  w.slice = (int64_t)conv_workspace_pairs(P->g64, pairs, sizeof(cpx<double>), slice_budget());
+  // FP64 slices get four times the FP32 budget: their column passes hold
+  // fewer columns per compute unit and gain more from longer launches
+  w.slice = (int64_t)conv_workspace_pairs(P->g64, pairs, sizeof(cpx<double>), 4 * slice_budget());
   if (!P->g64.single()) w.Z = cv.take<cpx<double>>((size_t)w.slice * (size_t)P->L);
   return w;
 }
