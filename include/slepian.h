@@ -395,7 +395,11 @@ int slepian_coeffs(slepian_plan_t plan, const float *x, int64_t ldx, float *c, i
  *                      products; each correction e then adds B e and B (B e)
  *                      from FP32 products (rounding near 1e-7 ||e||, far
  *                      below the tolerance), so a sweep costs two FP32
- *                      products and the fast operator M.
+ *                      products and the fast operator M.  The residual so
+ *                      tracked (reported in rep) lies within about 1e-13 of
+ *                      ||B y|| of the one recomputed from scratch in FP64;
+ *                      convergence requires it to be <= tol - 1e-12, so a
+ *                      tol <= 1e-12 ends in ENOCONV after max_iter sweeps.
  *                      max_iter = 0 returns the fast operator's output.  alpha
  *                      must equal the plan's alpha (opts.alpha).
  * y: N x batch FP32; x: N x batch FP64 (FP64 so that the refined residual can

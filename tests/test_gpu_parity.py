@@ -180,6 +180,35 @@ def test_pinv_matches_oracle(plans, N, W, eps):
         assert dev.max() <= 3 * eps + 1e-5
 
 
+def test_tikhonov_residual_over_several_sweeps(plans):
+    """The refinement keeps B x and B^2 x of the iterate in FP64 and updates
+    them with FP32 products of each correction; after several sweeps (an
+    unreachable tolerance, so every sweep runs) the residual it reports must
+    still be the residual of the x it returns, recomputed from scratch on
+    the CPU in FP64 (Corollary 4's normal equations, residual definition)."""
+    import ctypes as C
+    N, W, eps, alpha, b = 2000, 0.1, 1e-6, 1e-2, 3
+    P = plans(N, W, eps, alpha)
+    y = synth.sinusoids(N, b, W, 20, 10.0, 77, device="cuda")
+    yh = y.double().cpu().numpy().T
+    By = o.apply_prolate(N, W, yh)
+    for sweeps in (1, 2, 3):
+        xd = torch.empty(y.shape, dtype=torch.float64, device="cuda")
+        rep = S.LsqReport()
+        st = S._lib.slepian_lsq(P.handle, S.SLEPIAN_TIKHONOV, alpha, S._ptr(y), N, S._ptr(xd), N, b, 0.0, sweeps,
+                                None, 0, None, C.byref(rep))
+        assert st == S.SLEPIAN_ENOCONV and rep.iterations == sweeps, (st, rep.iterations)
+        # the report describes the returned x (the residual after the last
+        # correction, computed from the incrementally updated B x, B^2 x)
+        xh = xd.cpu().numpy().T
+        res = By - o.apply_prolate(N, W, o.apply_prolate(N, W, xh)) - alpha * xh
+        cpu = float((np.linalg.norm(res, axis=0) / np.linalg.norm(By, axis=0)).max())
+        _log(f"sweeps {sweeps}: reported {rep.rel_residual:.3e}, CPU FP64 {cpu:.3e}")
+        assert abs(rep.rel_residual - cpu) <= 1e-12 + 1e-3 * cpu, (sweeps, rep.rel_residual, cpu)
+    exact = o.tikhonov_exact(N, W, alpha, yh).T
+    assert rel_err(xd.cpu().numpy(), exact).max() <= 1e-8
+
+
 @pytest.mark.parametrize("N,W,eps,alpha", [(1024, 1 / 16, 1e-6, 1e-3), (2000, 0.1, 1e-6, 1e-2)])
 def test_tikhonov_fast_and_refined(plans, N, W, eps, alpha):
     P = plans(N, W, eps, alpha)
