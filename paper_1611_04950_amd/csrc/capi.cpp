@@ -352,7 +352,7 @@ B64Ws carve_b64(const Plan *P, int64_t b, Carver &cv) {
 
 struct TikWs {
   float *x32, *rho32, *e32;
-  double *y64, *By, *t, *u, *rho, *nBy, *nr;
+  double *y64, *By, *t, *u, *nBy, *nr;
   double *npart = nullptr;                    // column-norm partial sums
   double *part64 = nullptr, *dC64 = nullptr;  // FP64 correction of the starting point
   ProjWs pw;
@@ -369,7 +369,6 @@ TikWs carve_tik(const Plan *P, int64_t b, Carver &cv) {
   w.By = cv.take<double>(nb);
   w.t = cv.take<double>(nb);
   w.u = cv.take<double>(nb);
-  w.rho = cv.take<double>(nb);
   w.nBy = cv.take<double>(b);
   w.nr = cv.take<double>(b);
   w.npart = cv.take<double>((size_t)b * kNormParts);
@@ -2405,8 +2404,7 @@ int slepian_lsq(slepian_plan_t P, int mode, double alpha, const float *y, int64_
     run_b64(P, x, ldx, w.t, N, b, w.bw, st);
     run_b64(P, w.t, N, w.u, N, b, w.bw, st);
     for (;; ++it) {
-      HIPCHK(lsq_residual(w.By, w.u, x, ldx, alpha, w.rho, N, b, st));
-      HIPCHK(col_norms(w.rho, N, N, b, w.nr, w.npart, st));
+      HIPCHK(lsq_residual_norms(w.By, w.u, x, ldx, alpha, w.rho32, N, b, w.nr, w.npart, st));
       HIPCHK(hipMemcpyAsync(nr.data(), w.nr, b * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       rel = 0.0;
@@ -2426,7 +2424,6 @@ int slepian_lsq(slepian_plan_t P, int mode, double alpha, const float *y, int64_
         break;
       }
       if (it >= max_iter) break;
-      HIPCHK(cast_f64_to_f32(w.rho, N, w.rho32, N, N, b, st));
       run_fast_op(P, P->tikm, betaM, gammaM, w.rho32, N, w.e32, N, b, w.pw, st);
       HIPCHK(add_f32_to_f64(w.e32, N, x, ldx, N, b, st));
       static const OpSet none;

@@ -296,9 +296,11 @@ hipError_t pack_scale(const float *c, int64_t ldc, int kf, int64_t N, int64_t b,
                       const float *w, float *dC, hipStream_t st);
 
 // ---- Least-squares refinement helpers (lsq.hip) ----
-// rho = By - u - alpha x (all FP64, N x b with leading dimension N except x: ldx)
-hipError_t lsq_residual(const double *By, const double *u, const double *x, int64_t ldx, double alpha, double *rho,
-                        int64_t N, int64_t b, hipStream_t st);
+// rho = By - u - alpha x formed in FP64 (N x b with leading dimension N except
+// x: ldx), written to rho32 as FP32, with the column norms of the FP64 values
+// (the same sums as col_norms; part: b * kNormParts doubles)
+hipError_t lsq_residual_norms(const double *By, const double *u, const double *x, int64_t ldx, double alpha,
+                              float *rho32, int64_t N, int64_t b, double *norms, double *part, hipStream_t st);
 // norms[s] = ||v_s||_2 (FP64, fixed summation order); part: b * kNormParts doubles of scratch
 constexpr int kNormParts = 256;
 hipError_t col_norms(const double *v, int64_t ldv, int64_t N, int64_t b, double *norms, double *part,
